@@ -1,0 +1,236 @@
+"""ln L(lambda) for the many-1D galaxy-catalogue likelihood (TEST INFRASTRUCTURE).
+
+Follows Sect. 2 of the paper:
+
+eq. hyperlike   ln L = sum_i ln I_i - N_obs ln xi   (reading: no additive
+                constant; the proportionality sign is taken as equality)
+eq. like-integrals + eq. gw-kernel-many1d
+                I_i = sum_{pixels r} c_ir sum_{j in r} w_j A_j,
+                A_j = sum_g tau_g N(z_g; z_j, h_i) n_r(z_g) g(z_g),
+                g(z) = psi(z) / [(1+z)^3 d d_L^gw/dz]   (eq. jacobian, with
+                p_cbc = p_cat psi, complete catalogue f_R = 1)
+                The KDE is (1/N_r) sum_j w_j N(z; z_j, h): not divided by
+                sum w (reading), the 1/N_r sits in c_ir.
+Sect. 2.2       xi = (1/N_inj) sum_{detected} s_j,
+                s_j = p(m1,m2) n_tot(z_j) psi(z_j) / [(1+z_j)^3 D'(z_j) p_draw_j]
+                (reading: the 1/p_draw of the cited estimators is restored;
+                the sky integral of p_cat is n_tot since detection does not
+                depend on the sky), N_eff as printed with sums over detected.
+
+Bandwidth (the paper is silent; reading): one Gaussian bandwidth per
+(event, lambda) from all of the event's in-region samples: Scott's rule with
+the Kish effective size n_eff = W1^2/W2 and the unbiased weighted variance,
+h = max(sigma * n_eff^(-1/5), 2 dz); sigma = 0 when W1^2 - W2 <= 1e-12 W1^2.
+This is scipy.stats.gaussian_kde's weighted Scott rule (the pin).
+
+Kernel support: T=None sums over the whole grid (the dense definition);
+a finite T keeps grid points with |z_g - z_j| <= T h (the paper evaluates
+the kernels only where samples are, Sect. 2.3).
+
+Degenerate values: I_i = 0 or xi = 0 gives ln L = -inf; a lambda outside the
+domain (H0 <= 0, Om outside (0,1], Xi0 <= 0, mmin >= mmax, sigma_g <= 0,
+lambda_g outside [0,1], z_p <= -1, non-finite, or d_L^gw not increasing on
+[0, 25]) gives -inf; a distance beyond d_L^gw(25) gives NaN.
+
+Pins: tests/test_oracle_likelihood.py (KDE vs scipy gaussian_kde, grid
+normalisation of the Gaussian, Gaussian-convolution closed form, constant
+rescalings, permutations, distance-scaling identity, the analytic xi of a
+draw density proportional to the population).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import cosmology as cosmo
+from .population import mass_weight, psi
+
+
+@dataclass
+class Pixel:
+    pix: int
+    c: float
+    dl: np.ndarray
+    m1d: np.ndarray
+    m2d: np.ndarray
+
+
+@dataclass
+class Event:
+    pixels: list = field(default_factory=list)
+
+
+@dataclass
+class Catalog:
+    grid: np.ndarray          # z_g, uniform
+    rows: dict                # HEALPix id -> n_r(z_g)
+    n_tot: np.ndarray
+
+
+@dataclass
+class InjectionSet:
+    dl: np.ndarray
+    m1d: np.ndarray
+    m2d: np.ndarray
+    ln_pdraw: np.ndarray
+    n_total: int
+
+
+def trapezoid(grid):
+    dz = grid[1] - grid[0]
+    tau = np.full(grid.size, dz)
+    tau[0] = tau[-1] = 0.5 * dz
+    return tau
+
+
+def lambda_in_domain(lam) -> bool:
+    lam = np.asarray(lam, dtype=np.float64)
+    if not np.all(np.isfinite(lam)):
+        return False
+    h0, om, xi0, _n, _a, _b, mmin, mmax, _mu, sg, lg, _g, _k, zp = lam
+    return (h0 > 0 and 0 < om <= 1 and xi0 > 0 and 0 < mmin < mmax and sg > 0
+            and 0 <= lg <= 1 and zp > -1)
+
+
+def redshift_and_weight(dl, m1d, m2d, lam):
+    """z_j from d_L^gw (Sect. 2.1), source masses m = m_det/(1+z), w = p(m1,m2)."""
+    z = cosmo.invert_dl(dl, lam[0], lam[1], lam[2], lam[3])
+    w = mass_weight(m1d / (1.0 + z), m2d / (1.0 + z), lam)
+    return z, w
+
+
+def bandwidth(z, w, dz):
+    w1 = np.sum(w)
+    if not w1 > 0:
+        return None
+    w2 = np.sum(w * w)
+    mu = np.sum(w * z) / w1
+    if w1 * w1 - w2 <= 1e-12 * w1 * w1:
+        var = 0.0
+    else:
+        var = np.sum(w * (z - mu) ** 2) / (w1 - w2 / w1)
+    neff = w1 * w1 / w2
+    return max(math.sqrt(var) * neff ** (-0.2), 2.0 * dz)
+
+
+def grid_factor(grid, lam):
+    h0, om, xi0, n = lam[0], lam[1], lam[2], lam[3]
+    return psi(grid, lam[11], lam[12], lam[13]) / (
+        (1.0 + grid) ** 3 * cosmo.ddl_gw_dz(grid, h0, om, xi0, n))
+
+
+def event_integral(pixels_z, pixels_w, pixels_c, pixels_row, grid, tau, gz, T=None):
+    """(I_i, h_i) of one event given its per-pixel (z, w, c, n_r)."""
+    dz = grid[1] - grid[0]
+    z_all = np.concatenate(pixels_z)
+    w_all = np.concatenate(pixels_w)
+    h = bandwidth(z_all, w_all, dz)
+    if h is None:
+        return 0.0, float("nan")
+    total = 0.0
+    norm = 1.0 / (h * math.sqrt(2.0 * math.pi))
+    for zr, wr, c, nr in zip(pixels_z, pixels_w, pixels_c, pixels_row):
+        f = tau * nr * gz
+        if T is None:
+            g = slice(None)
+        else:
+            lo = np.searchsorted(grid, zr.min() - T * h, side="left")
+            hi = np.searchsorted(grid, zr.max() + T * h, side="right")
+            g = slice(lo, hi)
+        diff = grid[g][None, :] - zr[:, None]
+        k = np.exp(-0.5 * (diff / h) ** 2) * norm
+        if T is not None:
+            k = np.where(np.abs(diff) <= T * h, k, 0.0)
+        a = k @ f[g]
+        total += c * float(wr @ a)
+    return total, h
+
+
+def selection(inj: InjectionSet, cat: Catalog, lam):
+    """(xi, N_eff) by the injection estimator of Sect. 2.2."""
+    z, w = redshift_and_weight(inj.dl, inj.m1d, inj.m2d, lam)
+    ntot = np.interp(z, cat.grid, cat.n_tot, left=0.0, right=0.0)
+    jac = (1.0 + z) ** 3 * cosmo.ddl_gw_dz(z, lam[0], lam[1], lam[2], lam[3])
+    s = w * ntot * psi(z, lam[11], lam[12], lam[13]) / (jac * np.exp(inj.ln_pdraw))
+    s1 = float(np.sum(s))
+    s2 = float(np.sum(s * s))
+    xi = s1 / inj.n_total
+    den = s2 - s1 * s1 / inj.n_total
+    neff = (s1 * s1 / den if den > 0 else np.inf) if s1 > 0 else 0.0
+    return xi, neff, z
+
+
+# -------------------------------------------------------------------------
+# ln L for one lambda
+# -------------------------------------------------------------------------
+_WORK: dict = {}
+
+
+def _event_worker(i):
+    d = _WORK
+    ev = d["events"][i]
+    zs, ws, cs, rs = [], [], [], []
+    for px in ev.pixels:
+        sl = d["slices"][i][len(zs)]
+        zs.append(d["z"][sl]); ws.append(d["w"][sl]); cs.append(px.c)
+        rs.append(d["cat"].rows[px.pix])
+    return event_integral(zs, ws, cs, rs, d["cat"].grid, d["tau"], d["gz"], d["T"])
+
+
+def lnl(events, cat: Catalog, inj: InjectionSet, lam, T=None, workers: int = 1,
+        event_subset=None):
+    """ln L and its parts at one lambda.
+
+    Returns dict(lnl, lnI[E] (NaN for events not in event_subset), h[E], ln_xi, neff).
+    With event_subset, lnl is the partial sum over those events minus
+    len(subset) ln xi (used for sampled parity checks).
+    """
+    lam = np.asarray(lam, dtype=np.float64)
+    E = len(events)
+    sub = list(range(E)) if event_subset is None else list(event_subset)
+    res = {"lnI": np.full(E, np.nan), "h": np.full(E, np.nan), "ln_xi": np.nan,
+           "neff": np.nan, "lnl": -np.inf}
+    if not lambda_in_domain(lam):
+        return res
+    # all samples of the selected events, inverted at once
+    dls, m1s, m2s, slices = [], [], [], {}
+    off = 0
+    for i in sub:
+        sl_i = []
+        for px in events[i].pixels:
+            n = px.dl.size
+            dls.append(px.dl); m1s.append(px.m1d); m2s.append(px.m2d)
+            sl_i.append(slice(off, off + n))
+            off += n
+        slices[i] = sl_i
+    try:
+        z, w = redshift_and_weight(np.concatenate(dls), np.concatenate(m1s),
+                                   np.concatenate(m2s), lam)
+        xi, neff, zi = selection(inj, cat, lam)
+    except cosmo.NonMonotone:
+        return res
+    if np.any(np.isnan(z)) or np.any(np.isnan(zi)):
+        res["lnl"] = np.nan
+        return res
+    _WORK.update(events=events, slices=slices, z=z, w=w, cat=cat, tau=trapezoid(cat.grid),
+                 gz=grid_factor(cat.grid, lam), T=T)
+    if workers > 1 and len(sub) > 1:
+        import multiprocessing as mp
+        with mp.get_context("fork").Pool(workers) as pool:
+            out = pool.map(_event_worker, sub, chunksize=max(1, len(sub) // (4 * workers)))
+    else:
+        out = [_event_worker(i) for i in sub]
+    _WORK.clear()
+    for i, (I, h) in zip(sub, out):
+        res["lnI"][i] = math.log(I) if I > 0 else -np.inf
+        res["h"][i] = h
+    res["ln_xi"] = math.log(xi) if xi > 0 else -np.inf
+    res["neff"] = neff
+    lnI = res["lnI"][sub]
+    if np.any(np.isneginf(lnI)) or xi <= 0:
+        res["lnl"] = -np.inf
+    else:
+        res["lnl"] = float(np.sum(lnI) - len(sub) * math.log(xi))
+    return res

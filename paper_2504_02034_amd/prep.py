@@ -1,0 +1,214 @@
+"""Lambda-independent preprocessing: raw catalogue / posterior samples -> the
+arrays the C-ABI library takes (``chimera_set_catalog``, ``chimera_add_events``).
+
+The paper computes these once before inference (Sect. 2.3 steps a-c; the
+many-1D kernel, eq. gw-kernel-many1d, reuses the pixelisation and the p_cat
+grid, and its 2-D sky-KDE normalisation factors are independent of lambda).
+
+* region (Sect. 2.3 step a; Fig. 1 caption): per event, pixels sorted by
+  sample count (descending, ties by ascending pixel id) until >= cred of the
+  samples are covered; samples outside the region are dropped;
+* sky factor (eq. gw-kernel-many1d, second factor): S_ir = pixel area x 2-D
+  Gaussian KDE of all the event's sky samples (tangent plane at their mean
+  direction, Scott bandwidth) at the pixel centre; c_ir = S_ir / N_ir where
+  N_ir is the pixel's sample count (the 1/N of the pixel's 1-D KDE);
+* catalogue density (eq. p-cat): each galaxy's Gaussian N(z; z_obs, sigma)
+  is projected on the grid's linear-interpolation (hat) basis, multiplied by
+  dV_c/dz at the node (frozen reference cosmology H0=70, Om=0.3) and
+  normalised so that sum_k tau_k q_k = 1 (tau = trapezoid weights).
+  n_r(z_k) = sum_{gal in r} q / (N_gal * pixel area); n_tot = area * sum_r n_r.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+
+import numpy as np
+from scipy.special import erf, roots_legendre
+
+from . import synth
+
+REF_H0 = 70.0
+REF_OM = 0.3
+SUPPORT_SIGMAS = 8.0
+
+
+@dataclass
+class Prepared:
+    """Arrays in the layout of the C-ABI (see include/chimera.h)."""
+    n_z: int
+    z_lo: float
+    z_hi: float
+    nz: np.ndarray            # [n_rows, n_z] float64 catalogue density rows
+    row_pix: np.ndarray       # [n_rows] HEALPix id of each row
+    nz_tot: np.ndarray        # [n_z]
+    ev_pix_off: np.ndarray    # [E+1] int64
+    pix_samp_off: np.ndarray  # [P+1] int64
+    pix_row: np.ndarray       # [P] int64 catalogue row of each (event, pixel)
+    pix_id: np.ndarray        # [P] HEALPix id of each (event, pixel)
+    c_ir: np.ndarray          # [P] float64
+    dl: np.ndarray            # [S] float64, sorted by (event, pixel, dl)
+    m1d: np.ndarray
+    m2d: np.ndarray
+
+    @property
+    def n_events(self) -> int:
+        return len(self.ev_pix_off) - 1
+
+
+def trapezoid_weights(n_z: int, z_lo: float, z_hi: float) -> np.ndarray:
+    dz = (z_hi - z_lo) / (n_z - 1)
+    tau = np.full(n_z, dz)
+    tau[0] = tau[-1] = 0.5 * dz
+    return tau
+
+
+def _comoving_shape(z: np.ndarray) -> np.ndarray:
+    """chi(z)^2 / E(z) at the reference cosmology (dV_c/dz up to a constant)."""
+    x, w = roots_legendre(24)
+    z = np.asarray(z, dtype=np.float64)
+    # chi(z) = int_0^z dz'/E: composite Gauss-Legendre on panels of width <= 0.05
+    chi = np.zeros_like(z)
+    n_pan = np.maximum(1, np.ceil(z / 0.05)).astype(np.int64)
+    for i in range(z.size):
+        edges = np.linspace(0.0, z.flat[i], n_pan.flat[i] + 1)
+        a, b = edges[:-1, None], edges[1:, None]
+        t = 0.5 * (b - a) * x[None, :] + 0.5 * (a + b)
+        f = 1.0 / np.sqrt(REF_OM * (1 + t) ** 3 + 1 - REF_OM)
+        chi.flat[i] = np.sum(0.5 * (b - a) * f * w[None, :])
+    e = np.sqrt(REF_OM * (1 + z) ** 3 + 1 - REF_OM)
+    return chi ** 2 / e
+
+
+def _hat_projection(mu, sig, z_lo, dz, n_z, k0, width):
+    """J[g, m] = int N(z; mu_g, sig_g) Lambda_{k0_g+m}(z) dz for m in [0, width)."""
+    k = k0[:, None] + np.arange(width)[None, :]          # node index
+    valid = (k >= 0) & (k < n_z)
+    # edges: node k-1, k, k+1 clipped to the grid (half hats at the ends)
+    zk = z_lo + k * dz
+    lo = np.where(k > 0, zk - dz, zk)
+    hi = np.where(k < n_z - 1, zk + dz, zk)
+    m = mu[:, None]
+    s = sig[:, None]
+
+    def seg(a, b, c, sign):
+        # int_a^b N(z) * sign * (z - c)/dz dz  (a <= b)
+        al = (a - m) / s
+        be = (b - m) / s
+        cdf = 0.5 * (erf(be / math.sqrt(2)) - erf(al / math.sqrt(2)))
+        pdf = (np.exp(-0.5 * al * al) - np.exp(-0.5 * be * be)) / math.sqrt(2 * math.pi)
+        return sign * (s * pdf + (m - c) * cdf) / dz
+
+    rise = seg(lo, zk, lo, 1.0)         # (z - z_{k-1})/dz on [z_{k-1}, z_k]
+    fall = seg(zk, hi, hi, -1.0)        # (z_{k+1} - z)/dz on [z_k, z_{k+1}]
+    j = np.where(valid, rise + fall, 0.0)
+    return np.clip(k, 0, n_z - 1), j, valid
+
+
+def catalog_density(cat: synth.Catalog, n_z: int, z_lo: float, z_hi: float,
+                    rows_pix: np.ndarray, chunk: int = 200_000):
+    """(nz[n_rows, n_z], nz_tot[n_z], n_gal_used) for the HEALPix pixels rows_pix."""
+    dz = (z_hi - z_lo) / (n_z - 1)
+    tau = trapezoid_weights(n_z, z_lo, z_hi)
+    grid = z_lo + dz * np.arange(n_z)
+    vshape = _comoving_shape(grid)
+    area = synth.pixel_area(cat.nside)
+    row_of_pix = {int(p): i for i, p in enumerate(rows_pix)}
+    lut = np.full(synth.nside_npix(cat.nside), -1, dtype=np.int64)
+    lut[np.asarray(rows_pix, dtype=np.int64)] = np.arange(len(rows_pix))
+    n_rows = len(rows_pix)
+    acc_rows = np.zeros(n_rows * n_z)
+    acc_tot = np.zeros(n_z)
+    n_used = 0
+    for s0 in range(0, cat.z_obs.size, chunk):
+        mu = cat.z_obs[s0:s0 + chunk]
+        pix = cat.pix[s0:s0 + chunk]
+        sig = cat.sigma_z0 * (1.0 + mu)
+        keep = (mu + SUPPORT_SIGMAS * sig >= z_lo) & (mu - SUPPORT_SIGMAS * sig <= z_hi) & (sig > 0)
+        mu, pix, sig = mu[keep], pix[keep], sig[keep]
+        k0 = np.floor((mu - SUPPORT_SIGMAS * sig - z_lo) / dz).astype(np.int64) - 1
+        width = int(np.max(np.ceil(2 * SUPPORT_SIGMAS * sig / dz))) + 4 if mu.size else 0
+        if width == 0:
+            continue
+        kk, j, valid = _hat_projection(mu, sig, z_lo, dz, n_z, k0, width)
+        q = np.where(valid, j / tau[kk] * vshape[kk], 0.0)
+        norm = np.sum(np.where(valid, tau[kk] * q, 0.0), axis=1)
+        good = norm > 0
+        q = q[good] / norm[good, None]
+        kk, valid, pix = kk[good], valid[good], pix[good]
+        n_used += int(good.sum())
+        acc_tot += np.bincount(kk[valid], weights=q[valid], minlength=n_z)
+        r = lut[pix]
+        sel = r >= 0
+        if np.any(sel):
+            idx = (r[sel, None] * n_z + kk[sel])[valid[sel]]
+            acc_rows += np.bincount(idx, weights=q[sel][valid[sel]], minlength=n_rows * n_z)
+    nz = acc_rows.reshape(n_rows, n_z) / (n_used * area)
+    nz_tot = acc_tot / n_used
+    del row_of_pix
+    return nz, nz_tot, n_used
+
+
+def _sky_factors(theta, phi, centres_theta, centres_phi, area):
+    """area x 2-D Scott KDE of (theta, phi) samples at the centres (tangent plane)."""
+    v = synth.unit_vectors(theta, phi)
+    m = v.sum(axis=0)
+    m /= np.linalg.norm(m)
+    ph0 = math.atan2(m[1], m[0])
+    east = np.array([-math.sin(ph0), math.cos(ph0), 0.0])
+    north = np.cross(m, east)
+
+    def proj(u):
+        d = u @ m
+        return np.stack([(u @ east) / d, (u @ north) / d], axis=-1)
+
+    x = proj(v)
+    c = proj(synth.unit_vectors(centres_theta, centres_phi))
+    n = x.shape[0]
+    cov = np.cov(x.T, bias=False) * n ** (-1.0 / 3.0)
+    inv = np.linalg.inv(cov)
+    norm = 1.0 / (2 * math.pi * math.sqrt(np.linalg.det(cov)))
+    out = np.empty(c.shape[0])
+    for i in range(c.shape[0]):
+        d = x - c[i]
+        q = np.einsum("ij,jk,ik->i", d, inv, d)
+        out[i] = norm * np.mean(np.exp(-0.5 * q))
+    return area * out
+
+
+def prepare(cat: synth.Catalog, ev: synth.Events, n_z: int, z_lo: float, z_hi: float,
+            cred: float = 0.9) -> Prepared:
+    """Build the C-ABI arrays for one event set against one catalogue."""
+    area = synth.pixel_area(ev.nside)
+    ev_pix_off = [0]
+    samp_off = [0]
+    pix_id, c_list, dl_l, m1_l, m2_l = [], [], [], [], []
+    for e in range(ev.n_events):
+        sl = slice(ev.offsets[e], ev.offsets[e + 1])
+        pix = ev.pix[sl]
+        n_s = pix.size
+        uniq, cnt = np.unique(pix, return_counts=True)
+        order = np.lexsort((uniq, -cnt))              # count desc, id asc
+        cum = np.cumsum(cnt[order])
+        n_take = int(np.searchsorted(cum >= cred * n_s, True)) + 1
+        region = np.sort(uniq[order[:n_take]])
+        th_c, ph_c = synth.pix2ang_ring(ev.nside, region)
+        s_ir = _sky_factors(ev.theta[sl], ev.phi[sl], th_c, ph_c, area)
+        dle, m1e, m2e = ev.dl[sl], ev.m1d[sl], ev.m2d[sl]
+        for r, p in enumerate(region):
+            idx = np.nonzero(pix == p)[0]
+            idx = idx[np.argsort(dle[idx], kind="stable")]
+            pix_id.append(int(p))
+            c_list.append(s_ir[r] / idx.size)
+            dl_l.append(dle[idx]); m1_l.append(m1e[idx]); m2_l.append(m2e[idx])
+            samp_off.append(samp_off[-1] + idx.size)
+        ev_pix_off.append(len(pix_id))
+    pix_id = np.asarray(pix_id, dtype=np.int64)
+    rows_pix = np.unique(pix_id)
+    pix_row = np.searchsorted(rows_pix, pix_id).astype(np.int64)
+    nz, nz_tot, _ = catalog_density(cat, n_z, z_lo, z_hi, rows_pix)
+    return Prepared(n_z=n_z, z_lo=z_lo, z_hi=z_hi, nz=nz, row_pix=rows_pix, nz_tot=nz_tot,
+                    ev_pix_off=np.asarray(ev_pix_off, dtype=np.int64),
+                    pix_samp_off=np.asarray(samp_off, dtype=np.int64),
+                    pix_row=pix_row, pix_id=pix_id, c_ir=np.asarray(c_list),
+                    dl=np.concatenate(dl_l), m1d=np.concatenate(m1_l), m2d=np.concatenate(m2_l))
