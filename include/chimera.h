@@ -1,0 +1,152 @@
+/*
+ * chimera.h -- C-ABI of the MI355X library that evaluates the hierarchical
+ * standard-siren log-likelihood of Tagliazucchi et al. (2025),
+ * arXiv:2504.02034, at batches of hyperparameter points lambda.
+ *
+ *   ln L(lambda) = sum_i ln I_i(lambda) - N_ev ln xi(lambda)        (eq. hyperlike)
+ *
+ * I_i is the many-1D kernel integral of event i (eq. like-integrals with the
+ * KDE of eq. gw-kernel-many1d): for every sky pixel r of the event's region,
+ *   I_i = sum_r c_ir sum_{j in r} w_j sum_g tau_g N(z_g; z_j, h_i) n_r(z_g) g(z_g),
+ * where z_j solves d_L^gw(z) = d_j (eqs. dL-em and dL-mg, flat LCDM),
+ * w_j = p(m1_j) p(m2_j | m1_j) of the source-frame masses m = m_det/(1+z_j)
+ * (power law + Gaussian peak, Sect. 3.1), g(z) = psi(z) / [(1+z)^3 d d_L^gw/dz]
+ * (eq. jacobian with the Madau-Dickinson rate psi), tau_g the trapezoid
+ * weights of the uniform redshift grid, and h_i one Gaussian bandwidth per
+ * (event, lambda) from Scott's rule with the Kish effective sample size
+ * (the paper leaves the rule open).  xi is the injection estimator of
+ * Sect. 2.2 (with 1/p_draw).
+ *
+ * Conventions
+ *   units        distances in Mpc, H0 in km/s/Mpc, masses in solar masses
+ *   lambda       row-major double [B][14]:
+ *                H0, Om, Xi0, n, alpha, beta, mmin, mmax, mu_g, sigma_g,
+ *                lambda_g, gamma, kappa, z_p
+ *   gradient     row-major double [B][12], the same order without mmin, mmax
+ *   ownership    the caller owns every array it passes; the library copies
+ *                what it keeps (catalogue, events, injections) to the device
+ *                and owns those copies until chimera_release_events /
+ *                chimera_destroy
+ *   mem          CHIMERA_HOST: lam and outputs are host pointers; the call
+ *                returns when the outputs are written.
+ *                CHIMERA_DEVICE: lam and outputs are device pointers on the
+ *                context's device; the work is enqueued on hip_stream
+ *                (a hipStream_t, NULL = the null stream) and the call returns
+ *                without waiting.
+ *   per-lambda   a lambda outside the domain (non-finite entry, H0 <= 0,
+ *   results      Om outside (0,1], Xi0 <= 0, mmin <= 0, mmax <= mmin,
+ *                sigma_g <= 0, lambda_g outside [0,1], z_p <= -1), or for
+ *                which d_L^gw is not increasing on the distance table, gives
+ *                lnl = -inf; one for which a resident distance exceeds
+ *                d_L^gw(z_tab_max) gives lnl = NaN.  Neither is a call
+ *                error: the other points of the batch are unaffected.
+ *                An event with I_i = 0, or xi = 0, gives lnl = -inf.
+ *   errors       every call returns a chimera_status; on failure the
+ *                calling thread's chimera_last_error() describes it.
+ *   threads      one context may be used from several host threads and
+ *                streams at once for evaluation calls; chimera_set_* and
+ *                chimera_add_events / chimera_release_events serialise on
+ *                the context and must not race with evaluations that read
+ *                the data they replace.
+ */
+#ifndef CHIMERA_H
+#define CHIMERA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct chimera_ctx chimera_ctx;
+typedef struct chimera_events chimera_events;
+
+typedef enum {
+  CHIMERA_OK = 0,
+  CHIMERA_EINVAL = -1,   /* bad argument (null pointer, size, layout) */
+  CHIMERA_ENOMEM = -2,   /* device allocation failed or scratch > hbm_budget */
+  CHIMERA_EDEVICE = -3,  /* HIP runtime error */
+  CHIMERA_ERANGE = -4,   /* data outside what the context was configured for */
+  CHIMERA_ESTATE = -5    /* catalogue / injections not set yet */
+} chimera_status;
+
+enum { CHIMERA_FP64 = 0, CHIMERA_FP32 = 1 };
+enum { CHIMERA_HOST = 0, CHIMERA_DEVICE = 1 };
+
+#define CHIMERA_NLAM 14
+#define CHIMERA_NGRAD 12
+
+typedef struct {
+  int32_t n_z;          /* redshift grid points (>= 3)                                */
+  double z_lo, z_hi;    /* grid z_g = z_lo + g (z_hi - z_lo)/(n_z - 1)                 */
+  int32_t n_tab;        /* nodes of the per-lambda distance tables (>= 256)           */
+  double z_tab_max;     /* the tables cover z in [0, z_tab_max]                        */
+  double trunc_fp64;    /* kernel support |z_g - z_j| <= T h in FP64 mode (>= 8.6)     */
+  double trunc_fp32;    /* ... in FP32 mode                                            */
+  int32_t device;       /* HIP device ordinal                                          */
+  size_t hbm_budget;    /* max scratch bytes one call may take; 0 = no limit           */
+} chimera_config;
+
+/* Fill cfg with defaults: n_z 1000 on [0, 1.6], n_tab 8192, z_tab_max 25,
+ * trunc 8.6 / 5.8, device 0, no budget. */
+void chimera_default_config(chimera_config* cfg);
+
+/* Create a context on cfg->device.  Returns EINVAL for an inconsistent
+ * config, EDEVICE if the device cannot be used. */
+chimera_status chimera_create(const chimera_config* cfg, chimera_ctx** out);
+void chimera_destroy(chimera_ctx* ctx);
+
+/* Message of the calling thread's last failed call ("" if none). */
+const char* chimera_last_error(void);
+
+/* Galaxy-catalogue density on the grid (eq. p-cat, pre-computed once as in
+ * Sect. 2.3 step b): nz is row-major [n_rows][n_z], n_r(z_g) per unit z per
+ * steradian for each catalogue row that events refer to; nz_tot[n_z] is the
+ * all-sky density n_tot(z_g) = pixel area x sum over all pixels, used by the
+ * selection term.  Replaces any previous catalogue. */
+chimera_status chimera_set_catalog(chimera_ctx* ctx, int64_t n_rows, const double* nz,
+                                   const double* nz_tot);
+
+/* Detected injections (Sect. 2.2): n_det draws with d_L, detector-frame
+ * masses and ln p_draw (the draw density in (d_L, m1_det, m2_det)), out of
+ * n_inj_total draws in all.  Distances must be > 0.  Replaces any previous set. */
+chimera_status chimera_set_injections(chimera_ctx* ctx, int64_t n_det, int64_t n_inj_total,
+                                      const double* dl, const double* m1d, const double* m2d,
+                                      const double* ln_pdraw);
+
+/* One resident event set in CSR layout (many-1D kernel, eq. gw-kernel-many1d):
+ *   ev_pix_off[n_ev+1]      pixel rows of event i are [ev_pix_off[i], ev_pix_off[i+1])
+ *   pix_samp_off[P+1]       samples of pixel row p are [pix_samp_off[p], pix_samp_off[p+1])
+ *   pix_row[P]              catalogue row (index into nz) of pixel row p
+ *   c_ir[P]                 sky factor / sample count of pixel row p (> 0)
+ *   dl, m1d, m2d[n_samp]    samples, n_samp = pix_samp_off[P], ordered by
+ *                           (event, pixel); within a pixel, ascending dl runs
+ *                           fastest but any order is accepted
+ * Every event must have at least one sample.  Distances > 0.
+ * Returns EINVAL on a malformed layout, ERANGE when a pixel row refers past
+ * the catalogue or an event exceeds the largest size the kernels take. */
+chimera_status chimera_add_events(chimera_ctx* ctx, int32_t n_ev, const int64_t* ev_pix_off,
+                                  const int64_t* pix_samp_off, const int64_t* pix_row,
+                                  const double* c_ir, const double* dl, const double* m1d,
+                                  const double* m2d, chimera_events** out);
+chimera_status chimera_release_events(chimera_ctx* ctx, chimera_events* ev);
+
+/* ln L at B points (eq. hyperlike).  prec: CHIMERA_FP64, or CHIMERA_FP32 for
+ * FP32 bulk arithmetic (mass weights, kernel sums) with the distance tables,
+ * the inversion, the bandwidth moments and every per-event and per-lambda sum
+ * kept in FP64.  lnl[B]; lnI[B][n_ev] (ln I_i per point and event) may be NULL. */
+chimera_status chimera_lnl_batch(chimera_ctx* ctx, const chimera_events* ev, const double* lam,
+                                 int64_t B, int32_t prec, double* lnl, double* lnI, int32_t mem,
+                                 void* hip_stream);
+
+/* ln xi and the effective injection count N_eff (Sect. 2.2) at B points.
+ * n_eff may be NULL. */
+chimera_status chimera_selection_xi(chimera_ctx* ctx, const double* lam, int64_t B, int32_t prec,
+                                    double* ln_xi, double* n_eff, int32_t mem, void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CHIMERA_H */

@@ -43,6 +43,7 @@ import math
 from dataclasses import dataclass, field
 
 import numpy as np
+from scipy.special import ndtr
 
 from . import cosmology as cosmo
 from .population import mass_weight, psi
@@ -89,9 +90,13 @@ def lambda_in_domain(lam) -> bool:
     lam = np.asarray(lam, dtype=np.float64)
     if not np.all(np.isfinite(lam)):
         return False
-    h0, om, xi0, _n, _a, _b, mmin, mmax, _mu, sg, lg, _g, _k, zp = lam
-    return (h0 > 0 and 0 < om <= 1 and xi0 > 0 and 0 < mmin < mmax and sg > 0
-            and 0 <= lg <= 1 and zp > -1)
+    h0, om, xi0, _n, _a, _b, mmin, mmax, mu, sg, lg, _g, _k, zp = lam
+    if not (h0 > 0 and 0 < om <= 1 and xi0 > 0 and 0 < mmin < mmax and sg > 0
+            and 0 <= lg <= 1 and zp > -1):
+        return False
+    # reading: a Gaussian peak with no mass inside [mmin, mmax] cannot be normalised
+    a, b = (mmin - mu) / sg, (mmax - mu) / sg
+    return (ndtr(-a) - ndtr(-b) if a > 0 else ndtr(b) - ndtr(a)) > 0
 
 
 def redshift_and_weight(dl, m1d, m2d, lam):

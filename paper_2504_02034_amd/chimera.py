@@ -1,0 +1,254 @@
+"""ctypes binding of libchimera.so (include/chimera.h), argument marshalling only.
+
+Every step of the likelihood runs in the HIP library; this module converts
+numpy arrays and torch tensors into pointers.  Importing it raises if the
+library has not been built: there is no CPU fallback.
+
+Functions keep the C names (chimera_create, chimera_lnl_batch, ...); the
+classes Context / EventSet are thin owners of the opaque handles.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libchimera.so")
+
+CHIMERA_OK, CHIMERA_EINVAL, CHIMERA_ENOMEM, CHIMERA_EDEVICE, CHIMERA_ERANGE, CHIMERA_ESTATE = (
+    0, -1, -2, -3, -4, -5)
+CHIMERA_FP64, CHIMERA_FP32 = 0, 1
+CHIMERA_HOST, CHIMERA_DEVICE = 0, 1
+NLAM, NGRAD = 14, 12
+
+_STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ERANGE", -5: "ESTATE"}
+
+#: every symbol include/chimera.h declares
+EXPORTS = ("chimera_default_config", "chimera_create", "chimera_destroy", "chimera_last_error",
+           "chimera_set_catalog", "chimera_set_injections", "chimera_add_events",
+           "chimera_release_events", "chimera_lnl_batch", "chimera_selection_xi")
+
+
+class ChimeraError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Config(ctypes.Structure):
+    _fields_ = [("n_z", ctypes.c_int32), ("z_lo", ctypes.c_double), ("z_hi", ctypes.c_double),
+                ("n_tab", ctypes.c_int32), ("z_tab_max", ctypes.c_double),
+                ("trunc_fp64", ctypes.c_double), ("trunc_fp32", ctypes.c_double),
+                ("device", ctypes.c_int32), ("hbm_budget", ctypes.c_size_t)]
+
+
+_P = ctypes.c_void_p
+_I64 = ctypes.c_int64
+_I32 = ctypes.c_int32
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                          "(the likelihood has no CPU path)")
+    lib = ctypes.CDLL(LIB_PATH)
+    sig = {
+        "chimera_default_config": (None, [ctypes.POINTER(Config)]),
+        "chimera_create": (ctypes.c_int, [ctypes.POINTER(Config), ctypes.POINTER(_P)]),
+        "chimera_destroy": (None, [_P]),
+        "chimera_last_error": (ctypes.c_char_p, []),
+        "chimera_set_catalog": (ctypes.c_int, [_P, _I64, _P, _P]),
+        "chimera_set_injections": (ctypes.c_int, [_P, _I64, _I64, _P, _P, _P, _P]),
+        "chimera_add_events": (ctypes.c_int, [_P, _I32, _P, _P, _P, _P, _P, _P, _P,
+                                              ctypes.POINTER(_P)]),
+        "chimera_release_events": (ctypes.c_int, [_P, _P]),
+        "chimera_lnl_batch": (ctypes.c_int, [_P, _P, _P, _I64, _I32, _P, _P, _I32, _P]),
+        "chimera_selection_xi": (ctypes.c_int, [_P, _P, _I64, _I32, _P, _P, _I32, _P]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+lib = _load()
+
+
+def _check(status):
+    if status != CHIMERA_OK:
+        raise ChimeraError(status, lib.chimera_last_error().decode())
+
+
+def _host(a, dtype):
+    a = np.ascontiguousarray(a, dtype=dtype)
+    return a, a.ctypes.data_as(_P)
+
+
+def _is_torch(x) -> bool:
+    return type(x).__module__.startswith("torch")
+
+
+# ---------------------------------------------------------------------------
+# C names
+# ---------------------------------------------------------------------------
+def chimera_default_config() -> Config:
+    c = Config()
+    lib.chimera_default_config(ctypes.byref(c))
+    return c
+
+
+def chimera_create(cfg: Config):
+    h = _P()
+    _check(lib.chimera_create(ctypes.byref(cfg), ctypes.byref(h)))
+    return h
+
+
+def chimera_destroy(h):
+    lib.chimera_destroy(h)
+
+
+def chimera_set_catalog(h, nz, nz_tot):
+    nz, pnz = _host(nz, np.float64)
+    nt, pnt = _host(nz_tot, np.float64)
+    _check(lib.chimera_set_catalog(h, nz.shape[0] if nz.ndim == 2 else 0, pnz, pnt))
+
+
+def chimera_set_injections(h, dl, m1d, m2d, ln_pdraw, n_inj_total):
+    a = [_host(x, np.float64) for x in (dl, m1d, m2d, ln_pdraw)]
+    _check(lib.chimera_set_injections(h, a[0][0].size, int(n_inj_total), *[p for _, p in a]))
+
+
+def chimera_add_events(h, ev_pix_off, pix_samp_off, pix_row, c_ir, dl, m1d, m2d):
+    o1, p1 = _host(ev_pix_off, np.int64)
+    o2, p2 = _host(pix_samp_off, np.int64)
+    o3, p3 = _host(pix_row, np.int64)
+    rest = [_host(x, np.float64) for x in (c_ir, dl, m1d, m2d)]
+    ev = _P()
+    _check(lib.chimera_add_events(h, o1.size - 1, p1, p2, p3, *[p for _, p in rest],
+                                  ctypes.byref(ev)))
+    return ev
+
+
+def chimera_release_events(h, ev):
+    _check(lib.chimera_release_events(h, ev))
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        import torch
+        return _P(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return _P(stream)
+    return _P(stream.cuda_stream)
+
+
+def chimera_lnl_batch(h, ev, lam, prec=CHIMERA_FP64, lnl=None, lnI=None, n_ev=None, stream=None):
+    """lam: numpy [B,14] (host call) or a torch tensor on the device (async call)."""
+    if _is_torch(lam):
+        import torch
+        assert lam.is_cuda and lam.dtype == torch.float64 and lam.is_contiguous()
+        B = lam.shape[0]
+        if lnl is None:
+            lnl = torch.empty(B, dtype=torch.float64, device=lam.device)
+        _check(lib.chimera_lnl_batch(h, ev, _P(lam.data_ptr()), B, prec, _P(lnl.data_ptr()),
+                                     _P(lnI.data_ptr()) if lnI is not None else None,
+                                     CHIMERA_DEVICE, _stream_ptr(stream)))
+        return lnl
+    lam, pl = _host(np.atleast_2d(lam), np.float64)
+    B = lam.shape[0]
+    out = np.empty(B)
+    lnI_arr = None
+    if n_ev is not None:
+        lnI_arr = np.empty((B, n_ev))
+    _check(lib.chimera_lnl_batch(h, ev, pl, B, prec, out.ctypes.data_as(_P),
+                                 lnI_arr.ctypes.data_as(_P) if lnI_arr is not None else None,
+                                 CHIMERA_HOST, None))
+    return (out, lnI_arr) if n_ev is not None else out
+
+
+def chimera_selection_xi(h, lam, prec=CHIMERA_FP64, stream=None):
+    if _is_torch(lam):
+        import torch
+        B = lam.shape[0]
+        lx = torch.empty(B, dtype=torch.float64, device=lam.device)
+        ne = torch.empty(B, dtype=torch.float64, device=lam.device)
+        _check(lib.chimera_selection_xi(h, _P(lam.data_ptr()), B, prec, _P(lx.data_ptr()),
+                                        _P(ne.data_ptr()), CHIMERA_DEVICE, _stream_ptr(stream)))
+        return lx, ne
+    lam, pl = _host(np.atleast_2d(lam), np.float64)
+    B = lam.shape[0]
+    lx, ne = np.empty(B), np.empty(B)
+    _check(lib.chimera_selection_xi(h, pl, B, prec, lx.ctypes.data_as(_P), ne.ctypes.data_as(_P),
+                                    CHIMERA_HOST, None))
+    return lx, ne
+
+
+# ---------------------------------------------------------------------------
+# owners
+# ---------------------------------------------------------------------------
+class EventSet:
+    def __init__(self, ctx: "Context", handle, n_events: int):
+        self.ctx, self.handle, self.n_events = ctx, handle, n_events
+
+    def release(self):
+        if self.handle is not None and self.ctx.handle is not None:
+            chimera_release_events(self.ctx.handle, self.handle)
+        self.handle = None
+
+
+class Context:
+    """Owns one chimera_ctx: resident catalogue, injections and event sets."""
+
+    def __init__(self, n_z=1000, z_lo=0.0, z_hi=1.6, device=0, hbm_budget=0, **kw):
+        cfg = chimera_default_config()
+        cfg.n_z, cfg.z_lo, cfg.z_hi, cfg.device, cfg.hbm_budget = n_z, z_lo, z_hi, device, hbm_budget
+        for k, v in kw.items():
+            setattr(cfg, k, v)
+        self.cfg = cfg
+        self.handle = chimera_create(cfg)
+
+    def close(self):
+        if self.handle is not None:
+            chimera_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_catalog(self, nz, nz_tot):
+        chimera_set_catalog(self.handle, nz, nz_tot)
+
+    def set_injections(self, dl, m1d, m2d, ln_pdraw, n_inj_total):
+        chimera_set_injections(self.handle, dl, m1d, m2d, ln_pdraw, n_inj_total)
+
+    def add_events(self, ev_pix_off, pix_samp_off, pix_row, c_ir, dl, m1d, m2d) -> EventSet:
+        h = chimera_add_events(self.handle, ev_pix_off, pix_samp_off, pix_row, c_ir, dl, m1d, m2d)
+        return EventSet(self, h, len(ev_pix_off) - 1)
+
+    def add_prepared(self, p) -> EventSet:
+        """Resident event set from prep.Prepared."""
+        return self.add_events(p.ev_pix_off, p.pix_samp_off, p.pix_row, p.c_ir, p.dl, p.m1d, p.m2d)
+
+    def lnl(self, ev: EventSet, lam, prec=CHIMERA_FP64, with_lnI=False, lnl=None, lnI=None,
+            stream=None):
+        if _is_torch(lam):
+            return chimera_lnl_batch(self.handle, ev.handle, lam, prec, lnl=lnl, lnI=lnI,
+                                     stream=stream)
+        return chimera_lnl_batch(self.handle, ev.handle, lam, prec,
+                                 n_ev=ev.n_events if with_lnI else None)
+
+    def selection(self, lam, prec=CHIMERA_FP64, stream=None):
+        return chimera_selection_xi(self.handle, lam, prec, stream=stream)
+
+
+def context_from_prepared(p, inj, device=0, **kw) -> tuple:
+    """(Context, EventSet) with the catalogue rows, injections and events of prep.Prepared."""
+    ctx = Context(n_z=p.n_z, z_lo=p.z_lo, z_hi=p.z_hi, device=device, **kw)
+    ctx.set_catalog(p.nz, p.nz_tot)
+    ctx.set_injections(inj.dl, inj.m1d, inj.m2d, inj.ln_pdraw, inj.n_total)
+    return ctx, ctx.add_prepared(p)

@@ -1,0 +1,483 @@
+// Host side of the C-ABI in include/chimera.h: argument checks, resident
+// device data, per-call scratch (stream-ordered allocations) and launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <limits>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "chimera.h"
+#include "launch.h"
+
+using namespace chimera;
+
+namespace {
+
+thread_local std::string g_err;
+
+chimera_status fail(chimera_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+#define HIP_TRY(expr)                                                                   \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      return fail(e_ == hipErrorOutOfMemory ? CHIMERA_ENOMEM : CHIMERA_EDEVICE,         \
+                  std::string(#expr) + ": " + hipGetErrorString(e_));                   \
+  } while (0)
+
+template <class T>
+hipError_t upload(T** dst, const T* src, size_t n) {
+  *dst = nullptr;
+  if (n == 0) return hipSuccess;
+  hipError_t e = hipMalloc((void**)dst, n * sizeof(T));
+  if (e != hipSuccess) return e;
+  return hipMemcpy(*dst, src, n * sizeof(T), hipMemcpyHostToDevice);
+}
+
+void dfree(void* p) {
+  if (p) (void)hipFree(p);
+}
+
+bool finite_positive(const double* v, size_t n) {
+  for (size_t i = 0; i < n; ++i)
+    if (!(std::isfinite(v[i]) && v[i] > 0.0)) return false;
+  return true;
+}
+
+size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Bump allocator over one device block.
+struct Carve {
+  char* base = nullptr;
+  size_t off = 0;
+  template <class T>
+  T* take(size_t n) {
+    T* p = reinterpret_cast<T*>(base + off);
+    off += align_up(n * sizeof(T));
+    return p;
+  }
+};
+
+}  // namespace
+
+struct chimera_events {
+  int E = 0;
+  int64_t n_samp = 0;
+  int* ev_samp_off = nullptr;
+  double *dl = nullptr, *lndl = nullptr, *m1d = nullptr, *m2d = nullptr;
+  double *lnm1d = nullptr, *lnm2d = nullptr, *samp_c = nullptr;
+  int* samp_row = nullptr;
+  double dmin = 0.0, dmax = 0.0;
+};
+
+struct chimera_ctx {
+  chimera_config cfg;
+  std::mutex mu;
+  int64_t n_rows = 0;
+  double* nz64 = nullptr;
+  float* nz32 = nullptr;
+  double* ntot = nullptr;
+  int64_t n_det = 0, n_inj_total = 0;
+  double *inj_dl = nullptr, *inj_lndl = nullptr, *inj_m1d = nullptr, *inj_m2d = nullptr;
+  double *inj_lnm1d = nullptr, *inj_lnm2d = nullptr, *inj_lnp = nullptr;
+  double inj_dmin = 0.0, inj_dmax = 0.0;
+  bool has_cat = false, has_inj = false;
+  std::vector<chimera_events*> events;
+};
+
+namespace {
+
+void free_events(chimera_events* ev) {
+  dfree(ev->ev_samp_off);
+  dfree(ev->dl); dfree(ev->lndl); dfree(ev->m1d); dfree(ev->m2d);
+  dfree(ev->lnm1d); dfree(ev->lnm2d); dfree(ev->samp_c); dfree(ev->samp_row);
+  delete ev;
+}
+
+void free_injections(chimera_ctx* c) {
+  dfree(c->inj_dl); dfree(c->inj_lndl); dfree(c->inj_m1d); dfree(c->inj_m2d);
+  dfree(c->inj_lnm1d); dfree(c->inj_lnm2d); dfree(c->inj_lnp);
+  c->inj_dl = c->inj_lndl = c->inj_m1d = c->inj_m2d = nullptr;
+  c->inj_lnm1d = c->inj_lnm2d = c->inj_lnp = nullptr;
+  c->has_inj = false;
+}
+
+void free_catalog(chimera_ctx* c) {
+  dfree(c->nz64); dfree(c->nz32); dfree(c->ntot);
+  c->nz64 = nullptr; c->nz32 = nullptr; c->ntot = nullptr;
+  c->has_cat = false;
+}
+
+Geometry make_geometry(const chimera_ctx* c, double dmin, double dmax) {
+  Geometry g;
+  g.n_z = c->cfg.n_z;
+  g.z_lo = c->cfg.z_lo;
+  g.dz = (c->cfg.z_hi - c->cfg.z_lo) / (double)(c->cfg.n_z - 1);
+  g.n_t = c->cfg.n_tab;
+  g.dx = std::log1p(c->cfg.z_tab_max) / (double)(g.n_t - 1);
+  g.n_u = c->cfg.n_tab;
+  double ulo = std::log(dmin), uhi = std::log(dmax);
+  if (uhi - ulo < 1e-6) {
+    ulo -= 1e-3;
+    uhi += 1e-3;
+  }
+  g.u_lo = ulo;
+  g.du = (uhi - ulo) / (double)(g.n_u - 1);
+  return g;
+}
+
+struct Scratch {
+  LamParams* P;
+  double2* chi;
+  double2* inv;
+  double* gz64;
+  float* gz32;
+  int* flag_mono;
+  int* flag_range;
+  double* partial;
+  double* lam;
+  double* lnI;
+  double* ln_xi;
+  double* neff;
+  double* lnl;
+};
+
+// Lay out (or size, when base is null) the scratch of one call.
+size_t carve(Carve& cv, Scratch& s, const Geometry& g, int64_t B, int E, int nchunk,
+             bool need_lam, bool need_lnI, bool need_grid, bool need_outs) {
+  s.P = cv.take<LamParams>(B);
+  s.chi = cv.take<double2>((size_t)B * g.n_t);
+  s.inv = cv.take<double2>((size_t)B * g.n_u);
+  s.gz64 = need_grid ? cv.take<double>((size_t)B * g.n_z) : nullptr;
+  s.gz32 = need_grid ? cv.take<float>((size_t)B * g.n_z) : nullptr;
+  s.flag_mono = cv.take<int>(B);
+  s.flag_range = cv.take<int>(B);
+  s.partial = cv.take<double>((size_t)B * std::max(nchunk, 1) * 2);
+  s.lam = need_lam ? cv.take<double>((size_t)B * CHIMERA_NLAM) : nullptr;
+  s.lnI = need_lnI ? cv.take<double>((size_t)B * std::max(E, 1)) : nullptr;
+  s.ln_xi = cv.take<double>(B);
+  s.neff = need_outs ? cv.take<double>(B) : nullptr;
+  s.lnl = need_outs ? cv.take<double>(B) : nullptr;
+  return cv.off;
+}
+
+chimera_status check_common(chimera_ctx* ctx, const double* lam, int64_t B, int32_t prec,
+                            int32_t mem) {
+  if (!ctx) return fail(CHIMERA_EINVAL, "null context");
+  if (!lam) return fail(CHIMERA_EINVAL, "null lambda pointer");
+  if (B < 1 || B > (1 << 20)) return fail(CHIMERA_EINVAL, "batch size out of [1, 2^20]");
+  if (prec != CHIMERA_FP64 && prec != CHIMERA_FP32) return fail(CHIMERA_EINVAL, "bad precision");
+  if (mem != CHIMERA_HOST && mem != CHIMERA_DEVICE) return fail(CHIMERA_EINVAL, "bad mem kind");
+  if (!ctx->has_inj) return fail(CHIMERA_ESTATE, "injections not set");
+  if (!ctx->has_cat) return fail(CHIMERA_ESTATE, "catalogue not set");
+  return CHIMERA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void chimera_default_config(chimera_config* cfg) {
+  if (!cfg) return;
+  std::memset(cfg, 0, sizeof(*cfg));
+  cfg->n_z = 1000;
+  cfg->z_lo = 0.0;
+  cfg->z_hi = 1.6;
+  cfg->n_tab = 8192;
+  cfg->z_tab_max = 25.0;
+  cfg->trunc_fp64 = 8.6;
+  cfg->trunc_fp32 = 5.8;
+  cfg->device = 0;
+  cfg->hbm_budget = 0;
+}
+
+const char* chimera_last_error(void) { return g_err.c_str(); }
+
+chimera_status chimera_create(const chimera_config* cfg, chimera_ctx** out) {
+  if (!cfg || !out) return fail(CHIMERA_EINVAL, "null argument");
+  *out = nullptr;
+  if (cfg->n_z < 3 || !(cfg->z_hi > cfg->z_lo) || !(cfg->z_lo >= 0.0))
+    return fail(CHIMERA_EINVAL, "grid needs n_z >= 3 and 0 <= z_lo < z_hi");
+  if (cfg->n_tab < 256 || cfg->n_tab > 16 * 1024 + 1)
+    return fail(CHIMERA_EINVAL, "n_tab must be in [256, 16385]");
+  if (!(cfg->z_tab_max > cfg->z_hi)) return fail(CHIMERA_EINVAL, "z_tab_max must exceed z_hi");
+  if (!(cfg->trunc_fp64 >= 8.6) || !(cfg->trunc_fp32 >= 3.0))
+    return fail(CHIMERA_EINVAL, "trunc_fp64 must be >= 8.6 and trunc_fp32 >= 3");
+  int ndev = 0;
+  HIP_TRY(hipGetDeviceCount(&ndev));
+  if (cfg->device < 0 || cfg->device >= ndev) return fail(CHIMERA_EINVAL, "no such device");
+  HIP_TRY(hipSetDevice(cfg->device));
+  hipMemPool_t pool;
+  if (hipDeviceGetDefaultMemPool(&pool, cfg->device) == hipSuccess) {
+    uint64_t thr = std::numeric_limits<uint64_t>::max();
+    (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+  }
+  auto* c = new chimera_ctx();
+  c->cfg = *cfg;
+  *out = c;
+  return CHIMERA_OK;
+}
+
+void chimera_destroy(chimera_ctx* ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->cfg.device);
+  (void)hipDeviceSynchronize();
+  for (auto* e : ctx->events) free_events(e);
+  free_catalog(ctx);
+  free_injections(ctx);
+  delete ctx;
+}
+
+chimera_status chimera_set_catalog(chimera_ctx* ctx, int64_t n_rows, const double* nz,
+                                   const double* nz_tot) {
+  if (!ctx || !nz_tot || (n_rows > 0 && !nz)) return fail(CHIMERA_EINVAL, "null argument");
+  if (n_rows < 0) return fail(CHIMERA_EINVAL, "negative row count");
+  const size_t nzn = (size_t)ctx->cfg.n_z;
+  for (size_t i = 0; i < (size_t)n_rows * nzn; ++i)
+    if (!(std::isfinite(nz[i]) && nz[i] >= 0.0)) return fail(CHIMERA_EINVAL, "nz must be finite, >= 0");
+  for (size_t i = 0; i < nzn; ++i)
+    if (!(std::isfinite(nz_tot[i]) && nz_tot[i] >= 0.0))
+      return fail(CHIMERA_EINVAL, "nz_tot must be finite, >= 0");
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  HIP_TRY(hipSetDevice(ctx->cfg.device));
+  HIP_TRY(hipDeviceSynchronize());
+  free_catalog(ctx);
+  std::vector<float> f32((size_t)n_rows * nzn);
+  for (size_t i = 0; i < f32.size(); ++i) f32[i] = (float)nz[i];
+  HIP_TRY(upload(&ctx->nz64, nz, (size_t)n_rows * nzn));
+  HIP_TRY(upload(&ctx->nz32, f32.data(), f32.size()));
+  HIP_TRY(upload(&ctx->ntot, nz_tot, nzn));
+  ctx->n_rows = n_rows;
+  ctx->has_cat = true;
+  return CHIMERA_OK;
+}
+
+chimera_status chimera_set_injections(chimera_ctx* ctx, int64_t n_det, int64_t n_inj_total,
+                                      const double* dl, const double* m1d, const double* m2d,
+                                      const double* ln_pdraw) {
+  if (!ctx) return fail(CHIMERA_EINVAL, "null context");
+  if (n_det < 0 || n_inj_total < 1 || n_det > n_inj_total)
+    return fail(CHIMERA_EINVAL, "need 0 <= n_det <= n_inj_total, n_inj_total >= 1");
+  if (n_det > 0 && (!dl || !m1d || !m2d || !ln_pdraw)) return fail(CHIMERA_EINVAL, "null array");
+  const size_t n = (size_t)n_det;
+  if (!finite_positive(dl, n) || !finite_positive(m1d, n) || !finite_positive(m2d, n))
+    return fail(CHIMERA_EINVAL, "injection distances and masses must be finite and > 0");
+  for (size_t i = 0; i < n; ++i)
+    if (!std::isfinite(ln_pdraw[i])) return fail(CHIMERA_EINVAL, "ln_pdraw must be finite");
+  std::vector<double> ld(n), l1(n), l2(n);
+  double dmin = std::numeric_limits<double>::infinity(), dmax = 0.0;
+  for (size_t i = 0; i < n; ++i) {
+    ld[i] = std::log(dl[i]);
+    l1[i] = std::log(m1d[i]);
+    l2[i] = std::log(m2d[i]);
+    dmin = std::min(dmin, dl[i]);
+    dmax = std::max(dmax, dl[i]);
+  }
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  HIP_TRY(hipSetDevice(ctx->cfg.device));
+  HIP_TRY(hipDeviceSynchronize());
+  free_injections(ctx);
+  HIP_TRY(upload(&ctx->inj_dl, dl, n));
+  HIP_TRY(upload(&ctx->inj_lndl, ld.data(), n));
+  HIP_TRY(upload(&ctx->inj_m1d, m1d, n));
+  HIP_TRY(upload(&ctx->inj_m2d, m2d, n));
+  HIP_TRY(upload(&ctx->inj_lnm1d, l1.data(), n));
+  HIP_TRY(upload(&ctx->inj_lnm2d, l2.data(), n));
+  HIP_TRY(upload(&ctx->inj_lnp, ln_pdraw, n));
+  ctx->n_det = n_det;
+  ctx->n_inj_total = n_inj_total;
+  ctx->inj_dmin = n ? dmin : 1.0;
+  ctx->inj_dmax = n ? dmax : 1.0;
+  ctx->has_inj = true;
+  return CHIMERA_OK;
+}
+
+chimera_status chimera_add_events(chimera_ctx* ctx, int32_t n_ev, const int64_t* ev_pix_off,
+                                  const int64_t* pix_samp_off, const int64_t* pix_row,
+                                  const double* c_ir, const double* dl, const double* m1d,
+                                  const double* m2d, chimera_events** out) {
+  if (!ctx || !out || !ev_pix_off || !pix_samp_off || !pix_row || !c_ir || !dl || !m1d || !m2d)
+    return fail(CHIMERA_EINVAL, "null argument");
+  *out = nullptr;
+  if (n_ev < 1) return fail(CHIMERA_EINVAL, "need at least one event");
+  if (!ctx->has_cat) return fail(CHIMERA_ESTATE, "set the catalogue before adding events");
+  if (ev_pix_off[0] != 0) return fail(CHIMERA_EINVAL, "ev_pix_off[0] must be 0");
+  for (int i = 0; i < n_ev; ++i)
+    if (ev_pix_off[i + 1] <= ev_pix_off[i])
+      return fail(CHIMERA_EINVAL, "every event needs at least one pixel row");
+  const int64_t P = ev_pix_off[n_ev];
+  if (pix_samp_off[0] != 0) return fail(CHIMERA_EINVAL, "pix_samp_off[0] must be 0");
+  for (int64_t p = 0; p < P; ++p) {
+    if (pix_samp_off[p + 1] <= pix_samp_off[p])
+      return fail(CHIMERA_EINVAL, "every pixel row needs at least one sample");
+    if (pix_row[p] < 0 || pix_row[p] >= ctx->n_rows)
+      return fail(CHIMERA_ERANGE, "pix_row refers past the catalogue");
+    if (!(std::isfinite(c_ir[p]) && c_ir[p] > 0.0))
+      return fail(CHIMERA_EINVAL, "c_ir must be finite and > 0");
+  }
+  const int64_t S = pix_samp_off[P];
+  if (S > (int64_t)0x7fffffff) return fail(CHIMERA_ERANGE, "too many samples in one set");
+  if (!finite_positive(dl, S) || !finite_positive(m1d, S) || !finite_positive(m2d, S))
+    return fail(CHIMERA_EINVAL, "sample distances and masses must be finite and > 0");
+  std::vector<int> evoff(n_ev + 1), row(S);
+  std::vector<double> c(S), ld(S), l1(S), l2(S);
+  for (int i = 0; i <= n_ev; ++i) evoff[i] = (int)pix_samp_off[ev_pix_off[i]];
+  for (int i = 0; i < n_ev; ++i)
+    if (evoff[i + 1] - evoff[i] > event_max_samples())
+      return fail(CHIMERA_ERANGE, "an event has more samples than the kernels take (" +
+                                      std::to_string(event_max_samples()) + ")");
+  double dmin = std::numeric_limits<double>::infinity(), dmax = 0.0;
+  for (int64_t p = 0; p < P; ++p)
+    for (int64_t j = pix_samp_off[p]; j < pix_samp_off[p + 1]; ++j) {
+      row[j] = (int)pix_row[p];
+      c[j] = c_ir[p];
+    }
+  for (int64_t j = 0; j < S; ++j) {
+    ld[j] = std::log(dl[j]);
+    l1[j] = std::log(m1d[j]);
+    l2[j] = std::log(m2d[j]);
+    dmin = std::min(dmin, dl[j]);
+    dmax = std::max(dmax, dl[j]);
+  }
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  HIP_TRY(hipSetDevice(ctx->cfg.device));
+  auto* ev = new chimera_events();
+  ev->E = n_ev;
+  ev->n_samp = S;
+  ev->dmin = dmin;
+  ev->dmax = dmax;
+  hipError_t e = hipSuccess;
+  if (e == hipSuccess) e = upload(&ev->ev_samp_off, evoff.data(), evoff.size());
+  if (e == hipSuccess) e = upload(&ev->dl, dl, S);
+  if (e == hipSuccess) e = upload(&ev->lndl, ld.data(), S);
+  if (e == hipSuccess) e = upload(&ev->m1d, m1d, S);
+  if (e == hipSuccess) e = upload(&ev->m2d, m2d, S);
+  if (e == hipSuccess) e = upload(&ev->lnm1d, l1.data(), S);
+  if (e == hipSuccess) e = upload(&ev->lnm2d, l2.data(), S);
+  if (e == hipSuccess) e = upload(&ev->samp_row, row.data(), S);
+  if (e == hipSuccess) e = upload(&ev->samp_c, c.data(), S);
+  if (e != hipSuccess) {
+    free_events(ev);
+    return fail(e == hipErrorOutOfMemory ? CHIMERA_ENOMEM : CHIMERA_EDEVICE,
+                std::string("uploading events: ") + hipGetErrorString(e));
+  }
+  ctx->events.push_back(ev);
+  *out = ev;
+  return CHIMERA_OK;
+}
+
+chimera_status chimera_release_events(chimera_ctx* ctx, chimera_events* ev) {
+  if (!ctx || !ev) return fail(CHIMERA_EINVAL, "null argument");
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  auto it = std::find(ctx->events.begin(), ctx->events.end(), ev);
+  if (it == ctx->events.end()) return fail(CHIMERA_EINVAL, "unknown event set");
+  HIP_TRY(hipSetDevice(ctx->cfg.device));
+  HIP_TRY(hipDeviceSynchronize());
+  ctx->events.erase(it);
+  free_events(ev);
+  return CHIMERA_OK;
+}
+
+static chimera_status run_batch(chimera_ctx* ctx, const chimera_events* ev, const double* lam,
+                                int64_t B, int32_t prec, double* lnl, double* lnI, double* ln_xi,
+                                double* n_eff, int32_t mem, void* hip_stream) {
+  hipStream_t st = (hipStream_t)hip_stream;
+  HIP_TRY(hipSetDevice(ctx->cfg.device));
+  const bool f32 = prec == CHIMERA_FP32;
+  const bool host = mem == CHIMERA_HOST;
+  const int E = ev ? ev->E : 0;
+  double dmin = ctx->n_det ? ctx->inj_dmin : std::numeric_limits<double>::infinity();
+  double dmax = ctx->n_det ? ctx->inj_dmax : 0.0;
+  if (ev) {
+    dmin = std::min(dmin, ev->dmin);
+    dmax = std::max(dmax, ev->dmax);
+  }
+  if (!(dmax > 0.0)) dmin = dmax = 1.0;
+  const Geometry g = make_geometry(ctx, dmin, dmax);
+  const int nchunk = selection_chunks(ctx->n_det);
+  Scratch s;
+  Carve probe;
+  const bool need_lnI = ev && (host || !lnI);
+  const size_t bytes = carve(probe, s, g, B, E, nchunk, host, need_lnI, ev != nullptr, host);
+  if (ctx->cfg.hbm_budget && bytes > ctx->cfg.hbm_budget)
+    return fail(CHIMERA_ENOMEM, "call needs " + std::to_string(bytes) +
+                                    " scratch bytes, over the context's hbm_budget");
+  void* base = nullptr;
+  HIP_TRY(hipMallocAsync(&base, bytes, st));
+  Carve cv;
+  cv.base = (char*)base;
+  carve(cv, s, g, B, E, nchunk, host, need_lnI, ev != nullptr, host);
+  const double* lam_dev = lam;
+  if (host) {
+    HIP_TRY(hipMemcpyAsync(s.lam, lam, (size_t)B * CHIMERA_NLAM * sizeof(double),
+                           hipMemcpyHostToDevice, st));
+    lam_dev = s.lam;
+  }
+  double* lnI_dev = need_lnI ? s.lnI : lnI;
+  double* lnxi_dev = (host || !ln_xi) ? s.ln_xi : ln_xi;
+  double* neff_dev = host ? (n_eff ? s.neff : nullptr) : n_eff;
+  double* lnl_dev = host ? s.lnl : lnl;
+  HIP_TRY(launch_tables(lam_dev, (int)B, g, s.P, s.chi, s.inv, ev ? s.gz64 : nullptr,
+                        ev ? s.gz32 : nullptr, s.flag_mono, s.flag_range, st));
+  SelArgs sa;
+  sa.P = s.P; sa.flag_mono = s.flag_mono; sa.flag_range = s.flag_range;
+  sa.chi = s.chi; sa.inv = s.inv; sa.g = g; sa.ntot = ctx->ntot;
+  sa.dl = ctx->inj_dl; sa.lndl = ctx->inj_lndl; sa.m1d = ctx->inj_m1d; sa.m2d = ctx->inj_m2d;
+  sa.lnm1d = ctx->inj_lnm1d; sa.lnm2d = ctx->inj_lnm2d; sa.ln_pdraw = ctx->inj_lnp;
+  sa.n_det = ctx->n_det; sa.n_total = ctx->n_inj_total; sa.B = (int)B; sa.nchunk = nchunk;
+  sa.partial = s.partial;
+  HIP_TRY(launch_selection(sa, f32, lnxi_dev, neff_dev, st));
+  if (ev) {
+    EventArgs a;
+    a.P = s.P; a.flag_mono = s.flag_mono; a.flag_range = s.flag_range;
+    a.chi = s.chi; a.inv = s.inv; a.g = g; a.gz64 = s.gz64; a.gz32 = s.gz32;
+    a.nz64 = ctx->nz64; a.nz32 = ctx->nz32; a.ev_samp_off = ev->ev_samp_off;
+    a.dl = ev->dl; a.lndl = ev->lndl; a.m1d = ev->m1d; a.m2d = ev->m2d;
+    a.lnm1d = ev->lnm1d; a.lnm2d = ev->lnm2d; a.samp_row = ev->samp_row; a.samp_c = ev->samp_c;
+    a.E = E; a.B = (int)B; a.trunc = f32 ? ctx->cfg.trunc_fp32 : ctx->cfg.trunc_fp64;
+    a.nchunk = 0; a.bc = 0; a.lnI = lnI_dev;
+    HIP_TRY(launch_events(a, f32, st));
+    HIP_TRY(launch_lnl_final(s.P, s.flag_mono, s.flag_range, lnI_dev, lnxi_dev, E, (int)B,
+                             lnl_dev, st));
+  }
+  if (host) {
+    if (ev) HIP_TRY(hipMemcpyAsync(lnl, lnl_dev, B * sizeof(double), hipMemcpyDeviceToHost, st));
+    if (ev && lnI)
+      HIP_TRY(hipMemcpyAsync(lnI, lnI_dev, (size_t)B * E * sizeof(double), hipMemcpyDeviceToHost,
+                             st));
+    if (ln_xi)
+      HIP_TRY(hipMemcpyAsync(ln_xi, lnxi_dev, B * sizeof(double), hipMemcpyDeviceToHost, st));
+    if (n_eff)
+      HIP_TRY(hipMemcpyAsync(n_eff, neff_dev, B * sizeof(double), hipMemcpyDeviceToHost, st));
+  }
+  HIP_TRY(hipFreeAsync(base, st));
+  if (host) HIP_TRY(hipStreamSynchronize(st));
+  return CHIMERA_OK;
+}
+
+chimera_status chimera_lnl_batch(chimera_ctx* ctx, const chimera_events* ev, const double* lam,
+                                 int64_t B, int32_t prec, double* lnl, double* lnI, int32_t mem,
+                                 void* hip_stream) {
+  chimera_status s = check_common(ctx, lam, B, prec, mem);
+  if (s != CHIMERA_OK) return s;
+  if (!ev) return fail(CHIMERA_EINVAL, "null event set");
+  if (!lnl) return fail(CHIMERA_EINVAL, "null output");
+  return run_batch(ctx, ev, lam, B, prec, lnl, lnI, nullptr, nullptr, mem, hip_stream);
+}
+
+chimera_status chimera_selection_xi(chimera_ctx* ctx, const double* lam, int64_t B, int32_t prec,
+                                    double* ln_xi, double* n_eff, int32_t mem, void* hip_stream) {
+  chimera_status s = check_common(ctx, lam, B, prec, mem);
+  if (s != CHIMERA_OK) return s;
+  if (!ln_xi) return fail(CHIMERA_EINVAL, "null output");
+  return run_batch(ctx, nullptr, lam, B, prec, nullptr, nullptr, ln_xi, n_eff, mem, hip_stream);
+}
+
+}  // extern "C"

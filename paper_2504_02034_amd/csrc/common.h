@@ -1,0 +1,130 @@
+// Device-side types and helpers of the likelihood library (gfx950).
+//
+// Notation follows arXiv:2504.02034: d_L^em (eq. dL-em), Xi (eq. dL-mg),
+// the detector-frame Jacobian (eq. jacobian), the PLP mass model and the
+// Madau-Dickinson rate (Sect. 3.1).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace chimera {
+
+constexpr double kCkms = 299792.458;   // speed of light [km/s]
+constexpr int kNlam = 14;
+constexpr double kInvSqrt2Pi = 0.39894228040143267794;
+
+// Flags of one lambda (bits).
+enum : int { kFlagDomain = 1, kFlagNonMonotone = 2, kFlagRange = 4 };
+
+// Per-lambda constants, computed once per call on the device.
+struct LamParams {
+  double h0, om, xi0, n, alpha, beta, mmin, mmax, mu, sigma, lg, gamma, kappa, zp;
+  double dh;        // c / H0 [Mpc]
+  double pl_coef;   // (1 - lambda_g) / int_mmin^mmax m^-alpha dm
+  double tg_coef;   // lambda_g / (sigma sqrt(2 pi) Z), Z = peak mass in [mmin, mmax]
+  double a2;        // 1 + beta
+  double mmin_a2;   // mmin^(1 + beta)
+  double ln_mmin, ln_mmax;
+  double ln1zp;     // ln(1 + z_p)
+  double inv_sigma;
+  int flag;         // kFlagDomain
+  int pad;
+};
+
+// Geometry shared by all lambdas of one call.
+struct Geometry {
+  int n_z;          // redshift grid
+  double z_lo, dz;
+  int n_t;          // chi table: x_k = k dx, x = ln(1+z)
+  double dx;
+  int n_u;          // inverse table: u_m = u_lo + m du, u = ln d
+  double u_lo, du;
+};
+
+// Cubic Hermite on [0,1]: values y0, y1 and slopes (times the step) s0, s1.
+__device__ __forceinline__ double hermite(double y0, double y1, double s0, double s1, double t) {
+  const double d = y1 - y0;
+  return y0 + t * (s0 + t * ((3.0 * d - 2.0 * s0 - s1) + t * (s0 + s1 - 2.0 * d)));
+}
+
+// chi(x) = int_0^z dz'/E from the per-lambda table of (chi_k, dchi/dx_k).
+__device__ __forceinline__ double chi_at(const double2* __restrict__ tab, const Geometry& g,
+                                         double x) {
+  // clamp in floating point first: NaN and huge values map into the table
+  const double p = fmin(fmax(x / g.dx, 0.0), (double)(g.n_t - 1));
+  int k = (int)p;
+  k = k > g.n_t - 2 ? g.n_t - 2 : k;
+  const double t = x / g.dx - (double)k;
+  const double2 a = tab[k], b = tab[k + 1];
+  return hermite(a.x, b.x, a.y * g.dx, b.y * g.dx, t);
+}
+
+__device__ __forceinline__ double efunc_of_zp1(double om, double zp1) {
+  return sqrt(om * zp1 * zp1 * zp1 + 1.0 - om);
+}
+
+// d_L^gw and its x-derivative at x = ln(1+z).  zp1 = e^x is passed in.
+__device__ __forceinline__ void dist_at(const LamParams& P, const double2* __restrict__ tab,
+                                        const Geometry& g, double x, double zp1, double& D,
+                                        double& dDdx) {
+  const double c = chi_at(tab, g, x);
+  const double cp = zp1 / efunc_of_zp1(P.om, zp1);       // dchi/dx
+  const double en = exp(-P.n * x);                        // (1+z)^-n
+  const double xi = P.xi0 + (1.0 - P.xi0) * en;
+  const double xi_x = -P.n * (1.0 - P.xi0) * en;
+  D = P.dh * zp1 * c * xi;
+  dDdx = P.dh * zp1 * (c * xi + cp * xi + c * xi_x);
+}
+
+// x = ln(1+z) solving d_L^gw(z) = d: per-lambda inverse table (Hermite in
+// u = ln d), then `polish` Newton steps on d_L^gw from the chi table.
+__device__ __forceinline__ double invert_x(const LamParams& P, const double2* __restrict__ chi,
+                                           const double2* __restrict__ inv, const Geometry& g,
+                                           double d, double lnd, int polish) {
+  const double pos = (lnd - g.u_lo) / g.du;
+  int m = (int)fmin(fmax(pos, 0.0), (double)(g.n_u - 1));
+  m = m > g.n_u - 2 ? g.n_u - 2 : m;
+  const double t = pos - (double)m;
+  const double2 a = inv[m], b = inv[m + 1];
+  double x = hermite(a.x, b.x, a.y * g.du, b.y * g.du, t);
+  for (int i = 0; i < polish; ++i) {
+    double D, Dx;
+    dist_at(P, chi, g, x, exp(x), D, Dx);
+    x -= (D - d) / Dx;
+  }
+  return x;
+}
+
+// p(m1) p(m2|m1) of the source-frame masses; 0 outside
+// mmin <= m2 <= m1 <= mmax (and m1 > mmin).  l1, l2 = ln m1, ln m2.
+__device__ __forceinline__ double mass_weight64(const LamParams& P, double m1, double m2,
+                                                double l1, double l2) {
+  if (!(m1 >= P.mmin && m1 <= P.mmax && m2 >= P.mmin && m2 <= m1 && m1 > P.mmin)) return 0.0;
+  const double pl = P.pl_coef * exp(-P.alpha * l1);
+  const double u = (m1 - P.mu) * P.inv_sigma;
+  const double tg = P.tg_coef * exp(-0.5 * u * u);
+  const double n2 = (P.a2 == 0.0) ? (l1 - P.ln_mmin)
+                                  : P.mmin_a2 * expm1(P.a2 * (l1 - P.ln_mmin)) / P.a2;
+  return (pl + tg) * exp(P.beta * l2) / n2;
+}
+
+__device__ __forceinline__ float mass_weight32(const LamParams& P, double m1, double m2,
+                                               double l1d, double l2d) {
+  if (!(m1 >= P.mmin && m1 <= P.mmax && m2 >= P.mmin && m2 <= m1 && m1 > P.mmin)) return 0.0f;
+  const float l1 = (float)l1d, l2 = (float)l2d;
+  const float pl = (float)P.pl_coef * __expf(-(float)P.alpha * l1);
+  const float u = ((float)m1 - (float)P.mu) * (float)P.inv_sigma;
+  const float tg = (float)P.tg_coef * __expf(-0.5f * u * u);
+  const float a2 = (float)P.a2;
+  const float r = l1 - (float)P.ln_mmin;
+  const float n2 = (P.a2 == 0.0) ? r : (float)P.mmin_a2 * expm1f(a2 * r) / a2;
+  return (pl + tg) * __expf((float)P.beta * l2) / n2;
+}
+
+// Madau-Dickinson psi at x = ln(1+z).
+__device__ __forceinline__ double psi_of_x(const LamParams& P, double x) {
+  return exp(P.gamma * x) / (1.0 + exp((P.gamma + P.kappa) * (x - P.ln1zp)));
+}
+
+}  // namespace chimera

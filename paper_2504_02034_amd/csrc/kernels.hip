@@ -1,0 +1,554 @@
+// HIP kernels (gfx950, wave64) of the many-1D standard-siren likelihood.
+//
+//   k_lam_prepare     per-lambda constants and domain checks (Table 1 layout)
+//   k_chi_table       chi(x) = int dz/E on x = ln(1+z) nodes, FP64 (eq. dL-em)
+//   k_inverse_table   x(ln d) with d_L^gw(x) = d (eqs. dL-em, dL-mg)
+//   k_grid_factor     tau_g psi(z_g) / [(1+z_g)^3 d d_L^gw/dz]   (eq. jacobian)
+//   k_event<F64|F32>  one (event, lambda) per workgroup: sample redshifts and
+//                     mass weights, bandwidth, kernel sums against n_r g,
+//                     ln I_i (eqs. like-integrals, gw-kernel-many1d)
+//   k_selection       injection sums of s_j and s_j^2 (Sect. 2.2)
+//   k_*_final         fixed-order reductions to ln xi, N_eff, ln L (eq. hyperlike)
+//
+// Every reduction runs in a fixed order that depends only on the launch
+// shape, so each lambda's result is bitwise independent of the other points
+// in its batch.
+#include <math.h>
+
+#include "common.h"
+#include "launch.h"
+
+namespace chimera {
+
+// ---------------------------------------------------------------------------
+// reductions
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  return v;
+}
+
+// Sum over the workgroup, fixed order; every thread gets the result.
+// red must hold BS/64 + 1 doubles; leaves red reusable on return.
+template <int BS>
+__device__ __forceinline__ double block_sum(double v, double* red) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) red[w] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+#pragma unroll
+    for (int i = 0; i < BS / 64; ++i) t += red[i];
+    red[BS / 64] = t;
+  }
+  __syncthreads();
+  const double r = red[BS / 64];
+  __syncthreads();
+  return r;
+}
+
+// ---------------------------------------------------------------------------
+// per-lambda constants
+// ---------------------------------------------------------------------------
+__device__ double ndtr_diff(double a, double b) {
+  // Phi(b) - Phi(a), from the tail that does not cancel
+  const double r = 0.70710678118654752440;
+  return a > 0.0 ? 0.5 * (erfc(a * r) - erfc(b * r)) : 0.5 * (erfc(-b * r) - erfc(-a * r));
+}
+
+__global__ void k_lam_prepare(const double* __restrict__ lam, int B, LamParams* __restrict__ out) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= B) return;
+  const double* l = lam + (size_t)b * kNlam;
+  LamParams P;
+  P.h0 = l[0]; P.om = l[1]; P.xi0 = l[2]; P.n = l[3]; P.alpha = l[4]; P.beta = l[5];
+  P.mmin = l[6]; P.mmax = l[7]; P.mu = l[8]; P.sigma = l[9]; P.lg = l[10];
+  P.gamma = l[11]; P.kappa = l[12]; P.zp = l[13];
+  bool ok = true;
+  for (int i = 0; i < kNlam; ++i) ok = ok && isfinite(l[i]);
+  ok = ok && P.h0 > 0.0 && P.om > 0.0 && P.om <= 1.0 && P.xi0 > 0.0 && P.mmin > 0.0 &&
+       P.mmax > P.mmin && P.sigma > 0.0 && P.lg >= 0.0 && P.lg <= 1.0 && P.zp > -1.0;
+  P.flag = 0;
+  P.pad = 0;
+  P.dh = kCkms / P.h0;
+  P.ln_mmin = log(P.mmin);
+  P.ln_mmax = log(P.mmax);
+  P.inv_sigma = 1.0 / P.sigma;
+  P.ln1zp = log1p(P.zp);
+  // int_mmin^mmax m^-alpha dm, stable for alpha -> 1
+  const double a1 = 1.0 - P.alpha;
+  const double lr = P.ln_mmax - P.ln_mmin;
+  const double npl = (a1 == 0.0) ? lr : exp(a1 * P.ln_mmin) * expm1(a1 * lr) / a1;
+  P.pl_coef = (1.0 - P.lg) / npl;
+  const double zg = ndtr_diff((P.mmin - P.mu) / P.sigma, (P.mmax - P.mu) / P.sigma);
+  ok = ok && zg > 0.0;
+  P.tg_coef = P.lg / (P.sigma * 2.50662827463100050242 * zg);
+  P.a2 = 1.0 + P.beta;
+  P.mmin_a2 = exp(P.a2 * P.ln_mmin);
+  if (!ok) P.flag = kFlagDomain;
+  out[b] = P;
+}
+
+// ---------------------------------------------------------------------------
+// chi table: one workgroup per lambda, block-wide scan of Gauss-Legendre
+// panel integrals of dchi/dx = e^x / E(e^x).
+// ---------------------------------------------------------------------------
+constexpr int kTabBS = 1024;
+
+__device__ __forceinline__ double dchi_dx(double om, double x) {
+  const double zp1 = exp(x);
+  return zp1 / efunc_of_zp1(om, zp1);
+}
+
+__global__ __launch_bounds__(kTabBS) void k_chi_table(const LamParams* __restrict__ Pv, Geometry g,
+                                                      double2* __restrict__ chi,
+                                                      int* __restrict__ flag_mono) {
+  const int b = blockIdx.x;
+  const LamParams P = Pv[b];
+  double2* tab = chi + (size_t)b * g.n_t;
+  __shared__ double wsum[kTabBS / 64 + 1];
+  __shared__ int bad;
+  if (threadIdx.x == 0) bad = 0;
+  const int nint = g.n_t - 1;
+  const int per = (nint + kTabBS - 1) / kTabBS;
+  const int k0 = threadIdx.x * per;
+  // 8-point Gauss-Legendre on [-1, 1]
+  const double gx[4] = {0.18343464249564980494, 0.52553240991632898582, 0.79666647741362673959,
+                        0.96028985649753623168};
+  const double gw[4] = {0.36268378337836198297, 0.31370664587788728734, 0.22238103445337447054,
+                        0.10122853629037625915};
+  double local[16];
+  double run = 0.0;
+  for (int i = 0; i < per; ++i) {
+    const int k = k0 + i;
+    double s = 0.0;
+    if (k < nint) {
+      const double mid = ((double)k + 0.5) * g.dx, half = 0.5 * g.dx;
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        s += gw[q] * (dchi_dx(P.om, mid - half * gx[q]) + dchi_dx(P.om, mid + half * gx[q]));
+      s *= half;
+    }
+    run += s;
+    if (i < 16) local[i] = run;
+  }
+  // exclusive scan of the per-thread totals (wave scan, then wave offsets)
+  double incl = run;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const double y = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += y;
+  }
+  if (lane == 63) wsum[w] = incl;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double acc = 0.0;
+    for (int i = 0; i < kTabBS / 64; ++i) {
+      const double t = wsum[i];
+      wsum[i] = acc;
+      acc += t;
+    }
+  }
+  __syncthreads();
+  const double base = wsum[w] + incl - run;
+  if (threadIdx.x == 0) tab[0] = make_double2(0.0, dchi_dx(P.om, 0.0));
+  int mybad = 0;
+  for (int i = 0; i < per && i < 16; ++i) {
+    const int k = k0 + i + 1;   // node index
+    if (k <= nint) {
+      const double x = (double)k * g.dx;
+      const double c = base + local[i];
+      const double cp = dchi_dx(P.om, x);
+      tab[k] = make_double2(c, cp);
+      const double en = exp(-P.n * x);
+      const double xi = P.xi0 + (1.0 - P.xi0) * en;
+      const double dd = c * xi + cp * xi - c * P.n * (1.0 - P.xi0) * en;
+      if (!(dd > 0.0)) mybad = 1;
+    }
+  }
+  if (mybad) atomicOr(&bad, 1);
+  __syncthreads();
+  if (threadIdx.x == 0) flag_mono[b] = bad ? kFlagNonMonotone : 0;
+}
+
+// ---------------------------------------------------------------------------
+// inverse table: x(u_m), u = ln d, and dx/du, one thread per (lambda, node)
+// ---------------------------------------------------------------------------
+__global__ void k_inverse_table(const LamParams* __restrict__ Pv, const double2* __restrict__ chi,
+                                Geometry g, int B, double2* __restrict__ inv,
+                                int* __restrict__ flag_range) {
+  const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= (long long)B * g.n_u) return;
+  const int b = (int)(id / g.n_u), m = (int)(id % g.n_u);
+  const LamParams P = Pv[b];
+  const double2* tab = chi + (size_t)b * g.n_t;
+  const double d = exp(g.u_lo + (double)m * g.du);
+  auto dnode = [&](int k) {
+    const double x = (double)k * g.dx;
+    return P.dh * exp(x) * tab[k].x * (P.xi0 + (1.0 - P.xi0) * exp(-P.n * x));
+  };
+  int lo = 0, hi = g.n_t - 1;
+  const double dmax = dnode(hi);
+  if (!(dmax >= d)) {   // beyond the table (or not finite)
+    inv[id] = make_double2((double)hi * g.dx, 0.0);
+    if (m == g.n_u - 1) flag_range[b] = kFlagRange;
+    return;
+  }
+  if (m == g.n_u - 1) flag_range[b] = 0;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (dnode(mid) <= d) lo = mid; else hi = mid;
+  }
+  double xl = (double)lo * g.dx, xh = (double)hi * g.dx;
+  const double dl0 = dnode(lo), dh0 = dnode(hi);
+  double x = xl + (d - dl0) / (dh0 - dl0) * (xh - xl);
+  double D = d, Dx = 1.0;
+  for (int it = 0; it < 12; ++it) {
+    dist_at(P, tab, g, x, exp(x), D, Dx);
+    const double f = D - d;
+    if (f < 0.0) xl = fmax(xl, x); else xh = fmin(xh, x);
+    double xn = x - f / Dx;
+    if (!(xn >= xl && xn <= xh)) xn = 0.5 * (xl + xh);
+    if (xn == x) break;
+    x = xn;
+  }
+  dist_at(P, tab, g, x, exp(x), D, Dx);
+  inv[id] = make_double2(x, D / Dx);
+}
+
+// ---------------------------------------------------------------------------
+// grid factor tau_g psi / [(1+z)^3 D'(z)]  =  tau_g psi / [(1+z)^2 dD/dx]
+// ---------------------------------------------------------------------------
+__global__ void k_grid_factor(const LamParams* __restrict__ Pv, const double2* __restrict__ chi,
+                              Geometry g, int B, double* __restrict__ gz64,
+                              float* __restrict__ gz32) {
+  const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= (long long)B * g.n_z) return;
+  const int b = (int)(id / g.n_z), k = (int)(id % g.n_z);
+  const LamParams P = Pv[b];
+  const double z = g.z_lo + (double)k * g.dz;
+  const double x = log1p(z);
+  double D, Dx;
+  dist_at(P, chi + (size_t)b * g.n_t, g, x, 1.0 + z, D, Dx);
+  const double tau = (k == 0 || k == g.n_z - 1) ? 0.5 * g.dz : g.dz;
+  const double zp1 = 1.0 + z;
+  double v = tau * psi_of_x(P, x) / (zp1 * zp1 * Dx);
+  if (!isfinite(v)) v = 0.0;
+  gz64[id] = v;
+  gz32[id] = (float)v;
+}
+
+// ---------------------------------------------------------------------------
+// event kernel
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool decode_event_block(const EventArgs& a, int& e, int& b) {
+  const int L = blockIdx.x;
+  const int xcd = L & 7, s = L >> 3;
+  const int u = (s / a.bc) * 8 + xcd;     // (event, lambda-chunk) unit on this XCD
+  e = u / a.nchunk;
+  b = (u % a.nchunk) * a.bc + (s % a.bc);
+  return e < a.E && b < a.B;
+}
+
+template <int BS, int SPT, bool F32>
+__global__ __launch_bounds__(BS) void k_event(EventArgs a) {
+  int e, b;
+  if (!decode_event_block(a, e, b)) return;
+  __shared__ double red[BS / 64 + 1];
+  __shared__ double z_ref;
+  const LamParams P = a.P[b];
+  const int flag = P.flag | a.flag_mono[b] | a.flag_range[b];
+  double* out = a.lnI + (size_t)b * a.E + e;
+  if (flag) {
+    if (threadIdx.x == 0) *out = (flag & kFlagRange) ? NAN : -INFINITY;
+    return;
+  }
+  const double2* chi = a.chi + (size_t)b * a.g.n_t;
+  const double2* inv = a.inv + (size_t)b * a.g.n_u;
+  const int s0 = a.ev_samp_off[e];
+  const int n = a.ev_samp_off[e + 1] - s0;
+  const int polish = F32 ? 0 : 1;
+
+  // --- sample redshifts and mass weights (Sect. 2.1; eq. gw-kernel) ---
+  double zr[SPT];
+  double wr[SPT];
+  if (threadIdx.x == 0) {
+    const int j = s0;
+    const double x = invert_x(P, chi, inv, a.g, a.dl[j], a.lndl[j], polish);
+    z_ref = expm1(x);
+  }
+  __syncthreads();
+  const double zref = z_ref;
+  double W1 = 0.0, W2 = 0.0, S1 = 0.0, S2 = 0.0;
+#pragma unroll
+  for (int k = 0; k < SPT; ++k) {
+    const int jj = threadIdx.x + k * BS;
+    zr[k] = 0.0;
+    wr[k] = 0.0;
+    if (jj < n) {
+      const int j = s0 + jj;
+      const double x = invert_x(P, chi, inv, a.g, a.dl[j], a.lndl[j], polish);
+      const double zp1 = exp(x);
+      const double z = expm1(x);
+      const double m1 = a.m1d[j] / zp1, m2 = a.m2d[j] / zp1;
+      const double l1 = a.lnm1d[j] - x, l2 = a.lnm2d[j] - x;
+      const double w = F32 ? (double)mass_weight32(P, m1, m2, l1, l2)
+                           : mass_weight64(P, m1, m2, l1, l2);
+      zr[k] = z;
+      wr[k] = w;
+      const double dz = z - zref;
+      W1 += w;
+      W2 += w * w;
+      S1 += w * dz;
+      S2 += w * dz * dz;
+    }
+  }
+  W1 = block_sum<BS>(W1, red);
+  W2 = block_sum<BS>(W2, red);
+  S1 = block_sum<BS>(S1, red);
+  S2 = block_sum<BS>(S2, red);
+  if (!(W1 > 0.0)) {
+    if (threadIdx.x == 0) *out = -INFINITY;
+    return;
+  }
+  // --- bandwidth: Scott's rule with Kish n_eff, unbiased weighted variance ---
+  const double den = W1 * W1 - W2;
+  double var = 0.0;
+  if (!(den <= 1e-12 * W1 * W1)) var = (S2 - S1 * S1 / W1) / (W1 - W2 / W1);
+  if (var < 0.0) var = 0.0;
+  const double neff = W1 * W1 / W2;
+  const double h = fmax(sqrt(var) * pow(neff, -0.2), 2.0 * a.g.dz);
+  const double T = a.trunc;
+
+  // --- kernel sums against n_r(z_g) g(z_g) on |z_g - z_j| <= T h ---
+  double acc = 0.0;
+#pragma unroll
+  for (int k = 0; k < SPT; ++k) {
+    const int jj = threadIdx.x + k * BS;
+    if (jj >= n || wr[k] == 0.0) continue;
+    const int j = s0 + jj;
+    const double z = zr[k];
+    // window in floating point, clamped before the integer conversion
+    const double lo_d = fmax(ceil((z - T * h - a.g.z_lo) / a.g.dz), 0.0);
+    const double hi_d = fmin(floor((z + T * h - a.g.z_lo) / a.g.dz), (double)(a.g.n_z - 1));
+    if (!(lo_d <= hi_d)) continue;
+    const int lo = (int)lo_d, hi = (int)hi_d;
+    const size_t row = (size_t)a.samp_row[j] * a.g.n_z;
+    if (!F32) {
+      const double* nr = a.nz64 + row;
+      const double* gz = a.gz64 + (size_t)b * a.g.n_z;
+      const double inv2h2 = 0.5 / (h * h);
+      const double d0 = (a.g.z_lo + (double)lo * a.g.dz) - z;
+      double ee = exp(-d0 * d0 * inv2h2);
+      double r = exp(-(2.0 * d0 * a.g.dz + a.g.dz * a.g.dz) * inv2h2);
+      const double q = exp(-2.0 * a.g.dz * a.g.dz * inv2h2);
+      double s = 0.0;
+      for (int gi = lo; gi <= hi; ++gi) {
+        s += ee * nr[gi] * gz[gi];
+        ee *= r;
+        r *= q;
+      }
+      acc += a.samp_c[j] * wr[k] * s;
+    } else {
+      const float* nr = a.nz32 + row;
+      const float* gz = a.gz32 + (size_t)b * a.g.n_z;
+      // exp2(-(u c)^2) with u = (z_g - z_j)/h, c^2 = log2(e)/2
+      const float c = (float)(0.84932180028801904272 / h);
+      const float base = (float)((a.g.z_lo + (double)lo * a.g.dz) - z) * c;
+      const float step = (float)a.g.dz * c;
+      float s = 0.0f;
+      for (int gi = lo; gi <= hi; ++gi) {
+        const float u = fmaf((float)(gi - lo), step, base);
+        s = fmaf(exp2f(-u * u), nr[gi] * gz[gi], s);
+      }
+      acc += a.samp_c[j] * wr[k] * (double)s;
+    }
+  }
+  acc = block_sum<BS>(acc, red);
+  if (threadIdx.x == 0) {
+    const double I = acc * kInvSqrt2Pi / h;
+    *out = I > 0.0 ? log(I) : -INFINITY;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// selection: partial sums of s_j and s_j^2 per (injection chunk, lambda)
+// ---------------------------------------------------------------------------
+constexpr int kSelBS = 256;
+constexpr int kSelPer = 4;
+
+template <bool F32>
+__global__ __launch_bounds__(kSelBS) void k_selection(SelArgs a) {
+  const int chunk = blockIdx.x, b = blockIdx.y;
+  __shared__ double red[kSelBS / 64 + 1];
+  const LamParams P = a.P[b];
+  const int flag = P.flag | a.flag_mono[b] | a.flag_range[b];
+  if (flag) {
+    if (threadIdx.x == 0) {
+      a.partial[((size_t)b * a.nchunk + chunk) * 2] = 0.0;
+      a.partial[((size_t)b * a.nchunk + chunk) * 2 + 1] = 0.0;
+    }
+    return;
+  }
+  const double2* chi = a.chi + (size_t)b * a.g.n_t;
+  const double2* inv = a.inv + (size_t)b * a.g.n_u;
+  double s1 = 0.0, s2 = 0.0;
+  for (int k = 0; k < kSelPer; ++k) {
+    const long long j = (long long)chunk * kSelBS * kSelPer + k * kSelBS + threadIdx.x;
+    if (j >= a.n_det) break;
+    const double x = invert_x(P, chi, inv, a.g, a.dl[j], a.lndl[j], F32 ? 0 : 1);
+    const double zp1 = exp(x);
+    const double z = expm1(x);
+    const double m1 = a.m1d[j] / zp1, m2 = a.m2d[j] / zp1;
+    const double l1 = a.lnm1d[j] - x, l2 = a.lnm2d[j] - x;
+    const double w = F32 ? (double)mass_weight32(P, m1, m2, l1, l2)
+                         : mass_weight64(P, m1, m2, l1, l2);
+    if (w == 0.0) continue;
+    // n_tot(z) by linear interpolation on the grid, 0 outside
+    const double pos = (z - a.g.z_lo) / a.g.dz;
+    double nt = 0.0;
+    if (pos >= 0.0 && pos <= (double)(a.g.n_z - 1)) {
+      int kk = (int)pos;
+      if (kk >= a.g.n_z - 1) {
+        nt = a.ntot[a.g.n_z - 1];
+      } else {
+        const double t = pos - (double)kk;
+        nt = a.ntot[kk] + t * (a.ntot[kk + 1] - a.ntot[kk]);
+      }
+    }
+    if (nt == 0.0) continue;
+    double D, Dx;
+    dist_at(P, chi, a.g, x, zp1, D, Dx);
+    const double s = w * nt * psi_of_x(P, x) / (zp1 * zp1 * Dx * exp(a.ln_pdraw[j]));
+    s1 += s;
+    s2 += s * s;
+  }
+  s1 = block_sum<kSelBS>(s1, red);
+  s2 = block_sum<kSelBS>(s2, red);
+  if (threadIdx.x == 0) {
+    a.partial[((size_t)b * a.nchunk + chunk) * 2] = s1;
+    a.partial[((size_t)b * a.nchunk + chunk) * 2 + 1] = s2;
+  }
+}
+
+__global__ void k_selection_final(SelArgs a, double* __restrict__ ln_xi,
+                                  double* __restrict__ neff) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= a.B) return;
+  const int flag = a.P[b].flag | a.flag_mono[b] | a.flag_range[b];
+  double s1 = 0.0, s2 = 0.0;
+  for (int c = 0; c < a.nchunk; ++c) {
+    s1 += a.partial[((size_t)b * a.nchunk + c) * 2];
+    s2 += a.partial[((size_t)b * a.nchunk + c) * 2 + 1];
+  }
+  const double xi = s1 / (double)a.n_total;
+  double lx = xi > 0.0 ? log(xi) : -INFINITY;
+  const double dd = s2 - s1 * s1 / (double)a.n_total;
+  double ne = s1 > 0.0 ? (dd > 0.0 ? s1 * s1 / dd : INFINITY) : 0.0;
+  if (flag) {
+    lx = NAN;
+    ne = NAN;
+  }
+  ln_xi[b] = lx;
+  if (neff) neff[b] = ne;
+}
+
+// ln L_b = sum_i ln I_ib - E ln xi_b
+constexpr int kFinBS = 256;
+__global__ __launch_bounds__(kFinBS) void k_lnl_final(const LamParams* __restrict__ Pv,
+                                                      const int* __restrict__ flag_mono,
+                                                      const int* __restrict__ flag_range,
+                                                      const double* __restrict__ lnI,
+                                                      const double* __restrict__ ln_xi, int E,
+                                                      double* __restrict__ lnl) {
+  const int b = blockIdx.x;
+  __shared__ double red[kFinBS / 64 + 1];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < E; i += kFinBS) s += lnI[(size_t)b * E + i];
+  s = block_sum<kFinBS>(s, red);
+  if (threadIdx.x == 0) {
+    const int flag = Pv[b].flag | flag_mono[b] | flag_range[b];
+    const double lx = ln_xi[b];
+    double v;
+    if (flag & kFlagRange) v = NAN;
+    else if (flag) v = -INFINITY;
+    else if (isnan(s) || isnan(lx)) v = NAN;
+    else if (s == -INFINITY || lx == -INFINITY) v = -INFINITY;
+    else v = s - (double)E * lx;
+    lnl[b] = v;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+#define CH_LAUNCH_CHECK()                        \
+  do {                                           \
+    hipError_t _e = hipGetLastError();           \
+    if (_e != hipSuccess) return _e;             \
+  } while (0)
+
+hipError_t launch_tables(const double* lam, int B, const Geometry& g, LamParams* P,
+                         double2* chi, double2* inv, double* gz64, float* gz32, int* flag_mono,
+                         int* flag_range, hipStream_t st) {
+  k_lam_prepare<<<(B + 63) / 64, 64, 0, st>>>(lam, B, P);
+  CH_LAUNCH_CHECK();
+  k_chi_table<<<B, kTabBS, 0, st>>>(P, g, chi, flag_mono);
+  CH_LAUNCH_CHECK();
+  const long long ni = (long long)B * g.n_u;
+  k_inverse_table<<<(unsigned)((ni + 255) / 256), 256, 0, st>>>(P, chi, g, B, inv, flag_range);
+  CH_LAUNCH_CHECK();
+  if (gz64) {
+    const long long ng = (long long)B * g.n_z;
+    k_grid_factor<<<(unsigned)((ng + 255) / 256), 256, 0, st>>>(P, chi, g, B, gz64, gz32);
+    CH_LAUNCH_CHECK();
+  }
+  return hipSuccess;
+}
+
+int event_max_samples() { return kEventBS * kEventSPT; }
+
+hipError_t launch_events(const EventArgs& a0, bool f32, hipStream_t st) {
+  EventArgs a = a0;
+  a.bc = a.B < 32 ? a.B : 32;
+  a.nchunk = (a.B + a.bc - 1) / a.bc;
+  const long long units = (long long)a.E * a.nchunk;
+  const long long blocks = ((units + 7) / 8) * 8 * a.bc;
+  if (f32)
+    k_event<kEventBS, kEventSPT, true><<<(unsigned)blocks, kEventBS, 0, st>>>(a);
+  else
+    k_event<kEventBS, kEventSPT, false><<<(unsigned)blocks, kEventBS, 0, st>>>(a);
+  CH_LAUNCH_CHECK();
+  return hipSuccess;
+}
+
+int selection_chunks(long long n_det) {
+  const long long per = (long long)kSelBS * kSelPer;
+  return (int)((n_det + per - 1) / per);
+}
+
+hipError_t launch_selection(const SelArgs& a, bool f32, double* ln_xi, double* neff,
+                            hipStream_t st) {
+  if (a.nchunk > 0) {
+    dim3 grid(a.nchunk, a.B);
+    if (f32) k_selection<true><<<grid, kSelBS, 0, st>>>(a);
+    else k_selection<false><<<grid, kSelBS, 0, st>>>(a);
+    CH_LAUNCH_CHECK();
+  }
+  k_selection_final<<<(a.B + 63) / 64, 64, 0, st>>>(a, ln_xi, neff);
+  CH_LAUNCH_CHECK();
+  return hipSuccess;
+}
+
+hipError_t launch_lnl_final(const LamParams* P, const int* flag_mono, const int* flag_range,
+                            const double* lnI, const double* ln_xi, int E, int B, double* lnl,
+                            hipStream_t st) {
+  k_lnl_final<<<B, kFinBS, 0, st>>>(P, flag_mono, flag_range, lnI, ln_xi, E, lnl);
+  CH_LAUNCH_CHECK();
+  return hipSuccess;
+}
+
+}  // namespace chimera

@@ -12,8 +12,9 @@ grid, and its 2-D sky-KDE normalisation factors are independent of lambda).
   Gaussian KDE of all the event's sky samples (tangent plane at their mean
   direction, Scott bandwidth) at the pixel centre; c_ir = S_ir / N_ir where
   N_ir is the pixel's sample count (the 1/N of the pixel's 1-D KDE);
-* catalogue density (eq. p-cat): each galaxy's Gaussian N(z; z_obs, sigma)
-  is projected on the grid's linear-interpolation (hat) basis, multiplied by
+* catalogue density (eq. p-cat): each galaxy's Gaussian N(z; z_obs, sigma),
+  truncated at 8 sigma, is projected on the grid's linear-interpolation (hat)
+  basis, multiplied by
   dV_c/dz at the node (frozen reference cosmology H0=70, Om=0.3) and
   normalised so that sum_k tau_k q_k = 1 (tau = trapezoid weights).
   n_r(z_k) = sum_{gal in r} q / (N_gal * pixel area); n_tot = area * sum_r n_r.
@@ -24,7 +25,7 @@ import math
 from dataclasses import dataclass
 
 import numpy as np
-from scipy.special import erf, roots_legendre
+from scipy.special import ndtr, roots_legendre
 
 from . import synth
 
@@ -80,28 +81,39 @@ def _comoving_shape(z: np.ndarray) -> np.ndarray:
     return chi ** 2 / e
 
 
+def _phi_diff(al, be):
+    """Phi(be) - Phi(al) for al <= be, from the tail that does not cancel."""
+    return np.where(al >= 0.0, ndtr(-al) - ndtr(-be), ndtr(be) - ndtr(al))
+
+
 def _hat_projection(mu, sig, z_lo, dz, n_z, k0, width):
-    """J[g, m] = int N(z; mu_g, sig_g) Lambda_{k0_g+m}(z) dz for m in [0, width)."""
+    """J[g, m] = int N(z; mu_g, sig_g) Lambda_{k0_g+m}(z) dz over |z - mu_g| <= 8 sig_g."""
     k = k0[:, None] + np.arange(width)[None, :]          # node index
     valid = (k >= 0) & (k < n_z)
-    # edges: node k-1, k, k+1 clipped to the grid (half hats at the ends)
+    # hat edges: node k-1, k, k+1 clipped to the grid (half hats at the ends)
     zk = z_lo + k * dz
     lo = np.where(k > 0, zk - dz, zk)
     hi = np.where(k < n_z - 1, zk + dz, zk)
     m = mu[:, None]
     s = sig[:, None]
+    t_lo = m - SUPPORT_SIGMAS * s
+    t_hi = m + SUPPORT_SIGMAS * s
 
     def seg(a, b, c, sign):
-        # int_a^b N(z) * sign * (z - c)/dz dz  (a <= b)
-        al = (a - m) / s
-        be = (b - m) / s
-        cdf = 0.5 * (erf(be / math.sqrt(2)) - erf(al / math.sqrt(2)))
+        # int_a^b N(z) * sign * (z - c)/dz dz on [a, b] clipped to the truncated support
+        a2 = np.maximum(a, t_lo)
+        b2 = np.minimum(b, t_hi)
+        ok = b2 > a2
+        al = np.where(ok, (a2 - m) / s, 0.0)
+        be = np.where(ok, (b2 - m) / s, 0.0)
+        cdf = _phi_diff(al, be)
         pdf = (np.exp(-0.5 * al * al) - np.exp(-0.5 * be * be)) / math.sqrt(2 * math.pi)
-        return sign * (s * pdf + (m - c) * cdf) / dz
+        return np.where(ok, sign * (s * pdf + (m - c) * cdf) / dz, 0.0)
 
     rise = seg(lo, zk, lo, 1.0)         # (z - z_{k-1})/dz on [z_{k-1}, z_k]
     fall = seg(zk, hi, hi, -1.0)        # (z_{k+1} - z)/dz on [z_k, z_{k+1}]
-    j = np.where(valid, rise + fall, 0.0)
+    # the node integrals are >= 0; rounding can leave values a few ulp below
+    j = np.where(valid, np.maximum(rise + fall, 0.0), 0.0)
     return np.clip(k, 0, n_z - 1), j, valid
 
 

@@ -1,0 +1,119 @@
+"""Parity of the HIP library (through the C-ABI) with the CPU oracle on the
+10-event workload and small variations of it."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2504_02034_amd import synth
+
+pytestmark = pytest.mark.gpu
+REL64 = 1e-10          # FP64 bar on ln L (relative)
+ABS32 = 1e-3           # FP32-bulk bar on |Delta ln L|
+
+
+@pytest.fixture(scope="module")
+def gpu_small(small_data):
+    from paper_2504_02034_amd import chimera
+    ctx, es = chimera.context_from_prepared(small_data.prep, small_data.inj)
+    yield chimera, ctx, es
+    ctx.close()
+
+
+def prior_batch(n, seed):
+    wl = synth.WORKLOADS["precision_300ev"]
+    lam = synth.make_lambdas(wl, batch=n, child=100 + seed)
+    lam[0] = synth.LAMBDA_TRUTH
+    return lam
+
+
+def oracle_lnl(d, lam, T=8.6):
+    import oracle
+    return oracle.likelihood.lnl(d.o_events, d.o_cat, d.o_inj, lam, T=T)
+
+
+def same_value(a, b, rel):
+    if math.isnan(b):
+        return math.isnan(a)
+    if math.isinf(b):
+        return a == b
+    return abs(a - b) <= rel * max(1.0, abs(b))
+
+
+def test_fp64_truth_point(small_data, gpu_small):
+    chimera, ctx, es = gpu_small
+    lam = synth.LAMBDA_TRUTH[None, :]
+    lnl, lnI = ctx.lnl(es, lam, chimera.CHIMERA_FP64, with_lnI=True)
+    ref = oracle_lnl(small_data, lam[0])
+    print("gpu", lnl[0], "oracle", ref["lnl"])
+    assert abs(lnl[0] - ref["lnl"]) <= REL64 * abs(ref["lnl"])
+    assert np.allclose(lnI[0], ref["lnI"], rtol=REL64, atol=0)
+
+
+def test_fp64_prior_batch(small_data, gpu_small):
+    chimera, ctx, es = gpu_small
+    lam = prior_batch(12, 1)
+    lnl, lnI = ctx.lnl(es, lam, chimera.CHIMERA_FP64, with_lnI=True)
+    for b in range(lam.shape[0]):
+        ref = oracle_lnl(small_data, lam[b])
+        print(b, lam[b, :4], lnl[b], ref["lnl"])
+        assert same_value(lnl[b], ref["lnl"], REL64), (b, lnl[b], ref["lnl"])
+        for i in range(lnI.shape[1]):
+            assert same_value(lnI[b, i], ref["lnI"][i], REL64), (b, i, lnI[b, i], ref["lnI"][i])
+
+
+def test_fp32_within_budget(small_data, gpu_small):
+    chimera, ctx, es = gpu_small
+    lam = prior_batch(12, 1)
+    l32 = ctx.lnl(es, lam, chimera.CHIMERA_FP32)
+    l64 = ctx.lnl(es, lam, chimera.CHIMERA_FP64)
+    fin = np.isfinite(l64)
+    print("max |dlnL| fp32-fp64", np.max(np.abs(l32[fin] - l64[fin])))
+    assert np.array_equal(np.isfinite(l32), fin)
+    assert np.max(np.abs(l32[fin] - l64[fin])) <= ABS32
+
+
+def test_selection_matches_oracle(small_data, gpu_small):
+    import oracle
+    chimera, ctx, es = gpu_small
+    lam = prior_batch(6, 2)
+    lx, ne = ctx.selection(lam, chimera.CHIMERA_FP64)
+    for b in range(lam.shape[0]):
+        xi, neff, _ = oracle.likelihood.selection(small_data.o_inj, small_data.o_cat, lam[b])
+        assert lx[b] == pytest.approx(math.log(xi), rel=1e-12, abs=1e-12)
+        assert ne[b] == pytest.approx(neff, rel=1e-9)
+
+
+def test_invalid_points_are_isolated(small_data, gpu_small):
+    chimera, ctx, es = gpu_small
+    lam = np.tile(synth.LAMBDA_TRUTH, (5, 1))
+    lam[1, 7] = 3.0            # mmax < mmin -> -inf
+    lam[2, 0] = 1e6            # distances beyond the table -> NaN
+    lam[3, 1] = np.nan         # non-finite -> -inf
+    lnl = ctx.lnl(es, lam, chimera.CHIMERA_FP64)
+    alone = ctx.lnl(es, lam[:1], chimera.CHIMERA_FP64)
+    assert lnl[1] == -np.inf and math.isnan(lnl[2]) and lnl[3] == -np.inf
+    assert lnl[0] == alone[0] and lnl[4] == alone[0]
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_alone_equals_in_mix_bitwise(gpu_small, prec):
+    chimera, ctx, es = gpu_small
+    lam = prior_batch(40, 3)
+    mix = ctx.lnl(es, lam, prec)
+    for b in (0, 7, 39):
+        alone = ctx.lnl(es, lam[b:b + 1], prec)
+        assert alone[0] == mix[b] or (math.isnan(alone[0]) and math.isnan(mix[b]))
+
+
+def test_device_pointers_and_stream(gpu_small):
+    import torch
+    chimera, ctx, es = gpu_small
+    lam = prior_batch(9, 4)
+    host = ctx.lnl(es, lam, chimera.CHIMERA_FP64)
+    s = torch.cuda.Stream()
+    t = torch.from_numpy(lam).cuda()
+    with torch.cuda.stream(s):
+        out = ctx.lnl(es, t, chimera.CHIMERA_FP64, stream=s)
+    s.synchronize()
+    assert np.array_equal(out.cpu().numpy(), host, equal_nan=True)

@@ -130,9 +130,11 @@ def test_domain_and_range(small_data):
     assert _run(d, bad)["lnl"] == -np.inf
     far = LAM.copy(); far[0] = 1e6            # huge H0: distances beyond d(z=25)
     assert math.isnan(_run(d, far)["lnl"])
-    empty = LAM.copy(); empty[6] = 200.0; empty[7] = 300.0   # no sample inside the mass support
+    empty = LAM.copy(); empty[6] = 200.0; empty[7] = 300.0; empty[8] = 250.0  # no sample in the support
     r = _run(d, empty)
     assert r["lnl"] == -np.inf and np.all(np.isneginf(r["lnI"]))
+    nopeak = LAM.copy(); nopeak[8] = 500.0; nopeak[9] = 1.0  # peak has no mass in [mmin, mmax]
+    assert _run(d, nopeak)["lnl"] == -np.inf
 
 
 def test_selection_identical_injections():

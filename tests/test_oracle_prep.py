@@ -35,8 +35,9 @@ def test_hat_integrals(mu, sig):
     grid = np.linspace(0.0, 1.6, 1000)
     j = P.hat_integrals(mu, sig, grid)
     dz = grid[1] - grid[0]
-    # partition of unity of the hat basis on [z_lo, z_hi]
-    tot = stats.norm.cdf(grid[-1], mu, sig) - stats.norm.cdf(grid[0], mu, sig)
+    # partition of unity of the hat basis on [z_lo, z_hi] (within the 8 sigma support)
+    tot = (stats.norm.cdf(min(grid[-1], mu + 8 * sig), mu, sig)
+           - stats.norm.cdf(max(grid[0], mu - 8 * sig), mu, sig))
     assert j.sum() == pytest.approx(tot, rel=1e-11)
     k0 = int(round((mu - grid[0]) / dz))
     for k in sorted({0, max(k0 - 1, 0), k0, min(k0 + 1, 999), 999}):
@@ -45,6 +46,25 @@ def test_hat_integrals(mu, sig):
         ref = quad(lambda z: hat(z) * stats.norm.pdf(z, mu, sig), a, b, points=[grid[k]],
                    epsabs=1e-15, epsrel=1e-12)[0]
         assert j[k] == pytest.approx(ref, rel=1e-8, abs=1e-13)
+
+
+def test_hat_integrals_far_tail_mpmath():
+    """Nodes 5-8 sigma from the mean: relative accuracy against 40-digit quadrature."""
+    import mpmath
+    mpmath.mp.dps = 40
+    grid = np.linspace(0.0, 1.6, 1000)
+    dz = grid[1] - grid[0]
+    mu, sig = 0.70013, 0.0017
+    j = P.hat_integrals(mu, sig, grid)
+    for k in range(grid.size):
+        u = abs(grid[k] - mu) / sig
+        if not 5.0 <= u <= 7.0:
+            continue
+        f = lambda z: (max(0, 1 - abs(z - grid[k]) / dz)
+                       * mpmath.exp(-(z - mu) ** 2 / (2 * sig ** 2)) / (sig * mpmath.sqrt(2 * mpmath.pi)))
+        lo, hi = max(grid[k - 1], mu - 8 * sig), min(grid[k + 1], mu + 8 * sig)
+        ref = mpmath.quad(f, [lo, grid[k], hi]) if lo < grid[k] < hi else mpmath.quad(f, [lo, hi])
+        assert j[k] == pytest.approx(float(ref), rel=1e-11)
 
 
 def test_catalog_normalisation_all_pixels():
