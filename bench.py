@@ -1,0 +1,195 @@
+#!/usr/bin/env python3
+"""Throughput of the batched ln L hot path on one MI355X.
+
+One step = one chimera_lnl_batch call over a batch of lambda points: the
+per-lambda distance tables, the grid factor, the injection sums (xi) and the
+per-(event, lambda) kernel sums for every event, then ln L (the whole path).
+Inputs are resident in HBM before the timed region; lambda stays on the
+device and the call is asynchronous on torch's current stream.
+
+Workload (default): 300 events x 5000 posterior samples, 1e6 spectroscopic
+galaxies on HEALPix nside 64, 1000-point redshift grid, 1e6 injections, a
+batch of 256 lambda drawn from the priors H0 in [20,140], Om in [0.1,0.5],
+Xi0 in [0.3,3], n in [0,10].  Synthetic, seeded.
+
+Prints one JSON line.  `value` is the FP32-bulk form's ln L evaluations per
+second; the plain FP64 path is reported beside it with the FP32-FP64
+|Delta lnL| of the same batch.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}     # MI355X published dense vector peaks
+FLOPS_PER_EVAL = 2.0                            # one multiply-add per kernel evaluation
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def build_inputs(wl_name, batch):
+    from paper_2504_02034_amd import prep, synth
+    wl = synth.WORKLOADS[wl_name]
+    t = time.time()
+    cf = synth.make_catalog(wl)
+    ev = synth.make_events(wl, cf)
+    inj = synth.make_injections(wl)
+    p = prep.prepare(cf[0], ev, wl.n_z, wl.z_lo, wl.z_hi, cred=wl.cred)
+    lam = synth.make_lambdas(wl, batch=batch)
+    log(f"inputs ready in {time.time() - t:.1f}s: {p.n_events} events, {p.dl.size} samples, "
+        f"{p.nz.shape[0]} catalogue rows, {inj.dl.size} detected injections")
+    return wl, cf, ev, inj, p, lam
+
+
+def time_precision(ctx, es, lam_t, prec, steps, warmup):
+    import torch
+    from paper_2504_02034_amd import chimera
+    out = torch.empty(lam_t.shape[0], dtype=torch.float64, device=lam_t.device)
+    for _ in range(warmup):
+        ctx.lnl(es, lam_t, prec, lnl=out)
+    torch.cuda.synchronize()
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    t0 = time.perf_counter()
+    for k in range(steps):
+        starts[k].record()
+        ctx.lnl(es, lam_t, prec, lnl=out)
+        ends[k].record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    lat = sorted(s.elapsed_time(e) for s, e in zip(starts, ends))
+    # the dominant kernel, timed with HIP events on the same stream
+    chimera.chimera_profile_enable(ctx.handle, True)
+    for _ in range(steps):
+        ctx.lnl(es, lam_t, prec, lnl=out)
+    torch.cuda.synchronize()
+    n, ms, evals = chimera.chimera_profile_read(ctx.handle)
+    chimera.chimera_profile_enable(ctx.handle, False)
+    return out.cpu().numpy(), wall, lat, n, ms, evals
+
+
+def pct(v, q):
+    k = min(len(v) - 1, max(0, int(math.ceil(q / 100.0 * len(v))) - 1))
+    return v[k]
+
+
+def cpu_baseline(wl, cf, ev, inj, lam, n_events):
+    """The oracle as it stands on this host: one lambda, a subset of events."""
+    import numpy as np
+
+    import oracle
+    from paper_2504_02034_amd import synth
+    grid = synth.z_grid(wl)
+    area = synth.pixel_area(wl.nside)
+    sub = synth.Events(offsets=ev.offsets[:n_events + 1], dl=ev.dl, m1d=ev.m1d, m2d=ev.m2d,
+                       theta=ev.theta, phi=ev.phi, pix=ev.pix, nside=ev.nside)
+    o_ev = oracle.prep.events(sub.offsets, sub.dl, sub.m1d, sub.m2d, sub.theta, sub.phi, sub.pix,
+                              lambda q: synth.pix2ang_ring(wl.nside, q), area, cred=wl.cred)
+    rows = sorted({px.pix for e in o_ev for px in e.pixels})
+    o_cat = oracle.prep.catalog(cf[0].z_obs, cf[0].pix, cf[0].sigma_z0, grid, np.asarray(rows),
+                                area)
+    o_inj = oracle.likelihood.InjectionSet(inj.dl, inj.m1d, inj.m2d, inj.ln_pdraw, inj.n_total)
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    cores = max(1, min(cores, 16))
+    t = time.perf_counter()
+    oracle.likelihood.selection(o_inj, o_cat, lam)
+    t_sel = time.perf_counter() - t
+    t = time.perf_counter()
+    oracle.likelihood.lnl(o_ev, o_cat, o_inj, lam, T=8.6, workers=cores)
+    t_all = time.perf_counter() - t
+    t_ev = max(t_all - t_sel, 1e-9)
+    per_lambda = t_sel + t_ev * wl.n_events / n_events
+    return {"value": 1.0 / per_lambda, "unit": "lnL evals/s", "cores": cores, "kind": "oracle",
+            "sample": f"1 lambda, {n_events} of {wl.n_events} events (T=8.6 windows) plus the "
+                      f"selection sum over all {inj.dl.size} detected injections; event time "
+                      f"scaled by {wl.n_events}/{n_events}; measured {t_all:.1f}s"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="precision_300ev")
+    ap.add_argument("--batch", type=int, default=None)
+    ap.add_argument("--cpu-events", type=int, default=60)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU: this build runs on a single MI355X and has no "
+              f"multi-GPU path (asked for --gpus {args.gpus})", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2504_02034_amd import chimera
+
+    wl, cf, ev, inj, p, lam = build_inputs(args.workload, args.batch)
+    B = lam.shape[0]
+    ctx, es = chimera.context_from_prepared(p, inj, device=0, n_tab=8192)
+    lam_t = torch.from_numpy(lam).cuda()
+    res = {}
+    for name, prec in (("fp64", chimera.CHIMERA_FP64), ("fp32", chimera.CHIMERA_FP32)):
+        out, wall, lat, n, ms, evals = time_precision(ctx, es, lam_t, prec, args.steps,
+                                                      args.warmup)
+        avg_ms = ms / max(n, 1)
+        per_launch = evals / max(n, 1)
+        achieved = per_launch * FLOPS_PER_EVAL / (avg_ms * 1e-3) / 1e12
+        res[name] = dict(out=out, wall=wall, lat=lat, avg_ms=avg_ms, evals=per_launch,
+                         achieved=achieved)
+        log(f"{name}: {wall / args.steps * 1e3:.2f} ms/step, event kernel {avg_ms:.2f} ms, "
+            f"{per_launch:.3e} evals/launch, {achieved:.2f} TFLOP/s")
+    l32, l64 = res["fp32"]["out"], res["fp64"]["out"]
+    fin = np.isfinite(l64) & np.isfinite(l32)
+    dmax = float(np.max(np.abs(l32[fin] - l64[fin]))) if fin.any() else None
+    same_mask = bool(np.array_equal(np.isfinite(l32), np.isfinite(l64)))
+
+    def roof(name):
+        r = res[name]
+        return {"bound": "alu", "achieved": round(r["achieved"], 3), "peak": PEAK_TFLOPS[name],
+                "unit": "TFLOP/s", "frac": round(r["achieved"] / PEAK_TFLOPS[name], 4),
+                "traffic": None, "kernel": f"k_event<{name}>",
+                "kernel_ms": round(r["avg_ms"], 4), "evals_per_launch": int(r["evals"])}
+
+    k = args.steps
+    w32 = res["fp32"]["wall"]
+    line = {
+        "metric": "lnL evals/s at 300 ev x 5k samples (FP32 vs FP64), p50/p99 latency, |dlnL|",
+        "value": round(B * k / w32, 2),
+        "unit": "lnL evals/s",
+        "n_gpus": 1, "steps": k, "warmup": args.warmup,
+        "ms_per_step": round(w32 / k * 1e3, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": wl.name, "events": wl.n_events, "samples_per_event": wl.n_samples,
+                   "galaxies": wl.n_galaxies, "nside": wl.nside, "n_z": wl.n_z,
+                   "injections": wl.n_inj, "batch": B},
+        "latency_ms": {"p50": round(pct(res["fp32"]["lat"], 50), 4),
+                       "p99": round(pct(res["fp32"]["lat"], 99), 4)},
+        "fp64": {"value": round(B * k / res["fp64"]["wall"], 2),
+                 "ms_per_step": round(res["fp64"]["wall"] / k * 1e3, 4),
+                 "latency_ms": {"p50": round(pct(res["fp64"]["lat"], 50), 4),
+                                "p99": round(pct(res["fp64"]["lat"], 99), 4)}},
+        "speedup_fp32_over_fp64": round(res["fp64"]["wall"] / w32, 3),
+        "abs_dlnL_fp32_vs_fp64": {"max": dmax, "same_finite_mask": same_mask,
+                                  "finite_points": int(fin.sum())},
+        "roofline": roof("fp32"),
+        "roofline_fp64": roof("fp64"),
+    }
+    ctx.close()
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle (cpu_baseline)")
+        line["cpu_baseline"] = cpu_baseline(wl, cf, ev, inj, lam[0], args.cpu_events)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

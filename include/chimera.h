@@ -145,6 +145,17 @@ chimera_status chimera_lnl_batch(chimera_ctx* ctx, const chimera_events* ev, con
 chimera_status chimera_selection_xi(chimera_ctx* ctx, const double* lam, int64_t B, int32_t prec,
                                     double* ln_xi, double* n_eff, int32_t mem, void* hip_stream);
 
+/* Diagnostics.  With profiling on, every chimera_lnl_batch call on this
+ * context brackets its event kernel with HIP events recorded on the call's
+ * stream, and the kernel counts the (sample, grid point) pairs it evaluates
+ * (the windows |z_g - z_j| <= T h of samples with nonzero weight).
+ * chimera_profile_read waits for the recorded events, returns the number of
+ * event-kernel launches, their summed duration in milliseconds and the summed
+ * evaluation count since the last read, and resets them. */
+chimera_status chimera_profile_enable(chimera_ctx* ctx, int32_t on);
+chimera_status chimera_profile_read(chimera_ctx* ctx, int64_t* n_launches, double* total_ms,
+                                    int64_t* n_evals);
+
 #ifdef __cplusplus
 }
 #endif

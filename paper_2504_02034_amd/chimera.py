@@ -27,7 +27,8 @@ _STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ERANGE", -5:
 #: every symbol include/chimera.h declares
 EXPORTS = ("chimera_default_config", "chimera_create", "chimera_destroy", "chimera_last_error",
            "chimera_set_catalog", "chimera_set_injections", "chimera_add_events",
-           "chimera_release_events", "chimera_lnl_batch", "chimera_selection_xi")
+           "chimera_release_events", "chimera_lnl_batch", "chimera_selection_xi",
+           "chimera_profile_enable", "chimera_profile_read")
 
 
 class ChimeraError(RuntimeError):
@@ -65,6 +66,10 @@ def _load():
         "chimera_release_events": (ctypes.c_int, [_P, _P]),
         "chimera_lnl_batch": (ctypes.c_int, [_P, _P, _P, _I64, _I32, _P, _P, _I32, _P]),
         "chimera_selection_xi": (ctypes.c_int, [_P, _P, _I64, _I32, _P, _P, _I32, _P]),
+        "chimera_profile_enable": (ctypes.c_int, [_P, _I32]),
+        "chimera_profile_read": (ctypes.c_int, [_P, ctypes.POINTER(_I64),
+                                                ctypes.POINTER(ctypes.c_double),
+                                                ctypes.POINTER(_I64)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -183,6 +188,17 @@ def chimera_selection_xi(h, lam, prec=CHIMERA_FP64, stream=None):
     _check(lib.chimera_selection_xi(h, pl, B, prec, lx.ctypes.data_as(_P), ne.ctypes.data_as(_P),
                                     CHIMERA_HOST, None))
     return lx, ne
+
+
+def chimera_profile_enable(h, on=True):
+    _check(lib.chimera_profile_enable(h, 1 if on else 0))
+
+
+def chimera_profile_read(h):
+    """(event-kernel launches, their summed ms, summed (sample, grid point) evaluations)."""
+    n, ms, ev = _I64(), ctypes.c_double(), _I64()
+    _check(lib.chimera_profile_read(h, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(ev)))
+    return n.value, ms.value, ev.value
 
 
 # ---------------------------------------------------------------------------

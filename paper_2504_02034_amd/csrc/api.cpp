@@ -70,10 +70,17 @@ struct Carve {
 struct chimera_events {
   int E = 0;
   int64_t n_samp = 0;
-  int* ev_samp_off = nullptr;
+  int max_groups = 0;
+  // per event: group and pixel-slot ranges
+  int* ev_grp_off = nullptr;
+  int* ev_slot_off = nullptr;
+  int* slot_row = nullptr;
+  // per group
+  int *grp_first = nullptr, *grp_cnt = nullptr, *grp_slot = nullptr;
+  double* grp_c = nullptr;
+  // samples in group order
   double *dl = nullptr, *lndl = nullptr, *m1d = nullptr, *m2d = nullptr;
-  double *lnm1d = nullptr, *lnm2d = nullptr, *samp_c = nullptr;
-  int* samp_row = nullptr;
+  double *lnm1d = nullptr, *lnm2d = nullptr;
   double dmin = 0.0, dmax = 0.0;
 };
 
@@ -90,14 +97,19 @@ struct chimera_ctx {
   double inj_dmin = 0.0, inj_dmax = 0.0;
   bool has_cat = false, has_inj = false;
   std::vector<chimera_events*> events;
+  // diagnostics
+  bool profile = false;
+  unsigned long long* d_count = nullptr;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> marks;
 };
 
 namespace {
 
 void free_events(chimera_events* ev) {
-  dfree(ev->ev_samp_off);
+  dfree(ev->ev_grp_off); dfree(ev->ev_slot_off); dfree(ev->slot_row);
+  dfree(ev->grp_first); dfree(ev->grp_cnt); dfree(ev->grp_slot); dfree(ev->grp_c);
   dfree(ev->dl); dfree(ev->lndl); dfree(ev->m1d); dfree(ev->m2d);
-  dfree(ev->lnm1d); dfree(ev->lnm2d); dfree(ev->samp_c); dfree(ev->samp_row);
+  dfree(ev->lnm1d); dfree(ev->lnm2d);
   delete ev;
 }
 
@@ -229,6 +241,11 @@ void chimera_destroy(chimera_ctx* ctx) {
   if (!ctx) return;
   (void)hipSetDevice(ctx->cfg.device);
   (void)hipDeviceSynchronize();
+  for (auto& m : ctx->marks) {
+    (void)hipEventDestroy(m.first);
+    (void)hipEventDestroy(m.second);
+  }
+  dfree(ctx->d_count);
   for (auto* e : ctx->events) free_events(e);
   free_catalog(ctx);
   free_injections(ctx);
@@ -326,43 +343,96 @@ chimera_status chimera_add_events(chimera_ctx* ctx, int32_t n_ev, const int64_t*
   if (S > (int64_t)0x7fffffff) return fail(CHIMERA_ERANGE, "too many samples in one set");
   if (!finite_positive(dl, S) || !finite_positive(m1d, S) || !finite_positive(m2d, S))
     return fail(CHIMERA_EINVAL, "sample distances and masses must be finite and > 0");
-  std::vector<int> evoff(n_ev + 1), row(S);
-  std::vector<double> c(S), ld(S), l1(S), l2(S);
-  for (int i = 0; i <= n_ev; ++i) evoff[i] = (int)pix_samp_off[ev_pix_off[i]];
-  for (int i = 0; i < n_ev; ++i)
-    if (evoff[i + 1] - evoff[i] > event_max_samples())
-      return fail(CHIMERA_ERANGE, "an event has more samples than the kernels take (" +
-                                      std::to_string(event_max_samples()) + ")");
-  double dmin = std::numeric_limits<double>::infinity(), dmax = 0.0;
-  for (int64_t p = 0; p < P; ++p)
-    for (int64_t j = pix_samp_off[p]; j < pix_samp_off[p + 1]; ++j) {
-      row[j] = (int)pix_row[p];
-      c[j] = c_ir[p];
+  // Groups: <= kGroupK samples of one pixel, consecutive in distance, spanning
+  // at most kGroupSpread times the event's distance spread; the event's groups
+  // are then ordered by mean distance (the same order in redshift for every
+  // lambda, since d_L^gw is increasing).
+  const double kGroupSpread = 0.6;
+  std::vector<int> ev_grp(n_ev + 1, 0), ev_slot(n_ev + 1), srow(P);
+  std::vector<int> gfirst, gcnt, gslot;
+  std::vector<double> gc;
+  std::vector<double> odl, om1, om2;
+  odl.reserve(S); om1.reserve(S); om2.reserve(S);
+  int max_groups = 0;
+  for (int64_t p = 0; p < P; ++p) srow[p] = (int)pix_row[p];
+  for (int i = 0; i <= n_ev; ++i) ev_slot[i] = (int)ev_pix_off[i];
+  struct G { double mean; int slot; std::vector<int64_t> idx; };
+  for (int e = 0; e < n_ev; ++e) {
+    const int64_t a0 = pix_samp_off[ev_pix_off[e]], a1 = pix_samp_off[ev_pix_off[e + 1]];
+    double m = 0.0, m2 = 0.0;
+    for (int64_t j = a0; j < a1; ++j) m += dl[j];
+    m /= (double)(a1 - a0);
+    for (int64_t j = a0; j < a1; ++j) m2 += (dl[j] - m) * (dl[j] - m);
+    const double spread = kGroupSpread * std::sqrt(m2 / (double)std::max<int64_t>(a1 - a0, 1));
+    std::vector<G> groups;
+    for (int64_t p = ev_pix_off[e]; p < ev_pix_off[e + 1]; ++p) {
+      std::vector<int64_t> idx;
+      for (int64_t j = pix_samp_off[p]; j < pix_samp_off[p + 1]; ++j) idx.push_back(j);
+      std::stable_sort(idx.begin(), idx.end(), [&](int64_t x, int64_t y) { return dl[x] < dl[y]; });
+      size_t k = 0;
+      while (k < idx.size()) {
+        G g;
+        g.slot = (int)(p - ev_pix_off[e]);
+        const double d0 = dl[idx[k]];
+        while (k < idx.size() && (int)g.idx.size() < kGroupK && dl[idx[k]] - d0 <= spread)
+          g.idx.push_back(idx[k++]);
+        double s = 0.0;
+        for (auto j : g.idx) s += dl[j];
+        g.mean = s / (double)g.idx.size();
+        groups.push_back(std::move(g));
+      }
     }
+    std::stable_sort(groups.begin(), groups.end(), [](const G& x, const G& y) {
+      return x.mean < y.mean || (x.mean == y.mean && x.slot < y.slot);
+    });
+    if ((int)groups.size() > kGroupMaxPerEvent)
+      return fail(CHIMERA_ERANGE, "an event needs more sample groups than the kernel takes (" +
+                                      std::to_string(kGroupMaxPerEvent) + ")");
+    max_groups = std::max(max_groups, (int)groups.size());
+    for (auto& g : groups) {
+      gfirst.push_back((int)odl.size());
+      gcnt.push_back((int)g.idx.size());
+      gslot.push_back(g.slot);
+      gc.push_back(c_ir[ev_pix_off[e] + g.slot]);
+      for (auto j : g.idx) {
+        odl.push_back(dl[j]);
+        om1.push_back(m1d[j]);
+        om2.push_back(m2d[j]);
+      }
+    }
+    ev_grp[e + 1] = (int)gfirst.size();
+  }
+  std::vector<double> ld(S), l1(S), l2(S);
+  double dmin = std::numeric_limits<double>::infinity(), dmax = 0.0;
   for (int64_t j = 0; j < S; ++j) {
-    ld[j] = std::log(dl[j]);
-    l1[j] = std::log(m1d[j]);
-    l2[j] = std::log(m2d[j]);
-    dmin = std::min(dmin, dl[j]);
-    dmax = std::max(dmax, dl[j]);
+    ld[j] = std::log(odl[j]);
+    l1[j] = std::log(om1[j]);
+    l2[j] = std::log(om2[j]);
+    dmin = std::min(dmin, odl[j]);
+    dmax = std::max(dmax, odl[j]);
   }
   std::lock_guard<std::mutex> lk(ctx->mu);
   HIP_TRY(hipSetDevice(ctx->cfg.device));
   auto* ev = new chimera_events();
   ev->E = n_ev;
   ev->n_samp = S;
+  ev->max_groups = max_groups;
   ev->dmin = dmin;
   ev->dmax = dmax;
   hipError_t e = hipSuccess;
-  if (e == hipSuccess) e = upload(&ev->ev_samp_off, evoff.data(), evoff.size());
-  if (e == hipSuccess) e = upload(&ev->dl, dl, S);
+  if (e == hipSuccess) e = upload(&ev->ev_grp_off, ev_grp.data(), ev_grp.size());
+  if (e == hipSuccess) e = upload(&ev->ev_slot_off, ev_slot.data(), ev_slot.size());
+  if (e == hipSuccess) e = upload(&ev->slot_row, srow.data(), srow.size());
+  if (e == hipSuccess) e = upload(&ev->grp_first, gfirst.data(), gfirst.size());
+  if (e == hipSuccess) e = upload(&ev->grp_cnt, gcnt.data(), gcnt.size());
+  if (e == hipSuccess) e = upload(&ev->grp_slot, gslot.data(), gslot.size());
+  if (e == hipSuccess) e = upload(&ev->grp_c, gc.data(), gc.size());
+  if (e == hipSuccess) e = upload(&ev->dl, odl.data(), S);
   if (e == hipSuccess) e = upload(&ev->lndl, ld.data(), S);
-  if (e == hipSuccess) e = upload(&ev->m1d, m1d, S);
-  if (e == hipSuccess) e = upload(&ev->m2d, m2d, S);
+  if (e == hipSuccess) e = upload(&ev->m1d, om1.data(), S);
+  if (e == hipSuccess) e = upload(&ev->m2d, om2.data(), S);
   if (e == hipSuccess) e = upload(&ev->lnm1d, l1.data(), S);
   if (e == hipSuccess) e = upload(&ev->lnm2d, l2.data(), S);
-  if (e == hipSuccess) e = upload(&ev->samp_row, row.data(), S);
-  if (e == hipSuccess) e = upload(&ev->samp_c, c.data(), S);
   if (e != hipSuccess) {
     free_events(ev);
     return fail(e == hipErrorOutOfMemory ? CHIMERA_ENOMEM : CHIMERA_EDEVICE,
@@ -435,15 +505,32 @@ static chimera_status run_batch(chimera_ctx* ctx, const chimera_events* ev, cons
   sa.partial = s.partial;
   HIP_TRY(launch_selection(sa, f32, lnxi_dev, neff_dev, st));
   if (ev) {
-    EventArgs a;
+    GroupedArgs a;
     a.P = s.P; a.flag_mono = s.flag_mono; a.flag_range = s.flag_range;
     a.chi = s.chi; a.inv = s.inv; a.g = g; a.gz64 = s.gz64; a.gz32 = s.gz32;
-    a.nz64 = ctx->nz64; a.nz32 = ctx->nz32; a.ev_samp_off = ev->ev_samp_off;
+    a.nz64 = ctx->nz64; a.nz32 = ctx->nz32;
+    a.ev_grp_off = ev->ev_grp_off; a.ev_slot_off = ev->ev_slot_off; a.slot_row = ev->slot_row;
+    a.grp_first = ev->grp_first; a.grp_cnt = ev->grp_cnt; a.grp_slot = ev->grp_slot;
+    a.grp_c = ev->grp_c;
     a.dl = ev->dl; a.lndl = ev->lndl; a.m1d = ev->m1d; a.m2d = ev->m2d;
-    a.lnm1d = ev->lnm1d; a.lnm2d = ev->lnm2d; a.samp_row = ev->samp_row; a.samp_c = ev->samp_c;
+    a.lnm1d = ev->lnm1d; a.lnm2d = ev->lnm2d;
     a.E = E; a.B = (int)B; a.trunc = f32 ? ctx->cfg.trunc_fp32 : ctx->cfg.trunc_fp64;
-    a.nchunk = 0; a.bc = 0; a.lnI = lnI_dev;
-    HIP_TRY(launch_events(a, f32, st));
+    a.nchunk = 0; a.bc = 0; a.f_bytes = 0; a.g_cap = 0; a.lnI = lnI_dev;
+    a.count = nullptr;
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    if (ctx->profile) {
+      std::lock_guard<std::mutex> lk(ctx->mu);
+      a.count = ctx->d_count;
+      HIP_TRY(hipEventCreate(&t0));
+      HIP_TRY(hipEventCreate(&t1));
+      HIP_TRY(hipEventRecord(t0, st));
+    }
+    HIP_TRY(launch_events_grouped(a, f32, ev->max_groups, st));
+    if (t0) {
+      HIP_TRY(hipEventRecord(t1, st));
+      std::lock_guard<std::mutex> lk(ctx->mu);
+      ctx->marks.emplace_back(t0, t1);
+    }
     HIP_TRY(launch_lnl_final(s.P, s.flag_mono, s.flag_range, lnI_dev, lnxi_dev, E, (int)B,
                              lnl_dev, st));
   }
@@ -478,6 +565,46 @@ chimera_status chimera_selection_xi(chimera_ctx* ctx, const double* lam, int64_t
   if (s != CHIMERA_OK) return s;
   if (!ln_xi) return fail(CHIMERA_EINVAL, "null output");
   return run_batch(ctx, nullptr, lam, B, prec, nullptr, nullptr, ln_xi, n_eff, mem, hip_stream);
+}
+
+chimera_status chimera_profile_enable(chimera_ctx* ctx, int32_t on) {
+  if (!ctx) return fail(CHIMERA_EINVAL, "null context");
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  HIP_TRY(hipSetDevice(ctx->cfg.device));
+  if (on && !ctx->d_count) {
+    HIP_TRY(hipMalloc((void**)&ctx->d_count, sizeof(unsigned long long)));
+    HIP_TRY(hipMemset(ctx->d_count, 0, sizeof(unsigned long long)));
+  }
+  ctx->profile = on != 0;
+  return CHIMERA_OK;
+}
+
+chimera_status chimera_profile_read(chimera_ctx* ctx, int64_t* n_launches, double* total_ms,
+                                    int64_t* n_evals) {
+  if (!ctx) return fail(CHIMERA_EINVAL, "null context");
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  HIP_TRY(hipSetDevice(ctx->cfg.device));
+  double ms = 0.0;
+  for (auto& m : ctx->marks) {
+    HIP_TRY(hipEventSynchronize(m.second));
+    float t = 0.0f;
+    HIP_TRY(hipEventElapsedTime(&t, m.first, m.second));
+    ms += t;
+    (void)hipEventDestroy(m.first);
+    (void)hipEventDestroy(m.second);
+  }
+  const int64_t n = (int64_t)ctx->marks.size();
+  ctx->marks.clear();
+  unsigned long long cnt = 0;
+  if (ctx->d_count) {
+    HIP_TRY(hipDeviceSynchronize());
+    HIP_TRY(hipMemcpy(&cnt, ctx->d_count, sizeof(cnt), hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemset(ctx->d_count, 0, sizeof(cnt)));
+  }
+  if (n_launches) *n_launches = n;
+  if (total_ms) *total_ms = ms;
+  if (n_evals) *n_evals = (int64_t)cnt;
+  return CHIMERA_OK;
 }
 
 }  // extern "C"

@@ -4,9 +4,7 @@
 //   k_chi_table       chi(x) = int dz/E on x = ln(1+z) nodes, FP64 (eq. dL-em)
 //   k_inverse_table   x(ln d) with d_L^gw(x) = d (eqs. dL-em, dL-mg)
 //   k_grid_factor     tau_g psi(z_g) / [(1+z_g)^3 d d_L^gw/dz]   (eq. jacobian)
-//   k_event<F64|F32>  one (event, lambda) per workgroup: sample redshifts and
-//                     mass weights, bandwidth, kernel sums against n_r g,
-//                     ln I_i (eqs. like-integrals, gw-kernel-many1d)
+//   (the per-(event, lambda) kernel sums are in event_grouped.hip)
 //   k_selection       injection sums of s_j and s_j^2 (Sect. 2.2)
 //   k_*_final         fixed-order reductions to ln xi, N_eff, ln L (eq. hyperlike)
 //
@@ -17,37 +15,9 @@
 
 #include "common.h"
 #include "launch.h"
+#include "reduce.h"
 
 namespace chimera {
-
-// ---------------------------------------------------------------------------
-// reductions
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
-  return v;
-}
-
-// Sum over the workgroup, fixed order; every thread gets the result.
-// red must hold BS/64 + 1 doubles; leaves red reusable on return.
-template <int BS>
-__device__ __forceinline__ double block_sum(double v, double* red) {
-  v = wave_sum(v);
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  if (lane == 0) red[w] = v;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double t = 0.0;
-#pragma unroll
-    for (int i = 0; i < BS / 64; ++i) t += red[i];
-    red[BS / 64] = t;
-  }
-  __syncthreads();
-  const double r = red[BS / 64];
-  __syncthreads();
-  return r;
-}
 
 // ---------------------------------------------------------------------------
 // per-lambda constants
@@ -242,139 +212,6 @@ __global__ void k_grid_factor(const LamParams* __restrict__ Pv, const double2* _
 }
 
 // ---------------------------------------------------------------------------
-// event kernel
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ bool decode_event_block(const EventArgs& a, int& e, int& b) {
-  const int L = blockIdx.x;
-  const int xcd = L & 7, s = L >> 3;
-  const int u = (s / a.bc) * 8 + xcd;     // (event, lambda-chunk) unit on this XCD
-  e = u / a.nchunk;
-  b = (u % a.nchunk) * a.bc + (s % a.bc);
-  return e < a.E && b < a.B;
-}
-
-template <int BS, int SPT, bool F32>
-__global__ __launch_bounds__(BS) void k_event(EventArgs a) {
-  int e, b;
-  if (!decode_event_block(a, e, b)) return;
-  __shared__ double red[BS / 64 + 1];
-  __shared__ double z_ref;
-  const LamParams P = a.P[b];
-  const int flag = P.flag | a.flag_mono[b] | a.flag_range[b];
-  double* out = a.lnI + (size_t)b * a.E + e;
-  if (flag) {
-    if (threadIdx.x == 0) *out = (flag & kFlagRange) ? NAN : -INFINITY;
-    return;
-  }
-  const double2* chi = a.chi + (size_t)b * a.g.n_t;
-  const double2* inv = a.inv + (size_t)b * a.g.n_u;
-  const int s0 = a.ev_samp_off[e];
-  const int n = a.ev_samp_off[e + 1] - s0;
-  const int polish = F32 ? 0 : 1;
-
-  // --- sample redshifts and mass weights (Sect. 2.1; eq. gw-kernel) ---
-  double zr[SPT];
-  double wr[SPT];
-  if (threadIdx.x == 0) {
-    const int j = s0;
-    const double x = invert_x(P, chi, inv, a.g, a.dl[j], a.lndl[j], polish);
-    z_ref = expm1(x);
-  }
-  __syncthreads();
-  const double zref = z_ref;
-  double W1 = 0.0, W2 = 0.0, S1 = 0.0, S2 = 0.0;
-#pragma unroll
-  for (int k = 0; k < SPT; ++k) {
-    const int jj = threadIdx.x + k * BS;
-    zr[k] = 0.0;
-    wr[k] = 0.0;
-    if (jj < n) {
-      const int j = s0 + jj;
-      const double x = invert_x(P, chi, inv, a.g, a.dl[j], a.lndl[j], polish);
-      const double zp1 = exp(x);
-      const double z = expm1(x);
-      const double m1 = a.m1d[j] / zp1, m2 = a.m2d[j] / zp1;
-      const double l1 = a.lnm1d[j] - x, l2 = a.lnm2d[j] - x;
-      const double w = F32 ? (double)mass_weight32(P, m1, m2, l1, l2)
-                           : mass_weight64(P, m1, m2, l1, l2);
-      zr[k] = z;
-      wr[k] = w;
-      const double dz = z - zref;
-      W1 += w;
-      W2 += w * w;
-      S1 += w * dz;
-      S2 += w * dz * dz;
-    }
-  }
-  W1 = block_sum<BS>(W1, red);
-  W2 = block_sum<BS>(W2, red);
-  S1 = block_sum<BS>(S1, red);
-  S2 = block_sum<BS>(S2, red);
-  if (!(W1 > 0.0)) {
-    if (threadIdx.x == 0) *out = -INFINITY;
-    return;
-  }
-  // --- bandwidth: Scott's rule with Kish n_eff, unbiased weighted variance ---
-  const double den = W1 * W1 - W2;
-  double var = 0.0;
-  if (!(den <= 1e-12 * W1 * W1)) var = (S2 - S1 * S1 / W1) / (W1 - W2 / W1);
-  if (var < 0.0) var = 0.0;
-  const double neff = W1 * W1 / W2;
-  const double h = fmax(sqrt(var) * pow(neff, -0.2), 2.0 * a.g.dz);
-  const double T = a.trunc;
-
-  // --- kernel sums against n_r(z_g) g(z_g) on |z_g - z_j| <= T h ---
-  double acc = 0.0;
-#pragma unroll
-  for (int k = 0; k < SPT; ++k) {
-    const int jj = threadIdx.x + k * BS;
-    if (jj >= n || wr[k] == 0.0) continue;
-    const int j = s0 + jj;
-    const double z = zr[k];
-    // window in floating point, clamped before the integer conversion
-    const double lo_d = fmax(ceil((z - T * h - a.g.z_lo) / a.g.dz), 0.0);
-    const double hi_d = fmin(floor((z + T * h - a.g.z_lo) / a.g.dz), (double)(a.g.n_z - 1));
-    if (!(lo_d <= hi_d)) continue;
-    const int lo = (int)lo_d, hi = (int)hi_d;
-    const size_t row = (size_t)a.samp_row[j] * a.g.n_z;
-    if (!F32) {
-      const double* nr = a.nz64 + row;
-      const double* gz = a.gz64 + (size_t)b * a.g.n_z;
-      const double inv2h2 = 0.5 / (h * h);
-      const double d0 = (a.g.z_lo + (double)lo * a.g.dz) - z;
-      double ee = exp(-d0 * d0 * inv2h2);
-      double r = exp(-(2.0 * d0 * a.g.dz + a.g.dz * a.g.dz) * inv2h2);
-      const double q = exp(-2.0 * a.g.dz * a.g.dz * inv2h2);
-      double s = 0.0;
-      for (int gi = lo; gi <= hi; ++gi) {
-        s += ee * nr[gi] * gz[gi];
-        ee *= r;
-        r *= q;
-      }
-      acc += a.samp_c[j] * wr[k] * s;
-    } else {
-      const float* nr = a.nz32 + row;
-      const float* gz = a.gz32 + (size_t)b * a.g.n_z;
-      // exp2(-(u c)^2) with u = (z_g - z_j)/h, c^2 = log2(e)/2
-      const float c = (float)(0.84932180028801904272 / h);
-      const float base = (float)((a.g.z_lo + (double)lo * a.g.dz) - z) * c;
-      const float step = (float)a.g.dz * c;
-      float s = 0.0f;
-      for (int gi = lo; gi <= hi; ++gi) {
-        const float u = fmaf((float)(gi - lo), step, base);
-        s = fmaf(exp2f(-u * u), nr[gi] * gz[gi], s);
-      }
-      acc += a.samp_c[j] * wr[k] * (double)s;
-    }
-  }
-  acc = block_sum<BS>(acc, red);
-  if (threadIdx.x == 0) {
-    const double I = acc * kInvSqrt2Pi / h;
-    *out = I > 0.0 ? log(I) : -INFINITY;
-  }
-}
-
-// ---------------------------------------------------------------------------
 // selection: partial sums of s_j and s_j^2 per (injection chunk, lambda)
 // ---------------------------------------------------------------------------
 constexpr int kSelBS = 256;
@@ -506,22 +343,6 @@ hipError_t launch_tables(const double* lam, int B, const Geometry& g, LamParams*
     k_grid_factor<<<(unsigned)((ng + 255) / 256), 256, 0, st>>>(P, chi, g, B, gz64, gz32);
     CH_LAUNCH_CHECK();
   }
-  return hipSuccess;
-}
-
-int event_max_samples() { return kEventBS * kEventSPT; }
-
-hipError_t launch_events(const EventArgs& a0, bool f32, hipStream_t st) {
-  EventArgs a = a0;
-  a.bc = a.B < 32 ? a.B : 32;
-  a.nchunk = (a.B + a.bc - 1) / a.bc;
-  const long long units = (long long)a.E * a.nchunk;
-  const long long blocks = ((units + 7) / 8) * 8 * a.bc;
-  if (f32)
-    k_event<kEventBS, kEventSPT, true><<<(unsigned)blocks, kEventBS, 0, st>>>(a);
-  else
-    k_event<kEventBS, kEventSPT, false><<<(unsigned)blocks, kEventBS, 0, st>>>(a);
-  CH_LAUNCH_CHECK();
   return hipSuccess;
 }
 
