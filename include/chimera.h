@@ -83,13 +83,13 @@ typedef struct {
   int32_t n_tab;        /* nodes of the per-lambda distance tables (>= 256)           */
   double z_tab_max;     /* the tables cover z in [0, z_tab_max]                        */
   double trunc_fp64;    /* kernel support |z_g - z_j| <= T h in FP64 mode (>= 8.6)     */
-  double trunc_fp32;    /* ... in FP32 mode                                            */
+  double trunc_fp32;    /* ... in FP32 mode (same quantity: keep it equal to trunc_fp64) */
   int32_t device;       /* HIP device ordinal                                          */
   size_t hbm_budget;    /* max scratch bytes one call may take; 0 = no limit           */
 } chimera_config;
 
 /* Fill cfg with defaults: n_z 1000 on [0, 1.6], n_tab 8192, z_tab_max 25,
- * trunc 8.6 / 5.8, device 0, no budget. */
+ * trunc 8.6 in both precisions, device 0, no budget. */
 void chimera_default_config(chimera_config* cfg);
 
 /* Create a context on cfg->device.  Returns EINVAL for an inconsistent

@@ -53,6 +53,13 @@ def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
                           "(the likelihood has no CPU path)")
+    # One HIP runtime per process: torch ships its own libamdhip64.so.7; when
+    # it is loaded first, the library's dependency on that soname resolves to
+    # the same copy, so device pointers and streams from torch are valid here.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(LIB_PATH)
     sig = {
         "chimera_default_config": (None, [ctypes.POINTER(Config)]),

@@ -205,7 +205,7 @@ void chimera_default_config(chimera_config* cfg) {
   cfg->n_tab = 8192;
   cfg->z_tab_max = 25.0;
   cfg->trunc_fp64 = 8.6;
-  cfg->trunc_fp32 = 5.8;
+  cfg->trunc_fp32 = 8.6;
   cfg->device = 0;
   cfg->hbm_budget = 0;
 }

@@ -16,9 +16,9 @@
 //        sum_g F_g N(z_g; z_k, h) = C_k rho_k^(lo-c) sum_g F_g G_(g-c) rho_k^(g-lo),
 //      so one LDS read of F and one of G feed K fused multiply-adds; the
 //      Horner chains continue from slice to slice (slices run downwards).
-// Every lane's window [c - M, c + M] covers each of its samples'
-// |z_g - z_j| <= T h; the extra grid points beyond T h add terms below
-// exp(-T^2/2) of the kernel's peak.
+// Each sample's sum runs over exactly |z_g - z_j| <= T h: the chains of a
+// group share the Horner steps where all of them are inside their windows
+// and are masked one by one on the few edge points where they are not.
 #include <math.h>
 
 #include <type_traits>
@@ -63,6 +63,20 @@ __device__ __forceinline__ void horner_span(A (&acc)[K], const A (&rho)[K],
   }
 }
 
+// The same step with chain k restricted to its own window [lo_k, hi_k]:
+// before the window the chain stays 0, after it the chain is left as is.
+template <class A, int K>
+__device__ __forceinline__ void horner_masked(A (&acc)[K], const A (&rho)[K], const int (&lo_k)[K],
+                                              const int (&hi_k)[K], const A* __restrict__ F,
+                                              const A* __restrict__ G, int hi, int lo) {
+  for (int g = hi; g >= lo; --g) {
+    const A av = F[g] * G[g];
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+      if (g >= lo_k[k]) acc[k] = fma(acc[k], rho[k], g <= hi_k[k] ? av : (A)0);
+  }
+}
+
 }  // namespace
 
 template <int BS, int K, int GT, bool F32>
@@ -77,7 +91,7 @@ __global__ __launch_bounds__(BS) void k_event_grouped(GroupedArgs a) {
   const int flag = P.flag | a.flag_mono[b] | a.flag_range[b];
   double* out = a.lnI + (size_t)b * a.E + e;
   if (flag) {
-    if (threadIdx.x == 0) *out = (flag & kFlagRange) ? NAN : -INFINITY;
+    if (threadIdx.x == 0) *out = (flag & (kFlagDomain | kFlagNonMonotone)) ? -INFINITY : NAN;
     return;
   }
   const double2* chi = a.chi + (size_t)b * a.g.n_t;
@@ -143,58 +157,61 @@ __global__ __launch_bounds__(BS) void k_event_grouped(GroupedArgs a) {
   const double h = fmax(sqrt(var) * pow(W1 * W1 / W2, -0.2), 2.0 * dz);
   const double T = a.trunc;
 
-  // ---- group centres, common half-width M, event window ----------------------
-  int cc[GT];
-  double hs_loc = 0.0;
+  // ---- per-sample windows |z_g - z_j| <= T h, group windows ----------------
+  // chain k of a group covers exactly its own window [lo_k, hi_k]; the group
+  // runs Horner over [lo_G, hi_G] = union, masking per chain only on the
+  // edges outside [L_int, H_int] = intersection.
+  int klo[GT][K], khi[GT][K];
+  int glo[GT], ghi[GT], gli[GT], ghi_i[GT], cc[GT];
+  double lo_loc = 1e9, hi_loc = -1e9, mg_loc = 0.0;
 #pragma unroll
   for (int t = 0; t < GT; ++t) {
-    double zs = 0.0, wn = 0.0, zmin = 1e300, zmax = -1e300;
+    int lo_u = 1 << 30, hi_u = -(1 << 30), lo_i = -(1 << 30), hi_i = 1 << 30;
 #pragma unroll
-    for (int k = 0; k < K; ++k)
+    for (int k = 0; k < K; ++k) {
+      klo[t][k] = 1;
+      khi[t][k] = 0;
       if (ww[t][k] > 0.0) {
-        zs += zz[t][k];
-        wn += 1.0;
-        zmin = fmin(zmin, zz[t][k]);
-        zmax = fmax(zmax, zz[t][k]);
+        const double lo_d = fmax(ceil((zz[t][k] - T * h - a.g.z_lo) / dz), 0.0);
+        const double hi_d = fmin(floor((zz[t][k] + T * h - a.g.z_lo) / dz), (double)(a.g.n_z - 1));
+        if (lo_d <= hi_d) {
+          klo[t][k] = (int)lo_d;
+          khi[t][k] = (int)hi_d;
+          lo_u = min(lo_u, klo[t][k]);
+          hi_u = max(hi_u, khi[t][k]);
+          lo_i = max(lo_i, klo[t][k]);
+          hi_i = min(hi_i, khi[t][k]);
+        }
       }
+    }
+    glo[t] = lo_u;
+    ghi[t] = hi_u;
+    gli[t] = lo_i;
+    ghi_i[t] = hi_i;
     cc[t] = 0;
-    if (wn > 0.0) {
-      // grid index nearest the group's mid-range, clamped to a safe integer range
-      const double cd = fmin(fmax(rint((0.5 * (zmin + zmax) - a.g.z_lo) / dz), -1e6), 1e6);
-      cc[t] = (int)cd;
-      const double zc = a.g.z_lo + cd * dz;
-      hs_loc = fmax(hs_loc, fmax(zmax - zc, zc - zmin) / dz);
-    }
-  }
-  const double hs = block_max<BS>(hs_loc, red);
-  const double Md = fmin(ceil(T * h / dz + hs) + 1.0, 4.0 * a.g.n_z + 8.0);
-  const int M = (int)Md;
-  // event window: union of the lanes' [c - M, c + M] clipped to the grid
-  double lo_loc = 1e9, hi_loc = -1e9;
-  int lo_g[GT], hi_g[GT];
-#pragma unroll
-  for (int t = 0; t < GT; ++t) {
-    bool any = false;
-#pragma unroll
-    for (int k = 0; k < K; ++k) any = any || ww[t][k] > 0.0;
-    lo_g[t] = max(cc[t] - M, 0);
-    hi_g[t] = min(cc[t] + M, a.g.n_z - 1);
-    if (!any) {
-      lo_g[t] = 1;
-      hi_g[t] = 0;
-    }
-    if (lo_g[t] <= hi_g[t]) {
-      lo_loc = fmin(lo_loc, (double)lo_g[t]);
-      hi_loc = fmax(hi_loc, (double)hi_g[t]);
+    if (lo_u <= hi_u) {
+      cc[t] = (lo_u + hi_u) >> 1;
+      lo_loc = fmin(lo_loc, (double)lo_u);
+      hi_loc = fmax(hi_loc, (double)hi_u);
+      mg_loc = fmax(mg_loc, (double)max(hi_u - cc[t], cc[t] - lo_u));
     }
   }
   const int A_lo = (int)(-block_max<BS>(-lo_loc, red));
   const int A_hi = (int)block_max<BS>(hi_loc, red);
+  const int M = (int)block_max<BS>(mg_loc, red);     // |g - c| <= M over every group window
 
   // ---- Horner chains: rho_k, exponent bound -----------------------------------
   const double inv_h2 = 1.0 / (h * h);
-  // |ln rho^t| over a window is at most 2M dz |delta| / h^2, |delta| <= hs dz
-  const double ebound = 2.0 * Md * hs * dz * dz * inv_h2 + 0.5 * hs * hs * dz * dz * inv_h2;
+  double dmax_loc = 0.0;
+#pragma unroll
+  for (int t = 0; t < GT; ++t)
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+      if (klo[t][k] <= khi[t][k])
+        dmax_loc = fmax(dmax_loc, fabs(zz[t][k] - (a.g.z_lo + (double)cc[t] * dz)));
+  const double dmax = block_max<BS>(dmax_loc, red);
+  // |ln (rho^t G)| over a window is at most 2M dz |delta| / h^2 + delta^2 / 2h^2
+  const double ebound = 2.0 * (double)M * dz * dmax * inv_h2 + 0.5 * dmax * dmax * inv_h2;
   // chains in the path's precision; FP32 chains need the bound well inside
   // the float range, FP64 chains inside the double range
   using CT = typename std::conditional<F32, float, double>::type;
@@ -203,7 +220,6 @@ __global__ __launch_bounds__(BS) void k_event_grouped(GroupedArgs a) {
   double npts = 0.0;
 
   // G_m = exp(-m^2 dz^2 / 2h^2), m in [-M, M], in LDS after the F slice
-  // (float when the chains are float)
   const int esz = F32 ? 4 : 8;
   const int f_elems = a.f_bytes / esz;
   CT* Gt = (CT*)(smem + a.f_bytes);
@@ -246,28 +262,35 @@ __global__ __launch_bounds__(BS) void k_event_grouped(GroupedArgs a) {
 #pragma unroll
       for (int t = 0; t < GT; ++t) {
         const int gi = threadIdx.x + t * BS;
-        if (gi >= ng) continue;
-        const int hi = min(hi_g[t], s_hi), lo = max(lo_g[t], s_lo);
+        if (gi >= ng || glo[t] > ghi[t]) continue;
+        const int hi = min(ghi[t], s_hi), lo = max(glo[t], s_lo);
         if (lo > hi) continue;
-        const int slot = a.grp_slot[g0 + gi];
-        const CT* Fp = (const CT*)smem + slot * Ls - s_lo;
-        horner_span<CT, CT, CT, K>(acc[t], rho[t], Fp, Gt + (M - cc[t]), hi, lo);
+        const CT* Fp = (const CT*)smem + a.grp_slot[g0 + gi] * Ls - s_lo;
+        const CT* Gp = Gt + (M - cc[t]);
+        if (gli[t] <= ghi_i[t]) {
+          // upper edge (masked), shared bulk, lower edge (masked)
+          horner_masked<CT, K>(acc[t], rho[t], klo[t], khi[t], Fp, Gp, hi, max(lo, ghi_i[t] + 1));
+          horner_span<CT, CT, CT, K>(acc[t], rho[t], Fp, Gp, min(hi, ghi_i[t]), max(lo, gli[t]));
+          horner_masked<CT, K>(acc[t], rho[t], klo[t], khi[t], Fp, Gp, min(hi, gli[t] - 1), lo);
+        } else {
+          horner_masked<CT, K>(acc[t], rho[t], klo[t], khi[t], Fp, Gp, hi, lo);
+        }
       }
     }
-    // prefactor C_k rho_k^(lo - c) and the sum over the event's samples
+    // prefactor C_k rho_k^(lo_k - c) and the sum over the event's samples
 #pragma unroll
     for (int t = 0; t < GT; ++t) {
       const int gi = threadIdx.x + t * BS;
-      if (gi >= ng || lo_g[t] > hi_g[t]) continue;
+      if (gi >= ng || glo[t] > ghi[t]) continue;
       const double cir = a.grp_c[g0 + gi];
       const double zc = a.g.z_lo + (double)cc[t] * dz;
 #pragma unroll
       for (int k = 0; k < K; ++k) {
-        if (!(ww[t][k] > 0.0)) continue;
+        if (klo[t][k] > khi[t][k]) continue;
         const double av = (double)acc[t][k];
         if (av == 0.0) continue;
         const double delta = zz[t][k] - zc;
-        const double lg = -0.5 * delta * delta * inv_h2 + (double)(lo_g[t] - cc[t]) * dz * delta * inv_h2;
+        const double lg = -0.5 * delta * delta * inv_h2 + (double)(klo[t][k] - cc[t]) * dz * delta * inv_h2;
         total += cir * ww[t][k] * exp(lg) * av;
       }
     }
@@ -277,18 +300,18 @@ __global__ __launch_bounds__(BS) void k_event_grouped(GroupedArgs a) {
 #pragma unroll
     for (int t = 0; t < GT; ++t) {
       const int gi = threadIdx.x + t * BS;
-      if (gi >= ng || lo_g[t] > hi_g[t]) continue;
+      if (gi >= ng) continue;
       const double cir = a.grp_c[g0 + gi];
       const size_t row = (size_t)a.slot_row[p0 + a.grp_slot[g0 + gi]] * a.g.n_z;
 #pragma unroll
       for (int k = 0; k < K; ++k) {
-        if (!(ww[t][k] > 0.0)) continue;
-        double s = 0.0;
-        for (int g = lo_g[t]; g <= hi_g[t]; ++g) {
+        if (klo[t][k] > khi[t][k]) continue;
+        double sacc = 0.0;
+        for (int g = klo[t][k]; g <= khi[t][k]; ++g) {
           const double u = (a.g.z_lo + (double)g * dz - zz[t][k]);
-          s += exp(-0.5 * u * u * inv_h2) * a.nz64[row + g] * gzb[g];
+          sacc += exp(-0.5 * u * u * inv_h2) * a.nz64[row + g] * gzb[g];
         }
-        total += cir * ww[t][k] * s;
+        total += cir * ww[t][k] * sacc;
       }
     }
   }
@@ -297,12 +320,8 @@ __global__ __launch_bounds__(BS) void k_event_grouped(GroupedArgs a) {
 #pragma unroll
     for (int t = 0; t < GT; ++t)
 #pragma unroll
-      for (int k = 0; k < K; ++k) {
-        if (!(ww[t][k] > 0.0)) continue;
-        const double lo_d = fmax(ceil((zz[t][k] - T * h - a.g.z_lo) / dz), 0.0);
-        const double hi_d = fmin(floor((zz[t][k] + T * h - a.g.z_lo) / dz), (double)(a.g.n_z - 1));
-        if (lo_d <= hi_d) npts += hi_d - lo_d + 1.0;
-      }
+      for (int k = 0; k < K; ++k)
+        if (klo[t][k] <= khi[t][k]) npts += (double)(khi[t][k] - klo[t][k] + 1);
   }
   total = block_sum<BS>(total, red);
   if (a.count) {

@@ -310,8 +310,10 @@ __global__ __launch_bounds__(kFinBS) void k_lnl_final(const LamParams* __restric
     const int flag = Pv[b].flag | flag_mono[b] | flag_range[b];
     const double lx = ln_xi[b];
     double v;
-    if (flag & kFlagRange) v = NAN;
-    else if (flag) v = -INFINITY;
+    // a point outside the domain or with a non-monotone distance is -inf even
+    // if its tables also ran out of range; out of range alone is NaN
+    if (flag & (kFlagDomain | kFlagNonMonotone)) v = -INFINITY;
+    else if (flag) v = NAN;
     else if (isnan(s) || isnan(lx)) v = NAN;
     else if (s == -INFINITY || lx == -INFINITY) v = -INFINITY;
     else v = s - (double)E * lx;

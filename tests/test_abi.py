@@ -44,7 +44,7 @@ def test_default_config_values():
     from paper_2504_02034_amd import chimera
     c = chimera.chimera_default_config()
     assert (c.n_z, c.z_lo, c.z_hi, c.n_tab, c.z_tab_max) == (1000, 0.0, 1.6, 8192, 25.0)
-    assert (c.trunc_fp64, c.trunc_fp32, c.device, c.hbm_budget) == (8.6, 5.8, 0, 0)
+    assert (c.trunc_fp64, c.trunc_fp32, c.device, c.hbm_budget) == (8.6, 8.6, 0, 0)
 
 
 def test_bad_config_rejected_without_device():
