@@ -119,7 +119,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="precision_300ev")
     ap.add_argument("--batch", type=int, default=None)
-    ap.add_argument("--cpu-events", type=int, default=60)
+    ap.add_argument("--cpu-events", type=int, default=300)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:

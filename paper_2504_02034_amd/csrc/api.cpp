@@ -73,6 +73,7 @@ struct chimera_events {
   int max_groups = 0;
   // per event: group and pixel-slot ranges
   int* ev_grp_off = nullptr;
+  int* ev_samp_off = nullptr;
   int* ev_slot_off = nullptr;
   int* slot_row = nullptr;
   // per group
@@ -106,7 +107,7 @@ struct chimera_ctx {
 namespace {
 
 void free_events(chimera_events* ev) {
-  dfree(ev->ev_grp_off); dfree(ev->ev_slot_off); dfree(ev->slot_row);
+  dfree(ev->ev_grp_off); dfree(ev->ev_samp_off); dfree(ev->ev_slot_off); dfree(ev->slot_row);
   dfree(ev->grp_first); dfree(ev->grp_cnt); dfree(ev->grp_slot); dfree(ev->grp_c);
   dfree(ev->dl); dfree(ev->lndl); dfree(ev->m1d); dfree(ev->m2d);
   dfree(ev->lnm1d); dfree(ev->lnm2d);
@@ -348,7 +349,7 @@ chimera_status chimera_add_events(chimera_ctx* ctx, int32_t n_ev, const int64_t*
   // are then ordered by mean distance (the same order in redshift for every
   // lambda, since d_L^gw is increasing).
   const double kGroupSpread = 0.6;
-  std::vector<int> ev_grp(n_ev + 1, 0), ev_slot(n_ev + 1), srow(P);
+  std::vector<int> ev_grp(n_ev + 1, 0), ev_samp(n_ev + 1, 0), ev_slot(n_ev + 1), srow(P);
   std::vector<int> gfirst, gcnt, gslot;
   std::vector<double> gc;
   std::vector<double> odl, om1, om2;
@@ -401,6 +402,10 @@ chimera_status chimera_add_events(chimera_ctx* ctx, int32_t n_ev, const int64_t*
       }
     }
     ev_grp[e + 1] = (int)gfirst.size();
+    ev_samp[e + 1] = (int)odl.size();
+    if (ev_samp[e + 1] - ev_samp[e] > kGroupMaxSamples)
+      return fail(CHIMERA_ERANGE, "an event has more samples than the kernel takes (" +
+                                      std::to_string(kGroupMaxSamples) + ")");
   }
   std::vector<double> ld(S), l1(S), l2(S);
   double dmin = std::numeric_limits<double>::infinity(), dmax = 0.0;
@@ -421,6 +426,7 @@ chimera_status chimera_add_events(chimera_ctx* ctx, int32_t n_ev, const int64_t*
   ev->dmax = dmax;
   hipError_t e = hipSuccess;
   if (e == hipSuccess) e = upload(&ev->ev_grp_off, ev_grp.data(), ev_grp.size());
+  if (e == hipSuccess) e = upload(&ev->ev_samp_off, ev_samp.data(), ev_samp.size());
   if (e == hipSuccess) e = upload(&ev->ev_slot_off, ev_slot.data(), ev_slot.size());
   if (e == hipSuccess) e = upload(&ev->slot_row, srow.data(), srow.size());
   if (e == hipSuccess) e = upload(&ev->grp_first, gfirst.data(), gfirst.size());
@@ -509,7 +515,8 @@ static chimera_status run_batch(chimera_ctx* ctx, const chimera_events* ev, cons
     a.P = s.P; a.flag_mono = s.flag_mono; a.flag_range = s.flag_range;
     a.chi = s.chi; a.inv = s.inv; a.g = g; a.gz64 = s.gz64; a.gz32 = s.gz32;
     a.nz64 = ctx->nz64; a.nz32 = ctx->nz32;
-    a.ev_grp_off = ev->ev_grp_off; a.ev_slot_off = ev->ev_slot_off; a.slot_row = ev->slot_row;
+    a.ev_grp_off = ev->ev_grp_off; a.ev_samp_off = ev->ev_samp_off;
+    a.ev_slot_off = ev->ev_slot_off; a.slot_row = ev->slot_row;
     a.grp_first = ev->grp_first; a.grp_cnt = ev->grp_cnt; a.grp_slot = ev->grp_slot;
     a.grp_c = ev->grp_c;
     a.dl = ev->dl; a.lndl = ev->lndl; a.m1d = ev->m1d; a.m2d = ev->m2d;

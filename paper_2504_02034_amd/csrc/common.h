@@ -96,6 +96,17 @@ __device__ __forceinline__ double invert_x(const LamParams& P, const double2* __
   return x;
 }
 
+// Redshift and mass weight of one sample (Sect. 2.1: z from d_L^gw; the
+// masses in the source frame m = m_det / (1+z); eq. gw-kernel weight
+// p(m1) p(m2|m1) with uniform PE priors).  FP64 path: table + one Newton
+// step, whose e^x update reuses the exponential; FP32 path: table only and
+// the mass model in FP32.
+template <bool F32>
+__device__ __forceinline__ void sample_zw(const LamParams& P, const double2* __restrict__ chi,
+                                          const double2* __restrict__ inv, const Geometry& g,
+                                          double d, double lnd, double m1d, double m2d,
+                                          double lnm1d, double lnm2d, double& z, double& w);
+
 // p(m1) p(m2|m1) of the source-frame masses; 0 outside
 // mmin <= m2 <= m1 <= mmax (and m1 > mmin).  l1, l2 = ln m1, ln m2.
 __device__ __forceinline__ double mass_weight64(const LamParams& P, double m1, double m2,
@@ -120,6 +131,27 @@ __device__ __forceinline__ float mass_weight32(const LamParams& P, double m1, do
   const float r = l1 - (float)P.ln_mmin;
   const float n2 = (P.a2 == 0.0) ? r : (float)P.mmin_a2 * expm1f(a2 * r) / a2;
   return (pl + tg) * __expf((float)P.beta * l2) / n2;
+}
+
+template <bool F32>
+__device__ __forceinline__ void sample_zw(const LamParams& P, const double2* __restrict__ chi,
+                                          const double2* __restrict__ inv, const Geometry& g,
+                                          double d, double lnd, double m1d, double m2d,
+                                          double lnm1d, double lnm2d, double& z, double& w) {
+  double x = invert_x(P, chi, inv, g, d, lnd, 0);
+  double zp1 = exp(x);
+  if (!F32) {
+    double D, Dx;
+    dist_at(P, chi, g, x, zp1, D, Dx);
+    const double dx = (D - d) / Dx;           // |dx| is at the table's error, ~1e-12
+    x -= dx;
+    zp1 *= 1.0 - dx + 0.5 * dx * dx;          // e^(x - dx)
+  }
+  z = zp1 - 1.0;
+  const double r = 1.0 / zp1;
+  const double m1 = m1d * r, m2 = m2d * r;
+  const double l1 = lnm1d - x, l2 = lnm2d - x;
+  w = F32 ? (double)mass_weight32(P, m1, m2, l1, l2) : mass_weight64(P, m1, m2, l1, l2);
 }
 
 // Madau-Dickinson psi at x = ln(1+z).

@@ -36,6 +36,8 @@ constexpr int kGroupFBytes64 = 96 * 1024;  // LDS for the staged F slice, FP64 p
 constexpr int kGroupFBytes32 = 96 * 1024;  // ... FP32 path
 constexpr int kGroupGCap = 2048;         // entries of the G_m table
 constexpr int kGroupMaxPerEvent = kGroupBS;   // one group per thread
+// samples of one event, kept as (z, w) in the F region during phase 1
+constexpr int kGroupMaxSamples = kGroupFBytes64 / 16 < kGroupFBytes32 / 16 ? kGroupFBytes64 / 16 : kGroupFBytes32 / 16;
 
 struct GroupedArgs {
   const LamParams* P;
@@ -49,6 +51,7 @@ struct GroupedArgs {
   const double* nz64;
   const float* nz32;
   const int* ev_grp_off;    // [E+1] groups of each event
+  const int* ev_samp_off;   // [E+1] samples of each event (group order)
   const int* ev_slot_off;   // [E+1] pixel slots of each event
   const int* slot_row;      // catalogue row of each pixel slot
   const int* grp_first;     // first sample of each group

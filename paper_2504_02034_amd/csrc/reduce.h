@@ -50,4 +50,33 @@ __device__ __forceinline__ double block_max(double v, double* red) {
   return r;
 }
 
+// N sums (or maxima) over the workgroup in one pass: 3 barriers instead of 3N.
+template <int BS, int N, bool MAX>
+__device__ __forceinline__ void block_reduce(double (&v)[N], double* red /* >= N*(BS/64+1) */) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      const double y = __shfl_down(v[i], o, 64);
+      v[i] = MAX ? fmax(v[i], y) : v[i] + y;
+    }
+    if (lane == 0) red[i * (BS / 64 + 1) + w] = v[i];
+  }
+  __syncthreads();
+  if (threadIdx.x < N) {
+    const int i = threadIdx.x;
+    double t = red[i * (BS / 64 + 1)];
+    for (int k = 1; k < BS / 64; ++k) {
+      const double y = red[i * (BS / 64 + 1) + k];
+      t = MAX ? fmax(t, y) : t + y;
+    }
+    red[i * (BS / 64 + 1) + BS / 64] = t;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < N; ++i) v[i] = red[i * (BS / 64 + 1) + BS / 64];
+  __syncthreads();
+}
+
 }  // namespace chimera
