@@ -70,12 +70,12 @@ struct Carve {
 struct chimera_events {
   int E = 0;
   int64_t n_samp = 0;
-  int max_groups = 0;
-  // per event: group and pixel-slot ranges
-  int* ev_grp_off = nullptr;
+  int U = 0;
   int* ev_samp_off = nullptr;
   int* ev_slot_off = nullptr;
+  int* ev_unit_off = nullptr;
   int* slot_row = nullptr;
+  int *unit_event = nullptr, *unit_grp0 = nullptr, *unit_ngrp = nullptr;
   // per group
   int *grp_first = nullptr, *grp_cnt = nullptr, *grp_slot = nullptr;
   double* grp_c = nullptr;
@@ -107,7 +107,8 @@ struct chimera_ctx {
 namespace {
 
 void free_events(chimera_events* ev) {
-  dfree(ev->ev_grp_off); dfree(ev->ev_samp_off); dfree(ev->ev_slot_off); dfree(ev->slot_row);
+  dfree(ev->ev_samp_off); dfree(ev->ev_slot_off); dfree(ev->ev_unit_off); dfree(ev->slot_row);
+  dfree(ev->unit_event); dfree(ev->unit_grp0); dfree(ev->unit_ngrp);
   dfree(ev->grp_first); dfree(ev->grp_cnt); dfree(ev->grp_slot); dfree(ev->grp_c);
   dfree(ev->dl); dfree(ev->lndl); dfree(ev->m1d); dfree(ev->m2d);
   dfree(ev->lnm1d); dfree(ev->lnm2d);
@@ -160,11 +161,16 @@ struct Scratch {
   double* ln_xi;
   double* neff;
   double* lnl;
+  double* zbuf;
+  void* wbuf;
+  double* hbuf;
+  double* part;
 };
 
 // Lay out (or size, when base is null) the scratch of one call.
 size_t carve(Carve& cv, Scratch& s, const Geometry& g, int64_t B, int E, int nchunk,
-             bool need_lam, bool need_lnI, bool need_grid, bool need_outs) {
+             bool need_lam, bool need_lnI, bool need_grid, bool need_outs, int64_t S = 0,
+             int U = 0, bool f32 = false) {
   s.P = cv.take<LamParams>(B);
   s.chi = cv.take<double2>((size_t)B * g.n_t);
   s.inv = cv.take<double2>((size_t)B * g.n_u);
@@ -178,6 +184,11 @@ size_t carve(Carve& cv, Scratch& s, const Geometry& g, int64_t B, int E, int nch
   s.ln_xi = cv.take<double>(B);
   s.neff = need_outs ? cv.take<double>(B) : nullptr;
   s.lnl = need_outs ? cv.take<double>(B) : nullptr;
+  s.zbuf = S ? cv.take<double>((size_t)B * S) : nullptr;
+  s.wbuf = S ? (f32 ? (void*)cv.take<float>((size_t)B * S) : (void*)cv.take<double>((size_t)B * S))
+             : nullptr;
+  s.hbuf = S ? cv.take<double>((size_t)B * E) : nullptr;
+  s.part = S ? cv.take<double>((size_t)B * std::max(U, 1)) : nullptr;
   return cv.off;
 }
 
@@ -349,12 +360,12 @@ chimera_status chimera_add_events(chimera_ctx* ctx, int32_t n_ev, const int64_t*
   // are then ordered by mean distance (the same order in redshift for every
   // lambda, since d_L^gw is increasing).
   const double kGroupSpread = 0.6;
-  std::vector<int> ev_grp(n_ev + 1, 0), ev_samp(n_ev + 1, 0), ev_slot(n_ev + 1), srow(P);
+  std::vector<int> ev_samp(n_ev + 1, 0), ev_slot(n_ev + 1), ev_unit(n_ev + 1, 0), srow(P);
+  std::vector<int> u_event, u_grp0, u_ngrp;
   std::vector<int> gfirst, gcnt, gslot;
   std::vector<double> gc;
   std::vector<double> odl, om1, om2;
   odl.reserve(S); om1.reserve(S); om2.reserve(S);
-  int max_groups = 0;
   for (int64_t p = 0; p < P; ++p) srow[p] = (int)pix_row[p];
   for (int i = 0; i <= n_ev; ++i) ev_slot[i] = (int)ev_pix_off[i];
   struct G { double mean; int slot; std::vector<int64_t> idx; };
@@ -386,10 +397,17 @@ chimera_status chimera_add_events(chimera_ctx* ctx, int32_t n_ev, const int64_t*
     std::stable_sort(groups.begin(), groups.end(), [](const G& x, const G& y) {
       return x.mean < y.mean || (x.mean == y.mean && x.slot < y.slot);
     });
-    if ((int)groups.size() > kGroupMaxPerEvent)
-      return fail(CHIMERA_ERANGE, "an event needs more sample groups than the kernel takes (" +
-                                      std::to_string(kGroupMaxPerEvent) + ")");
-    max_groups = std::max(max_groups, (int)groups.size());
+    // work units: the event's groups in R nearly equal runs of <= kUnitGroups
+    const int ng = (int)groups.size();
+    const int R = (ng + kUnitGroups - 1) / kUnitGroups;
+    const int gbase = (int)gfirst.size();
+    for (int r = 0; r < R; ++r) {
+      const int a = (int)((long long)ng * r / R), z = (int)((long long)ng * (r + 1) / R);
+      u_event.push_back(e);
+      u_grp0.push_back(gbase + a);
+      u_ngrp.push_back(z - a);
+    }
+    ev_unit[e + 1] = (int)u_event.size();
     for (auto& g : groups) {
       gfirst.push_back((int)odl.size());
       gcnt.push_back((int)g.idx.size());
@@ -401,11 +419,7 @@ chimera_status chimera_add_events(chimera_ctx* ctx, int32_t n_ev, const int64_t*
         om2.push_back(m2d[j]);
       }
     }
-    ev_grp[e + 1] = (int)gfirst.size();
     ev_samp[e + 1] = (int)odl.size();
-    if (ev_samp[e + 1] - ev_samp[e] > kGroupMaxSamples)
-      return fail(CHIMERA_ERANGE, "an event has more samples than the kernel takes (" +
-                                      std::to_string(kGroupMaxSamples) + ")");
   }
   std::vector<double> ld(S), l1(S), l2(S);
   double dmin = std::numeric_limits<double>::infinity(), dmax = 0.0;
@@ -421,11 +435,14 @@ chimera_status chimera_add_events(chimera_ctx* ctx, int32_t n_ev, const int64_t*
   auto* ev = new chimera_events();
   ev->E = n_ev;
   ev->n_samp = S;
-  ev->max_groups = max_groups;
+  ev->U = (int)u_event.size();
   ev->dmin = dmin;
   ev->dmax = dmax;
   hipError_t e = hipSuccess;
-  if (e == hipSuccess) e = upload(&ev->ev_grp_off, ev_grp.data(), ev_grp.size());
+  if (e == hipSuccess) e = upload(&ev->ev_unit_off, ev_unit.data(), ev_unit.size());
+  if (e == hipSuccess) e = upload(&ev->unit_event, u_event.data(), u_event.size());
+  if (e == hipSuccess) e = upload(&ev->unit_grp0, u_grp0.data(), u_grp0.size());
+  if (e == hipSuccess) e = upload(&ev->unit_ngrp, u_ngrp.data(), u_ngrp.size());
   if (e == hipSuccess) e = upload(&ev->ev_samp_off, ev_samp.data(), ev_samp.size());
   if (e == hipSuccess) e = upload(&ev->ev_slot_off, ev_slot.data(), ev_slot.size());
   if (e == hipSuccess) e = upload(&ev->slot_row, srow.data(), srow.size());
@@ -481,7 +498,10 @@ static chimera_status run_batch(chimera_ctx* ctx, const chimera_events* ev, cons
   Scratch s;
   Carve probe;
   const bool need_lnI = ev && (host || !lnI);
-  const size_t bytes = carve(probe, s, g, B, E, nchunk, host, need_lnI, ev != nullptr, host);
+  const int64_t S_ev = ev ? ev->n_samp : 0;
+  const int U_ev = ev ? ev->U : 0;
+  const size_t bytes = carve(probe, s, g, B, E, nchunk, host, need_lnI, ev != nullptr, host,
+                             S_ev, U_ev, f32);
   if (ctx->cfg.hbm_budget && bytes > ctx->cfg.hbm_budget)
     return fail(CHIMERA_ENOMEM, "call needs " + std::to_string(bytes) +
                                     " scratch bytes, over the context's hbm_budget");
@@ -489,7 +509,7 @@ static chimera_status run_batch(chimera_ctx* ctx, const chimera_events* ev, cons
   HIP_TRY(hipMallocAsync(&base, bytes, st));
   Carve cv;
   cv.base = (char*)base;
-  carve(cv, s, g, B, E, nchunk, host, need_lnI, ev != nullptr, host);
+  carve(cv, s, g, B, E, nchunk, host, need_lnI, ev != nullptr, host, S_ev, U_ev, f32);
   const double* lam_dev = lam;
   if (host) {
     HIP_TRY(hipMemcpyAsync(s.lam, lam, (size_t)B * CHIMERA_NLAM * sizeof(double),
@@ -511,18 +531,20 @@ static chimera_status run_batch(chimera_ctx* ctx, const chimera_events* ev, cons
   sa.partial = s.partial;
   HIP_TRY(launch_selection(sa, f32, lnxi_dev, neff_dev, st));
   if (ev) {
-    GroupedArgs a;
+    EventArgs a;
     a.P = s.P; a.flag_mono = s.flag_mono; a.flag_range = s.flag_range;
     a.chi = s.chi; a.inv = s.inv; a.g = g; a.gz64 = s.gz64; a.gz32 = s.gz32;
     a.nz64 = ctx->nz64; a.nz32 = ctx->nz32;
-    a.ev_grp_off = ev->ev_grp_off; a.ev_samp_off = ev->ev_samp_off;
-    a.ev_slot_off = ev->ev_slot_off; a.slot_row = ev->slot_row;
+    a.ev_samp_off = ev->ev_samp_off; a.ev_slot_off = ev->ev_slot_off;
+    a.ev_unit_off = ev->ev_unit_off; a.slot_row = ev->slot_row;
     a.grp_first = ev->grp_first; a.grp_cnt = ev->grp_cnt; a.grp_slot = ev->grp_slot;
     a.grp_c = ev->grp_c;
+    a.unit_event = ev->unit_event; a.unit_grp0 = ev->unit_grp0; a.unit_ngrp = ev->unit_ngrp;
     a.dl = ev->dl; a.lndl = ev->lndl; a.m1d = ev->m1d; a.m2d = ev->m2d;
     a.lnm1d = ev->lnm1d; a.lnm2d = ev->lnm2d;
-    a.E = E; a.B = (int)B; a.trunc = f32 ? ctx->cfg.trunc_fp32 : ctx->cfg.trunc_fp64;
-    a.nchunk = 0; a.bc = 0; a.f_bytes = 0; a.g_cap = 0; a.lnI = lnI_dev;
+    a.E = E; a.U = ev->U; a.B = (int)B; a.S = ev->n_samp;
+    a.trunc = f32 ? ctx->cfg.trunc_fp32 : ctx->cfg.trunc_fp64;
+    a.zbuf = s.zbuf; a.wbuf = s.wbuf; a.hbuf = s.hbuf; a.part = s.part; a.lnI = lnI_dev;
     a.count = nullptr;
     hipEvent_t t0 = nullptr, t1 = nullptr;
     if (ctx->profile) {
@@ -530,11 +552,10 @@ static chimera_status run_batch(chimera_ctx* ctx, const chimera_events* ev, cons
       a.count = ctx->d_count;
       HIP_TRY(hipEventCreate(&t0));
       HIP_TRY(hipEventCreate(&t1));
-      HIP_TRY(hipEventRecord(t0, st));
     }
-    HIP_TRY(launch_events_grouped(a, f32, ev->max_groups, st));
+    // t0 / t1 bracket the smoothing kernel (the dominant one) on stream st
+    HIP_TRY(launch_events(a, f32, st, t0, t1));
     if (t0) {
-      HIP_TRY(hipEventRecord(t1, st));
       std::lock_guard<std::mutex> lk(ctx->mu);
       ctx->marks.emplace_back(t0, t1);
     }

@@ -29,17 +29,15 @@ struct SelArgs {
   double* partial;          // [B][nchunk][2]
 };
 
-// grouped event kernel (event_grouped.hip)
-constexpr int kGroupBS = 1024;           // threads per (event, lambda) workgroup
+// event kernels (event.hip)
+constexpr int kZwBS = 256;               // k_event_zw: threads per (event, lambda)
+constexpr int kSmBS = 256;               // k_event_smooth: one sample group per thread
 constexpr int kGroupK = 8;               // samples per group (Horner chains per lane)
-constexpr int kGroupFBytes64 = 96 * 1024;  // LDS for the staged F slice, FP64 path
-constexpr int kGroupFBytes32 = 96 * 1024;  // ... FP32 path
-constexpr int kGroupGCap = 2048;         // entries of the G_m table
-constexpr int kGroupMaxPerEvent = kGroupBS;   // one group per thread
-// samples of one event, kept as (z, w) in the F region during phase 1
-constexpr int kGroupMaxSamples = kGroupFBytes64 / 16 < kGroupFBytes32 / 16 ? kGroupFBytes64 / 16 : kGroupFBytes32 / 16;
+constexpr int kUnitGroups = kSmBS;       // groups per work unit (chunk of one event)
+constexpr int kSmFBytes = 40 * 1024;     // LDS for the staged F slice
+constexpr int kSmGCap = 1024;            // entries of the G_m table
 
-struct GroupedArgs {
+struct EventArgs {
   const LamParams* P;
   const int* flag_mono;
   const int* flag_range;
@@ -50,29 +48,38 @@ struct GroupedArgs {
   const float* gz32;
   const double* nz64;
   const float* nz32;
-  const int* ev_grp_off;    // [E+1] groups of each event
+  // event set
   const int* ev_samp_off;   // [E+1] samples of each event (group order)
   const int* ev_slot_off;   // [E+1] pixel slots of each event
+  const int* ev_unit_off;   // [E+1] work units of each event
   const int* slot_row;      // catalogue row of each pixel slot
-  const int* grp_first;     // first sample of each group
+  const int* grp_first;     // first sample (absolute) of each group
   const int* grp_cnt;       // samples in the group (<= kGroupK)
   const int* grp_slot;      // pixel slot of the group, relative to its event
   const double* grp_c;      // c_ir of the group's pixel
+  const int* unit_event;    // [U] event of each unit
+  const int* unit_grp0;     // [U] first group (absolute) of each unit
+  const int* unit_ngrp;     // [U] groups in each unit (<= kUnitGroups)
   const double* dl;         // samples in group order
   const double* lndl;
   const double* m1d;
   const double* m2d;
   const double* lnm1d;
   const double* lnm2d;
-  int E, B;
+  int E, U, B;
+  long long S;
   double trunc;
-  int nchunk, bc;
-  int f_bytes, g_cap;
-  double* lnI;
+  // scratch
+  double* zbuf;             // [B][S] redshift of each sample
+  void* wbuf;               // [B][S] mass weight (double, or float in FP32 mode)
+  double* hbuf;             // [B][E] bandwidth (<= 0: no weight in the event)
+  double* part;             // [B][U] partial kernel sums
+  double* lnI;              // [B][E]
   unsigned long long* count;
 };
 
-hipError_t launch_events_grouped(const GroupedArgs& a, bool f32, int max_groups, hipStream_t st);
+hipError_t launch_events(const EventArgs& a, bool f32, hipStream_t st, hipEvent_t t0 = nullptr,
+                         hipEvent_t t1 = nullptr);
 
 hipError_t launch_tables(const double* lam, int B, const Geometry& g, LamParams* P, double2* chi,
                          double2* inv, double* gz64, float* gz32, int* flag_mono,

@@ -1,0 +1,96 @@
+"""Parity at the benchmark's full size and launch configuration (300 events x
+5000 samples, 1e6 galaxies, 1e6 injections, B = 256): per-event ln I_i on
+sampled events and lambdas, and the full ln L on two lambdas, against the
+oracle; plus a ragged medium case (B not a multiple of the 32-lambda block
+chunk, events of several work units)."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2504_02034_amd import synth
+
+pytestmark = pytest.mark.gpu
+REL64 = 1e-10
+
+
+@pytest.fixture(scope="module")
+def full():
+    from tests.datasets import build
+    from paper_2504_02034_amd import chimera
+    d = build(synth.WORKLOADS["precision_300ev"])
+    ctx, es = chimera.context_from_prepared(d.prep, d.inj)
+    yield d, chimera, ctx, es
+    ctx.close()
+
+
+def close(a, b, rel):
+    if math.isnan(b):
+        return math.isnan(a)
+    if math.isinf(b):
+        return a == b
+    return abs(a - b) <= rel * max(1.0, abs(b))
+
+
+def test_full_size_sampled_events(full):
+    import oracle
+    d, chimera, ctx, es = full
+    lam = d.lam                                     # the bench batch, B = 256
+    lnl, lnI = ctx.lnl(es, lam, chimera.CHIMERA_FP64, with_lnI=True)
+    rng = np.random.default_rng(11)
+    lams = [0, 1, 127, 255] + list(rng.choice(np.arange(2, 255), 4, replace=False))
+    evs = [0, 299] + list(rng.choice(np.arange(1, 299), 6, replace=False))
+    for b in lams:
+        ref = oracle.likelihood.lnl(d.o_events, d.o_cat, d.o_inj, lam[b], T=8.6,
+                                    event_subset=evs)
+        print(b, lam[b, :4], [(i, lnI[b, i], ref["lnI"][i]) for i in evs[:3]])
+        for i in evs:
+            assert close(lnI[b, i], ref["lnI"][i], REL64), (b, i, lnI[b, i], ref["lnI"][i])
+
+
+def test_full_size_lnl(full):
+    import oracle
+    d, chimera, ctx, es = full
+    lam = d.lam
+    lnl = ctx.lnl(es, lam, chimera.CHIMERA_FP64)
+    for b in (0, 17):
+        ref = oracle.likelihood.lnl(d.o_events, d.o_cat, d.o_inj, lam[b], T=8.6, workers=8)
+        print(b, lnl[b], ref["lnl"])
+        assert close(lnl[b], ref["lnl"], REL64)
+
+
+def test_full_size_fp32_budget(full):
+    d, chimera, ctx, es = full
+    l64 = ctx.lnl(es, d.lam, chimera.CHIMERA_FP64)
+    l32 = ctx.lnl(es, d.lam, chimera.CHIMERA_FP32)
+    fin = np.isfinite(l64)
+    assert np.array_equal(np.isfinite(l32), fin)
+    dmax = float(np.max(np.abs(l32[fin] - l64[fin])))
+    print("finite", int(fin.sum()), "max |dlnL| fp32 vs fp64", dmax)
+    assert dmax <= 1e-3
+
+
+@pytest.fixture(scope="module")
+def medium():
+    from tests.datasets import build
+    from paper_2504_02034_amd import chimera
+    wl = synth.WORKLOADS["precision_300ev"].scaled(name="medium", n_events=24, n_samples=2600,
+                                                   n_galaxies=200_000, n_inj=200_000,
+                                                   batch=37, seed_index=7)
+    d = build(wl)
+    ctx, es = chimera.context_from_prepared(d.prep, d.inj)
+    yield d, chimera, ctx, es
+    ctx.close()
+
+
+def test_medium_ragged_batch(medium):
+    import oracle
+    d, chimera, ctx, es = medium
+    lam = d.lam
+    assert lam.shape[0] == 37
+    lnl, lnI = ctx.lnl(es, lam, chimera.CHIMERA_FP64, with_lnI=True)
+    for b in (0, 31, 32, 36):
+        ref = oracle.likelihood.lnl(d.o_events, d.o_cat, d.o_inj, lam[b], T=8.6)
+        assert close(lnl[b], ref["lnl"], REL64), (b, lnl[b], ref["lnl"])
+        for i in range(lnI.shape[1]):
+            assert close(lnI[b, i], ref["lnI"][i], REL64), (b, i)
