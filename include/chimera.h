@@ -62,6 +62,10 @@ extern "C" {
 typedef struct chimera_ctx chimera_ctx;
 typedef struct chimera_events chimera_events;
 
+/* Largest number of pixel rows of one event (one row per pixel must fit the
+ * kernels' on-chip slice of the catalogue density). */
+#define CHIMERA_MAX_EVENT_PIXELS 2560
+
 typedef enum {
   CHIMERA_OK = 0,
   CHIMERA_EINVAL = -1,   /* bad argument (null pointer, size, layout) */
@@ -123,7 +127,8 @@ chimera_status chimera_set_injections(chimera_ctx* ctx, int64_t n_det, int64_t n
  *   dl, m1d, m2d[n_samp]    samples, n_samp = pix_samp_off[P], ordered by
  *                           (event, pixel); within a pixel, ascending dl runs
  *                           fastest but any order is accepted
- * Every event must have at least one sample.  Distances > 0.
+ * Every event must have at least one sample.  Distances > 0.  An event may
+ * have at most CHIMERA_MAX_EVENT_PIXELS pixel rows.
  * Returns EINVAL on a malformed layout, ERANGE when a pixel row refers past
  * the catalogue or an event exceeds the largest size the kernels take. */
 chimera_status chimera_add_events(chimera_ctx* ctx, int32_t n_ev, const int64_t* ev_pix_off,

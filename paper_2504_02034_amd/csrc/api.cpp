@@ -338,9 +338,12 @@ chimera_status chimera_add_events(chimera_ctx* ctx, int32_t n_ev, const int64_t*
   if (n_ev < 1) return fail(CHIMERA_EINVAL, "need at least one event");
   if (!ctx->has_cat) return fail(CHIMERA_ESTATE, "set the catalogue before adding events");
   if (ev_pix_off[0] != 0) return fail(CHIMERA_EINVAL, "ev_pix_off[0] must be 0");
-  for (int i = 0; i < n_ev; ++i)
+  for (int i = 0; i < n_ev; ++i) {
     if (ev_pix_off[i + 1] <= ev_pix_off[i])
       return fail(CHIMERA_EINVAL, "every event needs at least one pixel row");
+    if (ev_pix_off[i + 1] - ev_pix_off[i] > CHIMERA_MAX_EVENT_PIXELS)
+      return fail(CHIMERA_ERANGE, "an event has more pixel rows than CHIMERA_MAX_EVENT_PIXELS");
+  }
   const int64_t P = ev_pix_off[n_ev];
   if (pix_samp_off[0] != 0) return fail(CHIMERA_EINVAL, "pix_samp_off[0] must be 0");
   for (int64_t p = 0; p < P; ++p) {

@@ -1,30 +1,33 @@
 // Per-(event, lambda) kernel sums of the many-1D likelihood (eqs.
 // like-integrals and gw-kernel-many1d), gfx950.
 //
-// k_event_zw      one (event, lambda) per workgroup, one sample per thread:
-//                 z_j from d_L^gw, w_j = p(m1) p(m2|m1) into scratch, and the
-//                 event's bandwidth h (Scott's rule, Kish effective size,
-//                 unbiased weighted variance by two passes about the mean).
-// k_event_smooth  one work unit (<= 256 sample groups of one event, ordered by
-//                 distance, so a narrow redshift range) at one lambda per
-//                 workgroup:
-//                   - every thread takes one group (<= K consecutive samples of
-//                     one pixel); each sample's window |z_g - z_j| <= T h;
-//                   - the unit's redshift range is cut into slices; for each
-//                     slice F_r(z_g) = n_r(z_g) g(z_g) of every pixel of the
-//                     event is staged in LDS;
-//                   - each lane evaluates its group's K Gaussian sums by
-//                     Horner's rule in rho_k = exp(dz delta_k / h^2) about the
-//                     group's centre c, with G_m = exp(-m^2 dz^2 / 2h^2):
-//                       sum_g F_g N(z_g; z_k, h)
-//                         = C_k rho_k^(lo_k - c) sum_g F_g G_(g-c) rho_k^(g-lo_k),
-//                     so one LDS read of F and one of G feed K fused
-//                     multiply-adds; the chains continue from slice to slice
-//                     and are masked one by one only on the few edge points
-//                     where a sample's window and the group's differ;
-//                   - the unit's partial sum of c_ir w_j A_j goes to scratch.
-// k_event_final   per (event, lambda): the units' partial sums in a fixed
-//                 order, I_i = sum / (h sqrt(2 pi)), ln I_i.
+// k_event_zw        one (event, lambda) per workgroup, one sample per thread:
+//                   z_j from d_L^gw, w_j = p(m1) p(m2|m1) into scratch, and the
+//                   event's bandwidth h (Scott's rule, Kish effective size,
+//                   unbiased weighted variance by two passes about the mean).
+// k_event_smooth64  one work unit (<= 256 sample groups of one event, ordered
+// k_event_smooth32  by distance, so a narrow redshift range) at one lambda per
+//                   workgroup:
+//                     - every thread takes one group (<= K consecutive samples
+//                       of one pixel); each sample's window |z_g - z_j| <= T h;
+//                     - the unit's redshift range is cut into slices; for each
+//                       slice F_r(z_g) = n_r(z_g) g(z_g) of every pixel of the
+//                       event is staged in LDS, one row segment per wave
+//                       instruction;
+//                     - each lane evaluates its group's K Gaussian sums by
+//                       Horner's rule in rho_k = exp(dz delta_k / h^2) about the
+//                       group's centre c, with G_m = exp(-m^2 dz^2 / 2h^2):
+//                         sum_g F_g N(z_g; z_k, h)
+//                           = C_k rho_k^(lo_k - c) sum_g F_g G_(g-c) rho_k^(g-lo_k),
+//                       so one LDS read of F and one of G feed K fused
+//                       multiply-adds; the chains continue from slice to slice
+//                       and are masked one bound at a time only on the edge
+//                       points where a sample's window and the group's differ;
+//                     - the unit's partial sum of c_ir w_j A_j goes to scratch.
+//                   FP64 runs three workgroups per CU (registers), FP32 four
+//                   (smaller slice, chain factors formed after the sweep).
+// k_event_final     per (event, lambda): the units' partial sums in a fixed
+//                   order, I_i = sum / (h sqrt(2 pi)), ln I_i.
 #include <math.h>
 
 #include <type_traits>
@@ -80,8 +83,36 @@ __device__ __forceinline__ void horner_span(A (&acc)[K], const A (&rho)[K], cons
   }
 }
 
-// The same step with chain k restricted to its own window [lo_k, hi_k]:
-// before the window the chain stays 0, after it the chain is left as is.
+// Edge steps, where the group's windows differ.  Above the common part every
+// chain has passed its lower bound, so only g <= hi_k is tested (a chain that
+// has not entered its window is 0); below it every chain is inside its upper
+// bound, so only g >= lo_k is tested (a chain past its window is left as is).
+template <class A, int K>
+__device__ __forceinline__ void horner_upper(A (&acc)[K], const A (&rho)[K], const int (&hi_k)[K],
+                                             const A* __restrict__ F, const A* __restrict__ G,
+                                             int hi, int lo) {
+  for (int g = hi; g >= lo; --g) {
+    const A av = F[g] * G[g];
+#pragma unroll
+    for (int k = 0; k < K; ++k) acc[k] = fma(acc[k], rho[k], g <= hi_k[k] ? av : (A)0);
+  }
+}
+
+template <class A, int K>
+__device__ __forceinline__ void horner_lower(A (&acc)[K], const A (&rho)[K], const int (&lo_k)[K],
+                                             const A* __restrict__ F, const A* __restrict__ G,
+                                             int hi, int lo) {
+  for (int g = hi; g >= lo; --g) {
+    const A av = F[g] * G[g];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const A t = fma(acc[k], rho[k], av);
+      acc[k] = g >= lo_k[k] ? t : acc[k];
+    }
+  }
+}
+
+// Both bounds tested (groups whose windows have no common part).
 template <class A, int K>
 __device__ __forceinline__ void horner_masked(A (&acc)[K], const A (&rho)[K], const int (&lo_k)[K],
                                               const int (&hi_k)[K], const A* __restrict__ F,
@@ -148,7 +179,7 @@ __global__ __launch_bounds__(kZwBS) void k_event_zw(EventArgs a) {
 
 // ---------------------------------------------------------------------------
 template <bool F32>
-__global__ __launch_bounds__(kSmBS) void k_event_smooth(EventArgs a) {
+__device__ __forceinline__ void event_smooth(const EventArgs& a) {
   constexpr int K = kGroupK;
   constexpr int BS = kSmBS;
   int u, b;
@@ -170,6 +201,7 @@ __global__ __launch_bounds__(kSmBS) void k_event_smooth(EventArgs a) {
   const double dz = a.g.dz;
   const double T = a.trunc;
   const double inv_h2 = 1.0 / (h * h);
+  const double inv_dz = 1.0 / dz;
   const double* zb = a.zbuf + (size_t)b * a.S;
   const CT* wb = (const CT*)a.wbuf + (size_t)b * a.S;
 
@@ -192,8 +224,8 @@ __global__ __launch_bounds__(kSmBS) void k_event_smooth(EventArgs a) {
       zk[k] = zb[first + k];
       wk[k] = (double)wb[first + k];
       if (wk[k] > 0.0) {
-        const double lo_d = fmax(ceil((zk[k] - T * h - a.g.z_lo) / dz), 0.0);
-        const double hi_d = fmin(floor((zk[k] + T * h - a.g.z_lo) / dz), (double)(a.g.n_z - 1));
+        const double lo_d = fmax(ceil((zk[k] - T * h - a.g.z_lo) * inv_dz), 0.0);
+        const double hi_d = fmin(floor((zk[k] + T * h - a.g.z_lo) * inv_dz), (double)(a.g.n_z - 1));
         if (lo_d <= hi_d) {
           klo[k] = (int)lo_d;
           khi[k] = (int)hi_d;
@@ -210,7 +242,7 @@ __global__ __launch_bounds__(kSmBS) void k_event_smooth(EventArgs a) {
   int c = 0;
   double mloc = 0.0, dloc = 0.0;
   if (zn > 0.0) {
-    const double cd = fmin(fmax(rint((zsum / zn - a.g.z_lo) / dz), -4.0 * a.g.n_z), 8.0 * a.g.n_z);
+    const double cd = fmin(fmax(rint((zsum / zn - a.g.z_lo) * inv_dz), -4.0 * a.g.n_z), 8.0 * a.g.n_z);
     c = (int)cd;
     mloc = (double)max(hi_u - c, c - lo_u);
     const double zc0 = a.g.z_lo + cd * dz;
@@ -232,27 +264,31 @@ __global__ __launch_bounds__(kSmBS) void k_event_smooth(EventArgs a) {
   const bool horner_ok = ebound < (F32 ? 60.0 : 600.0);
   const double zc = a.g.z_lo + (double)c * dz;
   const double cir = has ? a.grp_c[gi] : 0.0;
+  // c_ir w_k C_k rho_k^(lo_k - c), the factor of chain k: in FP64 computed
+  // here; in FP32 after the sweep from z_k and w_k read again, which keeps the
+  // registers low enough for four waves per SIMD
+  auto chain_coef = [&](int k, double zkk, double wkk) {
+    const double delta = zkk - zc;
+    const double x = -0.5 * delta * delta * inv_h2 + (double)(klo[k] - c) * dz * delta * inv_h2;
+    return cir * wkk * (F32 ? (double)__expf((float)x) : exp(x));
+  };
   CT acc[K], rho[K];
-  double coef[K];                        // c_ir w_k C_k rho_k^(lo_k - c)
+  double coef[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     const double delta = zk[k] - zc;
     acc[k] = (CT)0;
     coef[k] = 0.0;
+    // a chain without a window (zero weight, or outside the grid) still runs
+    // through the shared bulk; rho = 0 keeps it finite (the ratio of a
+    // far-away sample would overflow) and it is left out of the sum
     if (klo[k] > khi[k]) {
-      // a chain without a window (zero weight, or outside the grid) still runs
-      // through the shared bulk; rho = 0 keeps it finite (the ratio of a
-      // far-away sample would overflow) and coef = 0 drops it
       rho[k] = (CT)0;
     } else if (F32) {
       rho[k] = (CT)__expf((float)(dz * delta * inv_h2));
-      coef[k] = cir * wk[k] *
-                (double)__expf((float)(-0.5 * delta * delta * inv_h2 +
-                                       (double)(klo[k] - c) * dz * delta * inv_h2));
     } else {
       rho[k] = (CT)exp(dz * delta * inv_h2);
-      coef[k] = cir * wk[k] *
-                exp(-0.5 * delta * delta * inv_h2 + (double)(klo[k] - c) * dz * delta * inv_h2);
+      coef[k] = chain_coef(k, zk[k], wk[k]);
     }
   }
   double total = 0.0, npts = 0.0;
@@ -263,8 +299,8 @@ __global__ __launch_bounds__(kSmBS) void k_event_smooth(EventArgs a) {
   }
 
   // G_m = exp(-m^2 dz^2 / 2h^2), m in [-M, M], in LDS after the F slice
-  const int f_elems = kSmFBytes / (int)sizeof(CT);
-  CT* Gt = (CT*)(smem + kSmFBytes);
+  const int f_elems = sm_fbytes(F32) / (int)sizeof(CT);
+  CT* Gt = (CT*)(smem + sm_fbytes(F32));
   const int gcount = 2 * M + 1;
   const bool gtab = gcount <= kSmGCap;
   if (gtab) {
@@ -273,41 +309,78 @@ __global__ __launch_bounds__(kSmBS) void k_event_smooth(EventArgs a) {
       Gt[q] = (CT)exp(-0.5 * x * x * inv_h2);
     }
   }
-  // slice length per pixel row (odd row stride spreads the LDS banks)
-  int L = f_elems / (np > 0 ? np : 1) - 1;
-  L = L < 1 ? 1 : L;
-  const int Ls = L | 1;
+  // Slice of the event's F rows in LDS, row stride Ls = L + 1 (odd: spreads the
+  // banks).  L is a multiple of 64 when a row of 64 fits, so that one wave
+  // stages one row segment per instruction (row base uniform per wave);
+  // otherwise a power of two W < 64 and 64 / W rows per wave instruction.
+  int L, lgW;
+  {
+    const int cap = f_elems / (np > 0 ? np : 1) - 1;   // >= 1: pixel rows are bounded
+    if (cap >= 64) {
+      L = cap & ~63;
+      lgW = 6;
+    } else {
+      lgW = 31 - __clz(cap);
+      L = 1 << lgW;
+    }
+  }
+  const int Ls = L + 1;
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  constexpr int NWV = BS / 64;
 
   if (gtab && A_lo <= A_hi && horner_ok) {
-    const double* gzb = a.gz64 + (size_t)b * a.g.n_z;
-    const float* gzf = a.gz32 + (size_t)b * a.g.n_z;
+    const CT* gz = F32 ? (const CT*)(a.gz32 + (size_t)b * a.g.n_z)
+                       : (const CT*)(a.gz64 + (size_t)b * a.g.n_z);
+    const CT* nzt = F32 ? (const CT*)a.nz32 : (const CT*)a.nz64;
     for (int s_hi = A_hi; s_hi >= A_lo; s_hi -= L) {
       const int s_lo = max(s_hi - L + 1, A_lo);
       const int len = s_hi - s_lo + 1;
       __syncthreads();   // the previous slice is consumed (and G is written)
-      // F_r(z_g) = n_r(z_g) g(z_g); several independent loads in flight per
-      // thread before the LDS stores
-      const int nst = np * len;
-      constexpr int UR = F32 ? 8 : 4;
-      for (int i0 = threadIdx.x; i0 < nst; i0 += BS * UR) {
-        CT v[UR];
-        int dst[UR];
+      // F_r(z_g) = n_r(z_g) g(z_g); UR independent loads in flight per thread
+      constexpr int UR = 8;
+      if (lgW == 6) {
+        for (int q0 = 0; q0 < len; q0 += 64) {
+          const int q = q0 + lane;
+          const bool qv = q < len;
+          const int gg = s_lo + (qv ? q : 0);
+          const CT gv = gz[gg];
+          for (int pb = wv; pb < np; pb += NWV * UR) {
+            CT v[UR];
 #pragma unroll
-        for (int r = 0; r < UR; ++r) {
-          const int idx = i0 + r * BS;
-          dst[r] = -1;
-          v[r] = (CT)0;
-          if (idx < nst) {
-            const int p = idx / len, gg = s_lo + idx - p * len;
-            const size_t src = (size_t)a.slot_row[p0 + p] * a.g.n_z + gg;
-            dst[r] = p * Ls + (gg - s_lo);
-            if (F32) v[r] = (CT)(a.nz32[src] * gzf[gg]);
-            else v[r] = (CT)(a.nz64[src] * gzb[gg]);
+            for (int r = 0; r < UR; ++r) {
+              const int p = pb + r * NWV;
+              v[r] = (CT)0;
+              if (p < np) v[r] = nzt[(size_t)a.slot_row[p0 + p] * a.g.n_z + gg];
+            }
+#pragma unroll
+            for (int r = 0; r < UR; ++r) {
+              const int p = pb + r * NWV;
+              if (p < np && qv) ((CT*)smem)[p * Ls + q] = v[r] * gv;
+            }
           }
         }
+      } else {
+        const int RPW = 64 >> lgW;                 // rows per wave instruction
+        const int q = lane & ((1 << lgW) - 1);
+        const int sub = lane >> lgW;
+        const bool qv = q < len;
+        const int gg = s_lo + (qv ? q : 0);
+        const CT gv = gz[gg];
+        for (int pb = wv * RPW + sub; pb < np; pb += NWV * RPW * UR) {
+          CT v[UR];
 #pragma unroll
-        for (int r = 0; r < UR; ++r)
-          if (dst[r] >= 0) ((CT*)smem)[dst[r]] = v[r];
+          for (int r = 0; r < UR; ++r) {
+            const int p = pb + r * NWV * RPW;
+            v[r] = (CT)0;
+            if (p < np) v[r] = nzt[(size_t)a.slot_row[p0 + p] * a.g.n_z + gg];
+          }
+#pragma unroll
+          for (int r = 0; r < UR; ++r) {
+            const int p = pb + r * NWV * RPW;
+            if (p < np && qv) ((CT*)smem)[p * Ls + q] = v[r] * gv;
+          }
+        }
       }
       __syncthreads();
       if (has && lo_u <= hi_u) {
@@ -317,18 +390,23 @@ __global__ __launch_bounds__(kSmBS) void k_event_smooth(EventArgs a) {
           const CT* Gp = Gt + (M - c);
           if (lo_i <= hi_i) {
             // upper edge (masked), shared bulk, lower edge (masked)
-            horner_masked<CT, K>(acc, rho, klo, khi, Fp, Gp, hi, max(lo, hi_i + 1));
+            horner_upper<CT, K>(acc, rho, khi, Fp, Gp, hi, max(lo, hi_i + 1));
             horner_span<CT, K>(acc, rho, Fp, Gp, min(hi, hi_i), max(lo, lo_i));
-            horner_masked<CT, K>(acc, rho, klo, khi, Fp, Gp, min(hi, lo_i - 1), lo);
+            horner_lower<CT, K>(acc, rho, klo, Fp, Gp, min(hi, lo_i - 1), lo);
           } else {
             horner_masked<CT, K>(acc, rho, klo, khi, Fp, Gp, hi, lo);
           }
         }
       }
     }
+    if (F32) asm volatile("" ::: "memory");   // read z_k, w_k again
 #pragma unroll
-    for (int k = 0; k < K; ++k)
-      if (klo[k] <= khi[k]) total += coef[k] * (double)acc[k];
+    for (int k = 0; k < K; ++k) {
+      if (klo[k] <= khi[k]) {
+        const double ck = F32 ? chain_coef(k, zb[first + k], (double)wb[first + k]) : coef[k];
+        total += ck * (double)acc[k];
+      }
+    }
   } else if (A_lo <= A_hi && has) {
     // fallback (windows too wide for the tables or the chain range): direct sums
     const double* gzb = a.gz64 + (size_t)b * a.g.n_z;
@@ -351,6 +429,11 @@ __global__ __launch_bounds__(kSmBS) void k_event_smooth(EventArgs a) {
     if (a.count) atomicAdd(a.count, (unsigned long long)fin[1]);
   }
 }
+
+__global__ __launch_bounds__(kSmBS) void k_event_smooth64(EventArgs a) { event_smooth<false>(a); }
+
+__global__ __launch_bounds__(kSmBS) __attribute__((amdgpu_waves_per_eu(4)))
+void k_event_smooth32(EventArgs a) { event_smooth<true>(a); }
 
 // ---------------------------------------------------------------------------
 __global__ void k_event_final(EventArgs a) {
@@ -376,25 +459,17 @@ hipError_t launch_events(const EventArgs& a, bool f32, hipStream_t st, hipEvent_
                          hipEvent_t t1) {
   const long long bz = grid_blocks(a.E, a.B);
   const long long bs = grid_blocks(a.U, a.B);
-  const size_t lds = (size_t)kSmFBytes + (size_t)kSmGCap * (f32 ? sizeof(float) : sizeof(double));
+  const size_t lds = (size_t)sm_fbytes(f32) + (size_t)kSmGCap * (f32 ? sizeof(float) : sizeof(double));
+  const void* smooth = f32 ? (const void*)k_event_smooth32 : (const void*)k_event_smooth64;
   hipError_t err;
-  if (f32) {
-    k_event_zw<true><<<(unsigned)bz, kZwBS, 0, st>>>(a);
-    err = hipFuncSetAttribute((const void*)k_event_smooth<true>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (err != hipSuccess) return err;
-    if (t0 && (err = hipEventRecord(t0, st)) != hipSuccess) return err;
-    k_event_smooth<true><<<(unsigned)bs, kSmBS, lds, st>>>(a);
-    if (t1 && (err = hipEventRecord(t1, st)) != hipSuccess) return err;
-  } else {
-    k_event_zw<false><<<(unsigned)bz, kZwBS, 0, st>>>(a);
-    err = hipFuncSetAttribute((const void*)k_event_smooth<false>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (err != hipSuccess) return err;
-    if (t0 && (err = hipEventRecord(t0, st)) != hipSuccess) return err;
-    k_event_smooth<false><<<(unsigned)bs, kSmBS, lds, st>>>(a);
-    if (t1 && (err = hipEventRecord(t1, st)) != hipSuccess) return err;
-  }
+  if (f32) k_event_zw<true><<<(unsigned)bz, kZwBS, 0, st>>>(a);
+  else k_event_zw<false><<<(unsigned)bz, kZwBS, 0, st>>>(a);
+  err = hipFuncSetAttribute(smooth, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (err != hipSuccess) return err;
+  if (t0 && (err = hipEventRecord(t0, st)) != hipSuccess) return err;
+  if (f32) k_event_smooth32<<<(unsigned)bs, kSmBS, lds, st>>>(a);
+  else k_event_smooth64<<<(unsigned)bs, kSmBS, lds, st>>>(a);
+  if (t1 && (err = hipEventRecord(t1, st)) != hipSuccess) return err;
   const long long nf = (long long)a.B * a.E;
   k_event_final<<<(unsigned)((nf + 255) / 256), 256, 0, st>>>(a);
   return hipGetLastError();

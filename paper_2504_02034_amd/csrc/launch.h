@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include "chimera.h"
 #include "common.h"
 
 namespace chimera {
@@ -34,8 +35,15 @@ constexpr int kZwBS = 256;               // k_event_zw: threads per (event, lamb
 constexpr int kSmBS = 256;               // k_event_smooth: one sample group per thread
 constexpr int kGroupK = 8;               // samples per group (Horner chains per lane)
 constexpr int kUnitGroups = kSmBS;       // groups per work unit (chunk of one event)
-constexpr int kSmFBytes = 40 * 1024;     // LDS for the staged F slice
-constexpr int kSmGCap = 1024;            // entries of the G_m table
+// LDS for the staged F slice: FP64 44 KB (three workgroups per CU, as the
+// registers allow), FP32 36 KB (four workgroups per CU)
+constexpr int kSmFBytes64 = 44 * 1024;
+constexpr int kSmFBytes32 = 36 * 1024;
+constexpr int sm_fbytes(bool f32) { return f32 ? kSmFBytes32 : kSmFBytes64; }
+constexpr int kSmGCap = 512;             // entries of the G_m table
+// every pixel row of an event needs a row of >= 2 slots in the F slice
+static_assert(CHIMERA_MAX_EVENT_PIXELS * 2 * (int)sizeof(double) <= kSmFBytes64, "F slice too small");
+static_assert(CHIMERA_MAX_EVENT_PIXELS * 2 * (int)sizeof(float) <= kSmFBytes32, "F slice too small");
 
 struct EventArgs {
   const LamParams* P;
