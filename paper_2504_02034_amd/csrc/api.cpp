@@ -136,6 +136,7 @@ Geometry make_geometry(const chimera_ctx* c, double dmin, double dmax) {
   g.dz = (c->cfg.z_hi - c->cfg.z_lo) / (double)(c->cfg.n_z - 1);
   g.n_t = c->cfg.n_tab;
   g.dx = std::log1p(c->cfg.z_tab_max) / (double)(g.n_t - 1);
+  g.inv_dx = 1.0 / g.dx;
   g.n_u = c->cfg.n_tab;
   double ulo = std::log(dmin), uhi = std::log(dmax);
   if (uhi - ulo < 1e-6) {
@@ -144,6 +145,7 @@ Geometry make_geometry(const chimera_ctx* c, double dmin, double dmax) {
   }
   g.u_lo = ulo;
   g.du = (uhi - ulo) / (double)(g.n_u - 1);
+  g.inv_du = 1.0 / g.du;
   return g;
 }
 
@@ -151,6 +153,7 @@ struct Scratch {
   LamParams* P;
   double2* chi;
   double2* inv;
+  double2* dtab;
   double* gz64;
   float* gz32;
   int* flag_mono;
@@ -174,6 +177,7 @@ size_t carve(Carve& cv, Scratch& s, const Geometry& g, int64_t B, int E, int nch
   s.P = cv.take<LamParams>(B);
   s.chi = cv.take<double2>((size_t)B * g.n_t);
   s.inv = cv.take<double2>((size_t)B * g.n_u);
+  s.dtab = need_grid ? cv.take<double2>((size_t)B * g.n_t) : nullptr;
   s.gz64 = need_grid ? cv.take<double>((size_t)B * g.n_z) : nullptr;
   s.gz32 = need_grid ? cv.take<float>((size_t)B * g.n_z) : nullptr;
   s.flag_mono = cv.take<int>(B);
@@ -523,7 +527,8 @@ static chimera_status run_batch(chimera_ctx* ctx, const chimera_events* ev, cons
   double* lnxi_dev = (host || !ln_xi) ? s.ln_xi : ln_xi;
   double* neff_dev = host ? (n_eff ? s.neff : nullptr) : n_eff;
   double* lnl_dev = host ? s.lnl : lnl;
-  HIP_TRY(launch_tables(lam_dev, (int)B, g, s.P, s.chi, s.inv, ev ? s.gz64 : nullptr,
+  HIP_TRY(launch_tables(lam_dev, (int)B, g, s.P, s.chi, s.inv, ev ? s.dtab : nullptr,
+                        ev ? s.gz64 : nullptr,
                         ev ? s.gz32 : nullptr, s.flag_mono, s.flag_range, st));
   SelArgs sa;
   sa.P = s.P; sa.flag_mono = s.flag_mono; sa.flag_range = s.flag_range;
@@ -536,7 +541,7 @@ static chimera_status run_batch(chimera_ctx* ctx, const chimera_events* ev, cons
   if (ev) {
     EventArgs a;
     a.P = s.P; a.flag_mono = s.flag_mono; a.flag_range = s.flag_range;
-    a.chi = s.chi; a.inv = s.inv; a.g = g; a.gz64 = s.gz64; a.gz32 = s.gz32;
+    a.chi = s.chi; a.inv = s.inv; a.dtab = s.dtab; a.g = g; a.gz64 = s.gz64; a.gz32 = s.gz32;
     a.nz64 = ctx->nz64; a.nz32 = ctx->nz32;
     a.ev_samp_off = ev->ev_samp_off; a.ev_slot_off = ev->ev_slot_off;
     a.ev_unit_off = ev->ev_unit_off; a.slot_row = ev->slot_row;

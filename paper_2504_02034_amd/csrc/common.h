@@ -37,9 +37,9 @@ struct Geometry {
   int n_z;          // redshift grid
   double z_lo, dz;
   int n_t;          // chi table: x_k = k dx, x = ln(1+z)
-  double dx;
+  double dx, inv_dx;
   int n_u;          // inverse table: u_m = u_lo + m du, u = ln d
-  double u_lo, du;
+  double u_lo, du, inv_du;
 };
 
 // Cubic Hermite on [0,1]: values y0, y1 and slopes (times the step) s0, s1.
@@ -52,12 +52,29 @@ __device__ __forceinline__ double hermite(double y0, double y1, double s0, doubl
 __device__ __forceinline__ double chi_at(const double2* __restrict__ tab, const Geometry& g,
                                          double x) {
   // clamp in floating point first: NaN and huge values map into the table
-  const double p = fmin(fmax(x / g.dx, 0.0), (double)(g.n_t - 1));
+  const double q = x * g.inv_dx;
+  const double p = fmin(fmax(q, 0.0), (double)(g.n_t - 1));
   int k = (int)p;
   k = k > g.n_t - 2 ? g.n_t - 2 : k;
-  const double t = x / g.dx - (double)k;
+  const double t = q - (double)k;
   const double2 a = tab[k], b = tab[k + 1];
   return hermite(a.x, b.x, a.y * g.dx, b.y * g.dx, t);
+}
+
+// d_L^gw(x) and dd_L^gw/dx from the per-lambda node table of (D_k, dD/dx_k):
+// the cubic Hermite and the derivative of the same cubic.
+__device__ __forceinline__ void dist_tab_at(const double2* __restrict__ tab, const Geometry& g,
+                                            double x, double& D, double& Dx) {
+  const double q = x * g.inv_dx;
+  const double p = fmin(fmax(q, 0.0), (double)(g.n_t - 1));
+  int k = (int)p;
+  k = k > g.n_t - 2 ? g.n_t - 2 : k;
+  const double t = q - (double)k;
+  const double2 a = tab[k], b = tab[k + 1];
+  const double s0 = a.y * g.dx, s1 = b.y * g.dx, d = b.x - a.x;
+  const double c2 = 3.0 * d - 2.0 * s0 - s1, c3 = s0 + s1 - 2.0 * d;
+  D = a.x + t * (s0 + t * (c2 + t * c3));
+  Dx = (s0 + t * (2.0 * c2 + 3.0 * t * c3)) * g.inv_dx;
 }
 
 __device__ __forceinline__ double efunc_of_zp1(double om, double zp1) {
@@ -82,7 +99,7 @@ __device__ __forceinline__ void dist_at(const LamParams& P, const double2* __res
 __device__ __forceinline__ double invert_x(const LamParams& P, const double2* __restrict__ chi,
                                            const double2* __restrict__ inv, const Geometry& g,
                                            double d, double lnd, int polish) {
-  const double pos = (lnd - g.u_lo) / g.du;
+  const double pos = (lnd - g.u_lo) * g.inv_du;
   int m = (int)fmin(fmax(pos, 0.0), (double)(g.n_u - 1));
   m = m > g.n_u - 2 ? g.n_u - 2 : m;
   const double t = pos - (double)m;
@@ -98,52 +115,56 @@ __device__ __forceinline__ double invert_x(const LamParams& P, const double2* __
 
 // Redshift and mass weight of one sample (Sect. 2.1: z from d_L^gw; the
 // masses in the source frame m = m_det / (1+z); eq. gw-kernel weight
-// p(m1) p(m2|m1) with uniform PE priors).  FP64 path: table + one Newton
-// step, whose e^x update reuses the exponential; FP32 path: table only and
-// the mass model in FP32.
+// p(m1) p(m2|m1) with uniform PE priors).  FP64 path: inverse table + one
+// Newton step on the d_L^gw node table, whose e^x update reuses the
+// exponential; FP32 path: inverse table only and the mass model in FP32.
 template <bool F32>
-__device__ __forceinline__ void sample_zw(const LamParams& P, const double2* __restrict__ chi,
+__device__ __forceinline__ void sample_zw(const LamParams& P, const double2* __restrict__ dtab,
                                           const double2* __restrict__ inv, const Geometry& g,
                                           double d, double lnd, double m1d, double m2d,
                                           double lnm1d, double lnm2d, double& z, double& w);
 
 // p(m1) p(m2|m1) of the source-frame masses; 0 outside
 // mmin <= m2 <= m1 <= mmax (and m1 > mmin).  l1, l2 = ln m1, ln m2.
+// With a = 1 + beta the pairing term is p(m2|m1) = a m2^beta m1^-a /
+// (1 - (mmin/m1)^a) (m2^-1 / ln(m1/mmin) at a = 0), so that
+//   w = a [c_pl e^(beta l2 - (a + alpha) l1) + c_tg e^(beta l2 - a l1 - u^2/2)]
+//       / (-expm1(a (ln mmin - l1)))
+// with c_pl, c_tg the normalised power-law and peak coefficients of p(m1).
 __device__ __forceinline__ double mass_weight64(const LamParams& P, double m1, double m2,
                                                 double l1, double l2) {
   if (!(m1 >= P.mmin && m1 <= P.mmax && m2 >= P.mmin && m2 <= m1 && m1 > P.mmin)) return 0.0;
-  const double pl = P.pl_coef * exp(-P.alpha * l1);
+  const double lead = P.beta * l2 - P.a2 * l1;
   const double u = (m1 - P.mu) * P.inv_sigma;
-  const double tg = P.tg_coef * exp(-0.5 * u * u);
-  const double n2 = (P.a2 == 0.0) ? (l1 - P.ln_mmin)
-                                  : P.mmin_a2 * expm1(P.a2 * (l1 - P.ln_mmin)) / P.a2;
-  return (pl + tg) * exp(P.beta * l2) / n2;
+  const double num = P.pl_coef * exp(lead - P.alpha * l1) + P.tg_coef * exp(lead - 0.5 * u * u);
+  if (P.a2 == 0.0) return num / (l1 - P.ln_mmin);
+  return P.a2 * num / -expm1(P.a2 * (P.ln_mmin - l1));
 }
 
 __device__ __forceinline__ float mass_weight32(const LamParams& P, double m1, double m2,
                                                double l1d, double l2d) {
   if (!(m1 >= P.mmin && m1 <= P.mmax && m2 >= P.mmin && m2 <= m1 && m1 > P.mmin)) return 0.0f;
   const float l1 = (float)l1d, l2 = (float)l2d;
-  const float pl = (float)P.pl_coef * __expf(-(float)P.alpha * l1);
-  const float u = ((float)m1 - (float)P.mu) * (float)P.inv_sigma;
-  const float tg = (float)P.tg_coef * __expf(-0.5f * u * u);
   const float a2 = (float)P.a2;
-  const float r = l1 - (float)P.ln_mmin;
-  const float n2 = (P.a2 == 0.0) ? r : (float)P.mmin_a2 * expm1f(a2 * r) / a2;
-  return (pl + tg) * __expf((float)P.beta * l2) / n2;
+  const float lead = (float)P.beta * l2 - a2 * l1;
+  const float u = ((float)m1 - (float)P.mu) * (float)P.inv_sigma;
+  const float num = (float)P.pl_coef * __expf(lead - (float)P.alpha * l1) +
+                    (float)P.tg_coef * __expf(lead - 0.5f * u * u);
+  if (P.a2 == 0.0) return num / (l1 - (float)P.ln_mmin);
+  return a2 * num / -expm1f(a2 * ((float)P.ln_mmin - l1));
 }
 
 template <bool F32>
-__device__ __forceinline__ void sample_zw(const LamParams& P, const double2* __restrict__ chi,
+__device__ __forceinline__ void sample_zw(const LamParams& P, const double2* __restrict__ dtab,
                                           const double2* __restrict__ inv, const Geometry& g,
                                           double d, double lnd, double m1d, double m2d,
                                           double lnm1d, double lnm2d, double& z, double& w) {
-  double x = invert_x(P, chi, inv, g, d, lnd, 0);
+  double x = invert_x(P, nullptr, inv, g, d, lnd, 0);
   double zp1 = exp(x);
   if (!F32) {
     double D, Dx;
-    dist_at(P, chi, g, x, zp1, D, Dx);
-    const double dx = (D - d) / Dx;           // |dx| is at the table's error, ~1e-12
+    dist_tab_at(dtab, g, x, D, Dx);
+    const double dx = (D - d) / Dx;           // |dx| is at the inverse table's error
     x -= dx;
     zp1 *= 1.0 - dx + 0.5 * dx * dx;          // e^(x - dx)
   }

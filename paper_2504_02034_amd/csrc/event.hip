@@ -137,7 +137,7 @@ __global__ __launch_bounds__(kZwBS) void k_event_zw(EventArgs a) {
   __shared__ double red[3 * NW];
   const LamParams P = a.P[b];
   if (P.flag | a.flag_mono[b] | a.flag_range[b]) return;   // the final kernel reports it
-  const double2* chi = a.chi + (size_t)b * a.g.n_t;
+  const double2* dtab = a.dtab + (size_t)b * a.g.n_t;
   const double2* inv = a.inv + (size_t)b * a.g.n_u;
   const int s0 = a.ev_samp_off[e];
   const int ns = a.ev_samp_off[e + 1] - s0;
@@ -147,7 +147,7 @@ __global__ __launch_bounds__(kZwBS) void k_event_zw(EventArgs a) {
   for (int j = threadIdx.x; j < ns; j += kZwBS) {
     const int q = s0 + j;
     double z, w;
-    sample_zw<F32>(P, chi, inv, a.g, a.dl[q], a.lndl[q], a.m1d[q], a.m2d[q], a.lnm1d[q],
+    sample_zw<F32>(P, dtab, inv, a.g, a.dl[q], a.lndl[q], a.m1d[q], a.m2d[q], a.lnm1d[q],
                    a.lnm2d[q], z, w);
     const CT wc = (CT)w;
     zb[j] = z;

@@ -190,6 +190,22 @@ __global__ void k_inverse_table(const LamParams* __restrict__ Pv, const double2*
 }
 
 // ---------------------------------------------------------------------------
+// d_L^gw and dd_L^gw/dx on the nodes x_k = k dx (Hermite data for the Newton
+// step of the sample transform)
+// ---------------------------------------------------------------------------
+__global__ void k_dist_table(const LamParams* __restrict__ Pv, const double2* __restrict__ chi,
+                             Geometry g, int B, double2* __restrict__ dtab) {
+  const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= (long long)B * g.n_t) return;
+  const int b = (int)(id / g.n_t), k = (int)(id % g.n_t);
+  const LamParams P = Pv[b];
+  const double x = (double)k * g.dx;
+  double D, Dx;
+  dist_at(P, chi + (size_t)b * g.n_t, g, x, exp(x), D, Dx);
+  dtab[id] = make_double2(D, Dx);
+}
+
+// ---------------------------------------------------------------------------
 // grid factor tau_g psi / [(1+z)^3 D'(z)]  =  tau_g psi / [(1+z)^2 dD/dx]
 // ---------------------------------------------------------------------------
 __global__ void k_grid_factor(const LamParams* __restrict__ Pv, const double2* __restrict__ chi,
@@ -331,8 +347,8 @@ __global__ __launch_bounds__(kFinBS) void k_lnl_final(const LamParams* __restric
   } while (0)
 
 hipError_t launch_tables(const double* lam, int B, const Geometry& g, LamParams* P,
-                         double2* chi, double2* inv, double* gz64, float* gz32, int* flag_mono,
-                         int* flag_range, hipStream_t st) {
+                         double2* chi, double2* inv, double2* dtab, double* gz64, float* gz32,
+                         int* flag_mono, int* flag_range, hipStream_t st) {
   k_lam_prepare<<<(B + 63) / 64, 64, 0, st>>>(lam, B, P);
   CH_LAUNCH_CHECK();
   k_chi_table<<<B, kTabBS, 0, st>>>(P, g, chi, flag_mono);
@@ -340,6 +356,11 @@ hipError_t launch_tables(const double* lam, int B, const Geometry& g, LamParams*
   const long long ni = (long long)B * g.n_u;
   k_inverse_table<<<(unsigned)((ni + 255) / 256), 256, 0, st>>>(P, chi, g, B, inv, flag_range);
   CH_LAUNCH_CHECK();
+  if (dtab) {
+    const long long nt = (long long)B * g.n_t;
+    k_dist_table<<<(unsigned)((nt + 255) / 256), 256, 0, st>>>(P, chi, g, B, dtab);
+    CH_LAUNCH_CHECK();
+  }
   if (gz64) {
     const long long ng = (long long)B * g.n_z;
     k_grid_factor<<<(unsigned)((ng + 255) / 256), 256, 0, st>>>(P, chi, g, B, gz64, gz32);

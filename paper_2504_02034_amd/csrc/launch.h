@@ -51,6 +51,7 @@ struct EventArgs {
   const int* flag_range;
   const double2* chi;
   const double2* inv;
+  const double2* dtab;      // [B][n_t] (d_L^gw, dd_L^gw/dx) on the x nodes
   Geometry g;
   const double* gz64;
   const float* gz32;
@@ -90,7 +91,7 @@ hipError_t launch_events(const EventArgs& a, bool f32, hipStream_t st, hipEvent_
                          hipEvent_t t1 = nullptr);
 
 hipError_t launch_tables(const double* lam, int B, const Geometry& g, LamParams* P, double2* chi,
-                         double2* inv, double* gz64, float* gz32, int* flag_mono,
+                         double2* inv, double2* dtab, double* gz64, float* gz32, int* flag_mono,
                          int* flag_range, hipStream_t st);
 hipError_t launch_selection(const SelArgs& a, bool f32, double* ln_xi, double* neff,
                             hipStream_t st);
