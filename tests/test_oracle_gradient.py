@@ -1,0 +1,162 @@
+"""Pins of the oracle gradient (oracle/gradient.py): every piece against
+Richardson central differences of the oracle function it differentiates,
+the whole d ln L / d lambda against differences of likelihood.lnl on small
+inputs, and the exact zeros of the modified-propagation derivatives at
+their GR points (eq. dL-mg: Xi = 1 at Xi0 = 1 for every n, and at n = 0 for
+every Xi0)."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import cosmology as cosmo
+from oracle import gradient as G
+from oracle import likelihood as L
+from paper_2504_02034_amd import synth
+from tests.datasets import handcrafted, handcrafted_oracle
+
+TRUTH = synth.LAMBDA_TRUTH
+OTHER = np.array([88.0, 0.41, 1.7, 3.2, 2.6, 0.7, 5.0, 87.0, 31.0, 4.4, 0.3, 2.1, 2.4, 1.6])
+
+
+def rel_close(a, b, tol, floor=1.0):
+    a, b = np.asarray(a, float), np.asarray(b, float)
+    return np.all(np.abs(a - b) <= tol * np.maximum(floor, np.abs(b)))
+
+
+@pytest.mark.parametrize("om", [0.1, 0.3, 0.93])
+def test_dchi_dom(om):
+    z = np.array([0.05, 0.4, 1.3, 4.0, 17.0])
+    fd = G.richardson(lambda l: cosmo.chi(z, l[1]), np.array([70.0, om, 1, 0]), 1)
+    assert rel_close(G.dchi_dom(z, om), fd, 1e-9, floor=1e-12)
+
+
+@pytest.mark.parametrize("lam", [TRUTH, OTHER])
+def test_distance_parts(lam):
+    z = np.array([0.02, 0.3, 0.9, 1.6, 6.0])
+    D, Dz, Dzz, dD, dDz = G.distance_parts(z, lam)
+    assert rel_close(D, cosmo.dl_gw(z, *lam[:4]), 1e-14)
+    assert rel_close(Dz, cosmo.ddl_gw_dz(z, *lam[:4]), 1e-14)
+    # d2D/dz2: differences of dD/dz in z (z shifted by s - 1 around s = 1)
+    fz = G.richardson(lambda s: cosmo.ddl_gw_dz(z + (s[0] - 1.0), *lam[:4]), np.array([1.0]), 0,
+                      rel_step=1e-4)
+    assert rel_close(Dzz, fz, 1e-8)
+    for p in range(4):
+        fd = G.richardson(lambda l: cosmo.dl_gw(z, *l[:4]), lam, p)
+        fdz = G.richardson(lambda l: cosmo.ddl_gw_dz(z, *l[:4]), lam, p)
+        assert rel_close(dD[p], fd, 1e-8, floor=1e-6 * np.abs(D).max()), p
+        assert rel_close(dDz[p], fdz, 1e-8, floor=1e-6 * np.abs(Dz).max()), p
+
+
+def test_redshift_derivative_is_the_inverse_function_derivative():
+    d = np.array([300.0, 2500.0, 9000.0, 21000.0])
+    for lam in (TRUTH, OTHER):
+        z = cosmo.invert_dl(d, *lam[:4])
+        dz = G.dz_dparams(z, lam)
+        for p in range(4):
+            fd = G.richardson(lambda l: cosmo.invert_dl(d, *l[:4]), lam, p)
+            assert rel_close(dz[p], fd, 1e-7, floor=1e-9), p
+        assert np.all(dz[4:] == 0.0)
+
+
+@pytest.mark.parametrize("lam", [TRUTH, OTHER])
+def test_mass_log_derivatives(lam):
+    rng = np.random.default_rng(3)
+    m1 = rng.uniform(8.0, 80.0, 40)
+    m2 = m1 * rng.uniform(0.3, 0.98, 40)
+    m2 = np.maximum(m2, 5.5)
+    d, mdm = G.mass_log_derivs(m1, m2, lam)
+    lw = lambda l: np.log(oracle.population.mass_weight(m1, m2, l))  # noqa: E731
+    for k, p in enumerate((4, 5, 8, 9, 10)):
+        fd = G.richardson(lw, lam, p, rel_step=1e-4, abs_floor=1e-5)
+        assert rel_close(d[k], fd, 2e-7, floor=1e-4), p
+    # m1 dlnw/dm1 + m2 dlnw/dm2 = d ln w(s m1, s m2) / d ln s at s = 1
+    fs = G.richardson(lambda s: np.log(oracle.population.mass_weight(m1 * s[0], m2 * s[0], lam)),
+                      np.array([1.0]), 0, rel_step=1e-5)
+    assert rel_close(mdm, fs, 2e-7)
+
+
+def test_mass_log_derivatives_at_special_forms():
+    m1 = np.array([12.0, 40.0, 70.0])
+    m2 = np.array([9.0, 20.0, 50.0])
+    for a, b in ((1.0, 1.1), (3.4, -1.0)):
+        lam = TRUTH.copy()
+        lam[4], lam[5] = a, b
+        d, _ = G.mass_log_derivs(m1, m2, lam)
+        lw = lambda l: np.log(oracle.population.mass_weight(m1, m2, l))  # noqa: E731
+        for k, p in enumerate((4, 5)):
+            fd = G.richardson(lw, lam, p, rel_step=1e-4)
+            assert rel_close(d[k], fd, 1e-6, floor=1e-6), (a, b, p)
+
+
+def test_psi_log_derivatives():
+    z = np.array([0.0, 0.4, 1.2, 3.0])
+    for lam in (TRUTH, OTHER):
+        d, dz = G.psi_log_derivs(z, lam)
+        lp = lambda l: np.log(oracle.population.psi(z, l[11], l[12], l[13]))  # noqa: E731
+        for k, p in enumerate((11, 12, 13)):
+            assert rel_close(d[k], G.richardson(lp, lam, p), 1e-8, floor=1e-8)
+        fz = G.richardson(lambda s: np.log(oracle.population.psi(z + s[0] - 1.0, *lam[11:])),
+                          np.array([1.0]), 0)
+        assert rel_close(dz, fz, 1e-8, floor=1e-8)
+
+
+@pytest.fixture(scope="module")
+def hand():
+    h = handcrafted()
+    return h, handcrafted_oracle(h)
+
+
+def _lnl(structs, T):
+    events, cat, inj = structs
+    return lambda l: L.lnl(events, cat, inj, l, T=T)["lnl"]
+
+
+def _xi(structs):
+    events, cat, inj = structs
+    return lambda l: np.log(L.selection(inj, cat, l)[0])
+
+
+@pytest.mark.parametrize("lam", [TRUTH, OTHER], ids=["truth", "other"])
+def test_selection_gradient_vs_differences(hand, lam):
+    _, structs = hand
+    events, cat, inj = structs
+    xi, dlnxi = G.selection_grad(inj, cat, lam)
+    assert xi == pytest.approx(L.selection(inj, cat, lam)[0], rel=1e-14)
+    f = _xi(structs)
+    for k, p in enumerate(G.GRAD_INDEX):
+        fd = G.richardson(f, lam, p, rel_step=1e-6)
+        assert abs(dlnxi[k] - fd) <= 1e-6 * max(1.0, abs(fd)), (k, dlnxi[k], fd)
+
+
+@pytest.mark.parametrize("T", [None, 8.6], ids=["dense", "T8.6"])
+@pytest.mark.parametrize("lam", [TRUTH, OTHER], ids=["truth", "other"])
+def test_lnl_gradient_vs_differences(hand, lam, T):
+    _, structs = hand
+    events, cat, inj = structs
+    res = G.lnl_grad(events, cat, inj, lam, T=T)
+    ref = L.lnl(events, cat, inj, lam, T=T)
+    assert res["lnl"] == pytest.approx(ref["lnl"], rel=1e-13)
+    f = _lnl(structs, T)
+    for k, p in enumerate(G.GRAD_INDEX):
+        fd = G.richardson(f, lam, p, rel_step=1e-6)
+        assert abs(res["grad"][k] - fd) <= 1e-6 * max(1.0, abs(fd)), (k, res["grad"][k], fd)
+
+
+def test_modified_propagation_derivatives_vanish_at_gr(hand):
+    _, (events, cat, inj) = hand
+    gr = OTHER.copy()
+    gr[2] = 1.0
+    g = G.lnl_grad(events, cat, inj, gr)["grad"]
+    assert g[3] == 0.0 and np.all(np.isfinite(g))
+    n0 = OTHER.copy()
+    n0[3] = 0.0
+    g = G.lnl_grad(events, cat, inj, n0)["grad"]
+    assert g[2] == 0.0 and np.all(np.isfinite(g))
+
+
+def test_gradient_nan_outside_domain(hand):
+    _, (events, cat, inj) = hand
+    bad = TRUTH.copy()
+    bad[1] = 1.5
+    r = G.lnl_grad(events, cat, inj, bad)
+    assert r["lnl"] == -np.inf and np.all(np.isnan(r["grad"]))
