@@ -150,6 +150,21 @@ chimera_status chimera_lnl_batch(chimera_ctx* ctx, const chimera_events* ev, con
 chimera_status chimera_selection_xi(chimera_ctx* ctx, const double* lam, int64_t B, int32_t prec,
                                     double* ln_xi, double* n_eff, int32_t mem, void* hip_stream);
 
+/* ln L and its gradient at B points (the adjoint of eq. hyperlike through
+ * every step above: the redshift of each sample as an implicit function of
+ * d_L^gw(z_j) = d_j, the mass weights, the bandwidth, the kernel sums, the
+ * grid factor and the selection estimator).  lnl[B]; grad[B][12] =
+ * d ln L / d(H0, Om, Xi0, n, alpha, beta, mu_g, sigma_g, lambda_g, gamma,
+ * kappa, z_p); mmin and mmax are edges of the mass support and are not
+ * differentiated.  The window edges |z_g - z_j| = T h are held fixed.  prec:
+ * CHIMERA_FP64, or CHIMERA_FP32 for the per-sample window sums in FP32 (the
+ * sample transform, bandwidth, selection and every sum over samples, events
+ * and injections in FP64).  lnl follows chimera_lnl_batch's rules; grad is
+ * NaN where lnl is not finite.  The per-lambda layout is the same as above. */
+chimera_status chimera_lnl_grad(chimera_ctx* ctx, const chimera_events* ev, const double* lam,
+                                int64_t B, int32_t prec, double* lnl, double* grad, int32_t mem,
+                                void* hip_stream);
+
 /* Diagnostics.  With profiling on, every chimera_lnl_batch call on this
  * context brackets its event kernel with HIP events recorded on the call's
  * stream, and the kernel counts the (sample, grid point) pairs it evaluates

@@ -28,7 +28,7 @@ _STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ERANGE", -5:
 EXPORTS = ("chimera_default_config", "chimera_create", "chimera_destroy", "chimera_last_error",
            "chimera_set_catalog", "chimera_set_injections", "chimera_add_events",
            "chimera_release_events", "chimera_lnl_batch", "chimera_selection_xi",
-           "chimera_profile_enable", "chimera_profile_read")
+           "chimera_lnl_grad", "chimera_profile_enable", "chimera_profile_read")
 
 
 class ChimeraError(RuntimeError):
@@ -73,6 +73,7 @@ def _load():
         "chimera_release_events": (ctypes.c_int, [_P, _P]),
         "chimera_lnl_batch": (ctypes.c_int, [_P, _P, _P, _I64, _I32, _P, _P, _I32, _P]),
         "chimera_selection_xi": (ctypes.c_int, [_P, _P, _I64, _I32, _P, _P, _I32, _P]),
+        "chimera_lnl_grad": (ctypes.c_int, [_P, _P, _P, _I64, _I32, _P, _P, _I32, _P]),
         "chimera_profile_enable": (ctypes.c_int, [_P, _I32]),
         "chimera_profile_read": (ctypes.c_int, [_P, ctypes.POINTER(_I64),
                                                 ctypes.POINTER(ctypes.c_double),
@@ -197,6 +198,27 @@ def chimera_selection_xi(h, lam, prec=CHIMERA_FP64, stream=None):
     return lx, ne
 
 
+def chimera_lnl_grad(h, ev, lam, prec=CHIMERA_FP64, lnl=None, grad=None, stream=None):
+    """(lnl [B], grad [B,12]); lam numpy [B,14] (host call) or a device tensor (async)."""
+    if _is_torch(lam):
+        import torch
+        assert lam.is_cuda and lam.dtype == torch.float64 and lam.is_contiguous()
+        B = lam.shape[0]
+        if lnl is None:
+            lnl = torch.empty(B, dtype=torch.float64, device=lam.device)
+        if grad is None:
+            grad = torch.empty(B, NGRAD, dtype=torch.float64, device=lam.device)
+        _check(lib.chimera_lnl_grad(h, ev, _P(lam.data_ptr()), B, prec, _P(lnl.data_ptr()),
+                                    _P(grad.data_ptr()), CHIMERA_DEVICE, _stream_ptr(stream)))
+        return lnl, grad
+    lam, pl = _host(np.atleast_2d(lam), np.float64)
+    B = lam.shape[0]
+    out, g = np.empty(B), np.empty((B, NGRAD))
+    _check(lib.chimera_lnl_grad(h, ev, pl, B, prec, out.ctypes.data_as(_P), g.ctypes.data_as(_P),
+                                CHIMERA_HOST, None))
+    return out, g
+
+
 def chimera_profile_enable(h, on=True):
     _check(lib.chimera_profile_enable(h, 1 if on else 0))
 
@@ -267,6 +289,10 @@ class Context:
 
     def selection(self, lam, prec=CHIMERA_FP64, stream=None):
         return chimera_selection_xi(self.handle, lam, prec, stream=stream)
+
+    def lnl_grad(self, ev: EventSet, lam, prec=CHIMERA_FP64, stream=None):
+        """(ln L [B], d ln L / d(GRAD_NAMES) [B, 12])."""
+        return chimera_lnl_grad(self.handle, ev.handle, lam, prec, stream=stream)
 
 
 def context_from_prepared(p, inj, device=0, **kw) -> tuple:

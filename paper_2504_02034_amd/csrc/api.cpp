@@ -82,6 +82,8 @@ struct chimera_events {
   // samples in group order
   double *dl = nullptr, *lndl = nullptr, *m1d = nullptr, *m2d = nullptr;
   double *lnm1d = nullptr, *lnm2d = nullptr;
+  int* samp_row = nullptr;      // catalogue row of each sample (adjoint)
+  double* samp_c = nullptr;     // c_ir of each sample's pixel (adjoint)
   double dmin = 0.0, dmax = 0.0;
 };
 
@@ -111,7 +113,7 @@ void free_events(chimera_events* ev) {
   dfree(ev->unit_event); dfree(ev->unit_grp0); dfree(ev->unit_ngrp);
   dfree(ev->grp_first); dfree(ev->grp_cnt); dfree(ev->grp_slot); dfree(ev->grp_c);
   dfree(ev->dl); dfree(ev->lndl); dfree(ev->m1d); dfree(ev->m2d);
-  dfree(ev->lnm1d); dfree(ev->lnm2d);
+  dfree(ev->lnm1d); dfree(ev->lnm2d); dfree(ev->samp_row); dfree(ev->samp_c);
   delete ev;
 }
 
@@ -134,6 +136,7 @@ Geometry make_geometry(const chimera_ctx* c, double dmin, double dmax) {
   g.n_z = c->cfg.n_z;
   g.z_lo = c->cfg.z_lo;
   g.dz = (c->cfg.z_hi - c->cfg.z_lo) / (double)(c->cfg.n_z - 1);
+  g.inv_dz = 1.0 / g.dz;
   g.n_t = c->cfg.n_tab;
   g.dx = std::log1p(c->cfg.z_tab_max) / (double)(g.n_t - 1);
   g.inv_dx = 1.0 / g.dx;
@@ -371,8 +374,9 @@ chimera_status chimera_add_events(chimera_ctx* ctx, int32_t n_ev, const int64_t*
   std::vector<int> u_event, u_grp0, u_ngrp;
   std::vector<int> gfirst, gcnt, gslot;
   std::vector<double> gc;
-  std::vector<double> odl, om1, om2;
-  odl.reserve(S); om1.reserve(S); om2.reserve(S);
+  std::vector<double> odl, om1, om2, oc;
+  std::vector<int> orow;
+  odl.reserve(S); om1.reserve(S); om2.reserve(S); oc.reserve(S); orow.reserve(S);
   for (int64_t p = 0; p < P; ++p) srow[p] = (int)pix_row[p];
   for (int i = 0; i <= n_ev; ++i) ev_slot[i] = (int)ev_pix_off[i];
   struct G { double mean; int slot; std::vector<int64_t> idx; };
@@ -424,6 +428,8 @@ chimera_status chimera_add_events(chimera_ctx* ctx, int32_t n_ev, const int64_t*
         odl.push_back(dl[j]);
         om1.push_back(m1d[j]);
         om2.push_back(m2d[j]);
+        oc.push_back(c_ir[ev_pix_off[e] + g.slot]);
+        orow.push_back(srow[ev_pix_off[e] + g.slot]);
       }
     }
     ev_samp[e + 1] = (int)odl.size();
@@ -463,6 +469,8 @@ chimera_status chimera_add_events(chimera_ctx* ctx, int32_t n_ev, const int64_t*
   if (e == hipSuccess) e = upload(&ev->m2d, om2.data(), S);
   if (e == hipSuccess) e = upload(&ev->lnm1d, l1.data(), S);
   if (e == hipSuccess) e = upload(&ev->lnm2d, l2.data(), S);
+  if (e == hipSuccess) e = upload(&ev->samp_row, orow.data(), S);
+  if (e == hipSuccess) e = upload(&ev->samp_c, oc.data(), S);
   if (e != hipSuccess) {
     free_events(ev);
     return fail(e == hipErrorOutOfMemory ? CHIMERA_ENOMEM : CHIMERA_EDEVICE,
@@ -601,6 +609,107 @@ chimera_status chimera_selection_xi(chimera_ctx* ctx, const double* lam, int64_t
   if (s != CHIMERA_OK) return s;
   if (!ln_xi) return fail(CHIMERA_EINVAL, "null output");
   return run_batch(ctx, nullptr, lam, B, prec, nullptr, nullptr, ln_xi, n_eff, mem, hip_stream);
+}
+
+static chimera_status run_grad(chimera_ctx* ctx, const chimera_events* ev, const double* lam,
+                               int64_t B, int32_t prec, double* lnl, double* grad, int32_t mem,
+                               void* hip_stream) {
+  hipStream_t st = (hipStream_t)hip_stream;
+  HIP_TRY(hipSetDevice(ctx->cfg.device));
+  const bool f32 = prec == CHIMERA_FP32;
+  const bool host = mem == CHIMERA_HOST;
+  const int E = ev->E;
+  double dmin = ev->dmin, dmax = ev->dmax;
+  if (ctx->n_det) {
+    dmin = std::min(dmin, ctx->inj_dmin);
+    dmax = std::max(dmax, ctx->inj_dmax);
+  }
+  const Geometry g = make_geometry(ctx, dmin, dmax);
+  const int nchunk = selection_grad_chunks(ctx->n_det);
+  auto lay = [&](Carve& cv, GradArgs& a, SelGradArgs& sa, GradFinalArgs& fa, double** lam_d,
+                 LamParams** P, double2** chi, double2** inv, double2** dtab, double2** chio,
+                 double** gz64, float** gz32, int** fm, int** fr) {
+    *P = cv.take<LamParams>(B);
+    a.Q = cv.take<GradParams>(B);
+    *chi = cv.take<double2>((size_t)B * g.n_t);
+    *chio = cv.take<double2>((size_t)B * g.n_t);
+    *inv = cv.take<double2>((size_t)B * g.n_u);
+    *dtab = cv.take<double2>((size_t)B * g.n_t);
+    *gz64 = cv.take<double>((size_t)B * g.n_z);
+    *gz32 = cv.take<float>((size_t)B * g.n_z);
+    a.gf64 = cv.take<double>((size_t)B * 6 * g.n_z);
+    a.gf32 = cv.take<float>((size_t)B * 6 * g.n_z);
+    *fm = cv.take<int>(B);
+    *fr = cv.take<int>(B);
+    sa.partial = cv.take<double>((size_t)B * std::max(nchunk, 1) * (1 + CHIMERA_NGRAD));
+    a.lnI = cv.take<double>((size_t)B * E);
+    a.dlnI = cv.take<double>((size_t)B * E * CHIMERA_NGRAD);
+    *lam_d = host ? cv.take<double>((size_t)B * CHIMERA_NLAM) : nullptr;
+    fa.lnl = host ? cv.take<double>(B) : lnl;
+    fa.grad = host ? cv.take<double>((size_t)B * CHIMERA_NGRAD) : grad;
+  };
+  GradArgs a{};
+  SelGradArgs sa{};
+  GradFinalArgs fa{};
+  double* lam_d;
+  LamParams* P;
+  double2 *chi, *inv, *dtab, *chio;
+  double* gz64;
+  float* gz32;
+  int *fm, *fr;
+  Carve probe;
+  lay(probe, a, sa, fa, &lam_d, &P, &chi, &inv, &dtab, &chio, &gz64, &gz32, &fm, &fr);
+  const size_t bytes = probe.off;
+  if (ctx->cfg.hbm_budget && bytes > ctx->cfg.hbm_budget)
+    return fail(CHIMERA_ENOMEM, "call needs " + std::to_string(bytes) +
+                                    " scratch bytes, over the context's hbm_budget");
+  void* base = nullptr;
+  HIP_TRY(hipMallocAsync(&base, bytes, st));
+  Carve cv;
+  cv.base = (char*)base;
+  lay(cv, a, sa, fa, &lam_d, &P, &chi, &inv, &dtab, &chio, &gz64, &gz32, &fm, &fr);
+  const double* lam_dev = lam;
+  if (host) {
+    HIP_TRY(hipMemcpyAsync(lam_d, lam, (size_t)B * CHIMERA_NLAM * sizeof(double),
+                           hipMemcpyHostToDevice, st));
+    lam_dev = lam_d;
+  }
+  HIP_TRY(launch_tables(lam_dev, (int)B, g, P, chi, inv, dtab, gz64, gz32, fm, fr, st));
+  HIP_TRY(launch_chi_om_table(P, (int)B, g, chio, st));
+  a.P = P; a.flag_mono = fm; a.flag_range = fr;
+  a.chi = chi; a.chio = chio; a.inv = inv; a.dtab = dtab; a.g = g;
+  a.gz64 = gz64; a.gz32 = gz32; a.nz64 = ctx->nz64; a.nz32 = ctx->nz32;
+  a.ev_samp_off = ev->ev_samp_off; a.samp_row = ev->samp_row; a.samp_c = ev->samp_c;
+  a.dl = ev->dl; a.lndl = ev->lndl; a.m1d = ev->m1d; a.m2d = ev->m2d;
+  a.lnm1d = ev->lnm1d; a.lnm2d = ev->lnm2d;
+  a.E = E; a.B = (int)B;
+  a.trunc = f32 ? ctx->cfg.trunc_fp32 : ctx->cfg.trunc_fp64;
+  sa.P = P; sa.Q = a.Q; sa.flag_mono = fm; sa.flag_range = fr;
+  sa.chi = chi; sa.chio = chio; sa.inv = inv; sa.dtab = dtab; sa.g = g; sa.ntot = ctx->ntot;
+  sa.dl = ctx->inj_dl; sa.lndl = ctx->inj_lndl; sa.m1d = ctx->inj_m1d; sa.m2d = ctx->inj_m2d;
+  sa.lnm1d = ctx->inj_lnm1d; sa.lnm2d = ctx->inj_lnm2d; sa.ln_pdraw = ctx->inj_lnp;
+  sa.n_det = ctx->n_det; sa.B = (int)B; sa.nchunk = nchunk;
+  fa.P = P; fa.flag_mono = fm; fa.flag_range = fr; fa.partial = sa.partial; fa.nchunk = nchunk;
+  fa.lnI = a.lnI; fa.dlnI = a.dlnI; fa.E = E; fa.n_total = ctx->n_inj_total;
+  HIP_TRY(launch_grad(a, sa, fa, f32, st));
+  if (host) {
+    HIP_TRY(hipMemcpyAsync(lnl, fa.lnl, B * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(grad, fa.grad, (size_t)B * CHIMERA_NGRAD * sizeof(double),
+                           hipMemcpyDeviceToHost, st));
+  }
+  HIP_TRY(hipFreeAsync(base, st));
+  if (host) HIP_TRY(hipStreamSynchronize(st));
+  return CHIMERA_OK;
+}
+
+chimera_status chimera_lnl_grad(chimera_ctx* ctx, const chimera_events* ev, const double* lam,
+                                int64_t B, int32_t prec, double* lnl, double* grad, int32_t mem,
+                                void* hip_stream) {
+  chimera_status s = check_common(ctx, lam, B, prec, mem);
+  if (s != CHIMERA_OK) return s;
+  if (!ev) return fail(CHIMERA_EINVAL, "null event set");
+  if (!lnl || !grad) return fail(CHIMERA_EINVAL, "null output");
+  return run_grad(ctx, ev, lam, B, prec, lnl, grad, mem, hip_stream);
 }
 
 chimera_status chimera_profile_enable(chimera_ctx* ctx, int32_t on) {

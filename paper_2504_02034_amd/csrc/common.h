@@ -35,7 +35,7 @@ struct LamParams {
 // Geometry shared by all lambdas of one call.
 struct Geometry {
   int n_z;          // redshift grid
-  double z_lo, dz;
+  double z_lo, dz, inv_dz;
   int n_t;          // chi table: x_k = k dx, x = ln(1+z)
   double dx, inv_dx;
   int n_u;          // inverse table: u_m = u_lo + m du, u = ln d

@@ -40,27 +40,6 @@ namespace chimera {
 
 namespace {
 
-// XCD-aware block order: the blocks of one item (event or unit) at 32
-// consecutive lambdas land on one XCD (block id mod 8) back to back, so the
-// item's data stay in that XCD's L2.
-__device__ __forceinline__ bool decode_block(int n_items, int B, int& item, int& b) {
-  const int bc = B < 32 ? B : 32;
-  const int nchunk = (B + bc - 1) / bc;
-  const int L = blockIdx.x;
-  const int xcd = L & 7, s = L >> 3;
-  const int u = (s / bc) * 8 + xcd;
-  item = u / nchunk;
-  b = (u % nchunk) * bc + (s % bc);
-  return item < n_items && b < B;
-}
-
-long long grid_blocks(int n_items, int B) {
-  const int bc = B < 32 ? B : 32;
-  const long long nchunk = (B + bc - 1) / bc;
-  const long long units = (long long)n_items * nchunk;
-  return ((units + 7) / 8) * 8 * bc;
-}
-
 // acc_k <- acc_k rho_k + F_g G_(g-c) for g = hi down to lo (all chains inside
 // their windows).
 template <class A, int K>
@@ -131,7 +110,7 @@ __device__ __forceinline__ void horner_masked(A (&acc)[K], const A (&rho)[K], co
 template <bool F32>
 __global__ __launch_bounds__(kZwBS) void k_event_zw(EventArgs a) {
   int e, b;
-  if (!decode_block(a.E, a.B, e, b)) return;
+  if (!decode_item_lambda(a.E, a.B, e, b)) return;
   using CT = typename std::conditional<F32, float, double>::type;
   constexpr int NW = kZwBS / 64 + 1;
   __shared__ double red[3 * NW];
@@ -183,7 +162,7 @@ __device__ __forceinline__ void event_smooth(const EventArgs& a) {
   constexpr int K = kGroupK;
   constexpr int BS = kSmBS;
   int u, b;
-  if (!decode_block(a.U, a.B, u, b)) return;
+  if (!decode_item_lambda(a.U, a.B, u, b)) return;
   using CT = typename std::conditional<F32, float, double>::type;
   extern __shared__ __align__(16) unsigned char smem[];
   constexpr int NW = BS / 64 + 1;
@@ -457,8 +436,8 @@ __global__ void k_event_final(EventArgs a) {
 // ---------------------------------------------------------------------------
 hipError_t launch_events(const EventArgs& a, bool f32, hipStream_t st, hipEvent_t t0,
                          hipEvent_t t1) {
-  const long long bz = grid_blocks(a.E, a.B);
-  const long long bs = grid_blocks(a.U, a.B);
+  const long long bz = item_lambda_blocks(a.E, a.B);
+  const long long bs = item_lambda_blocks(a.U, a.B);
   const size_t lds = (size_t)sm_fbytes(f32) + (size_t)kSmGCap * (f32 ? sizeof(float) : sizeof(double));
   const void* smooth = f32 ? (const void*)k_event_smooth32 : (const void*)k_event_smooth64;
   hipError_t err;

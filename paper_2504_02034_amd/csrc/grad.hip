@@ -1,0 +1,511 @@
+// Adjoint of ln L (gradient with respect to the 12 differentiated parameters
+// H0, Om, Xi0, n, alpha, beta, mu_g, sigma_g, lambda_g, gamma, kappa, z_p;
+// mmin and mmax are hard edges of the mass model and are not differentiated).
+//
+// Chain rule, per event i with S_i = sum_r c_ir sum_j w_j A_j and
+// I_i = S_i / (h sqrt(2 pi)):
+//   d ln I_i / dp = (1/S_i) sum_j c_j w_j [ d ln w_j/dp A_j + dz_j/dp dA_j/dz_j
+//                                          + dA_j/dh dh/dp + sum_g F_g K_jg d ln g/dp ]
+//                   - d ln h / dp
+// with dA/dz_j = sum F K (z_g - z_j) / h^2, dA/dh = sum F K (z_g - z_j)^2 / h^3
+// (the window edges |z_g - z_j| = T h are not differentiated).  The redshift
+// of a sample moves as dx_j/dp = -(dD/dp) / (dD/dx) (x = ln(1+z), implicit in
+// d_L^gw(x_j) = d_j, eqs. dL-em and dL-mg).  The bandwidth derivative runs
+// through the moments W1, W2, sum w (z - s), sum w (z - s)^2 (s: a shift).
+// Selection: d ln xi / dp = sum_j s_j d ln s_j / dp / sum_j s_j.
+//
+// k_lam_grad_prepare  per-lambda normaliser derivatives of the mass model
+// k_grid_grad         g(z_g) d ln g / dp on the grid for p = Om, Xi0, n,
+//                     gamma, kappa, z_p (H0 enters g as a factor H0)
+// k_event_grad        one (event, lambda) per workgroup: pass 1 moments and
+//                     their derivatives -> h, d ln h/dp; pass 2 one sample per
+//                     thread, its window by the Gaussian ratio recurrence
+//                     K_(g+1) = K_g r_g, r_(g+1) = r_g exp(-dz^2/h^2)
+// k_selection_grad    per (injection chunk, lambda) partial sums
+// k_grad_final        ln L and d ln L / dp per lambda, fixed order
+#include <math.h>
+
+#include "common.h"
+#include "launch.h"
+#include "reduce.h"
+
+namespace chimera {
+
+namespace {
+
+constexpr int kNG = CHIMERA_NGRAD;   // 12
+constexpr int kNS = 9;               // parameters a sample depends on: H0, Om, Xi0, n, mass (5)
+constexpr int kGradBS = 256;
+
+__device__ __forceinline__ double phi_std(double t) {
+  return 0.39894228040143267794 * exp(-0.5 * t * t);
+}
+
+// f(y) = y / (1 - e^-y) - 1, with its series near 0
+__device__ __forceinline__ double f_pair(double y) {
+  if (fabs(y) < 1e-5) return y * (0.5 + y / 12.0);
+  return y / -expm1(-y) - 1.0;
+}
+
+// Per-sample redshift, weight and their derivatives.
+struct SampleGrad {
+  double x, zp1, w;
+  double dx[4];      // dx/dp for H0, Om, Xi0, n
+  double dlw[kNS];   // d ln w / dp (through z for the distance parameters)
+};
+
+// pieces of dD/dx = dh e^x (q + q'), q = chi Xi, q' = chi' Xi + chi Xi'
+struct DistPieces {
+  double chi, chio, chip, chiop, en, xi, xip, q, qp;
+};
+
+__device__ __forceinline__ DistPieces dist_pieces(const LamParams& P, const double2* chi,
+                                                  const double2* chio, const Geometry& g,
+                                                  double x, double zp1) {
+  DistPieces d;
+  const double e = efunc_of_zp1(P.om, zp1);
+  d.chi = chi_at(chi, g, x);
+  d.chio = chi_at(chio, g, x);
+  d.chip = zp1 / e;
+  d.chiop = -0.5 * zp1 * (zp1 * zp1 * zp1 - 1.0) / (e * e * e);
+  d.en = exp(-P.n * x);
+  d.xi = P.xi0 + (1.0 - P.xi0) * d.en;
+  d.xip = -P.n * (1.0 - P.xi0) * d.en;
+  d.q = d.chi * d.xi;
+  d.qp = d.chip * d.xi + d.chi * d.xip;
+  return d;
+}
+
+// d ln(dD/dx) / dp at fixed x for p = H0, Om, Xi0, n
+__device__ __forceinline__ void dlnDx(const LamParams& P, const DistPieces& d, double x,
+                                      double (&out)[4]) {
+  const double inv = 1.0 / (d.q + d.qp);
+  out[0] = -1.0 / P.h0;
+  out[1] = (d.chio * d.xi + d.chiop * d.xi + d.chio * d.xip) * inv;
+  const double xa = 1.0 - d.en, xap = P.n * d.en;                     // dXi, dXi'/dXi0
+  out[2] = (d.chi * xa + d.chip * xa + d.chi * xap) * inv;
+  const double xn = -(1.0 - P.xi0) * x * d.en;                        // dXi/dn
+  const double xnp = -(1.0 - P.xi0) * d.en * (1.0 - P.n * x);         // dXi'/dn
+  out[3] = (d.chi * xn + d.chip * xn + d.chi * xnp) * inv;
+}
+
+// d ln psi / d(gamma, kappa, z_p) at fixed x, and d ln psi / dx
+__device__ __forceinline__ void dlnpsi(const LamParams& P, double x, double (&out)[3],
+                                       double& ddx) {
+  const double lr = x - P.ln1zp;
+  const double r = exp((P.gamma + P.kappa) * lr);
+  const double s = r / (1.0 + r);
+  out[0] = x - s * lr;
+  out[1] = -s * lr;
+  out[2] = s * (P.gamma + P.kappa) / (1.0 + P.zp);
+  ddx = P.gamma - s * (P.gamma + P.kappa);
+}
+
+__device__ __forceinline__ void sample_grad(const LamParams& P, const GradParams& Q,
+                                            const double2* chi, const double2* chio,
+                                            const double2* dtab, const double2* inv,
+                                            const Geometry& g, double d, double lnd, double m1d,
+                                            double m2d, double lnm1d, double lnm2d,
+                                            SampleGrad& s, DistPieces& dp) {
+  double x = invert_x(P, nullptr, inv, g, d, lnd, 0);
+  double zp1 = exp(x);
+  {
+    double D, Dx;
+    dist_tab_at(dtab, g, x, D, Dx);
+    const double dxn = (D - d) / Dx;
+    x -= dxn;
+    zp1 *= 1.0 - dxn + 0.5 * dxn * dxn;
+  }
+  s.x = x;
+  s.zp1 = zp1;
+  dp = dist_pieces(P, chi, chio, g, x, zp1);
+  const double dem = P.dh * zp1 * dp.chi;
+  const double Dx = P.dh * zp1 * (dp.q + dp.qp);
+  // -dD/dp / (dD/dx)
+  s.dx[0] = (dem * dp.xi / P.h0) / Dx;
+  s.dx[1] = -(P.dh * zp1 * dp.chio * dp.xi) / Dx;
+  s.dx[2] = -(dem * (1.0 - dp.en)) / Dx;
+  s.dx[3] = (dem * (1.0 - P.xi0) * x * dp.en) / Dx;
+  const double r = 1.0 / zp1;
+  const double m1 = m1d * r, m2 = m2d * r;
+  const double l1 = lnm1d - x, l2 = lnm2d - x;
+  s.w = mass_weight64(P, m1, m2, l1, l2);
+#pragma unroll
+  for (int k = 0; k < kNS; ++k) s.dlw[k] = 0.0;
+  if (!(s.w > 0.0)) return;
+  const double u = (m1 - P.mu) * P.inv_sigma;
+  const double PL = Q.pl_unit * exp(-P.alpha * l1);
+  const double TG = Q.tg_unit * exp(-0.5 * u * u);
+  const double ip1 = 1.0 / ((1.0 - P.lg) * PL + P.lg * TG);
+  s.dlw[4] = (1.0 - P.lg) * PL * (-l1 - Q.dlnnpl_dalpha) * ip1;
+  const double L = l1 - P.ln_mmin;
+  const double y = P.a2 * L;
+  double pair_m1;                      // m1 d ln p(m2|m1) / d m1
+  if (P.a2 == 0.0) {
+    s.dlw[5] = l2 - P.ln_mmin - 0.5 * L;
+    pair_m1 = -1.0 / L;
+  } else {
+    s.dlw[5] = l2 - P.ln_mmin - f_pair(y) / P.a2;
+    pair_m1 = -P.a2 / -expm1(-y);
+  }
+  s.dlw[6] = P.lg * TG * (u * P.inv_sigma - Q.dlnz_dmu) * ip1;
+  s.dlw[7] = P.lg * TG * ((u * u - 1.0) * P.inv_sigma - Q.dlnz_dsigma) * ip1;
+  s.dlw[8] = (TG - PL) * ip1;
+  const double m1_p1 = ((1.0 - P.lg) * PL * -P.alpha + P.lg * TG * (-u * m1 * P.inv_sigma)) * ip1;
+  // m = m_det e^-x: d ln w / dx = -(m1 d/dm1 + m2 d/dm2) ln w
+  const double dlw_dx = -(m1_p1 + pair_m1 + P.beta);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) s.dlw[k] = dlw_dx * s.dx[k];
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+__global__ void k_lam_grad_prepare(const LamParams* __restrict__ Pv, int B,
+                                   GradParams* __restrict__ Qv) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= B) return;
+  const LamParams P = Pv[b];
+  GradParams Q;
+  // N_pl = int_mmin^mmax m^(a1-1) dm, a1 = 1 - alpha; d ln N_pl / d alpha =
+  // -(ln mmin + f(a1 ln(mmax/mmin)) / a1)
+  const double a1 = 1.0 - P.alpha;
+  const double lr = P.ln_mmax - P.ln_mmin;
+  const double npl = (a1 == 0.0) ? lr : exp(a1 * P.ln_mmin) * expm1(a1 * lr) / a1;
+  Q.pl_unit = 1.0 / npl;
+  Q.dlnnpl_dalpha = -(P.ln_mmin + (a1 == 0.0 ? 0.5 * lr : f_pair(a1 * lr) / a1));
+  const double a = (P.mmin - P.mu) * P.inv_sigma, bb = (P.mmax - P.mu) * P.inv_sigma;
+  const double r = 0.70710678118654752440;
+  const double Z = a > 0.0 ? 0.5 * (erfc(a * r) - erfc(bb * r)) : 0.5 * (erfc(-bb * r) - erfc(-a * r));
+  Q.tg_unit = 1.0 / (P.sigma * 2.50662827463100050242 * Z);
+  Q.dlnz_dmu = (phi_std(a) - phi_std(bb)) * P.inv_sigma / Z;
+  Q.dlnz_dsigma = (a * phi_std(a) - bb * phi_std(bb)) * P.inv_sigma / Z;
+  Qv[b] = Q;
+}
+
+// g d ln g / dp on the grid, p = Om, Xi0, n, gamma, kappa, z_p: [B][6][n_z]
+__global__ void k_grid_grad(const LamParams* __restrict__ Pv, const double2* __restrict__ chi,
+                            const double2* __restrict__ chio, const double* __restrict__ gz64,
+                            Geometry g, int B, double* __restrict__ gf64,
+                            float* __restrict__ gf32) {
+  const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= (long long)B * g.n_z) return;
+  const int b = (int)(id / g.n_z), k = (int)(id % g.n_z);
+  const LamParams P = Pv[b];
+  const double z = g.z_lo + (double)k * g.dz;
+  const double x = log1p(z);
+  const DistPieces d = dist_pieces(P, chi + (size_t)b * g.n_t, chio + (size_t)b * g.n_t, g, x,
+                                   1.0 + z);
+  double dd[4], dpsi[3], unused;
+  dlnDx(P, d, x, dd);
+  dlnpsi(P, x, dpsi, unused);
+  const double gv = gz64[id];
+  const double f[6] = {-dd[1], -dd[2], -dd[3], dpsi[0], dpsi[1], dpsi[2]};
+#pragma unroll
+  for (int p = 0; p < 6; ++p) {
+    const double v = isfinite(gv * f[p]) ? gv * f[p] : 0.0;
+    gf64[((size_t)b * 6 + p) * g.n_z + k] = v;
+    gf32[((size_t)b * 6 + p) * g.n_z + k] = (float)v;
+  }
+}
+
+// ---------------------------------------------------------------------------
+template <bool F32>
+__global__ __launch_bounds__(kGradBS) void k_event_grad(GradArgs a) {
+  int e, b;
+  if (!decode_item_lambda(a.E, a.B, e, b)) return;
+  using CT = typename std::conditional<F32, float, double>::type;
+  constexpr int NW = kGradBS / 64 + 1;
+  __shared__ double red[40 * NW];
+  __shared__ double shift;
+  const LamParams P = a.P[b];
+  double* lnI = a.lnI + (size_t)b * a.E + e;
+  double* dlnI = a.dlnI + ((size_t)b * a.E + e) * kNG;
+  if (P.flag | a.flag_mono[b] | a.flag_range[b]) {
+    if (threadIdx.x == 0) *lnI = NAN;                 // the final kernel reports the flag
+    return;
+  }
+  const GradParams Q = a.Q[b];
+  const double2* chi = a.chi + (size_t)b * a.g.n_t;
+  const double2* chio = a.chio + (size_t)b * a.g.n_t;
+  const double2* dtab = a.dtab + (size_t)b * a.g.n_t;
+  const double2* inv = a.inv + (size_t)b * a.g.n_u;
+  const int s0 = a.ev_samp_off[e];
+  const int ns = a.ev_samp_off[e + 1] - s0;
+  SampleGrad sg;
+  DistPieces dp;
+  if (threadIdx.x == 0) {
+    sample_grad(P, Q, chi, chio, dtab, inv, a.g, a.dl[s0], a.lndl[s0], a.m1d[s0], a.m2d[s0],
+                a.lnm1d[s0], a.lnm2d[s0], sg, dp);
+    shift = sg.zp1 - 1.0;
+  }
+  __syncthreads();
+  const double zs = shift;
+  // ---- pass 1: W1, W2, M1 = sum w (z - zs), M2 = sum w (z - zs)^2 and derivatives
+  double m[40];
+#pragma unroll
+  for (int i = 0; i < 40; ++i) m[i] = 0.0;
+  for (int j = threadIdx.x; j < ns; j += kGradBS) {
+    const int q = s0 + j;
+    sample_grad(P, Q, chi, chio, dtab, inv, a.g, a.dl[q], a.lndl[q], a.m1d[q], a.m2d[q],
+                a.lnm1d[q], a.lnm2d[q], sg, dp);
+    const double w = sg.w;
+    if (!(w > 0.0)) continue;
+    const double t = sg.zp1 - 1.0 - zs;
+    m[0] += w;
+    m[1] += w * w;
+    m[2] += w * t;
+    m[3] += w * t * t;
+#pragma unroll
+    for (int p = 0; p < kNS; ++p) {
+      const double dw = w * sg.dlw[p];
+      const double dzp = p < 4 ? sg.zp1 * sg.dx[p] : 0.0;
+      m[4 + p] += dw;
+      m[4 + kNS + p] += 2.0 * w * dw;
+      m[4 + 2 * kNS + p] += dw * t + w * dzp;
+      m[4 + 3 * kNS + p] += dw * t * t + 2.0 * w * t * dzp;
+    }
+  }
+  block_reduce<kGradBS, 40, false>(m, red);
+  const double W1 = m[0], W2 = m[1], M1 = m[2], M2 = m[3];
+  if (!(W1 > 0.0)) {
+    if (threadIdx.x == 0) {
+      *lnI = -INFINITY;
+      for (int p = 0; p < kNG; ++p) dlnI[p] = NAN;
+    }
+    return;
+  }
+  const double mu = M1 / W1;
+  const double den = W1 - W2 / W1;
+  double var = 0.0, V = 0.0;
+  const bool spread = !(W1 * W1 - W2 <= 1e-12 * W1 * W1);
+  if (spread) {
+    V = fmax(M2 - M1 * mu, 0.0);
+    var = V / den;
+  }
+  const double raw = sqrt(var) * pow(W1 * W1 / W2, -0.2);
+  const double h = fmax(raw, 2.0 * a.g.dz);
+  double dlnh[kNS];
+  const bool live = spread && V > 0.0 && raw >= 2.0 * a.g.dz;
+#pragma unroll
+  for (int p = 0; p < kNS; ++p) {
+    dlnh[p] = 0.0;
+    if (live) {
+      const double dW1 = m[4 + p], dW2 = m[4 + kNS + p];
+      const double dM1 = m[4 + 2 * kNS + p], dM2 = m[4 + 3 * kNS + p];
+      const double dV = dM2 - 2.0 * mu * dM1 + mu * mu * dW1;
+      const double dden = dW1 - dW2 / W1 + W2 * dW1 / (W1 * W1);
+      dlnh[p] = 0.5 * dV / V - 0.5 * dden / den - 0.2 * (2.0 * dW1 / W1 - dW2 / W2);
+    }
+  }
+  // ---- pass 2: kernel sums per sample, one sample per thread
+  const double dz = a.g.dz, inv_h2 = 1.0 / (h * h), T = a.trunc;
+  const CT qr = (CT)exp(-dz * dz * inv_h2);
+  const CT* nzt = F32 ? (const CT*)a.nz32 : (const CT*)a.nz64;
+  const CT* gzt = F32 ? (const CT*)(a.gz32 + (size_t)b * a.g.n_z)
+                      : (const CT*)(a.gz64 + (size_t)b * a.g.n_z);
+  const CT* gft = F32 ? (const CT*)(a.gf32 + (size_t)b * 6 * a.g.n_z)
+                      : (const CT*)(a.gf64 + (size_t)b * 6 * a.g.n_z);
+  const int nz = a.g.n_z;
+  double acc[1 + kNG];
+#pragma unroll
+  for (int i = 0; i <= kNG; ++i) acc[i] = 0.0;
+  for (int j = threadIdx.x; j < ns; j += kGradBS) {
+    const int q = s0 + j;
+    sample_grad(P, Q, chi, chio, dtab, inv, a.g, a.dl[q], a.lndl[q], a.m1d[q], a.m2d[q],
+                a.lnm1d[q], a.lnm2d[q], sg, dp);
+    if (!(sg.w > 0.0)) continue;
+    const double z = sg.zp1 - 1.0;
+    const double lo_d = fmax(ceil((z - T * h - a.g.z_lo) * a.g.inv_dz), 0.0);
+    const double hi_d = fmin(floor((z + T * h - a.g.z_lo) * a.g.inv_dz), (double)(nz - 1));
+    if (!(lo_d <= hi_d)) continue;
+    const int lo = (int)lo_d, hi = (int)hi_d;
+    const double u0 = a.g.z_lo + lo_d * dz - z;
+    CT K = (CT)exp(-0.5 * u0 * u0 * inv_h2);
+    CT r = (CT)exp(-(2.0 * u0 * dz + dz * dz) * 0.5 * inv_h2);
+    const CT* nrow = nzt + (size_t)a.samp_row[q] * nz;
+    CT sA = 0, sB = 0, sC = 0, sE[6] = {0, 0, 0, 0, 0, 0};
+    for (int gi = lo; gi <= hi; ++gi) {
+      const CT u = (CT)(u0 + (double)(gi - lo) * dz);
+      const CT bk = nrow[gi] * K;
+      const CT av = bk * gzt[gi];
+      sA += av;
+      const CT t = av * u;
+      sB += t;
+      sC = fma(t, u, sC);
+#pragma unroll
+      for (int p = 0; p < 6; ++p) sE[p] = fma(bk, gft[(size_t)p * nz + gi], sE[p]);
+      K *= r;
+      r *= qr;
+    }
+    const double cw = a.samp_c[q] * sg.w;
+    const double A = (double)sA, Bz = (double)sB * inv_h2, Ch = (double)sC * inv_h2 / h;
+    acc[0] += cw * A;
+    // distance parameters: weight, z-shift, bandwidth, grid factor (H0: g ~ H0)
+    const double Eg[4] = {A / P.h0, (double)sE[0], (double)sE[1], (double)sE[2]};
+#pragma unroll
+    for (int p = 0; p < 4; ++p)
+      acc[1 + p] += cw * (sg.dlw[p] * A + sg.zp1 * sg.dx[p] * Bz + Ch * h * dlnh[p] + Eg[p]);
+#pragma unroll
+    for (int p = 4; p < kNS; ++p) acc[1 + p] += cw * (sg.dlw[p] * A + Ch * h * dlnh[p]);
+#pragma unroll
+    for (int p = 0; p < 3; ++p) acc[1 + kNS + p] += cw * (double)sE[3 + p];
+  }
+  block_reduce<kGradBS, 1 + kNG, false>(acc, red);
+  if (threadIdx.x == 0) {
+    const double S = acc[0];
+    if (!(S > 0.0)) {
+      *lnI = -INFINITY;
+      for (int p = 0; p < kNG; ++p) dlnI[p] = NAN;
+    } else {
+      *lnI = log(S * kInvSqrt2Pi / h);
+      for (int p = 0; p < kNG; ++p) dlnI[p] = acc[1 + p] / S - (p < kNS ? dlnh[p] : 0.0);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+constexpr int kSelGradBS = 256;
+constexpr int kSelGradPer = 4;
+
+// FP64 in both modes: the selection sums are a small part of the work.
+__global__ __launch_bounds__(kSelGradBS) void k_selection_grad(SelGradArgs a) {
+  const int chunk = blockIdx.x, b = blockIdx.y;
+  __shared__ double red[(1 + kNG) * (kSelGradBS / 64 + 1)];
+  double* part = a.partial + ((size_t)b * a.nchunk + chunk) * (1 + kNG);
+  const LamParams P = a.P[b];
+  if (P.flag | a.flag_mono[b] | a.flag_range[b]) {
+    if (threadIdx.x == 0)
+      for (int i = 0; i <= kNG; ++i) part[i] = 0.0;
+    return;
+  }
+  const GradParams Q = a.Q[b];
+  const double2* chi = a.chi + (size_t)b * a.g.n_t;
+  const double2* chio = a.chio + (size_t)b * a.g.n_t;
+  const double2* dtab = a.dtab + (size_t)b * a.g.n_t;
+  const double2* inv = a.inv + (size_t)b * a.g.n_u;
+  double acc[1 + kNG];
+#pragma unroll
+  for (int i = 0; i <= kNG; ++i) acc[i] = 0.0;
+  for (int k = 0; k < kSelGradPer; ++k) {
+    const long long j = (long long)chunk * kSelGradBS * kSelGradPer + k * kSelGradBS + threadIdx.x;
+    if (j >= a.n_det) break;
+    SampleGrad sg;
+    DistPieces d;
+    sample_grad(P, Q, chi, chio, dtab, inv, a.g, a.dl[j], a.lndl[j], a.m1d[j], a.m2d[j],
+                a.lnm1d[j], a.lnm2d[j], sg, d);
+    if (!(sg.w > 0.0)) continue;
+    const double w = sg.w;
+    const double z = sg.zp1 - 1.0;
+    const double pos = (z - a.g.z_lo) * a.g.inv_dz;
+    if (!(pos >= 0.0 && pos <= (double)(a.g.n_z - 1))) continue;
+    int kk = (int)pos;
+    kk = kk > a.g.n_z - 2 ? a.g.n_z - 2 : kk;
+    const double t = pos - (double)kk;
+    const double nt = a.ntot[kk] + t * (a.ntot[kk + 1] - a.ntot[kk]);
+    if (!(nt > 0.0)) continue;
+    const double slope = (a.ntot[kk + 1] - a.ntot[kk]) * a.g.inv_dz;   // dn_tot/dz
+    const double x = sg.x, zp1 = sg.zp1;
+    const double Dx = P.dh * zp1 * (d.q + d.qp);
+    // second x-derivative of d_L^gw: dh e^x (q + 2 q' + q'')
+    const double e2 = P.om * zp1 * zp1 * zp1 + 1.0 - P.om;
+    const double chipp = d.chip * (1.0 - 1.5 * P.om * zp1 * zp1 * zp1 / e2);
+    const double xipp = P.n * P.n * (1.0 - P.xi0) * d.en;
+    const double qpp = chipp * d.xi + 2.0 * d.chip * d.xip + d.chi * xipp;
+    const double Dxx = P.dh * zp1 * (d.q + 2.0 * d.qp + qpp);
+    double dpsi[3], dlpsi_dx, dd[4];
+    dlnpsi(P, x, dpsi, dlpsi_dx);
+    dlnDx(P, d, x, dd);
+    const double s = w * nt * psi_of_x(P, x) / (zp1 * zp1 * Dx * exp(a.ln_pdraw[j]));
+    // d ln s / dx at fixed lambda (the weight's own z path is in dlw)
+    const double dls_dx = zp1 * slope / nt + dlpsi_dx - 2.0 - Dxx / Dx;
+    acc[0] += s;
+#pragma unroll
+    for (int p = 0; p < 4; ++p) acc[1 + p] += s * (sg.dlw[p] + dls_dx * sg.dx[p] - dd[p]);
+#pragma unroll
+    for (int p = 4; p < kNS; ++p) acc[1 + p] += s * sg.dlw[p];
+#pragma unroll
+    for (int p = 0; p < 3; ++p) acc[1 + kNS + p] += s * dpsi[p];
+  }
+  block_reduce<kSelGradBS, 1 + kNG, false>(acc, red);
+  if (threadIdx.x == 0)
+    for (int i = 0; i <= kNG; ++i) part[i] = acc[i];
+}
+
+// ---------------------------------------------------------------------------
+constexpr int kGFinBS = 256;
+
+__global__ __launch_bounds__(kGFinBS) void k_grad_final(GradFinalArgs a) {
+  const int b = blockIdx.x;
+  __shared__ double red[(1 + kNG) * (kGFinBS / 64 + 1)];
+  const LamParams P = a.P[b];
+  const int flag = P.flag | a.flag_mono[b] | a.flag_range[b];
+  // selection: chunks in a fixed order
+  double v[1 + kNG];
+#pragma unroll
+  for (int i = 0; i <= kNG; ++i) v[i] = 0.0;
+  for (int c = threadIdx.x; c < a.nchunk; c += kGFinBS)
+#pragma unroll
+    for (int i = 0; i <= kNG; ++i) v[i] += a.partial[((size_t)b * a.nchunk + c) * (1 + kNG) + i];
+  block_reduce<kGFinBS, 1 + kNG, false>(v, red);
+  const double S1 = v[0];
+  // events
+  double u[1 + kNG];
+#pragma unroll
+  for (int i = 0; i <= kNG; ++i) u[i] = 0.0;
+  int bad = 0;
+  for (int e = threadIdx.x; e < a.E; e += kGFinBS) {
+    const double li = a.lnI[(size_t)b * a.E + e];
+    if (!(li > -INFINITY) || isnan(li)) bad = 1;
+    u[0] += li;
+#pragma unroll
+    for (int p = 0; p < kNG; ++p) u[1 + p] += a.dlnI[((size_t)b * a.E + e) * kNG + p];
+  }
+  u[0] += bad ? -INFINITY : 0.0;
+  block_reduce<kGFinBS, 1 + kNG, false>(u, red);
+  if (threadIdx.x == 0) {
+    double* g = a.grad + (size_t)b * kNG;
+    if (flag) {
+      a.lnl[b] = (flag & (kFlagDomain | kFlagNonMonotone)) ? -INFINITY : NAN;
+      for (int p = 0; p < kNG; ++p) g[p] = NAN;
+      return;
+    }
+    const double lnl = S1 > 0.0 ? u[0] - (double)a.E * log(S1 / (double)a.n_total) : -INFINITY;
+    a.lnl[b] = lnl;
+    const bool ok = isfinite(lnl);
+    for (int p = 0; p < kNG; ++p)
+      g[p] = ok ? u[1 + p] - (double)a.E * v[1 + p] / S1 : NAN;
+  }
+}
+
+// ---------------------------------------------------------------------------
+hipError_t launch_grad(const GradArgs& a, const SelGradArgs& sa, GradFinalArgs fa, bool f32,
+                       hipStream_t st) {
+  k_lam_grad_prepare<<<(a.B + 63) / 64, 64, 0, st>>>(a.P, a.B, a.Q);
+  CH_LAUNCH_CHECK();
+  const long long ng = (long long)a.B * a.g.n_z;
+  k_grid_grad<<<(unsigned)((ng + 255) / 256), 256, 0, st>>>(a.P, a.chi, a.chio, a.gz64, a.g,
+                                                             a.B, a.gf64, a.gf32);
+  CH_LAUNCH_CHECK();
+  if (sa.nchunk > 0) {
+    dim3 grid(sa.nchunk, sa.B);
+    k_selection_grad<<<grid, kSelGradBS, 0, st>>>(sa);
+    CH_LAUNCH_CHECK();
+  }
+  const long long nb = item_lambda_blocks(a.E, a.B);
+  if (a.E > 0) {
+    if (f32) k_event_grad<true><<<(unsigned)nb, kGradBS, 0, st>>>(a);
+    else k_event_grad<false><<<(unsigned)nb, kGradBS, 0, st>>>(a);
+    CH_LAUNCH_CHECK();
+  }
+  k_grad_final<<<a.B, kGFinBS, 0, st>>>(fa);
+  CH_LAUNCH_CHECK();
+  return hipSuccess;
+}
+
+int selection_grad_chunks(long long n_det) {
+  const long long per = (long long)kSelGradBS * kSelGradPer;
+  return (int)((n_det + per - 1) / per);
+}
+
+}  // namespace chimera

@@ -4,7 +4,8 @@
 //   k_chi_table       chi(x) = int dz/E on x = ln(1+z) nodes, FP64 (eq. dL-em)
 //   k_inverse_table   x(ln d) with d_L^gw(x) = d (eqs. dL-em, dL-mg)
 //   k_grid_factor     tau_g psi(z_g) / [(1+z_g)^3 d d_L^gw/dz]   (eq. jacobian)
-//   (the per-(event, lambda) kernel sums are in event_grouped.hip)
+//   k_chi_om_table    dchi/dOm on the same nodes (gradient only)
+//   (the per-(event, lambda) kernel sums are in event.hip, the adjoint in grad.hip)
 //   k_selection       injection sums of s_j and s_j^2 (Sect. 2.2)
 //   k_*_final         fixed-order reductions to ln xi, N_eff, ln L (eq. hyperlike)
 //
@@ -72,9 +73,19 @@ __device__ __forceinline__ double dchi_dx(double om, double x) {
   return zp1 / efunc_of_zp1(om, zp1);
 }
 
-__global__ __launch_bounds__(kTabBS) void k_chi_table(const LamParams* __restrict__ Pv, Geometry g,
-                                                      double2* __restrict__ chi,
-                                                      int* __restrict__ flag_mono) {
+// d/dx of dchi/dOm = -1/2 int ((1+z)^3 - 1) / E^3 dz, in x = ln(1+z)
+__device__ __forceinline__ double dchiom_dx(double om, double x) {
+  const double zp1 = exp(x);
+  const double e = efunc_of_zp1(om, zp1);
+  return -0.5 * zp1 * (zp1 * zp1 * zp1 - 1.0) / (e * e * e);
+}
+
+// KIND 0: chi and the monotonicity flag of d_L^gw; KIND 1: dchi/dOm.
+template <int KIND>
+__global__ __launch_bounds__(kTabBS) void k_x_table(const LamParams* __restrict__ Pv, Geometry g,
+                                                    double2* __restrict__ chi,
+                                                    int* __restrict__ flag_mono) {
+  auto fx = [](double om, double x) { return KIND == 0 ? dchi_dx(om, x) : dchiom_dx(om, x); };
   const int b = blockIdx.x;
   const LamParams P = Pv[b];
   double2* tab = chi + (size_t)b * g.n_t;
@@ -98,7 +109,7 @@ __global__ __launch_bounds__(kTabBS) void k_chi_table(const LamParams* __restric
       const double mid = ((double)k + 0.5) * g.dx, half = 0.5 * g.dx;
 #pragma unroll
       for (int q = 0; q < 4; ++q)
-        s += gw[q] * (dchi_dx(P.om, mid - half * gx[q]) + dchi_dx(P.om, mid + half * gx[q]));
+        s += gw[q] * (fx(P.om, mid - half * gx[q]) + fx(P.om, mid + half * gx[q]));
       s *= half;
     }
     run += s;
@@ -124,24 +135,28 @@ __global__ __launch_bounds__(kTabBS) void k_chi_table(const LamParams* __restric
   }
   __syncthreads();
   const double base = wsum[w] + incl - run;
-  if (threadIdx.x == 0) tab[0] = make_double2(0.0, dchi_dx(P.om, 0.0));
+  if (threadIdx.x == 0) tab[0] = make_double2(0.0, fx(P.om, 0.0));
   int mybad = 0;
   for (int i = 0; i < per && i < 16; ++i) {
     const int k = k0 + i + 1;   // node index
     if (k <= nint) {
       const double x = (double)k * g.dx;
       const double c = base + local[i];
-      const double cp = dchi_dx(P.om, x);
+      const double cp = fx(P.om, x);
       tab[k] = make_double2(c, cp);
-      const double en = exp(-P.n * x);
-      const double xi = P.xi0 + (1.0 - P.xi0) * en;
-      const double dd = c * xi + cp * xi - c * P.n * (1.0 - P.xi0) * en;
-      if (!(dd > 0.0)) mybad = 1;
+      if (KIND == 0) {
+        const double en = exp(-P.n * x);
+        const double xi = P.xi0 + (1.0 - P.xi0) * en;
+        const double dd = c * xi + cp * xi - c * P.n * (1.0 - P.xi0) * en;
+        if (!(dd > 0.0)) mybad = 1;
+      }
     }
   }
-  if (mybad) atomicOr(&bad, 1);
-  __syncthreads();
-  if (threadIdx.x == 0) flag_mono[b] = bad ? kFlagNonMonotone : 0;
+  if (KIND == 0) {
+    if (mybad) atomicOr(&bad, 1);
+    __syncthreads();
+    if (threadIdx.x == 0) flag_mono[b] = bad ? kFlagNonMonotone : 0;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -340,18 +355,12 @@ __global__ __launch_bounds__(kFinBS) void k_lnl_final(const LamParams* __restric
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-#define CH_LAUNCH_CHECK()                        \
-  do {                                           \
-    hipError_t _e = hipGetLastError();           \
-    if (_e != hipSuccess) return _e;             \
-  } while (0)
-
 hipError_t launch_tables(const double* lam, int B, const Geometry& g, LamParams* P,
                          double2* chi, double2* inv, double2* dtab, double* gz64, float* gz32,
                          int* flag_mono, int* flag_range, hipStream_t st) {
   k_lam_prepare<<<(B + 63) / 64, 64, 0, st>>>(lam, B, P);
   CH_LAUNCH_CHECK();
-  k_chi_table<<<B, kTabBS, 0, st>>>(P, g, chi, flag_mono);
+  k_x_table<0><<<B, kTabBS, 0, st>>>(P, g, chi, flag_mono);
   CH_LAUNCH_CHECK();
   const long long ni = (long long)B * g.n_u;
   k_inverse_table<<<(unsigned)((ni + 255) / 256), 256, 0, st>>>(P, chi, g, B, inv, flag_range);
@@ -366,6 +375,13 @@ hipError_t launch_tables(const double* lam, int B, const Geometry& g, LamParams*
     k_grid_factor<<<(unsigned)((ng + 255) / 256), 256, 0, st>>>(P, chi, g, B, gz64, gz32);
     CH_LAUNCH_CHECK();
   }
+  return hipSuccess;
+}
+
+hipError_t launch_chi_om_table(const LamParams* P, int B, const Geometry& g, double2* chio,
+                               hipStream_t st) {
+  k_x_table<1><<<B, kTabBS, 0, st>>>(P, g, chio, nullptr);
+  CH_LAUNCH_CHECK();
   return hipSuccess;
 }
 

@@ -8,6 +8,33 @@
 
 namespace chimera {
 
+#define CH_LAUNCH_CHECK()                        \
+  do {                                           \
+    hipError_t _e = hipGetLastError();           \
+    if (_e != hipSuccess) return _e;             \
+  } while (0)
+
+// XCD-aware block order for the per-(item, lambda) kernels: the blocks of one
+// item (event or work unit) at 32 consecutive lambdas land on one XCD (block
+// id mod 8) back to back, so the item's data stay in that XCD's L2.
+__device__ __forceinline__ bool decode_item_lambda(int n_items, int B, int& item, int& b) {
+  const int bc = B < 32 ? B : 32;
+  const int nchunk = (B + bc - 1) / bc;
+  const int L = blockIdx.x;
+  const int xcd = L & 7, s = L >> 3;
+  const int u = (s / bc) * 8 + xcd;
+  item = u / nchunk;
+  b = (u % nchunk) * bc + (s % bc);
+  return item < n_items && b < B;
+}
+
+inline long long item_lambda_blocks(int n_items, int B) {
+  const int bc = B < 32 ? B : 32;
+  const long long nchunk = (B + bc - 1) / bc;
+  const long long units = (long long)n_items * nchunk;
+  return ((units + 7) / 8) * 8 * bc;
+}
+
 struct SelArgs {
   const LamParams* P;
   const int* flag_mono;
@@ -99,5 +126,91 @@ hipError_t launch_lnl_final(const LamParams* P, const int* flag_mono, const int*
                             const double* lnI, const double* ln_xi, int E, int B, double* lnl,
                             hipStream_t st);
 int selection_chunks(long long n_det);
+
+// ---------------------------------------------------------------------------
+// adjoint (grad.hip)
+// ---------------------------------------------------------------------------
+// Per-lambda constants of the mass-model derivatives.
+struct GradParams {
+  double pl_unit;          // 1 / int_mmin^mmax m^-alpha dm
+  double tg_unit;          // 1 / (sigma sqrt(2 pi) Z)
+  double dlnnpl_dalpha;    // d ln int m^-alpha dm / d alpha
+  double dlnz_dmu, dlnz_dsigma;
+};
+
+struct GradArgs {
+  const LamParams* P;
+  GradParams* Q;            // written by the prepare kernel
+  const int* flag_mono;
+  const int* flag_range;
+  const double2* chi;
+  const double2* chio;      // [B][n_t] (dchi/dOm, its x-derivative)
+  const double2* inv;
+  const double2* dtab;
+  Geometry g;
+  const double* gz64;
+  const float* gz32;
+  double* gf64;             // [B][6][n_z] g dln g/dp, p = Om, Xi0, n, gamma, kappa, z_p
+  float* gf32;
+  const double* nz64;
+  const float* nz32;
+  const int* ev_samp_off;
+  const int* samp_row;      // catalogue row of each sample
+  const double* samp_c;     // c_ir of each sample's pixel
+  const double* dl;
+  const double* lndl;
+  const double* m1d;
+  const double* m2d;
+  const double* lnm1d;
+  const double* lnm2d;
+  int E, B;
+  double trunc;
+  double* lnI;              // [B][E]
+  double* dlnI;             // [B][E][12]
+};
+
+struct SelGradArgs {
+  const LamParams* P;
+  const GradParams* Q;
+  const int* flag_mono;
+  const int* flag_range;
+  const double2* chi;
+  const double2* chio;
+  const double2* inv;
+  const double2* dtab;
+  Geometry g;
+  const double* ntot;
+  const double* dl;
+  const double* lndl;
+  const double* m1d;
+  const double* m2d;
+  const double* lnm1d;
+  const double* lnm2d;
+  const double* ln_pdraw;
+  long long n_det;
+  int B;
+  int nchunk;
+  double* partial;          // [B][nchunk][13]: sum s, sum s dln s/dp
+};
+
+struct GradFinalArgs {
+  const LamParams* P;
+  const int* flag_mono;
+  const int* flag_range;
+  const double* partial;
+  int nchunk;
+  const double* lnI;
+  const double* dlnI;
+  int E;
+  long long n_total;
+  double* lnl;              // [B]
+  double* grad;             // [B][12]
+};
+
+hipError_t launch_chi_om_table(const LamParams* P, int B, const Geometry& g, double2* chio,
+                               hipStream_t st);
+hipError_t launch_grad(const GradArgs& a, const SelGradArgs& sa, GradFinalArgs fa, bool f32,
+                       hipStream_t st);
+int selection_grad_chunks(long long n_det);
 
 }  // namespace chimera

@@ -224,3 +224,23 @@ def prepare(cat: synth.Catalog, ev: synth.Events, n_z: int, z_lo: float, z_hi: f
                     pix_samp_off=np.asarray(samp_off, dtype=np.int64),
                     pix_row=pix_row, pix_id=pix_id, c_ir=np.asarray(c_list),
                     dl=np.concatenate(dl_l), m1d=np.concatenate(m1_l), m2d=np.concatenate(m2_l))
+
+
+def subset(p: Prepared, events) -> Prepared:
+    """The prepared arrays of the listed events (in that order), sharing the
+    catalogue rows."""
+    ev_off = [0]
+    samp_off = [0]
+    rows, ids, cs, dls, m1s, m2s = [], [], [], [], [], []
+    for e in events:
+        for q in range(p.ev_pix_off[e], p.ev_pix_off[e + 1]):
+            a, b = p.pix_samp_off[q], p.pix_samp_off[q + 1]
+            rows.append(p.pix_row[q]); ids.append(p.pix_id[q]); cs.append(p.c_ir[q])
+            dls.append(p.dl[a:b]); m1s.append(p.m1d[a:b]); m2s.append(p.m2d[a:b])
+            samp_off.append(samp_off[-1] + (b - a))
+        ev_off.append(len(rows))
+    return Prepared(p.n_z, p.z_lo, p.z_hi, p.nz, p.row_pix, p.nz_tot,
+                    np.asarray(ev_off, np.int64), np.asarray(samp_off, np.int64),
+                    np.asarray(rows, np.int64), np.asarray(ids, np.int64),
+                    np.asarray(cs, np.float64), np.concatenate(dls), np.concatenate(m1s),
+                    np.concatenate(m2s))

@@ -1,0 +1,173 @@
+"""The adjoint (chimera_lnl_grad) against the oracle's analytic gradient and
+against central differences of the library's own ln L, on handcrafted inputs
+and on sampled events of the 300-event workload with its 1e6 injections
+(64 lambda points with population parameters jittered by 10 %)."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2504_02034_amd import synth
+from tests.datasets import handcrafted, handcrafted_oracle
+
+pytestmark = pytest.mark.gpu
+
+GRAD_INDEX = (0, 1, 2, 3, 4, 5, 8, 9, 10, 11, 12, 13)
+
+
+@pytest.fixture(scope="module")
+def hand():
+    from paper_2504_02034_amd import chimera
+    h = handcrafted()
+    ctx = chimera.Context(n_z=h["n_z"], z_lo=h["z_lo"], z_hi=h["z_hi"])
+    ctx.set_catalog(h["rows"], h["nz_tot"])
+    ctx.set_injections(h["idl"], h["im1"], h["im2"], h["lnp"], h["ninj"])
+    es = ctx.add_events(h["ev_pix_off"], h["pix_samp_off"], h["pix_row"], h["c_ir"], h["dl"],
+                        h["m1"], h["m2"])
+    yield h, chimera, ctx, es
+    ctx.close()
+
+
+def hand_lams():
+    t = synth.LAMBDA_TRUTH
+    o = np.array([88.0, 0.41, 1.7, 3.2, 2.6, 0.7, 5.0, 87.0, 31.0, 4.4, 0.3, 2.1, 2.4, 1.6])
+    a1 = t.copy(); a1[4] = 1.0
+    b1 = t.copy(); b1[5] = -1.0
+    gr = o.copy(); gr[2] = 1.0
+    n0 = o.copy(); n0[3] = 0.0
+    return np.stack([t, o, a1, b1, gr, n0])
+
+
+def test_grad_matches_oracle_handcrafted(hand):
+    from oracle import gradient as G
+    h, chimera, ctx, es = hand
+    events, cat, inj = handcrafted_oracle(h)
+    lam = hand_lams()
+    lnl, grad = ctx.lnl_grad(es, lam, chimera.CHIMERA_FP64)
+    lnl_f = ctx.lnl(es, lam, chimera.CHIMERA_FP64)
+    for b in range(lam.shape[0]):
+        ref = G.lnl_grad(events, cat, inj, lam[b], T=8.6)
+        print(b, lnl[b], ref["lnl"], "\n  gpu ", grad[b], "\n  orac", ref["grad"])
+        assert abs(lnl[b] - ref["lnl"]) <= 1e-10 * abs(ref["lnl"])
+        assert abs(lnl[b] - lnl_f[b]) <= 1e-11 * abs(lnl_f[b])
+        err = np.abs(grad[b] - ref["grad"]) / np.maximum(1.0, np.abs(ref["grad"]))
+        assert np.all(err <= 1e-8), (b, err)
+    # exact zeros at the GR points
+    assert grad[4, 3] == 0.0 and grad[5, 2] == 0.0
+
+
+def test_grad_matches_library_differences(hand):
+    """Central differences of the FP64 ln L of the library: at step 1e-5
+    relative, and Richardson-combined at 1e-7.  n_tot is linear between grid
+    nodes, so injections whose redshift crosses a node inside the step bend
+    the larger-step differences at the 1e-5 level (the tolerance of the first
+    check); the small-step check is tight."""
+    h, chimera, ctx, es = hand
+    lam = hand_lams()[:2]
+    _, grad = ctx.lnl_grad(es, lam, chimera.CHIMERA_FP64)
+
+    def f(l):
+        return ctx.lnl(es, l[None], chimera.CHIMERA_FP64)[0]
+
+    def central(l, p, st):
+        lp, lm = l.copy(), l.copy()
+        lp[p] += st
+        lm[p] -= st
+        return (f(lp) - f(lm)) / (2 * st)
+
+    for b in range(lam.shape[0]):
+        for k, p in enumerate(GRAD_INDEX):
+            st = 1e-5 * abs(lam[b, p])
+            fd = central(lam[b], p, st)
+            assert abs(grad[b, k] - fd) <= 3e-4 * max(1.0, abs(fd)), (b, p, grad[b, k], fd)
+            st = 1e-7 * abs(lam[b, p])
+            rich = (4.0 * central(lam[b], p, 0.5 * st) - central(lam[b], p, st)) / 3.0
+            assert abs(grad[b, k] - rich) <= 1e-6 * max(1.0, abs(rich)), (b, p, grad[b, k], rich)
+
+
+def test_grad_fp32_error_is_small(hand):
+    h, chimera, ctx, es = hand
+    lam = hand_lams()
+    _, g64 = ctx.lnl_grad(es, lam, chimera.CHIMERA_FP64)
+    _, g32 = ctx.lnl_grad(es, lam, chimera.CHIMERA_FP32)
+    err = np.abs(g32 - g64) / np.maximum(1.0, np.abs(g64))
+    print("max FP32 gradient error", err.max())
+    assert err.max() <= 1e-3
+
+
+def test_grad_invalid_points(hand):
+    h, chimera, ctx, es = hand
+    lam = np.stack([synth.LAMBDA_TRUTH] * 3)
+    lam[1, 1] = 1.5       # Om outside (0, 1]
+    lam[2, 9] = -1.0      # sigma_g <= 0
+    lnl, grad = ctx.lnl_grad(es, lam, chimera.CHIMERA_FP64)
+    assert np.isfinite(lnl[0]) and np.all(np.isfinite(grad[0]))
+    assert lnl[1] == -np.inf and lnl[2] == -np.inf
+    assert np.all(np.isnan(grad[1:]))
+    lnl1, g1 = ctx.lnl_grad(es, lam[:1], chimera.CHIMERA_FP64)
+    assert lnl1[0] == lnl[0] and np.array_equal(g1[0], grad[0])
+
+
+def test_autograd_function(hand):
+    import torch
+    from paper_2504_02034_amd import autograd
+    h, chimera, ctx, es = hand
+    lam_np = hand_lams()[:3]
+    lam = torch.tensor(lam_np, dtype=torch.float64, device="cuda", requires_grad=True)
+    out = autograd.lnl(lam, ctx, es)
+    (out * torch.tensor([1.0, 2.0, -0.5], dtype=torch.float64, device="cuda")).sum().backward()
+    _, g = ctx.lnl_grad(es, lam_np, chimera.CHIMERA_FP64)
+    got = lam.grad.cpu().numpy()
+    want = np.zeros_like(lam_np)
+    want[:, list(GRAD_INDEX)] = g * np.array([1.0, 2.0, -0.5])[:, None]
+    assert np.allclose(got, want, rtol=1e-14, atol=0.0)
+    assert np.all(got[:, 6] == 0.0) and np.all(got[:, 7] == 0.0)
+
+
+@pytest.fixture(scope="module")
+def c4():
+    """Six events of the 300-event workload, all its detected injections, and
+    the 64 lambda points of the differentiation check."""
+    from paper_2504_02034_amd import chimera, prep
+    from tests.datasets import build
+    import oracle
+    wl = synth.WORKLOADS["grad_300ev"]
+    d = build(wl)
+    pick = [0, 57, 133, 201, 250, 299]
+    p = d.prep
+    sub = prep.subset(p, pick)
+    ctx = chimera.Context(n_z=p.n_z, z_lo=p.z_lo, z_hi=p.z_hi)
+    ctx.set_catalog(p.nz, p.nz_tot)
+    ctx.set_injections(d.inj.dl, d.inj.m1d, d.inj.m2d, d.inj.ln_pdraw, d.inj.n_total)
+    es = ctx.add_prepared(sub)
+    o_events = [d.o_events[i] for i in pick]
+    yield d, chimera, ctx, es, o_events, oracle
+    ctx.close()
+
+
+def test_grad_c4_sampled_events_match_oracle(c4):
+    from oracle import gradient as G
+    d, chimera, ctx, es, o_events, oracle = c4
+    lam = d.lam
+    lnl, grad = ctx.lnl_grad(es, lam, chimera.CHIMERA_FP64)
+    _, g32 = ctx.lnl_grad(es, lam, chimera.CHIMERA_FP32)
+    assert lam.shape[0] == 64
+    worst = 0.0
+    fin = np.nonzero(np.isfinite(lnl))[0]
+    nonfin = np.nonzero(~np.isfinite(lnl))[0]
+    assert fin.size >= 4
+    pts = [int(fin[i]) for i in (0, fin.size // 3, 2 * fin.size // 3, fin.size - 1)]
+    pts += [int(nonfin[0])] if nonfin.size else []
+    for b in pts:
+        ref = G.lnl_grad(o_events, d.o_cat, d.o_inj, lam[b], T=8.6)
+        if not np.isfinite(ref["lnl"]):
+            assert not np.isfinite(lnl[b])
+            continue
+        assert abs(lnl[b] - ref["lnl"]) <= 1e-10 * abs(ref["lnl"])
+        err = np.abs(grad[b] - ref["grad"]) / np.maximum(1.0, np.abs(ref["grad"]))
+        worst = max(worst, err.max())
+        assert np.all(err <= 1e-7), (b, err)
+    fin = np.isfinite(lnl)
+    e32 = np.abs(g32[fin] - grad[fin]) / np.maximum(1.0, np.abs(grad[fin]))
+    print("worst FP64 rel err vs oracle", worst, "FP32 vs FP64 max", e32.max())
+    assert e32.max() <= 1e-2
