@@ -150,6 +150,14 @@ chimera_status chimera_lnl_batch(chimera_ctx* ctx, const chimera_events* ev, con
 chimera_status chimera_selection_xi(chimera_ctx* ctx, const double* lam, int64_t B, int32_t prec,
                                     double* ln_xi, double* n_eff, int32_t mem, void* hip_stream);
 
+/* Device scratch (bytes) that chimera_lnl_batch allocates on its stream for
+ * B points of event set ev (NULL: the selection alone) in precision prec and
+ * memory mode mem; the allocation lives until the call's work on the stream
+ * has finished.  For admission control by an HBM budget (chimera_config's
+ * hbm_budget bounds one call; a scheduler of concurrent calls sums these). */
+chimera_status chimera_scratch_bytes(chimera_ctx* ctx, const chimera_events* ev, int64_t B,
+                                     int32_t prec, int32_t mem, size_t* bytes);
+
 /* ln L and its gradient at B points (the adjoint of eq. hyperlike through
  * every step above: the redshift of each sample as an implicit function of
  * d_L^gw(z_j) = d_j, the mass weights, the bandwidth, the kernel sums, the

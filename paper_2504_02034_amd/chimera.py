@@ -28,7 +28,8 @@ _STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ERANGE", -5:
 EXPORTS = ("chimera_default_config", "chimera_create", "chimera_destroy", "chimera_last_error",
            "chimera_set_catalog", "chimera_set_injections", "chimera_add_events",
            "chimera_release_events", "chimera_lnl_batch", "chimera_selection_xi",
-           "chimera_lnl_grad", "chimera_profile_enable", "chimera_profile_read")
+           "chimera_lnl_grad", "chimera_scratch_bytes", "chimera_profile_enable",
+           "chimera_profile_read")
 
 
 class ChimeraError(RuntimeError):
@@ -74,6 +75,8 @@ def _load():
         "chimera_lnl_batch": (ctypes.c_int, [_P, _P, _P, _I64, _I32, _P, _P, _I32, _P]),
         "chimera_selection_xi": (ctypes.c_int, [_P, _P, _I64, _I32, _P, _P, _I32, _P]),
         "chimera_lnl_grad": (ctypes.c_int, [_P, _P, _P, _I64, _I32, _P, _P, _I32, _P]),
+        "chimera_scratch_bytes": (ctypes.c_int, [_P, _P, _I64, _I32, _I32,
+                                                 ctypes.POINTER(ctypes.c_size_t)]),
         "chimera_profile_enable": (ctypes.c_int, [_P, _I32]),
         "chimera_profile_read": (ctypes.c_int, [_P, ctypes.POINTER(_I64),
                                                 ctypes.POINTER(ctypes.c_double),
@@ -219,6 +222,12 @@ def chimera_lnl_grad(h, ev, lam, prec=CHIMERA_FP64, lnl=None, grad=None, stream=
     return out, g
 
 
+def chimera_scratch_bytes(h, ev, B, prec=CHIMERA_FP64, mem=CHIMERA_DEVICE) -> int:
+    out = ctypes.c_size_t()
+    _check(lib.chimera_scratch_bytes(h, ev, int(B), prec, mem, ctypes.byref(out)))
+    return out.value
+
+
 def chimera_profile_enable(h, on=True):
     _check(lib.chimera_profile_enable(h, 1 if on else 0))
 
@@ -289,6 +298,10 @@ class Context:
 
     def selection(self, lam, prec=CHIMERA_FP64, stream=None):
         return chimera_selection_xi(self.handle, lam, prec, stream=stream)
+
+    def scratch_bytes(self, ev: EventSet, B, prec=CHIMERA_FP64, mem=CHIMERA_DEVICE) -> int:
+        return chimera_scratch_bytes(self.handle, ev.handle if ev is not None else None, B, prec,
+                                     mem)
 
     def lnl_grad(self, ev: EventSet, lam, prec=CHIMERA_FP64, stream=None):
         """(ln L [B], d ln L / d(GRAD_NAMES) [B, 12])."""

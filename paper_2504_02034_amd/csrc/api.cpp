@@ -593,6 +593,23 @@ static chimera_status run_batch(chimera_ctx* ctx, const chimera_events* ev, cons
   return CHIMERA_OK;
 }
 
+chimera_status chimera_scratch_bytes(chimera_ctx* ctx, const chimera_events* ev, int64_t B,
+                                     int32_t prec, int32_t mem, size_t* bytes) {
+  if (!ctx || !bytes) return fail(CHIMERA_EINVAL, "null argument");
+  if (B < 1 || B > (1 << 20)) return fail(CHIMERA_EINVAL, "batch size out of [1, 2^20]");
+  if (prec != CHIMERA_FP64 && prec != CHIMERA_FP32) return fail(CHIMERA_EINVAL, "bad precision");
+  if (mem != CHIMERA_HOST && mem != CHIMERA_DEVICE) return fail(CHIMERA_EINVAL, "bad mem");
+  const bool host = mem == CHIMERA_HOST;
+  const int E = ev ? ev->E : 0;
+  double dmin = ev ? ev->dmin : 1.0, dmax = ev ? ev->dmax : 1.0;
+  const Geometry g = make_geometry(ctx, dmin, dmax);
+  Scratch s;
+  Carve probe;
+  *bytes = carve(probe, s, g, B, E, selection_chunks(ctx->n_det), host, ev && host, ev != nullptr,
+                 host, ev ? ev->n_samp : 0, ev ? ev->U : 0, prec == CHIMERA_FP32);
+  return CHIMERA_OK;
+}
+
 chimera_status chimera_lnl_batch(chimera_ctx* ctx, const chimera_events* ev, const double* lam,
                                  int64_t B, int32_t prec, double* lnl, double* lnI, int32_t mem,
                                  void* hip_stream) {

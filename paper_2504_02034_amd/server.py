@@ -1,0 +1,222 @@
+"""Continuous-batching server for ln L requests from many concurrent samplers.
+
+submit(events, lam [B, 14], prec) -> Ticket; wait(ticket) -> ln L [B];
+stats() -> evals/s, p50 / p99 latency and admission figures.
+
+The event sets, the catalogue and the injections stay resident in the
+library's context.  Worker threads, each with its own HIP stream, take work
+as they free up:
+
+* continuous batching: a free worker takes the oldest pending request and,
+  with it, every other pending request on the same event set and precision
+  (in arrival order) up to `max_fused` lambda points, and evaluates them in
+  one call; each point's result does not depend on the others in its batch
+  (every per-lambda reduction has a fixed order), so a request gets the same
+  numbers alone and in any mix;
+* admission by HBM budget: a launch starts only while the device scratch of
+  all launches in flight (chimera_scratch_bytes) stays within `hbm_budget`;
+  the oldest request is never passed over, so a large one waits for memory
+  rather than starving;
+* work of different workers overlaps on the device (one stream each).
+
+The executor is pluggable: HipExecutor runs the library; tests of the
+scheduling logic use a CPU stand-in.
+"""
+from __future__ import annotations
+
+import collections
+import threading
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+
+
+@dataclass
+class Ticket:
+    id: int
+    events: object
+    lam: np.ndarray
+    prec: int
+    t_submit: float
+    t_start: float = 0.0
+    t_done: float = 0.0
+    result: np.ndarray = None
+    error: BaseException = None
+    done: threading.Event = field(default_factory=threading.Event)
+
+    @property
+    def B(self) -> int:
+        return self.lam.shape[0]
+
+
+class HipExecutor:
+    """Runs fused requests through chimera_lnl_batch on a per-worker stream."""
+
+    def __init__(self, ctx):
+        import torch
+        self.torch = torch
+        self.ctx = ctx
+
+    def new_worker(self):
+        return self.torch.cuda.Stream()
+
+    def scratch_bytes(self, events, B, prec) -> int:
+        from . import chimera
+        # lambda and ln L device buffers of the call, plus the library's scratch
+        return self.ctx.scratch_bytes(events, B, prec, chimera.CHIMERA_DEVICE) + 15 * 8 * B
+
+    def run(self, stream, events, lam, prec) -> np.ndarray:
+        torch = self.torch
+        with torch.cuda.stream(stream):
+            lam_d = torch.from_numpy(lam).pin_memory().to("cuda", non_blocking=True)
+            out = self.ctx.lnl(events, lam_d, prec, stream=stream)
+            host = out.to("cpu", non_blocking=True)
+        stream.synchronize()
+        return host.numpy()
+
+
+class Server:
+    def __init__(self, executor, n_workers: int = 4, max_fused: int = 512,
+                 hbm_budget: int = 0):
+        if n_workers < 1 or max_fused < 1:
+            raise ValueError("n_workers and max_fused must be >= 1")
+        self.ex = executor
+        self.max_fused = max_fused
+        self.budget = int(hbm_budget)          # 0: no limit
+        self._mu = threading.Lock()
+        self._cv = threading.Condition(self._mu)
+        self._pending: collections.deque = collections.deque()
+        self._next_id = 0
+        self._in_use = 0
+        self._stop = False
+        # statistics
+        self._lat = []
+        self._evals = 0
+        self._launches = 0
+        self._fused_requests = 0
+        self._peak_bytes = 0
+        self._peak_inflight = 0
+        self._inflight = 0
+        self._t0 = None
+        self._t_last = None
+        self._workers = [threading.Thread(target=self._loop, args=(self.ex.new_worker(),),
+                                          daemon=True) for _ in range(n_workers)]
+        for w in self._workers:
+            w.start()
+
+    # ------------------------------------------------------------------
+    def submit(self, events, lam, prec: int = 0) -> Ticket:
+        lam = np.ascontiguousarray(np.atleast_2d(lam), dtype=np.float64)
+        if lam.ndim != 2 or lam.shape[1] != 14 or lam.shape[0] < 1:
+            raise ValueError("lam must be [B, 14] with B >= 1")
+        if lam.shape[0] > self.max_fused:
+            raise ValueError(f"B = {lam.shape[0]} exceeds max_fused = {self.max_fused}")
+        need = self.ex.scratch_bytes(events, lam.shape[0], prec)
+        if self.budget and need > self.budget:
+            raise MemoryError(f"request needs {need} bytes, over the budget of {self.budget}")
+        with self._cv:
+            if self._stop:
+                raise RuntimeError("server is closed")
+            t = Ticket(self._next_id, events, lam, prec, time.perf_counter())
+            self._next_id += 1
+            if self._t0 is None:
+                self._t0 = t.t_submit
+            self._pending.append(t)
+            self._cv.notify_all()
+        return t
+
+    def wait(self, ticket: Ticket, timeout=None) -> np.ndarray:
+        if not ticket.done.wait(timeout):
+            raise TimeoutError(f"request {ticket.id} not done")
+        if ticket.error is not None:
+            raise ticket.error
+        return ticket.result
+
+    def stats(self) -> dict:
+        with self._mu:
+            lat = np.array(self._lat) * 1e3
+            span = (self._t_last - self._t0) if self._t_last is not None else 0.0
+            return {
+                "completed": len(self._lat),
+                "evals": self._evals,
+                "evals_per_s": self._evals / span if span > 0 else 0.0,
+                "p50_ms": float(np.percentile(lat, 50)) if lat.size else float("nan"),
+                "p99_ms": float(np.percentile(lat, 99)) if lat.size else float("nan"),
+                "launches": self._launches,
+                "requests_per_launch": self._fused_requests / max(self._launches, 1),
+                "peak_bytes": self._peak_bytes,
+                "peak_inflight": self._peak_inflight,
+                "budget": self.budget,
+            }
+
+    def close(self):
+        with self._cv:
+            self._stop = True
+            self._cv.notify_all()
+        for w in self._workers:
+            w.join()
+
+    # ------------------------------------------------------------------
+    def _take(self):
+        """Under the lock: the fused group for a free worker, or None."""
+        if not self._pending:
+            return None
+        head = self._pending[0]
+        group, B = [head], head.B
+        for t in list(self._pending)[1:]:
+            if t.events is head.events and t.prec == head.prec and B + t.B <= self.max_fused:
+                group.append(t)
+                B += t.B
+        need = self.ex.scratch_bytes(head.events, B, head.prec)
+        # shrink to what the budget admits; the head alone always fits an idle device
+        while self.budget and self._in_use + need > self.budget and len(group) > 1:
+            B -= group.pop().B
+            need = self.ex.scratch_bytes(head.events, B, head.prec)
+        if self.budget and self._in_use + need > self.budget:
+            return None
+        for t in group:
+            self._pending.remove(t)
+        return group, B, need
+
+    def _loop(self, worker):
+        while True:
+            with self._cv:
+                while True:
+                    got = self._take()
+                    if got is not None or (self._stop and not self._pending):
+                        break
+                    self._cv.wait()
+                if got is None:
+                    return
+                group, B, need = got
+                self._in_use += need
+                self._inflight += 1
+                self._peak_bytes = max(self._peak_bytes, self._in_use)
+                self._peak_inflight = max(self._peak_inflight, self._inflight)
+            t_start = time.perf_counter()
+            lam = np.concatenate([t.lam for t in group]) if len(group) > 1 else group[0].lam
+            err, out = None, None
+            try:
+                out = self.ex.run(worker, group[0].events, lam, group[0].prec)
+            except BaseException as e:  # noqa: BLE001 - handed to the waiting caller
+                err = e
+            t_done = time.perf_counter()
+            with self._cv:
+                self._in_use -= need
+                self._inflight -= 1
+                self._launches += 1
+                self._fused_requests += len(group)
+                off = 0
+                for t in group:
+                    t.t_start, t.t_done = t_start, t_done
+                    if err is None:
+                        t.result = out[off:off + t.B].copy()
+                        self._lat.append(t_done - t.t_submit)
+                        self._evals += t.B
+                    else:
+                        t.error = err
+                    off += t.B
+                    t.done.set()
+                self._t_last = t_done
+                self._cv.notify_all()

@@ -1,0 +1,174 @@
+"""Scheduling logic of the continuous-batching server with a CPU stand-in
+for the device executor: results routed to the right requests whatever the
+fusion, the HBM budget never exceeded, fusion of queued requests on the same
+event set, first-come order under memory pressure, errors isolated to their
+requests, drain on close."""
+import threading
+import time
+
+import numpy as np
+import pytest
+
+from paper_2504_02034_amd.server import Server
+
+
+class Events:
+    def __init__(self, tag):
+        self.tag = tag
+
+
+class MockExec:
+    def __init__(self, per_point_s=2e-4, fail_tag=None):
+        self.per_point_s = per_point_s
+        self.fail_tag = fail_tag
+        self.mu = threading.Lock()
+        self.in_use = 0
+        self.peak = 0
+        self.calls = []
+
+    def new_worker(self):
+        return object()
+
+    def scratch_bytes(self, events, B, prec):
+        return 1000 + 100 * B
+
+    def run(self, worker, events, lam, prec):
+        need = self.scratch_bytes(events, lam.shape[0], prec)
+        with self.mu:
+            self.in_use += need
+            self.peak = max(self.peak, self.in_use)
+            self.calls.append((events.tag, lam.shape[0], prec, time.perf_counter()))
+        try:
+            time.sleep(lam.shape[0] * self.per_point_s)
+            if self.fail_tag is not None and events.tag == self.fail_tag:
+                raise ValueError("executor failure")
+            return value(events, lam, prec)
+        finally:
+            with self.mu:
+                self.in_use -= need
+
+
+def value(events, lam, prec):
+    return lam[:, 0] * 3.0 + lam[:, 5] + 1000.0 * events.tag + 0.5 * prec
+
+
+def lam_batch(rng, B):
+    lam = np.tile(np.arange(14, dtype=float), (B, 1))
+    lam[:, 0] = rng.normal(size=B)
+    lam[:, 5] = rng.normal(size=B)
+    return lam
+
+
+def test_results_follow_their_requests_under_concurrency():
+    ex = MockExec()
+    srv = Server(ex, n_workers=3, max_fused=64)
+    evs = [Events(0), Events(1), Events(2)]
+    out = []
+    lock = threading.Lock()
+
+    def client(seed):
+        rng = np.random.default_rng(seed)
+        for _ in range(15):
+            ev = evs[rng.integers(3)]
+            prec = int(rng.integers(2))
+            lam = lam_batch(rng, int(rng.integers(1, 20)))
+            t = srv.submit(ev, lam, prec)
+            with lock:
+                out.append((t, ev, lam, prec))
+
+    th = [threading.Thread(target=client, args=(s,)) for s in range(6)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    for t, ev, lam, prec in out:
+        assert np.array_equal(srv.wait(t, timeout=30), value(ev, lam, prec))
+    st = srv.stats()
+    srv.close()
+    assert st["completed"] == len(out)
+    assert st["evals"] == sum(lam.shape[0] for _, _, lam, _ in out)
+    assert st["launches"] <= len(out)
+    assert st["p99_ms"] >= st["p50_ms"] > 0.0
+
+
+def test_budget_is_never_exceeded_and_queued_requests_fuse():
+    ex = MockExec(per_point_s=1e-3)
+    budget = 2 * (1000 + 100 * 16)
+    srv = Server(ex, n_workers=4, max_fused=16, hbm_budget=budget)
+    ev = Events(0)
+    rng = np.random.default_rng(1)
+    ts = [(srv.submit(ev, lam, 0), lam) for lam in (lam_batch(rng, 4) for _ in range(24))]
+    for t, lam in ts:
+        assert np.array_equal(srv.wait(t, timeout=30), value(ev, lam, 0))
+    st = srv.stats()
+    srv.close()
+    assert ex.peak <= budget and st["peak_bytes"] <= budget
+    assert st["launches"] < len(ts)                     # queued requests were fused
+    assert max(b for _, b, _, _ in ex.calls) <= 16
+
+
+def test_fusion_keeps_event_sets_and_precisions_apart():
+    ex = MockExec(per_point_s=2e-3)
+    srv = Server(ex, n_workers=1, max_fused=512)
+    rng = np.random.default_rng(2)
+    blocker = srv.submit(Events(9), lam_batch(rng, 20), 0)     # keeps the worker busy
+    a, b = Events(0), Events(1)
+    reqs = [(srv.submit(e, lam, p), e, lam, p)
+            for e, p in ((a, 0), (b, 0), (a, 1), (a, 0), (b, 0), (a, 1))
+            for lam in [lam_batch(rng, 3)]]
+    srv.wait(blocker, timeout=30)
+    for t, e, lam, p in reqs:
+        assert np.array_equal(srv.wait(t, timeout=30), value(e, lam, p))
+    srv.close()
+    groups = [(tag, B, prec) for tag, B, prec, _ in ex.calls[1:]]
+    assert sorted(groups) == [(0, 6, 0), (0, 6, 1), (1, 6, 0)]
+
+
+def test_oldest_request_is_not_passed_over_under_memory_pressure():
+    ex = MockExec(per_point_s=5e-3)
+    big = 1000 + 100 * 30
+    srv = Server(ex, n_workers=3, max_fused=30, hbm_budget=big)
+    rng = np.random.default_rng(3)
+    first = srv.submit(Events(1), lam_batch(rng, 2), 0)        # runs at once
+    time.sleep(0.002)
+    large = srv.submit(Events(2), lam_batch(rng, 30), 0)       # must wait for memory
+    later = [srv.submit(Events(1), lam_batch(rng, 2), 0) for _ in range(3)]
+    for t in [first, large] + later:
+        srv.wait(t, timeout=30)
+    srv.close()
+    assert all(t.t_start >= large.t_start for t in later)
+
+
+def test_rejects_oversized_requests():
+    srv = Server(MockExec(), n_workers=1, max_fused=8, hbm_budget=1500)
+    rng = np.random.default_rng(4)
+    with pytest.raises(ValueError):
+        srv.submit(Events(0), lam_batch(rng, 9), 0)
+    with pytest.raises(MemoryError):
+        srv.submit(Events(0), lam_batch(rng, 8), 0)            # 1800 bytes > 1500
+    with pytest.raises(ValueError):
+        srv.submit(Events(0), np.zeros((2, 13)), 0)
+    srv.close()
+
+
+def test_executor_errors_stay_with_their_requests():
+    ex = MockExec(fail_tag=7)
+    srv = Server(ex, n_workers=2, max_fused=32)
+    rng = np.random.default_rng(5)
+    bad = srv.submit(Events(7), lam_batch(rng, 3), 0)
+    good = [(srv.submit(Events(1), lam, 0), lam) for lam in (lam_batch(rng, 2) for _ in range(5))]
+    with pytest.raises(ValueError):
+        srv.wait(bad, timeout=30)
+    for t, lam in good:
+        assert np.array_equal(srv.wait(t, timeout=30), value(Events(1), lam, 0))
+    srv.close()
+
+
+def test_close_drains_pending_requests():
+    srv = Server(MockExec(per_point_s=1e-3), n_workers=1, max_fused=4)
+    rng = np.random.default_rng(6)
+    ts = [srv.submit(Events(0), lam_batch(rng, 4), 0) for _ in range(5)]
+    srv.close()
+    assert all(t.done.is_set() and t.error is None for t in ts)
+    with pytest.raises(RuntimeError):
+        srv.submit(Events(0), lam_batch(rng, 1), 0)
