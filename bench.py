@@ -112,6 +112,102 @@ def cpu_baseline(wl, cf, ev, inj, lam, n_events):
                       f"scaled by {wl.n_events}/{n_events}; measured {t_all:.1f}s"}
 
 
+def tile_events(p, n_events):
+    """A prepared event set of n_events made by cycling through p's events
+    (same catalogue rows), for serving workloads larger than the generated set."""
+    from paper_2504_02034_amd import prep
+    return prep.subset(p, [i % p.n_events for i in range(n_events)])
+
+
+def time_grad(ctx, es, lam_t, prec, steps):
+    import torch
+    ctx.lnl_grad(es, lam_t, prec)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(steps):
+        ctx.lnl_grad(es, lam_t, prec)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t) / steps
+
+
+def serve_bench(ctx, p, n_requests=300, seed=5):
+    """Poisson trace against resident event sets of 50, 300 and 1000 events
+    sharing one catalogue and injection set: request sizes log-uniform in
+    1..512, event set uniform.  First the FP32 server is saturated (every
+    request queued at once) to measure its throughput; the open-loop trace
+    then arrives at 0.7 of that rate.  The FP32 server (continuous batching,
+    4 streams, HBM budget) and plain FP64 launches, one request at a time,
+    replay the same trace."""
+    import numpy as np
+
+    from paper_2504_02034_amd import chimera, prep, synth
+    from paper_2504_02034_amd.server import HipExecutor, Server
+    sizes = (50, 300, 1000)
+    sets = [ctx.add_prepared(prep.subset(p, list(range(50)))), ctx.add_prepared(p),
+            ctx.add_prepared(tile_events(p, 1000))]
+    rng = np.random.default_rng(seed)
+    B = np.clip(np.floor(np.exp(rng.uniform(0.0, math.log(513.0), n_requests))).astype(int), 1, 512)
+    which = rng.integers(0, 3, n_requests)
+    base = synth.make_lambdas(synth.WORKLOADS["precision_300ev"])
+    lams = [base[rng.integers(0, base.shape[0], b)] for b in B]
+    gaps = rng.exponential(1.0, n_requests)
+    ex = HipExecutor(ctx)
+    biggest = max(ex.scratch_bytes(sets[w], int(b), chimera.CHIMERA_FP32) for b, w in zip(B, which))
+    budget = int(2.5 * biggest)
+    srv = Server(ex, n_workers=4, max_fused=512, hbm_budget=budget)
+    srv.wait(srv.submit(sets[1], lams[0][:1], chimera.CHIMERA_FP32))      # warm up
+    # saturated throughput: the whole trace queued at once
+    srv.reset_stats()
+    t0 = time.perf_counter()
+    for t in [srv.submit(sets[which[i]], lams[i], chimera.CHIMERA_FP32) for i in range(n_requests)]:
+        srv.wait(t)
+    t_sat = time.perf_counter() - t0
+    sat = srv.stats()
+    rate = 0.7 * n_requests / t_sat                                   # requests per second
+    arrivals = np.cumsum(gaps / rate)
+    srv.reset_stats()
+    tickets = []
+    t0 = time.perf_counter()
+    for i in range(n_requests):
+        dt = arrivals[i] - (time.perf_counter() - t0)
+        if dt > 0:
+            time.sleep(dt)
+        tickets.append(srv.submit(sets[which[i]], lams[i], chimera.CHIMERA_FP32))
+    for t in tickets:
+        srv.wait(t)
+    st = srv.stats()
+    srv.close()
+    # plain FP64 launches, one request at a time, same trace
+    lat = []
+    t0 = time.perf_counter()
+    for i in range(n_requests):
+        dt = arrivals[i] - (time.perf_counter() - t0)
+        if dt > 0:
+            time.sleep(dt)
+        ctx.lnl(sets[which[i]], lams[i], chimera.CHIMERA_FP64)
+        lat.append(time.perf_counter() - t0 - arrivals[i])
+    span64 = time.perf_counter() - t0
+    lat = sorted(lat)
+    for es in sets:
+        es.release()
+    return {
+        "requests": n_requests, "event_sets": list(sizes), "batch": "log-uniform 1..512",
+        "saturated_fp32_evals_per_s": round(float(B.sum()) / t_sat, 1),
+        "saturated_requests_per_launch": round(sat["requests_per_launch"], 3),
+        "arrival_rate_req_s": round(rate, 2),
+        "fp32_server": {"evals_per_s": round(st["evals_per_s"], 1),
+                        "p50_ms": round(st["p50_ms"], 3), "p99_ms": round(st["p99_ms"], 3),
+                        "launches": st["launches"],
+                        "requests_per_launch": round(st["requests_per_launch"], 3),
+                        "peak_inflight": st["peak_inflight"],
+                        "peak_scratch_gb": round(st["peak_bytes"] / 2**30, 2),
+                        "hbm_budget_gb": round(budget / 2**30, 2)},
+        "fp64_plain": {"evals_per_s": round(float(B.sum()) / span64, 1),
+                       "p50_ms": round(pct(lat, 50) * 1e3, 3),
+                       "p99_ms": round(pct(lat, 99) * 1e3, 3)},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -121,6 +217,8 @@ def main():
     ap.add_argument("--batch", type=int, default=None)
     ap.add_argument("--cpu-events", type=int, default=300)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-grad", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: this build runs on a single MI355X and has no "
@@ -156,7 +254,7 @@ def main():
         r = res[name]
         return {"bound": "alu", "achieved": round(r["achieved"], 3), "peak": PEAK_TFLOPS[name],
                 "unit": "TFLOP/s", "frac": round(r["achieved"] / PEAK_TFLOPS[name], 4),
-                "traffic": None, "kernel": f"k_event<{name}>",
+                "traffic": None, "kernel": "k_event_smooth" + name[2:],
                 "kernel_ms": round(r["avg_ms"], 4), "evals_per_launch": int(r["evals"])}
 
     k = args.steps
@@ -184,6 +282,19 @@ def main():
         "roofline": roof("fp32"),
         "roofline_fp64": roof("fp64"),
     }
+    if not args.no_grad:
+        from paper_2504_02034_amd import synth
+        lam_g = torch.from_numpy(synth.make_lambdas(synth.WORKLOADS["grad_300ev"])).cuda()
+        g = {"batch": int(lam_g.shape[0]), "params": 12}
+        for name, prec in (("fp64", chimera.CHIMERA_FP64), ("fp32", chimera.CHIMERA_FP32)):
+            sec = time_grad(ctx, es, lam_g, prec, 3)
+            g[name] = {"ms": round(sec * 1e3, 3), "evals_per_s": round(lam_g.shape[0] / sec, 1),
+                       "over_forward": round(sec / (res[name]["wall"] / k * lam_g.shape[0] / B), 2)}
+            log(f"grad {name}: {sec * 1e3:.2f} ms for {lam_g.shape[0]} lambda")
+        line["grad"] = g
+    if not args.no_serve:
+        log("serving trace")
+        line["serving"] = serve_bench(ctx, p)
     ctx.close()
     if not args.no_cpu_baseline:
         log("timing the CPU oracle (cpu_baseline)")

@@ -140,7 +140,10 @@ chimera_status chimera_release_events(chimera_ctx* ctx, chimera_events* ev);
 /* ln L at B points (eq. hyperlike).  prec: CHIMERA_FP64, or CHIMERA_FP32 for
  * FP32 bulk arithmetic (mass weights, kernel sums) with the distance tables,
  * the inversion, the bandwidth moments and every per-event and per-lambda sum
- * kept in FP64.  lnl[B]; lnI[B][n_ev] (ln I_i per point and event) may be NULL. */
+ * kept in FP64.  lnl[B]; lnI[B][n_ev] (ln I_i per point and event) may be NULL.
+ * A call whose per-sample scratch (a redshift and a weight per sample and
+ * point) would exceed 8 GiB runs as consecutive chunks of points on the same
+ * stream; every point's result is independent of the chunking. */
 chimera_status chimera_lnl_batch(chimera_ctx* ctx, const chimera_events* ev, const double* lam,
                                  int64_t B, int32_t prec, double* lnl, double* lnI, int32_t mem,
                                  void* hip_stream);
@@ -150,11 +153,15 @@ chimera_status chimera_lnl_batch(chimera_ctx* ctx, const chimera_events* ev, con
 chimera_status chimera_selection_xi(chimera_ctx* ctx, const double* lam, int64_t B, int32_t prec,
                                     double* ln_xi, double* n_eff, int32_t mem, void* hip_stream);
 
-/* Device scratch (bytes) that chimera_lnl_batch allocates on its stream for
- * B points of event set ev (NULL: the selection alone) in precision prec and
- * memory mode mem; the allocation lives until the call's work on the stream
- * has finished.  For admission control by an HBM budget (chimera_config's
- * hbm_budget bounds one call; a scheduler of concurrent calls sums these). */
+/* Device scratch (bytes) that one launch sequence of chimera_lnl_batch uses
+ * for B points of event set ev (NULL: the selection alone) in precision prec
+ * and memory mode mem, rounded up to a power of two.  The context keeps one
+ * scratch block per stream, grown to the largest such size used on that
+ * stream and reused by later calls on it (work on a stream runs in order);
+ * the blocks are freed by chimera_destroy.  For admission control by an HBM
+ * budget: chimera_config's hbm_budget bounds one call; a scheduler of
+ * concurrent calls on several streams sums these.  For a chunked call (see
+ * chimera_lnl_batch) this is one chunk's scratch. */
 chimera_status chimera_scratch_bytes(chimera_ctx* ctx, const chimera_events* ev, int64_t B,
                                      int32_t prec, int32_t mem, size_t* bytes);
 

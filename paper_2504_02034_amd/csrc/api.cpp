@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstring>
 #include <limits>
+#include <map>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -52,6 +53,14 @@ bool finite_positive(const double* v, size_t n) {
 }
 
 size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Scratch is held per stream in power-of-two sizes (at least 1 MiB), so that
+// calls of varying batch size on a stream reuse one block.
+size_t pool_size(size_t bytes) {
+  size_t a = size_t(1) << 20;
+  while (a < bytes) a <<= 1;
+  return a;
+}
 
 // Bump allocator over one device block.
 struct Carve {
@@ -100,6 +109,8 @@ struct chimera_ctx {
   double inj_dmin = 0.0, inj_dmax = 0.0;
   bool has_cat = false, has_inj = false;
   std::vector<chimera_events*> events;
+  // per-stream scratch arenas (grow only; freed by chimera_destroy)
+  std::map<hipStream_t, std::pair<void*, size_t>> arenas;
   // diagnostics
   bool profile = false;
   unsigned long long* d_count = nullptr;
@@ -265,6 +276,7 @@ void chimera_destroy(chimera_ctx* ctx) {
     (void)hipEventDestroy(m.second);
   }
   dfree(ctx->d_count);
+  for (auto& a : ctx->arenas) dfree(a.second.first);
   for (auto* e : ctx->events) free_events(e);
   free_catalog(ctx);
   free_injections(ctx);
@@ -493,7 +505,40 @@ chimera_status chimera_release_events(chimera_ctx* ctx, chimera_events* ev) {
   return CHIMERA_OK;
 }
 
-static chimera_status run_batch(chimera_ctx* ctx, const chimera_events* ev, const double* lam,
+// Largest per-sample scratch (z_j, w_j for every sample and lambda) of one
+// launch sequence; a call over more lambda points runs in consecutive chunks.
+constexpr double kSampleScratchCap = 8.0 * (1ull << 30);
+
+int64_t lambda_chunk(const chimera_events* ev, int64_t B, bool f32) {
+  if (!ev) return B;
+  const double per = (double)ev->n_samp * (f32 ? 12.0 : 16.0) + 8.0 * (ev->E + ev->U);
+  const int64_t c = (int64_t)std::max(1.0, std::floor(kSampleScratchCap / per));
+  return std::min(B, c);
+}
+
+// The scratch block of stream st, at least `bytes` large.  Work on one stream
+// runs in order, so consecutive calls on it can share the block; a block that
+// has to grow is released in stream order (after the work that used it).
+static hipError_t stream_scratch(chimera_ctx* ctx, hipStream_t st, size_t bytes, void** out) {
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  auto& a = ctx->arenas[st];
+  if (a.second < bytes) {
+    if (a.first) {
+      hipError_t e = hipFreeAsync(a.first, st);
+      if (e != hipSuccess) return e;
+      a.first = nullptr;
+      a.second = 0;
+    }
+    const size_t n = pool_size(bytes);
+    hipError_t e = hipMallocAsync(&a.first, n, st);
+    if (e != hipSuccess) return e;
+    a.second = n;
+  }
+  *out = a.first;
+  return hipSuccess;
+}
+
+static chimera_status run_chunk(chimera_ctx* ctx, const chimera_events* ev, const double* lam,
                                 int64_t B, int32_t prec, double* lnl, double* lnI, double* ln_xi,
                                 double* n_eff, int32_t mem, void* hip_stream) {
   hipStream_t st = (hipStream_t)hip_stream;
@@ -517,11 +562,11 @@ static chimera_status run_batch(chimera_ctx* ctx, const chimera_events* ev, cons
   const int U_ev = ev ? ev->U : 0;
   const size_t bytes = carve(probe, s, g, B, E, nchunk, host, need_lnI, ev != nullptr, host,
                              S_ev, U_ev, f32);
-  if (ctx->cfg.hbm_budget && bytes > ctx->cfg.hbm_budget)
+  if (ctx->cfg.hbm_budget && pool_size(bytes) > ctx->cfg.hbm_budget)
     return fail(CHIMERA_ENOMEM, "call needs " + std::to_string(bytes) +
                                     " scratch bytes, over the context's hbm_budget");
   void* base = nullptr;
-  HIP_TRY(hipMallocAsync(&base, bytes, st));
+  HIP_TRY(stream_scratch(ctx, st, bytes, &base));
   Carve cv;
   cv.base = (char*)base;
   carve(cv, s, g, B, E, nchunk, host, need_lnI, ev != nullptr, host, S_ev, U_ev, f32);
@@ -588,8 +633,23 @@ static chimera_status run_batch(chimera_ctx* ctx, const chimera_events* ev, cons
     if (n_eff)
       HIP_TRY(hipMemcpyAsync(n_eff, neff_dev, B * sizeof(double), hipMemcpyDeviceToHost, st));
   }
-  HIP_TRY(hipFreeAsync(base, st));
   if (host) HIP_TRY(hipStreamSynchronize(st));
+  return CHIMERA_OK;
+}
+
+static chimera_status run_batch(chimera_ctx* ctx, const chimera_events* ev, const double* lam,
+                                int64_t B, int32_t prec, double* lnl, double* lnI, double* ln_xi,
+                                double* n_eff, int32_t mem, void* hip_stream) {
+  const int64_t Bc = lambda_chunk(ev, B, prec == CHIMERA_FP32);
+  const int64_t E = ev ? ev->E : 0;
+  for (int64_t c0 = 0; c0 < B; c0 += Bc) {
+    const int64_t n = std::min(Bc, B - c0);
+    chimera_status s =
+        run_chunk(ctx, ev, lam + c0 * CHIMERA_NLAM, n, prec, lnl ? lnl + c0 : nullptr,
+                  lnI ? lnI + c0 * E : nullptr, ln_xi ? ln_xi + c0 : nullptr,
+                  n_eff ? n_eff + c0 : nullptr, mem, hip_stream);
+    if (s != CHIMERA_OK) return s;
+  }
   return CHIMERA_OK;
 }
 
@@ -601,12 +661,14 @@ chimera_status chimera_scratch_bytes(chimera_ctx* ctx, const chimera_events* ev,
   if (mem != CHIMERA_HOST && mem != CHIMERA_DEVICE) return fail(CHIMERA_EINVAL, "bad mem");
   const bool host = mem == CHIMERA_HOST;
   const int E = ev ? ev->E : 0;
+  B = lambda_chunk(ev, B, prec == CHIMERA_FP32);
   double dmin = ev ? ev->dmin : 1.0, dmax = ev ? ev->dmax : 1.0;
   const Geometry g = make_geometry(ctx, dmin, dmax);
   Scratch s;
   Carve probe;
-  *bytes = carve(probe, s, g, B, E, selection_chunks(ctx->n_det), host, ev && host, ev != nullptr,
-                 host, ev ? ev->n_samp : 0, ev ? ev->U : 0, prec == CHIMERA_FP32);
+  *bytes = pool_size(carve(probe, s, g, B, E, selection_chunks(ctx->n_det), host, ev && host,
+                           ev != nullptr, host, ev ? ev->n_samp : 0, ev ? ev->U : 0,
+                           prec == CHIMERA_FP32));
   return CHIMERA_OK;
 }
 
@@ -677,11 +739,11 @@ static chimera_status run_grad(chimera_ctx* ctx, const chimera_events* ev, const
   Carve probe;
   lay(probe, a, sa, fa, &lam_d, &P, &chi, &inv, &dtab, &chio, &gz64, &gz32, &fm, &fr);
   const size_t bytes = probe.off;
-  if (ctx->cfg.hbm_budget && bytes > ctx->cfg.hbm_budget)
+  if (ctx->cfg.hbm_budget && pool_size(bytes) > ctx->cfg.hbm_budget)
     return fail(CHIMERA_ENOMEM, "call needs " + std::to_string(bytes) +
                                     " scratch bytes, over the context's hbm_budget");
   void* base = nullptr;
-  HIP_TRY(hipMallocAsync(&base, bytes, st));
+  HIP_TRY(stream_scratch(ctx, st, bytes, &base));
   Carve cv;
   cv.base = (char*)base;
   lay(cv, a, sa, fa, &lam_d, &P, &chi, &inv, &dtab, &chio, &gz64, &gz32, &fm, &fr);
@@ -714,7 +776,6 @@ static chimera_status run_grad(chimera_ctx* ctx, const chimera_events* ev, const
     HIP_TRY(hipMemcpyAsync(grad, fa.grad, (size_t)B * CHIMERA_NGRAD * sizeof(double),
                            hipMemcpyDeviceToHost, st));
   }
-  HIP_TRY(hipFreeAsync(base, st));
   if (host) HIP_TRY(hipStreamSynchronize(st));
   return CHIMERA_OK;
 }

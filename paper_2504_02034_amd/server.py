@@ -150,6 +150,13 @@ class Server:
                 "budget": self.budget,
             }
 
+    def reset_stats(self):
+        """Forget the statistics so far (e.g. after a warm-up request)."""
+        with self._mu:
+            self._lat, self._evals, self._launches, self._fused_requests = [], 0, 0, 0
+            self._peak_bytes, self._peak_inflight = self._in_use, self._inflight
+            self._t0, self._t_last = None, None
+
     def close(self):
         with self._cv:
             self._stop = True

@@ -70,6 +70,25 @@ def test_full_size_fp32_budget(full):
     assert dmax <= 1e-3
 
 
+def test_chunked_call_equals_its_parts(full):
+    """640 points in FP32 need more per-sample scratch than one launch sequence
+    takes (8 GiB), so the call runs in chunks; each point's ln L equals the
+    one from calls over the two halves."""
+    d, chimera, ctx, es = full
+    lam = np.concatenate([d.lam, d.lam[::-1], d.lam[:128]])
+    assert lam.shape[0] == 640
+    one = ctx.scratch_bytes(es, 640, chimera.CHIMERA_FP32)
+    assert one < 640 * es_samples(d) * 12          # one chunk's scratch, not the whole call's
+    whole = ctx.lnl(es, lam, chimera.CHIMERA_FP32)
+    parts = np.concatenate([ctx.lnl(es, lam[:320], chimera.CHIMERA_FP32),
+                            ctx.lnl(es, lam[320:], chimera.CHIMERA_FP32)])
+    assert np.array_equal(whole, parts, equal_nan=True)
+
+
+def es_samples(d):
+    return int(d.prep.dl.size)
+
+
 @pytest.fixture(scope="module")
 def medium():
     from tests.datasets import build
