@@ -75,6 +75,27 @@ def time_precision(ctx, es, lam_t, prec, steps, warmup):
     return out.cpu().numpy(), wall, lat, n, ms, evals
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_event_kernels_precision_300ev.json")
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` from the committed counter summary, or
+    None when the summary is absent, for another workload, or taken on sources
+    that differ from the ones built now."""
+    import hashlib
+    if workload != "precision_300ev" or not os.path.exists(TRAFFIC_FILE):
+        return None
+    with open(TRAFFIC_FILE) as f:
+        t = json.load(f)
+    h = hashlib.sha256()
+    for src in t["sources"]:
+        with open(os.path.join(ROOT, src), "rb") as f:
+            h.update(f.read())
+    if h.hexdigest() != t["sources_sha256"] or kernel not in t["kernels"]:
+        return None
+    return t["kernels"][kernel]["traffic_bytes"]
+
+
 def pct(v, q):
     k = min(len(v) - 1, max(0, int(math.ceil(q / 100.0 * len(v))) - 1))
     return v[k]
@@ -219,6 +240,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-grad", action="store_true")
+    ap.add_argument("--traffic-probe", action="store_true",
+                    help="first copy 1 GiB device to device (a kernel of known traffic "
+                         "for calibrating the FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: this build runs on a single MI355X and has no "
@@ -230,6 +254,12 @@ def main():
 
     from paper_2504_02034_amd import chimera
 
+    if args.traffic_probe:
+        a = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     wl, cf, ev, inj, p, lam = build_inputs(args.workload, args.batch)
     B = lam.shape[0]
     ctx, es = chimera.context_from_prepared(p, inj, device=0, n_tab=8192)
@@ -254,7 +284,8 @@ def main():
         r = res[name]
         return {"bound": "alu", "achieved": round(r["achieved"], 3), "peak": PEAK_TFLOPS[name],
                 "unit": "TFLOP/s", "frac": round(r["achieved"] / PEAK_TFLOPS[name], 4),
-                "traffic": None, "kernel": "k_event_smooth" + name[2:],
+                "traffic": measured_traffic("chimera::k_event_smooth" + name[2:], wl.name),
+                "kernel": "k_event_smooth" + name[2:],
                 "kernel_ms": round(r["avg_ms"], 4), "evals_per_launch": int(r["evals"])}
 
     k = args.steps
