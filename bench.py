@@ -229,6 +229,57 @@ def serve_bench(ctx, p, n_requests=300, seed=5):
     }
 
 
+def photo_bench(xi0_truths=(1.0,), steps=3):
+    """The photometric stress workload: 1000 events x 4096 samples, 1e7 photo-z
+    galaxies (catalogue density built on the device), 2000-point grid to
+    z = 2.4, 5e6 injections, B = 128; one event set and catalogue per Xi0 truth."""
+    import numpy as np
+    import torch
+
+    from paper_2504_02034_amd import chimera, prep, synth
+    out = []
+    for k, xt in enumerate(xi0_truths):
+        # Xi0 = 1 is the photo_1000ev workload itself; the other truths get seeds of their own
+        seed = {1.0: 2, 0.6: 3, 1.8: 4}.get(xt, 5 + k)
+        wl = synth.WORKLOADS["photo_1000ev"].scaled(xi0_truth=xt, seed_index=seed)
+        cf = synth.make_catalog(wl)
+        ev = synth.make_events(wl, cf)
+        inj = synth.make_injections(wl)
+        p = prep.prepare(cf[0], ev, wl.n_z, wl.z_lo, wl.z_hi, cred=wl.cred, with_catalog=False)
+        gal = prep.galaxy_arrays(cf[0], wl.n_z, wl.z_lo, wl.z_hi)
+        ctx = chimera.Context(n_z=wl.n_z, z_lo=wl.z_lo, z_hi=wl.z_hi)
+        t = time.perf_counter()
+        ctx.set_catalog_galaxies(*gal, p.row_pix)
+        t_cat = time.perf_counter() - t
+        ctx.set_injections(inj.dl, inj.m1d, inj.m2d, inj.ln_pdraw, inj.n_total)
+        es = ctx.add_prepared(p)
+        lam = torch.from_numpy(synth.make_lambdas(wl)).cuda()
+        r = {"xi0_truth": xt, "samples": int(p.dl.size), "catalogue_rows": int(len(p.row_pix)),
+             "catalogue_build_ms": round(t_cat * 1e3, 1)}
+        vals = {}
+        for name, prec in (("fp64", chimera.CHIMERA_FP64), ("fp32", chimera.CHIMERA_FP32)):
+            ctx.lnl(es, lam, prec)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            for _ in range(steps):
+                v = ctx.lnl(es, lam, prec)
+            torch.cuda.synchronize()
+            sec = (time.perf_counter() - t) / steps
+            vals[name] = v.cpu().numpy()
+            r[name] = {"ms_per_step": round(sec * 1e3, 3), "evals_per_s": round(lam.shape[0] / sec, 1)}
+        fin = np.isfinite(vals["fp64"]) & np.isfinite(vals["fp32"])
+        r["abs_dlnL_fp32_vs_fp64"] = {
+            "max": float(np.max(np.abs(vals["fp32"][fin] - vals["fp64"][fin]))) if fin.any() else None,
+            "same_finite_mask": bool(np.array_equal(np.isfinite(vals["fp32"]), np.isfinite(vals["fp64"]))),
+            "finite_points": int(fin.sum())}
+        out.append(r)
+        ctx.close()
+        log(f"photo-z Xi0={xt}: fp64 {r['fp64']['ms_per_step']} ms, fp32 {r['fp32']['ms_per_step']} ms "
+            f"per {lam.shape[0]} lambda; catalogue built in {r['catalogue_build_ms']} ms")
+    return {"workload": "photo_1000ev", "events": 1000, "samples_per_event": 4096,
+            "galaxies": 10_000_000, "n_z": 2000, "injections": 5_000_000, "batch": 128, "sets": out}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -240,6 +291,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-grad", action="store_true")
+    ap.add_argument("--no-photo", action="store_true")
+    ap.add_argument("--photo-all", action="store_true",
+                    help="the photometric workload for the three Xi0 truths 0.6, 1.0, 1.8")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="first copy 1 GiB device to device (a kernel of known traffic "
                          "for calibrating the FETCH_SIZE / WRITE_SIZE counters)")
@@ -327,6 +381,9 @@ def main():
         log("serving trace")
         line["serving"] = serve_bench(ctx, p)
     ctx.close()
+    if not args.no_photo:
+        log("photometric workload")
+        line["photometric"] = photo_bench((0.6, 1.0, 1.8) if args.photo_all else (1.0,))
     if not args.no_cpu_baseline:
         log("timing the CPU oracle (cpu_baseline)")
         line["cpu_baseline"] = cpu_baseline(wl, cf, ev, inj, lam[0], args.cpu_events)

@@ -112,6 +112,32 @@ const char* chimera_last_error(void);
 chimera_status chimera_set_catalog(chimera_ctx* ctx, int64_t n_rows, const double* nz,
                                    const double* nz_tot);
 
+/* The catalogue density built on the device from the galaxies (the same
+ * quantity as chimera_set_catalog's rows, eq. like-integrals' p_cat on the
+ * grid): each galaxy's N(z; z_obs, sigma_z) truncated to 8 sigma_z is
+ * projected on the grid's hat basis (half hats at the ends), weighted by
+ * vshape[k] (the comoving volume element shape at node k) and normalised to
+ * sum_k tau_k q_k = 1; then, over the n_used galaxies whose projection is not
+ * zero, n_r(z_k) = sum_{gal in pixel} q_k / (n_used pixel_area) for the
+ * pixels rows_pix[n_rows] (row r of the catalogue is pixel rows_pix[r]) and
+ * n_tot(z_k) = sum_{all galaxies} q_k / n_used.
+ *   gal_pix_off[n_pix+1]   galaxies of pixel p are [gal_pix_off[p], gal_pix_off[p+1])
+ *   z_obs, sigma_z[n_gal]  sorted by pixel; sigma_z = 0 drops a galaxy
+ *   vshape[n_z]            >= 0
+ * Host arrays; synchronous.  Replaces any previous catalogue.  n_used may be
+ * NULL.  Returns EINVAL on malformed input, ERANGE when a row names a pixel
+ * past n_pix, ENOMEM when the device cannot hold n_pix x n_z doubles. */
+chimera_status chimera_set_catalog_galaxies(chimera_ctx* ctx, int64_t n_pix, int64_t n_gal,
+                                            const int64_t* gal_pix_off, const double* z_obs,
+                                            const double* sigma_z, const double* vshape,
+                                            double pixel_area, int64_t n_rows,
+                                            const int64_t* rows_pix, int64_t* n_used);
+
+/* Copy the resident catalogue to the host: nz[n_rows][n_z] (FP64) and
+ * nz_tot[n_z]; either may be NULL.  Synchronous.  ESTATE before a catalogue
+ * is set. */
+chimera_status chimera_get_catalog(chimera_ctx* ctx, double* nz, double* nz_tot);
+
 /* Detected injections (Sect. 2.2): n_det draws with d_L, detector-frame
  * masses and ln p_draw (the draw density in (d_L, m1_det, m2_det)), out of
  * n_inj_total draws in all.  Distances must be > 0.  Replaces any previous set. */

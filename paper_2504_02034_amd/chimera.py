@@ -26,7 +26,9 @@ _STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ERANGE", -5:
 
 #: every symbol include/chimera.h declares
 EXPORTS = ("chimera_default_config", "chimera_create", "chimera_destroy", "chimera_last_error",
-           "chimera_set_catalog", "chimera_set_injections", "chimera_add_events",
+           "chimera_set_catalog", "chimera_set_catalog_galaxies", "chimera_get_catalog",
+           "chimera_set_injections",
+           "chimera_add_events",
            "chimera_release_events", "chimera_lnl_batch", "chimera_selection_xi",
            "chimera_lnl_grad", "chimera_scratch_bytes", "chimera_profile_enable",
            "chimera_profile_read")
@@ -69,6 +71,10 @@ def _load():
         "chimera_last_error": (ctypes.c_char_p, []),
         "chimera_set_catalog": (ctypes.c_int, [_P, _I64, _P, _P]),
         "chimera_set_injections": (ctypes.c_int, [_P, _I64, _I64, _P, _P, _P, _P]),
+        "chimera_get_catalog": (ctypes.c_int, [_P, _P, _P]),
+        "chimera_set_catalog_galaxies": (ctypes.c_int, [_P, _I64, _I64, _P, _P, _P, _P,
+                                                        ctypes.c_double, _I64, _P,
+                                                        ctypes.POINTER(_I64)]),
         "chimera_add_events": (ctypes.c_int, [_P, _I32, _P, _P, _P, _P, _P, _P, _P,
                                               ctypes.POINTER(_P)]),
         "chimera_release_events": (ctypes.c_int, [_P, _P]),
@@ -129,6 +135,27 @@ def chimera_set_catalog(h, nz, nz_tot):
     nz, pnz = _host(nz, np.float64)
     nt, pnt = _host(nz_tot, np.float64)
     _check(lib.chimera_set_catalog(h, nz.shape[0] if nz.ndim == 2 else 0, pnz, pnt))
+
+
+def chimera_set_catalog_galaxies(h, gal_pix_off, z_obs, sigma_z, vshape, pixel_area, rows_pix):
+    """Device-built catalogue rows; returns the number of galaxies used."""
+    o, po = _host(gal_pix_off, np.int64)
+    z, pz = _host(z_obs, np.float64)
+    sg, ps = _host(sigma_z, np.float64)
+    v, pv = _host(vshape, np.float64)
+    r, pr = _host(rows_pix, np.int64)
+    used = _I64()
+    _check(lib.chimera_set_catalog_galaxies(h, o.size - 1, z.size, po, pz, ps, pv,
+                                            float(pixel_area), r.size, pr, ctypes.byref(used)))
+    return used.value
+
+
+def chimera_get_catalog(h, n_rows, n_z):
+    """(nz [n_rows, n_z], nz_tot [n_z]) copied from the device."""
+    nz = np.empty((n_rows, n_z))
+    nt = np.empty(n_z)
+    _check(lib.chimera_get_catalog(h, nz.ctypes.data_as(_P), nt.ctypes.data_as(_P)))
+    return nz, nt
 
 
 def chimera_set_injections(h, dl, m1d, m2d, ln_pdraw, n_inj_total):
@@ -276,6 +303,13 @@ class Context:
 
     def set_catalog(self, nz, nz_tot):
         chimera_set_catalog(self.handle, nz, nz_tot)
+
+    def set_catalog_galaxies(self, gal_pix_off, z_obs, sigma_z, vshape, pixel_area, rows_pix):
+        return chimera_set_catalog_galaxies(self.handle, gal_pix_off, z_obs, sigma_z, vshape,
+                                            pixel_area, rows_pix)
+
+    def get_catalog(self, n_rows):
+        return chimera_get_catalog(self.handle, n_rows, self.cfg.n_z)
 
     def set_injections(self, dl, m1d, m2d, ln_pdraw, n_inj_total):
         chimera_set_injections(self.handle, dl, m1d, m2d, ln_pdraw, n_inj_total)

@@ -307,6 +307,104 @@ chimera_status chimera_set_catalog(chimera_ctx* ctx, int64_t n_rows, const doubl
   return CHIMERA_OK;
 }
 
+chimera_status chimera_set_catalog_galaxies(chimera_ctx* ctx, int64_t n_pix, int64_t n_gal,
+                                            const int64_t* gal_pix_off, const double* z_obs,
+                                            const double* sigma_z, const double* vshape,
+                                            double pixel_area, int64_t n_rows,
+                                            const int64_t* rows_pix, int64_t* n_used) {
+  if (!ctx || !gal_pix_off || !vshape || (n_gal > 0 && (!z_obs || !sigma_z)) ||
+      (n_rows > 0 && !rows_pix))
+    return fail(CHIMERA_EINVAL, "null argument");
+  if (n_pix < 1 || n_gal < 0 || n_rows < 0) return fail(CHIMERA_EINVAL, "bad sizes");
+  if (!(std::isfinite(pixel_area) && pixel_area > 0.0))
+    return fail(CHIMERA_EINVAL, "pixel_area must be finite and > 0");
+  if (gal_pix_off[0] != 0 || gal_pix_off[n_pix] != n_gal)
+    return fail(CHIMERA_EINVAL, "gal_pix_off must run from 0 to n_gal");
+  for (int64_t p = 0; p < n_pix; ++p)
+    if (gal_pix_off[p + 1] < gal_pix_off[p])
+      return fail(CHIMERA_EINVAL, "gal_pix_off must be non-decreasing");
+  for (int64_t i = 0; i < n_gal; ++i)
+    if (!std::isfinite(z_obs[i]) || !(std::isfinite(sigma_z[i]) && sigma_z[i] >= 0.0))
+      return fail(CHIMERA_EINVAL, "z_obs must be finite and sigma_z finite, >= 0");
+  const int nzn = ctx->cfg.n_z;
+  for (int k = 0; k < nzn; ++k)
+    if (!(std::isfinite(vshape[k]) && vshape[k] >= 0.0))
+      return fail(CHIMERA_EINVAL, "vshape must be finite, >= 0");
+  for (int64_t r = 0; r < n_rows; ++r)
+    if (rows_pix[r] < 0 || rows_pix[r] >= n_pix)
+      return fail(CHIMERA_ERANGE, "rows_pix refers past the pixels");
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  HIP_TRY(hipSetDevice(ctx->cfg.device));
+  HIP_TRY(hipDeviceSynchronize());
+  CatalogArgs c{};
+  c.g.n_z = nzn;
+  c.g.z_lo = ctx->cfg.z_lo;
+  c.g.z_hi = ctx->cfg.z_hi;
+  c.g.dz = (ctx->cfg.z_hi - ctx->cfg.z_lo) / (double)(nzn - 1);
+  c.n_gal = n_gal;
+  c.n_pix = n_pix;
+  c.n_rows = n_rows;
+  c.pixel_area = pixel_area;
+  long long *off = nullptr, *rp = nullptr;
+  double *mu = nullptr, *sig = nullptr, *vs = nullptr, *norm = nullptr, *rows_all = nullptr;
+  double *nz64 = nullptr, *ntot = nullptr;
+  float* nz32 = nullptr;
+  auto cleanup = [&]() {
+    dfree(off); dfree(rp); dfree(mu); dfree(sig); dfree(vs); dfree(norm); dfree(rows_all);
+  };
+  hipError_t e = hipSuccess;
+  static_assert(sizeof(long long) == sizeof(int64_t), "int64 layout");
+  if (e == hipSuccess) e = upload(&off, (const long long*)gal_pix_off, (size_t)n_pix + 1);
+  if (e == hipSuccess && n_rows) e = upload(&rp, (const long long*)rows_pix, (size_t)n_rows);
+  if (e == hipSuccess && n_gal) e = upload(&mu, z_obs, (size_t)n_gal);
+  if (e == hipSuccess && n_gal) e = upload(&sig, sigma_z, (size_t)n_gal);
+  if (e == hipSuccess) e = upload(&vs, vshape, (size_t)nzn);
+  if (e == hipSuccess && n_gal) e = hipMalloc((void**)&norm, (size_t)n_gal * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc((void**)&rows_all, (size_t)n_pix * nzn * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc((void**)&nz64, std::max<size_t>(1, (size_t)n_rows * nzn) * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc((void**)&nz32, std::max<size_t>(1, (size_t)n_rows * nzn) * sizeof(float));
+  if (e == hipSuccess) e = hipMalloc((void**)&ntot, (size_t)nzn * sizeof(double));
+  c.off = off; c.mu = mu; c.sig = sig; c.norm = norm; c.vshape = vs; c.rows_all = rows_all;
+  c.rows_pix = rp; c.ntot = ntot; c.nz64 = nz64; c.nz32 = nz32;
+  if (e == hipSuccess) e = launch_catalog(c, nullptr);
+  int64_t used = 0;
+  if (e == hipSuccess && n_gal) {
+    std::vector<double> h((size_t)n_gal);
+    e = hipMemcpy(h.data(), norm, (size_t)n_gal * sizeof(double), hipMemcpyDeviceToHost);
+    for (double v : h) used += v > 0.0;
+  }
+  if (e == hipSuccess) e = launch_catalog_finish(c, used, nullptr);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  cleanup();
+  if (e != hipSuccess) {
+    dfree(nz64); dfree(nz32); dfree(ntot);
+    return fail(e == hipErrorOutOfMemory ? CHIMERA_ENOMEM : CHIMERA_EDEVICE,
+                std::string("building the catalogue: ") + hipGetErrorString(e));
+  }
+  free_catalog(ctx);
+  ctx->nz64 = nz64;
+  ctx->nz32 = nz32;
+  ctx->ntot = ntot;
+  ctx->n_rows = n_rows;
+  ctx->has_cat = true;
+  if (n_used) *n_used = used;
+  return CHIMERA_OK;
+}
+
+chimera_status chimera_get_catalog(chimera_ctx* ctx, double* nz, double* nz_tot) {
+  if (!ctx) return fail(CHIMERA_EINVAL, "null context");
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  if (!ctx->has_cat) return fail(CHIMERA_ESTATE, "no catalogue set");
+  HIP_TRY(hipSetDevice(ctx->cfg.device));
+  HIP_TRY(hipDeviceSynchronize());
+  const size_t nzn = (size_t)ctx->cfg.n_z;
+  if (nz && ctx->n_rows)
+    HIP_TRY(hipMemcpy(nz, ctx->nz64, (size_t)ctx->n_rows * nzn * sizeof(double),
+                      hipMemcpyDeviceToHost));
+  if (nz_tot) HIP_TRY(hipMemcpy(nz_tot, ctx->ntot, nzn * sizeof(double), hipMemcpyDeviceToHost));
+  return CHIMERA_OK;
+}
+
 chimera_status chimera_set_injections(chimera_ctx* ctx, int64_t n_det, int64_t n_inj_total,
                                       const double* dl, const double* m1d, const double* m2d,
                                       const double* ln_pdraw) {

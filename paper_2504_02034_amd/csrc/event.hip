@@ -277,11 +277,14 @@ __device__ __forceinline__ void event_smooth(const EventArgs& a) {
       if (klo[k] <= khi[k]) npts += (double)(khi[k] - klo[k] + 1);
   }
 
-  // G_m = exp(-m^2 dz^2 / 2h^2), m in [-M, M], in LDS after the F slice
-  const int f_elems = sm_fbytes(F32) / (int)sizeof(CT);
-  CT* Gt = (CT*)(smem + sm_fbytes(F32));
+  // G_m = exp(-m^2 dz^2 / 2h^2), m in [-M, M], and the F slice share the
+  // workgroup's LDS: G takes its 2M + 1 entries at the end, the slice the
+  // rest, as long as every pixel row of the event keeps two slots
+  const int total_elems = (sm_fbytes(F32) + kSmGCap * (int)sizeof(CT)) / (int)sizeof(CT);
   const int gcount = 2 * M + 1;
-  const bool gtab = gcount <= kSmGCap;
+  const int f_elems = total_elems - gcount;
+  const bool gtab = gcount >= 1 && f_elems >= 2 * (np > 0 ? np : 1);
+  CT* Gt = (CT*)smem + (gtab ? f_elems : 0);
   if (gtab) {
     for (int q = threadIdx.x; q < gcount; q += BS) {
       const double x = (double)(q - M) * dz;
@@ -294,7 +297,7 @@ __device__ __forceinline__ void event_smooth(const EventArgs& a) {
   // otherwise a power of two W < 64 and 64 / W rows per wave instruction.
   int L, lgW;
   {
-    const int cap = f_elems / (np > 0 ? np : 1) - 1;   // >= 1: pixel rows are bounded
+    const int cap = max(f_elems / (np > 0 ? np : 1) - 1, 1);   // >= 1 whenever gtab
     if (cap >= 64) {
       L = cap & ~63;
       lgW = 6;

@@ -213,4 +213,32 @@ hipError_t launch_grad(const GradArgs& a, const SelGradArgs& sa, GradFinalArgs f
                        hipStream_t st);
 int selection_grad_chunks(long long n_det);
 
+// ---------------------------------------------------------------------------
+// catalogue density (catalog.hip)
+// ---------------------------------------------------------------------------
+struct CatalogGrid {
+  int n_z;
+  double z_lo, z_hi, dz;
+};
+
+struct CatalogArgs {
+  const long long* off;     // [n_pix+1] galaxies of pixel p: [off[p], off[p+1])
+  const double* mu;         // [n_gal] observed redshift, sorted by pixel
+  const double* sig;        // [n_gal] redshift uncertainty
+  double* norm;             // [n_gal] sum_k J_k V_k (written)
+  CatalogGrid g;
+  const double* vshape;     // [n_z] comoving volume element shape V_k
+  long long n_gal, n_pix;
+  double* rows_all;         // [n_pix][n_z] (written)
+  const long long* rows_pix;// [n_rows] pixel of each catalogue row
+  long long n_rows;
+  double pixel_area;
+  double* ntot;             // [n_z]
+  double* nz64;             // [n_rows][n_z]
+  float* nz32;
+};
+
+hipError_t launch_catalog(const CatalogArgs& c, hipStream_t st);
+hipError_t launch_catalog_finish(const CatalogArgs& c, long long n_used, hipStream_t st);
+
 }  // namespace chimera

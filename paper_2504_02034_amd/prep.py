@@ -189,8 +189,10 @@ def _sky_factors(theta, phi, centres_theta, centres_phi, area):
 
 
 def prepare(cat: synth.Catalog, ev: synth.Events, n_z: int, z_lo: float, z_hi: float,
-            cred: float = 0.9) -> Prepared:
-    """Build the C-ABI arrays for one event set against one catalogue."""
+            cred: float = 0.9, with_catalog: bool = True) -> Prepared:
+    """Build the C-ABI arrays for one event set against one catalogue.  With
+    with_catalog=False the catalogue rows are left to the device builder
+    (nz and nz_tot are None; see galaxy_arrays)."""
     area = synth.pixel_area(ev.nside)
     ev_pix_off = [0]
     samp_off = [0]
@@ -218,7 +220,9 @@ def prepare(cat: synth.Catalog, ev: synth.Events, n_z: int, z_lo: float, z_hi: f
     pix_id = np.asarray(pix_id, dtype=np.int64)
     rows_pix = np.unique(pix_id)
     pix_row = np.searchsorted(rows_pix, pix_id).astype(np.int64)
-    nz, nz_tot, _ = catalog_density(cat, n_z, z_lo, z_hi, rows_pix)
+    nz, nz_tot = None, None
+    if with_catalog:
+        nz, nz_tot, _ = catalog_density(cat, n_z, z_lo, z_hi, rows_pix)
     return Prepared(n_z=n_z, z_lo=z_lo, z_hi=z_hi, nz=nz, row_pix=rows_pix, nz_tot=nz_tot,
                     ev_pix_off=np.asarray(ev_pix_off, dtype=np.int64),
                     pix_samp_off=np.asarray(samp_off, dtype=np.int64),
@@ -244,3 +248,18 @@ def subset(p: Prepared, events) -> Prepared:
                     np.asarray(rows, np.int64), np.asarray(ids, np.int64),
                     np.asarray(cs, np.float64), np.concatenate(dls), np.concatenate(m1s),
                     np.concatenate(m2s))
+
+
+def galaxy_arrays(cat: synth.Catalog, n_z: int, z_lo: float, z_hi: float):
+    """Inputs of the device catalogue builder (chimera_set_catalog_galaxies):
+    galaxies sorted by pixel with their pixel offsets, sigma_z = sigma0 (1 + z_obs),
+    the comoving volume shape on the grid and the pixel area."""
+    npix = synth.nside_npix(cat.nside)
+    order = np.argsort(cat.pix, kind="stable")
+    pix = cat.pix[order]
+    off = np.searchsorted(pix, np.arange(npix + 1)).astype(np.int64)
+    z = np.ascontiguousarray(cat.z_obs[order], dtype=np.float64)
+    sig = cat.sigma_z0 * (1.0 + z)
+    grid = z_lo + (z_hi - z_lo) / (n_z - 1) * np.arange(n_z)
+    return off, z, sig, _comoving_shape(grid), synth.pixel_area(cat.nside)
+

@@ -92,3 +92,23 @@ def handcrafted_oracle(h):
                     n_tot=h["nz_tot"])
     inj = L.InjectionSet(h["idl"], h["im1"], h["im2"], h["lnp"], h["ninj"])
     return events, cat, inj
+
+
+def oracle_from_prepared(p, nz, nz_tot, inj, events=None):
+    """Oracle structures over prepared arrays and a catalogue given as rows (the
+    preprocessing output is data shared by both sides)."""
+    import oracle
+    L = oracle.likelihood
+    grid = p.z_lo + (p.z_hi - p.z_lo) / (p.n_z - 1) * np.arange(p.n_z)
+    out = []
+    for e in (range(p.n_events) if events is None else events):
+        ev = L.Event()
+        for q in range(p.ev_pix_off[e], p.ev_pix_off[e + 1]):
+            sl = slice(p.pix_samp_off[q], p.pix_samp_off[q + 1])
+            ev.pixels.append(L.Pixel(pix=int(p.pix_row[q]), c=float(p.c_ir[q]), dl=p.dl[sl],
+                                     m1d=p.m1d[sl], m2d=p.m2d[sl]))
+        out.append(ev)
+    rows = sorted({px.pix for ev in out for px in ev.pixels})
+    cat = L.Catalog(grid=grid, rows={r: nz[r] for r in rows}, n_tot=nz_tot)
+    o_inj = L.InjectionSet(inj.dl, inj.m1d, inj.m2d, inj.ln_pdraw, inj.n_total)
+    return out, cat, o_inj
