@@ -17,10 +17,14 @@
 // k_lam_grad_prepare  per-lambda normaliser derivatives of the mass model
 // k_grid_grad         g(z_g) d ln g / dp on the grid for p = Om, Xi0, n,
 //                     gamma, kappa, z_p (H0 enters g as a factor H0)
-// k_event_grad        one (event, lambda) per workgroup: pass 1 moments and
-//                     their derivatives -> h, d ln h/dp; pass 2 one sample per
-//                     thread, its window by the Gaussian ratio recurrence
-//                     K_(g+1) = K_g r_g, r_(g+1) = r_g exp(-dz^2/h^2)
+// k_event_bandwidth_grad  one (event, lambda) per workgroup: each sample's
+//                     z, w and their derivatives (stored, structure of
+//                     arrays), the bandwidth moments and their derivatives
+//                     -> h, d ln h/dp
+// k_event_grad        one (event, lambda) per workgroup, one sample per
+//                     thread, from the stored coefficients: its window by the
+//                     Gaussian ratio recurrence K_(g+1) = K_g r_g,
+//                     r_(g+1) = r_g exp(-dz^2/h^2)
 // k_selection_grad    per (injection chunk, lambda) partial sums
 // k_grad_final        ln L and d ln L / dp per lambda, fixed order
 #include <math.h>
@@ -36,6 +40,8 @@ namespace {
 constexpr int kNG = CHIMERA_NGRAD;   // 12
 constexpr int kNS = 9;               // parameters a sample depends on: H0, Om, Xi0, n, mass (5)
 constexpr int kGradBS = 256;
+constexpr int kSC = kGradSampleFields;
+static_assert(kSC == 2 + kNS + 4, "per-sample coefficient layout");
 
 __device__ __forceinline__ double phi_std(double t) {
   return 0.39894228040143267794 * exp(-0.5 * t * t);
@@ -210,21 +216,21 @@ __global__ void k_grid_grad(const LamParams* __restrict__ Pv, const double2* __r
 }
 
 // ---------------------------------------------------------------------------
-template <bool F32>
-__global__ __launch_bounds__(kGradBS) void k_event_grad(GradArgs a) {
+// Bandwidth and its derivatives, one (event, lambda) per workgroup: W1, W2,
+// M1 = sum w (z - s), M2 = sum w (z - s)^2 (s: the event's first redshift)
+// and their derivatives for the parameters a sample depends on.  Writes
+// hd[b][e] = (h, d ln h / dp for those 9 parameters), h < 0 marking W1 = 0,
+// and every sample's coefficients sc[b][field][sample]: z, c w (0: no
+// weight), d ln w / dp (9), dz / dp (4 distance parameters).
+__global__ __launch_bounds__(kGradBS) void k_event_bandwidth_grad(GradArgs a) {
   int e, b;
   if (!decode_item_lambda(a.E, a.B, e, b)) return;
-  using CT = typename std::conditional<F32, float, double>::type;
   constexpr int NW = kGradBS / 64 + 1;
   __shared__ double red[40 * NW];
   __shared__ double shift;
   const LamParams P = a.P[b];
-  double* lnI = a.lnI + (size_t)b * a.E + e;
-  double* dlnI = a.dlnI + ((size_t)b * a.E + e) * kNG;
-  if (P.flag | a.flag_mono[b] | a.flag_range[b]) {
-    if (threadIdx.x == 0) *lnI = NAN;                 // the final kernel reports the flag
-    return;
-  }
+  double* hd = a.hd + ((size_t)b * a.E + e) * (1 + kNS);
+  if (P.flag | a.flag_mono[b] | a.flag_range[b]) return;   // the final kernel reports it
   const GradParams Q = a.Q[b];
   const double2* chi = a.chi + (size_t)b * a.g.n_t;
   const double2* chio = a.chio + (size_t)b * a.g.n_t;
@@ -241,7 +247,6 @@ __global__ __launch_bounds__(kGradBS) void k_event_grad(GradArgs a) {
   }
   __syncthreads();
   const double zs = shift;
-  // ---- pass 1: W1, W2, M1 = sum w (z - zs), M2 = sum w (z - zs)^2 and derivatives
   double m[40];
 #pragma unroll
   for (int i = 0; i < 40; ++i) m[i] = 0.0;
@@ -250,6 +255,13 @@ __global__ __launch_bounds__(kGradBS) void k_event_grad(GradArgs a) {
     sample_grad(P, Q, chi, chio, dtab, inv, a.g, a.dl[q], a.lndl[q], a.m1d[q], a.m2d[q],
                 a.lnm1d[q], a.lnm2d[q], sg, dp);
     const double w = sg.w;
+    double* sc = a.sc + (size_t)b * kSC * a.S + q;
+    sc[0] = sg.zp1 - 1.0;
+    sc[a.S] = w > 0.0 ? a.samp_c[q] * w : 0.0;
+#pragma unroll
+    for (int p = 0; p < kNS; ++p) sc[(size_t)(2 + p) * a.S] = sg.dlw[p];
+#pragma unroll
+    for (int p = 0; p < 4; ++p) sc[(size_t)(2 + kNS + p) * a.S] = sg.zp1 * sg.dx[p];
     if (!(w > 0.0)) continue;
     const double t = sg.zp1 - 1.0 - zs;
     m[0] += w;
@@ -267,12 +279,10 @@ __global__ __launch_bounds__(kGradBS) void k_event_grad(GradArgs a) {
     }
   }
   block_reduce<kGradBS, 40, false>(m, red);
+  if (threadIdx.x != 0) return;
   const double W1 = m[0], W2 = m[1], M1 = m[2], M2 = m[3];
   if (!(W1 > 0.0)) {
-    if (threadIdx.x == 0) {
-      *lnI = -INFINITY;
-      for (int p = 0; p < kNG; ++p) dlnI[p] = NAN;
-    }
+    hd[0] = -1.0;
     return;
   }
   const double mu = M1 / W1;
@@ -284,21 +294,49 @@ __global__ __launch_bounds__(kGradBS) void k_event_grad(GradArgs a) {
     var = V / den;
   }
   const double raw = sqrt(var) * pow(W1 * W1 / W2, -0.2);
-  const double h = fmax(raw, 2.0 * a.g.dz);
-  double dlnh[kNS];
+  hd[0] = fmax(raw, 2.0 * a.g.dz);
   const bool live = spread && V > 0.0 && raw >= 2.0 * a.g.dz;
-#pragma unroll
   for (int p = 0; p < kNS; ++p) {
-    dlnh[p] = 0.0;
+    double v = 0.0;
     if (live) {
       const double dW1 = m[4 + p], dW2 = m[4 + kNS + p];
       const double dM1 = m[4 + 2 * kNS + p], dM2 = m[4 + 3 * kNS + p];
       const double dV = dM2 - 2.0 * mu * dM1 + mu * mu * dW1;
       const double dden = dW1 - dW2 / W1 + W2 * dW1 / (W1 * W1);
-      dlnh[p] = 0.5 * dV / V - 0.5 * dden / den - 0.2 * (2.0 * dW1 / W1 - dW2 / W2);
+      v = 0.5 * dV / V - 0.5 * dden / den - 0.2 * (2.0 * dW1 / W1 - dW2 / W2);
     }
+    hd[1 + p] = v;
   }
-  // ---- pass 2: kernel sums per sample, one sample per thread
+}
+
+// Kernel sums and their parameter contractions, one (event, lambda) per
+// workgroup, one sample per thread, from the coefficients the bandwidth
+// kernel stored.
+template <bool F32>
+__global__ __launch_bounds__(kGradBS) void k_event_grad(GradArgs a) {
+  int e, b;
+  if (!decode_item_lambda(a.E, a.B, e, b)) return;
+  using CT = typename std::conditional<F32, float, double>::type;
+  constexpr int NW = kGradBS / 64 + 1;
+  __shared__ double red[(1 + kNG) * NW];
+  const LamParams P = a.P[b];
+  double* lnI = a.lnI + (size_t)b * a.E + e;
+  double* dlnI = a.dlnI + ((size_t)b * a.E + e) * kNG;
+  if (P.flag | a.flag_mono[b] | a.flag_range[b]) {
+    if (threadIdx.x == 0) *lnI = NAN;                 // the final kernel reports the flag
+    return;
+  }
+  const double* hd = a.hd + ((size_t)b * a.E + e) * (1 + kNS);
+  const double h = hd[0];
+  if (!(h > 0.0)) {
+    if (threadIdx.x == 0) {
+      *lnI = -INFINITY;
+      for (int p = 0; p < kNG; ++p) dlnI[p] = NAN;
+    }
+    return;
+  }
+  const int s0 = a.ev_samp_off[e];
+  const int ns = a.ev_samp_off[e + 1] - s0;
   const double dz = a.g.dz, inv_h2 = 1.0 / (h * h), T = a.trunc;
   const CT qr = (CT)exp(-dz * dz * inv_h2);
   const CT* nzt = F32 ? (const CT*)a.nz32 : (const CT*)a.nz64;
@@ -307,15 +345,15 @@ __global__ __launch_bounds__(kGradBS) void k_event_grad(GradArgs a) {
   const CT* gft = F32 ? (const CT*)(a.gf32 + (size_t)b * 6 * a.g.n_z)
                       : (const CT*)(a.gf64 + (size_t)b * 6 * a.g.n_z);
   const int nz = a.g.n_z;
+  const double* scb = a.sc + (size_t)b * kSC * a.S;
   double acc[1 + kNG];
 #pragma unroll
   for (int i = 0; i <= kNG; ++i) acc[i] = 0.0;
   for (int j = threadIdx.x; j < ns; j += kGradBS) {
     const int q = s0 + j;
-    sample_grad(P, Q, chi, chio, dtab, inv, a.g, a.dl[q], a.lndl[q], a.m1d[q], a.m2d[q],
-                a.lnm1d[q], a.lnm2d[q], sg, dp);
-    if (!(sg.w > 0.0)) continue;
-    const double z = sg.zp1 - 1.0;
+    const double cw = scb[a.S + q];
+    if (!(cw > 0.0)) continue;
+    const double z = scb[q];
     const double lo_d = fmax(ceil((z - T * h - a.g.z_lo) * a.g.inv_dz), 0.0);
     const double hi_d = fmin(floor((z + T * h - a.g.z_lo) * a.g.inv_dz), (double)(nz - 1));
     if (!(lo_d <= hi_d)) continue;
@@ -338,16 +376,17 @@ __global__ __launch_bounds__(kGradBS) void k_event_grad(GradArgs a) {
       K *= r;
       r *= qr;
     }
-    const double cw = a.samp_c[q] * sg.w;
-    const double A = (double)sA, Bz = (double)sB * inv_h2, Ch = (double)sC * inv_h2 / h;
+    const double A = (double)sA, Bz = (double)sB * inv_h2, Chh = (double)sC * inv_h2;
     acc[0] += cw * A;
     // distance parameters: weight, z-shift, bandwidth, grid factor (H0: g ~ H0)
     const double Eg[4] = {A / P.h0, (double)sE[0], (double)sE[1], (double)sE[2]};
 #pragma unroll
     for (int p = 0; p < 4; ++p)
-      acc[1 + p] += cw * (sg.dlw[p] * A + sg.zp1 * sg.dx[p] * Bz + Ch * h * dlnh[p] + Eg[p]);
+      acc[1 + p] += cw * (scb[(size_t)(2 + p) * a.S + q] * A +
+                          scb[(size_t)(2 + kNS + p) * a.S + q] * Bz + Chh * hd[1 + p] + Eg[p]);
 #pragma unroll
-    for (int p = 4; p < kNS; ++p) acc[1 + p] += cw * (sg.dlw[p] * A + Ch * h * dlnh[p]);
+    for (int p = 4; p < kNS; ++p)
+      acc[1 + p] += cw * (scb[(size_t)(2 + p) * a.S + q] * A + Chh * hd[1 + p]);
 #pragma unroll
     for (int p = 0; p < 3; ++p) acc[1 + kNS + p] += cw * (double)sE[3 + p];
   }
@@ -359,7 +398,7 @@ __global__ __launch_bounds__(kGradBS) void k_event_grad(GradArgs a) {
       for (int p = 0; p < kNG; ++p) dlnI[p] = NAN;
     } else {
       *lnI = log(S * kInvSqrt2Pi / h);
-      for (int p = 0; p < kNG; ++p) dlnI[p] = acc[1 + p] / S - (p < kNS ? dlnh[p] : 0.0);
+      for (int p = 0; p < kNG; ++p) dlnI[p] = acc[1 + p] / S - (p < kNS ? hd[1 + p] : 0.0);
     }
   }
 }
@@ -494,6 +533,8 @@ hipError_t launch_grad(const GradArgs& a, const SelGradArgs& sa, GradFinalArgs f
   }
   const long long nb = item_lambda_blocks(a.E, a.B);
   if (a.E > 0) {
+    k_event_bandwidth_grad<<<(unsigned)nb, kGradBS, 0, st>>>(a);
+    CH_LAUNCH_CHECK();
     if (f32) k_event_grad<true><<<(unsigned)nb, kGradBS, 0, st>>>(a);
     else k_event_grad<false><<<(unsigned)nb, kGradBS, 0, st>>>(a);
     CH_LAUNCH_CHECK();

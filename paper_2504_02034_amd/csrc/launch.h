@@ -68,6 +68,8 @@ constexpr int kSmFBytes64 = 44 * 1024;
 constexpr int kSmFBytes32 = 36 * 1024;
 constexpr int sm_fbytes(bool f32) { return f32 ? kSmFBytes32 : kSmFBytes64; }
 constexpr int kSmGCap = 512;             // entries of the G_m table
+// per-sample gradient coefficients: z, c w, d ln w / dp (9), dz / dp (4)
+constexpr int kGradSampleFields = 15;
 // every pixel row of an event needs a row of >= 2 slots in the F slice
 static_assert(CHIMERA_MAX_EVENT_PIXELS * 2 * (int)sizeof(double) <= kSmFBytes64, "F slice too small");
 static_assert(CHIMERA_MAX_EVENT_PIXELS * 2 * (int)sizeof(float) <= kSmFBytes32, "F slice too small");
@@ -165,6 +167,9 @@ struct GradArgs {
   const double* lnm2d;
   int E, B;
   double trunc;
+  double* hd;               // [B][E][10] h and d ln h/dp (written by the bandwidth kernel)
+  double* sc;               // [B][kGradSampleFields][S] per-sample coefficients (bandwidth kernel)
+  long long S;              // samples of the event set
   double* lnI;              // [B][E]
   double* dlnI;             // [B][E][12]
 };
