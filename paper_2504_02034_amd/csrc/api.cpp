@@ -480,6 +480,7 @@ chimera_status chimera_add_events(chimera_ctx* ctx, int32_t n_ev, const int64_t*
   // are then ordered by mean distance (the same order in redshift for every
   // lambda, since d_L^gw is increasing).
   const double kGroupSpread = 0.6;
+  const int kSpreadRun = 128;
   std::vector<int> ev_samp(n_ev + 1, 0), ev_slot(n_ev + 1), ev_unit(n_ev + 1, 0), srow(P);
   std::vector<int> u_event, u_grp0, u_ngrp;
   std::vector<int> gfirst, gcnt, gslot;
@@ -529,6 +530,18 @@ chimera_status chimera_add_events(chimera_ctx* ctx, int32_t n_ev, const int64_t*
       u_ngrp.push_back(z - a);
     }
     ev_unit[e + 1] = (int)u_event.size();
+    // within each unit, runs of kSpreadRun groups (neighbours in distance) are
+    // ordered by their distance spread, so that the groups a wave takes have
+    // edges of similar length
+    for (int r = 0; r < R; ++r) {
+      const int a = (int)((long long)ng * r / R), z = (int)((long long)ng * (r + 1) / R);
+      for (int b0 = a; b0 < z; b0 += kSpreadRun) {
+        const int b1 = std::min(b0 + kSpreadRun, z);
+        std::stable_sort(groups.begin() + b0, groups.begin() + b1, [&](const G& x, const G& y) {
+          return dl[x.idx.back()] - dl[x.idx.front()] < dl[y.idx.back()] - dl[y.idx.front()];
+        });
+      }
+    }
     for (auto& g : groups) {
       gfirst.push_back((int)odl.size());
       gcnt.push_back((int)g.idx.size());

@@ -66,11 +66,22 @@ __device__ __forceinline__ void horner_span(A (&acc)[K], const A (&rho)[K], cons
 // chain has passed its lower bound, so only g <= hi_k is tested (a chain that
 // has not entered its window is 0); below it every chain is inside its upper
 // bound, so only g >= lo_k is tested (a chain past its window is left as is).
+// Two grid points per iteration keep two pairs of LDS reads in flight.
 template <class A, int K>
 __device__ __forceinline__ void horner_upper(A (&acc)[K], const A (&rho)[K], const int (&hi_k)[K],
                                              const A* __restrict__ F, const A* __restrict__ G,
                                              int hi, int lo) {
-  for (int g = hi; g >= lo; --g) {
+  int g = hi;
+  for (; g - 1 >= lo; g -= 2) {
+    const A a0 = F[g] * G[g];
+    const A a1 = F[g - 1] * G[g - 1];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      acc[k] = fma(acc[k], rho[k], g <= hi_k[k] ? a0 : (A)0);
+      acc[k] = fma(acc[k], rho[k], g - 1 <= hi_k[k] ? a1 : (A)0);
+    }
+  }
+  for (; g >= lo; --g) {
     const A av = F[g] * G[g];
 #pragma unroll
     for (int k = 0; k < K; ++k) acc[k] = fma(acc[k], rho[k], g <= hi_k[k] ? av : (A)0);
@@ -81,7 +92,19 @@ template <class A, int K>
 __device__ __forceinline__ void horner_lower(A (&acc)[K], const A (&rho)[K], const int (&lo_k)[K],
                                              const A* __restrict__ F, const A* __restrict__ G,
                                              int hi, int lo) {
-  for (int g = hi; g >= lo; --g) {
+  int g = hi;
+  for (; g - 1 >= lo; g -= 2) {
+    const A a0 = F[g] * G[g];
+    const A a1 = F[g - 1] * G[g - 1];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const A t0 = fma(acc[k], rho[k], a0);
+      const A u0 = g >= lo_k[k] ? t0 : acc[k];
+      const A t1 = fma(u0, rho[k], a1);
+      acc[k] = g - 1 >= lo_k[k] ? t1 : u0;
+    }
+  }
+  for (; g >= lo; --g) {
     const A av = F[g] * G[g];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
