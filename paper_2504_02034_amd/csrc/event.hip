@@ -342,22 +342,32 @@ __device__ __forceinline__ void event_smooth(const EventArgs& a) {
       const int s_lo = max(s_hi - L + 1, A_lo);
       const int len = s_hi - s_lo + 1;
       __syncthreads();   // the previous slice is consumed (and G is written)
-      // F_r(z_g) = n_r(z_g) g(z_g); UR independent loads in flight per thread
+      // F_r(z_g) = n_r(z_g) g(z_g); UR independent loads in flight per thread.
+      // The batch's row indices are read first (one wait), then its UR row
+      // segments are loaded together.
       constexpr int UR = 8;
       if (lgW == 6) {
-        for (int q0 = 0; q0 < len; q0 += 64) {
-          const int q = q0 + lane;
-          const bool qv = q < len;
-          const int gg = s_lo + (qv ? q : 0);
-          const CT gv = gz[gg];
-          for (int pb = wv; pb < np; pb += NWV * UR) {
+        // a wave takes UR rows (uniform row index: scalar base address) and
+        // sweeps the slice 64 points at a time
+        for (int pb = wv; pb < np; pb += NWV * UR) {
+          int rr[UR];
+#pragma unroll
+          for (int r = 0; r < UR; ++r) {
+            const int p = pb + r * NWV;
+            rr[r] = p < np ? a.slot_row[p0 + p] : 0;
+          }
+          const CT* rp[UR];
+#pragma unroll
+          for (int r = 0; r < UR; ++r)
+            rp[r] = nzt + (size_t)__builtin_amdgcn_readfirstlane(rr[r]) * a.g.n_z;
+          for (int q0 = 0; q0 < len; q0 += 64) {
+            const int q = q0 + lane;
+            const bool qv = q < len;
+            const int gg = s_lo + (qv ? q : 0);
+            const CT gv = gz[gg];
             CT v[UR];
 #pragma unroll
-            for (int r = 0; r < UR; ++r) {
-              const int p = pb + r * NWV;
-              v[r] = (CT)0;
-              if (p < np) v[r] = nzt[(size_t)a.slot_row[p0 + p] * a.g.n_z + gg];
-            }
+            for (int r = 0; r < UR; ++r) v[r] = pb + r * NWV < np ? rp[r][gg] : (CT)0;
 #pragma unroll
             for (int r = 0; r < UR; ++r) {
               const int p = pb + r * NWV;
@@ -373,12 +383,17 @@ __device__ __forceinline__ void event_smooth(const EventArgs& a) {
         const int gg = s_lo + (qv ? q : 0);
         const CT gv = gz[gg];
         for (int pb = wv * RPW + sub; pb < np; pb += NWV * RPW * UR) {
+          int rr[UR];
+#pragma unroll
+          for (int r = 0; r < UR; ++r) {
+            const int p = pb + r * NWV * RPW;
+            rr[r] = p < np ? a.slot_row[p0 + p] : 0;
+          }
           CT v[UR];
 #pragma unroll
           for (int r = 0; r < UR; ++r) {
             const int p = pb + r * NWV * RPW;
-            v[r] = (CT)0;
-            if (p < np) v[r] = nzt[(size_t)a.slot_row[p0 + p] * a.g.n_z + gg];
+            v[r] = p < np ? nzt[(size_t)rr[r] * a.g.n_z + gg] : (CT)0;
           }
 #pragma unroll
           for (int r = 0; r < UR; ++r) {
