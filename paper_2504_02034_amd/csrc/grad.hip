@@ -363,7 +363,35 @@ __global__ __launch_bounds__(kGradBS) void k_event_grad(GradArgs a) {
     CT r = (CT)exp(-(2.0 * u0 * dz + dz * dz) * 0.5 * inv_h2);
     const CT* nrow = nzt + (size_t)a.samp_row[q] * nz;
     CT sA = 0, sB = 0, sC = 0, sE[6] = {0, 0, 0, 0, 0, 0};
-    for (int gi = lo; gi <= hi; ++gi) {
+    // 4 grid points per iteration: their loads are issued together
+    int gi = lo;
+    for (; gi + 3 <= hi; gi += 4) {
+      CT nv[4], gv[4], fv[6][4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        nv[i] = nrow[gi + i];
+        gv[i] = gzt[gi + i];
+      }
+#pragma unroll
+      for (int p = 0; p < 6; ++p)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) fv[p][i] = gft[(size_t)p * nz + gi + i];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const CT u = (CT)(u0 + (double)(gi + i - lo) * dz);
+        const CT bk = nv[i] * K;
+        const CT av = bk * gv[i];
+        sA += av;
+        const CT t = av * u;
+        sB += t;
+        sC = fma(t, u, sC);
+#pragma unroll
+        for (int p = 0; p < 6; ++p) sE[p] = fma(bk, fv[p][i], sE[p]);
+        K *= r;
+        r *= qr;
+      }
+    }
+    for (; gi <= hi; ++gi) {
       const CT u = (CT)(u0 + (double)(gi - lo) * dz);
       const CT bk = nrow[gi] * K;
       const CT av = bk * gzt[gi];
