@@ -108,7 +108,9 @@ const char* chimera_last_error(void);
  * Sect. 2.3 step b): nz is row-major [n_rows][n_z], n_r(z_g) per unit z per
  * steradian for each catalogue row that events refer to; nz_tot[n_z] is the
  * all-sky density n_tot(z_g) = pixel area x sum over all pixels, used by the
- * selection term.  Replaces any previous catalogue. */
+ * selection term.  Replaces any previous catalogue; returns ERANGE (and keeps
+ * the current one) when a resident event set refers to a row at or past
+ * n_rows — release such sets first. */
 chimera_status chimera_set_catalog(chimera_ctx* ctx, int64_t n_rows, const double* nz,
                                    const double* nz_tot);
 
@@ -126,7 +128,9 @@ chimera_status chimera_set_catalog(chimera_ctx* ctx, int64_t n_rows, const doubl
  *   vshape[n_z]            >= 0
  * Host arrays; synchronous.  Replaces any previous catalogue.  n_used may be
  * NULL.  Returns EINVAL on malformed input, ERANGE when a row names a pixel
- * past n_pix, ENOMEM when the device cannot hold n_pix x n_z doubles. */
+ * past n_pix or when a resident event set refers to a row at or past n_rows
+ * (the current catalogue is kept), ENOMEM when the device cannot hold
+ * n_pix x n_z doubles. */
 chimera_status chimera_set_catalog_galaxies(chimera_ctx* ctx, int64_t n_pix, int64_t n_gal,
                                             const int64_t* gal_pix_off, const double* z_obs,
                                             const double* sigma_z, const double* vshape,

@@ -94,6 +94,7 @@ struct chimera_events {
   int* samp_row = nullptr;      // catalogue row of each sample (adjoint)
   double* samp_c = nullptr;     // c_ir of each sample's pixel (adjoint)
   double dmin = 0.0, dmax = 0.0;
+  int64_t rows_needed = 0;      // 1 + the largest catalogue row the set refers to
 };
 
 struct chimera_ctx {
@@ -283,6 +284,20 @@ void chimera_destroy(chimera_ctx* ctx) {
   delete ctx;
 }
 
+namespace {
+
+// A replacement catalogue must keep every row a resident event set refers to
+// (call with ctx->mu held).
+chimera_status check_resident_rows(const chimera_ctx* ctx, int64_t n_rows) {
+  for (const auto* e : ctx->events)
+    if (e->rows_needed > n_rows)
+      return fail(CHIMERA_ERANGE, "a resident event set refers to catalogue rows past the new "
+                                  "catalogue; release it first");
+  return CHIMERA_OK;
+}
+
+}  // namespace
+
 chimera_status chimera_set_catalog(chimera_ctx* ctx, int64_t n_rows, const double* nz,
                                    const double* nz_tot) {
   if (!ctx || !nz_tot || (n_rows > 0 && !nz)) return fail(CHIMERA_EINVAL, "null argument");
@@ -294,6 +309,7 @@ chimera_status chimera_set_catalog(chimera_ctx* ctx, int64_t n_rows, const doubl
     if (!(std::isfinite(nz_tot[i]) && nz_tot[i] >= 0.0))
       return fail(CHIMERA_EINVAL, "nz_tot must be finite, >= 0");
   std::lock_guard<std::mutex> lk(ctx->mu);
+  if (chimera_status st = check_resident_rows(ctx, n_rows); st != CHIMERA_OK) return st;
   HIP_TRY(hipSetDevice(ctx->cfg.device));
   HIP_TRY(hipDeviceSynchronize());
   free_catalog(ctx);
@@ -334,6 +350,7 @@ chimera_status chimera_set_catalog_galaxies(chimera_ctx* ctx, int64_t n_pix, int
     if (rows_pix[r] < 0 || rows_pix[r] >= n_pix)
       return fail(CHIMERA_ERANGE, "rows_pix refers past the pixels");
   std::lock_guard<std::mutex> lk(ctx->mu);
+  if (chimera_status st = check_resident_rows(ctx, n_rows); st != CHIMERA_OK) return st;
   HIP_TRY(hipSetDevice(ctx->cfg.device));
   HIP_TRY(hipDeviceSynchronize());
   CatalogArgs c{};
@@ -566,7 +583,11 @@ chimera_status chimera_add_events(chimera_ctx* ctx, int32_t n_ev, const int64_t*
     dmin = std::min(dmin, odl[j]);
     dmax = std::max(dmax, odl[j]);
   }
+  int64_t rows_needed = 0;
+  for (int64_t p = 0; p < P; ++p) rows_needed = std::max(rows_needed, pix_row[p] + 1);
   std::lock_guard<std::mutex> lk(ctx->mu);
+  if (rows_needed > ctx->n_rows)   // the catalogue changed since the check above
+    return fail(CHIMERA_ERANGE, "pix_row refers past the catalogue");
   HIP_TRY(hipSetDevice(ctx->cfg.device));
   auto* ev = new chimera_events();
   ev->E = n_ev;
@@ -574,6 +595,7 @@ chimera_status chimera_add_events(chimera_ctx* ctx, int32_t n_ev, const int64_t*
   ev->U = (int)u_event.size();
   ev->dmin = dmin;
   ev->dmax = dmax;
+  ev->rows_needed = rows_needed;
   hipError_t e = hipSuccess;
   if (e == hipSuccess) e = upload(&ev->ev_unit_off, ev_unit.data(), ev_unit.size());
   if (e == hipSuccess) e = upload(&ev->unit_event, u_event.data(), u_event.size());
