@@ -4,7 +4,8 @@
 // k_event_zw        one (event, lambda) per workgroup, one sample per thread:
 //                   z_j from d_L^gw, w_j = p(m1) p(m2|m1) into scratch, and the
 //                   event's bandwidth h (Scott's rule, Kish effective size,
-//                   unbiased weighted variance by two passes about the mean).
+//                   unbiased weighted variance from moments about a shift
+//                   inside the data, one pass).
 // k_event_smooth64  one work unit (<= 256 sample groups of one event, ordered
 // k_event_smooth32  by distance, so a narrow redshift range) at one lambda per
 //                   workgroup:
@@ -136,7 +137,7 @@ __global__ __launch_bounds__(kZwBS) void k_event_zw(EventArgs a) {
   if (!decode_item_lambda(a.E, a.B, e, b)) return;
   using CT = typename std::conditional<F32, float, double>::type;
   constexpr int NW = kZwBS / 64 + 1;
-  __shared__ double red[3 * NW];
+  __shared__ double red[4 * NW];
   const LamParams P = a.P[b];
   if (P.flag | a.flag_mono[b] | a.flag_range[b]) return;   // the final kernel reports it
   const double2* dtab = a.dtab + (size_t)b * a.g.n_t;
@@ -145,7 +146,11 @@ __global__ __launch_bounds__(kZwBS) void k_event_zw(EventArgs a) {
   const int ns = a.ev_samp_off[e + 1] - s0;
   double* zb = a.zbuf + (size_t)b * a.S + s0;
   CT* wb = (CT*)a.wbuf + (size_t)b * a.S + s0;
-  double m[3] = {0.0, 0.0, 0.0};   // W1, W2, sum w z
+  // weighted moments about a shift s near the data (the redshift of the
+  // event's first sample from the inverse table, the same in every thread):
+  // W1, W2, sum w (z - s), sum w (z - s)^2
+  const double s = exp(invert_x(P, nullptr, inv, a.g, a.dl[s0], a.lndl[s0], 0)) - 1.0;
+  double m[4] = {0.0, 0.0, 0.0, 0.0};
   for (int j = threadIdx.x; j < ns; j += kZwBS) {
     const int q = s0 + j;
     double z, w;
@@ -154,27 +159,22 @@ __global__ __launch_bounds__(kZwBS) void k_event_zw(EventArgs a) {
     const CT wc = (CT)w;
     zb[j] = z;
     wb[j] = wc;
-    const double wd = (double)wc;
+    const double wd = (double)wc, t = z - s;
     m[0] += wd;
     m[1] += wd * wd;
-    m[2] += wd * z;
+    m[2] += wd * t;
+    m[3] += wd * t * t;
   }
-  block_reduce<kZwBS, 3, false>(m, red);
+  block_reduce<kZwBS, 4, false>(m, red);
   const double W1 = m[0], W2 = m[1];
   if (!(W1 > 0.0)) {
     if (threadIdx.x == 0) a.hbuf[(size_t)b * a.E + e] = -1.0;
     return;
   }
-  const double mu = m[2] / W1;
-  double v[1] = {0.0};
-  for (int j = threadIdx.x; j < ns; j += kZwBS) {   // this thread's own writes
-    const double d = zb[j] - mu;
-    v[0] += (double)wb[j] * d * d;
-  }
-  block_reduce<kZwBS, 1, false>(v, red);
   if (threadIdx.x == 0) {
     double var = 0.0;
-    if (!(W1 * W1 - W2 <= 1e-12 * W1 * W1)) var = v[0] / (W1 - W2 / W1);
+    if (!(W1 * W1 - W2 <= 1e-12 * W1 * W1))
+      var = fmax(m[3] - m[2] * (m[2] / W1), 0.0) / (W1 - W2 / W1);
     a.hbuf[(size_t)b * a.E + e] = fmax(sqrt(var) * pow(W1 * W1 / W2, -0.2), 2.0 * a.g.dz);
   }
 }
