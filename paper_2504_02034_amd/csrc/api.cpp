@@ -183,6 +183,7 @@ struct Scratch {
   void* wbuf;
   double* hbuf;
   double* part;
+  long long* pcount;
 };
 
 // Lay out (or size, when base is null) the scratch of one call.
@@ -208,6 +209,7 @@ size_t carve(Carve& cv, Scratch& s, const Geometry& g, int64_t B, int E, int nch
              : nullptr;
   s.hbuf = S ? cv.take<double>((size_t)B * E) : nullptr;
   s.part = S ? cv.take<double>((size_t)B * std::max(U, 1)) : nullptr;
+  s.pcount = S ? cv.take<long long>((size_t)B * std::max(U, 1)) : nullptr;
   return cv.off;
 }
 
@@ -740,6 +742,7 @@ static chimera_status run_chunk(chimera_ctx* ctx, const chimera_events* ev, cons
     a.trunc = f32 ? ctx->cfg.trunc_fp32 : ctx->cfg.trunc_fp64;
     a.zbuf = s.zbuf; a.wbuf = s.wbuf; a.hbuf = s.hbuf; a.part = s.part; a.lnI = lnI_dev;
     a.count = nullptr;
+    a.pcount = s.pcount;
     hipEvent_t t0 = nullptr, t1 = nullptr;
     if (ctx->profile) {
       std::lock_guard<std::mutex> lk(ctx->mu);

@@ -195,7 +195,10 @@ __device__ __forceinline__ void event_smooth(const EventArgs& a) {
   const LamParams P = a.P[b];
   const double h = a.hbuf[(size_t)b * a.E + e];
   if ((P.flag | a.flag_mono[b] | a.flag_range[b]) || !(h > 0.0)) {
-    if (threadIdx.x == 0) *part = 0.0;
+    if (threadIdx.x == 0) {
+      *part = 0.0;
+      if (a.count) a.pcount[(size_t)b * a.U + u] = 0;
+    }
     return;
   }
   const int p0 = a.ev_slot_off[e];
@@ -252,13 +255,18 @@ __device__ __forceinline__ void event_smooth(const EventArgs& a) {
     for (int k = 0; k < K; ++k)
       if (klo[k] <= khi[k]) dloc = fmax(dloc, fabs(zk[k] - zc0));
   }
-  double mx[4] = {lo_u <= hi_u ? -(double)lo_u : -1e9, lo_u <= hi_u ? (double)hi_u : -1e9, mloc,
-                  dloc};
-  block_reduce<BS, 4, true>(mx, red);
-  const int A_lo = (int)(-mx[0]);
-  const int A_hi = (int)mx[1];
-  const int M = (int)mx[2];              // |g - c| <= M over every group window of the unit
-  const double dmax = mx[3];
+  // unit bounds, chain range and the largest |z_k - centre| (rounded up to
+  // FP32 and compared as its bit pattern, which orders non-negative floats)
+  float dl32 = (float)dloc;
+  if ((double)dl32 < dloc) dl32 = __int_as_float(__float_as_int(dl32) + 1);
+  __shared__ int redi[4 * (BS / 64)];
+  int mx[4] = {lo_u <= hi_u ? -lo_u : -(1 << 30), lo_u <= hi_u ? hi_u : -(1 << 30), (int)mloc,
+               __float_as_int(dl32)};
+  block_max_i32<BS, 4>(mx, redi);
+  const int A_lo = max(-mx[0], 0);
+  const int A_hi = min(mx[1], a.g.n_z - 1);
+  const int M = mx[2];                   // |g - c| <= M over every group window of the unit
+  const double dmax = (double)__int_as_float(mx[3]);
 
   // Horner's partial sums are the kernel values times rho^(c - lo) / C: at
   // most exp(M dz |delta| / h^2 + delta^2 / 2h^2) away from the true values
@@ -442,11 +450,22 @@ __device__ __forceinline__ void event_smooth(const EventArgs& a) {
       total += cir * wk[k] * sacc;
     }
   }
-  double fin[2] = {total, npts};
-  block_reduce<BS, 2, false>(fin, red);
-  if (threadIdx.x == 0) {
-    *part = fin[0];
-    if (a.count) atomicAdd(a.count, (unsigned long long)fin[1]);
+  double fin[1] = {total};
+  block_reduce<BS, 1, false>(fin, red);
+  if (threadIdx.x == 0) *part = fin[0];
+  if (a.count) {   // profiling: the pairs this workgroup evaluated, summed after the kernel
+    long long n = (long long)npts;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) n += __shfl_xor(n, o, 64);
+    __shared__ long long redc[NWV];
+    if (lane == 0) redc[wv] = n;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      long long t = 0;
+#pragma unroll
+      for (int k = 0; k < NWV; ++k) t += redc[k];
+      a.pcount[(size_t)b * a.U + u] = t;
+    }
   }
 }
 
@@ -454,6 +473,19 @@ __global__ __launch_bounds__(kSmBS) void k_event_smooth64(EventArgs a) { event_s
 
 __global__ __launch_bounds__(kSmBS) __attribute__((amdgpu_waves_per_eu(4)))
 void k_event_smooth32(EventArgs a) { event_smooth<true>(a); }
+
+// profiling: the pair counts of one launch into the context's counter
+__global__ __launch_bounds__(256) void k_count_sum(const long long* __restrict__ pc, long long n,
+                                                   unsigned long long* __restrict__ count) {
+  long long t = 0;
+  for (long long i = threadIdx.x; i < n; i += 256) t += pc[i];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
+  __shared__ long long r[4];
+  if ((threadIdx.x & 63) == 0) r[threadIdx.x >> 6] = t;
+  __syncthreads();
+  if (threadIdx.x == 0) atomicAdd(count, (unsigned long long)(r[0] + r[1] + r[2] + r[3]));
+}
 
 // ---------------------------------------------------------------------------
 __global__ void k_event_final(EventArgs a) {
@@ -490,6 +522,7 @@ hipError_t launch_events(const EventArgs& a, bool f32, hipStream_t st, hipEvent_
   if (f32) k_event_smooth32<<<(unsigned)bs, kSmBS, lds, st>>>(a);
   else k_event_smooth64<<<(unsigned)bs, kSmBS, lds, st>>>(a);
   if (t1 && (err = hipEventRecord(t1, st)) != hipSuccess) return err;
+  if (a.count) k_count_sum<<<1, 256, 0, st>>>(a.pcount, (long long)a.B * a.U, a.count);
   const long long nf = (long long)a.B * a.E;
   k_event_final<<<(unsigned)((nf + 255) / 256), 256, 0, st>>>(a);
   return hipGetLastError();

@@ -113,7 +113,8 @@ struct EventArgs {
   double* hbuf;             // [B][E] bandwidth (<= 0: no weight in the event)
   double* part;             // [B][U] partial kernel sums
   double* lnI;              // [B][E]
-  unsigned long long* count;
+  unsigned long long* count;  // pairs evaluated, while profiling (else null)
+  long long* pcount;        // [B][U] pairs per (unit, lambda), summed into count
 };
 
 hipError_t launch_events(const EventArgs& a, bool f32, hipStream_t st, hipEvent_t t0 = nullptr,

@@ -79,4 +79,27 @@ __device__ __forceinline__ void block_reduce(double (&v)[N], double* red /* >= N
   __syncthreads();
 }
 
+// Maxima over the workgroup of N ints; every thread gets them (max is exact,
+// so the order does not matter).  red must hold N*(BS/64) ints and is not
+// touched again by this call after its barrier.
+template <int BS, int N>
+__device__ __forceinline__ void block_max_i32(int (&v)[N], int* red) {
+  constexpr int NW = BS / 64;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v[i] = max(v[i], __shfl_xor(v[i], o, 64));
+    if (lane == 0) red[i * NW + w] = v[i];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    int t = red[i * NW];
+#pragma unroll
+    for (int k = 1; k < NW; ++k) t = max(t, red[i * NW + k]);
+    v[i] = t;
+  }
+}
+
 }  // namespace chimera

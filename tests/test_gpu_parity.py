@@ -117,3 +117,41 @@ def test_device_pointers_and_stream(gpu_small):
         out = ctx.lnl(es, t, chimera.CHIMERA_FP64, stream=s)
     s.synchronize()
     assert np.array_equal(out.cpu().numpy(), host, equal_nan=True)
+
+
+def test_profile_counts_the_window_pairs(small_data, gpu_small):
+    """chimera_profile_read counts the (sample, grid point) pairs of one call:
+    samples with w > 0 and every grid point with |z_g - z_j| <= T h, from the
+    oracle's own redshifts, weights and bandwidths."""
+    import oracle
+    L = oracle.likelihood
+    chimera, ctx, es = gpu_small
+    # points with a finite ln L on this data, so every one is evaluated (a
+    # flagged point skips its sums, while ln L = -inf from I_i = 0 or xi = 0
+    # would not tell whether it did)
+    lam = np.tile(synth.LAMBDA_TRUTH, (6, 1))
+    lam[:, :2] = [[60.0, 0.25], [67.0, 0.3], [70.0, 0.3], [74.0, 0.35], [80.0, 0.25], [80.0, 0.35]]
+    chimera.chimera_profile_enable(ctx.handle, True)
+    chimera.chimera_profile_read(ctx.handle)            # start from zero
+    out = ctx.lnl(es, lam, chimera.CHIMERA_FP64)
+    n, ms, got = chimera.chimera_profile_read(ctx.handle)
+    chimera.chimera_profile_enable(ctx.handle, False)
+    assert n == 1 and ms > 0.0
+    grid = small_data.o_cat.grid
+    dz, T = grid[1] - grid[0], 8.6
+    want = 0
+    assert np.all(np.isfinite(out))
+    for b in range(lam.shape[0]):
+        for ev in small_data.o_events:
+            z, w = L.redshift_and_weight(np.concatenate([p.dl for p in ev.pixels]),
+                                         np.concatenate([p.m1d for p in ev.pixels]),
+                                         np.concatenate([p.m2d for p in ev.pixels]), lam[b])
+            h = L.bandwidth(z, w, dz)
+            if h is None:
+                continue
+            lo = np.maximum(np.ceil((z - T * h - grid[0]) / dz), 0)
+            hi = np.minimum(np.floor((z + T * h - grid[0]) / dz), grid.size - 1)
+            ok = (w > 0) & (lo <= hi)
+            want += int(np.sum(hi[ok] - lo[ok] + 1))
+    print("pairs", got, want)
+    assert want > 0 and got == want
