@@ -151,11 +151,23 @@ __global__ __launch_bounds__(kZwBS) void k_event_zw(EventArgs a) {
   // W1, W2, sum w (z - s), sum w (z - s)^2
   const double s = exp(invert_x(P, nullptr, inv, a.g, a.dl[s0], a.lndl[s0], 0)) - 1.0;
   double m[4] = {0.0, 0.0, 0.0, 0.0};
+  // software pipeline: the next sample's inputs are loaded while this one is
+  // transformed (indices past the end read this event's first sample)
+  auto in = [&](int j, double (&v)[6]) {
+    const int q = s0 + (j < ns ? j : 0);
+    v[0] = F32 ? 0.0 : a.dl[q];   // the FP32 transform uses ln d only
+    v[1] = a.lndl[q]; v[2] = a.m1d[q];
+    v[3] = a.m2d[q]; v[4] = a.lnm1d[q]; v[5] = a.lnm2d[q];
+  };
+  double cur[6];
+  in(threadIdx.x, cur);
   for (int j = threadIdx.x; j < ns; j += kZwBS) {
-    const int q = s0 + j;
+    double nxt[6];
+    in(j + kZwBS, nxt);
     double z, w;
-    sample_zw<F32>(P, dtab, inv, a.g, a.dl[q], a.lndl[q], a.m1d[q], a.m2d[q], a.lnm1d[q],
-                   a.lnm2d[q], z, w);
+    sample_zw<F32>(P, dtab, inv, a.g, cur[0], cur[1], cur[2], cur[3], cur[4], cur[5], z, w);
+#pragma unroll
+    for (int i = 0; i < 6; ++i) cur[i] = nxt[i];
     const CT wc = (CT)w;
     zb[j] = z;
     wb[j] = wc;
