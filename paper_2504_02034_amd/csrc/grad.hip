@@ -250,10 +250,23 @@ __global__ __launch_bounds__(kGradBS) void k_event_bandwidth_grad(GradArgs a) {
   double m[40];
 #pragma unroll
   for (int i = 0; i < 40; ++i) m[i] = 0.0;
+  // software pipeline: the next sample's inputs load while this one is
+  // evaluated (indices past the end read this event's first sample)
+  auto in = [&](int j, double (&v)[6]) {
+    const int q = s0 + (j < ns ? j : 0);
+    v[0] = a.dl[q]; v[1] = a.lndl[q]; v[2] = a.m1d[q];
+    v[3] = a.m2d[q]; v[4] = a.lnm1d[q]; v[5] = a.lnm2d[q];
+  };
+  double cur[6];
+  in(threadIdx.x, cur);
   for (int j = threadIdx.x; j < ns; j += kGradBS) {
     const int q = s0 + j;
-    sample_grad(P, Q, chi, chio, dtab, inv, a.g, a.dl[q], a.lndl[q], a.m1d[q], a.m2d[q],
-                a.lnm1d[q], a.lnm2d[q], sg, dp);
+    double nxt[6];
+    in(j + kGradBS, nxt);
+    sample_grad(P, Q, chi, chio, dtab, inv, a.g, cur[0], cur[1], cur[2], cur[3], cur[4], cur[5],
+                sg, dp);
+#pragma unroll
+    for (int i = 0; i < 6; ++i) cur[i] = nxt[i];
     const double w = sg.w;
     double* sc = a.sc + (size_t)b * kSC * a.S + q;
     sc[0] = sg.zp1 - 1.0;
