@@ -41,6 +41,7 @@ constexpr int kNG = CHIMERA_NGRAD;   // 12
 constexpr int kNS = 9;               // parameters a sample depends on: H0, Om, Xi0, n, mass (5)
 constexpr int kGradBS = 256;
 constexpr int kSC = kGradSampleFields;
+constexpr int kGradStageElems = 6144;   // LDS copy of g and g dln g/dp: 7 x span values
 static_assert(kSC == 2 + kNS + 4, "per-sample coefficient layout");
 
 __device__ __forceinline__ double phi_std(double t) {
@@ -322,9 +323,64 @@ __global__ __launch_bounds__(kGradBS) void k_event_bandwidth_grad(GradArgs a) {
   }
 }
 
+// A sample's window sums: A = sum a, sum a u, sum a u^2 (a = n_r g K) and six
+// sum n_r K g dln g/dp, by the Gaussian ratio recurrence.  Grid point g of
+// the grid factor is gz[g - off], of derivative p gf[p fstride + g - off]
+// (the workgroup's LDS copy or the tables themselves); 4 points per
+// iteration keep their loads in flight together.
+template <class CT>
+__device__ __forceinline__ void window_sums(const CT* __restrict__ nrow,
+                                            const CT* __restrict__ gz,
+                                            const CT* __restrict__ gf, int fstride, int off,
+                                            int lo, int hi, double u0, double dz, CT K, CT r,
+                                            CT qr, CT& sA, CT& sB, CT& sC, CT (&sE)[6]) {
+  int gi = lo;
+  for (; gi + 3 <= hi; gi += 4) {
+    CT nv[4], gv[4], fv[6][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      nv[i] = nrow[gi + i];
+      gv[i] = gz[gi + i - off];
+    }
+#pragma unroll
+    for (int p = 0; p < 6; ++p)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) fv[p][i] = gf[p * fstride + gi + i - off];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const CT u = (CT)(u0 + (double)(gi + i - lo) * dz);
+      const CT bk = nv[i] * K;
+      const CT av = bk * gv[i];
+      sA += av;
+      const CT t = av * u;
+      sB += t;
+      sC = fma(t, u, sC);
+#pragma unroll
+      for (int p = 0; p < 6; ++p) sE[p] = fma(bk, fv[p][i], sE[p]);
+      K *= r;
+      r *= qr;
+    }
+  }
+  for (; gi <= hi; ++gi) {
+    const CT u = (CT)(u0 + (double)(gi - lo) * dz);
+    const CT bk = nrow[gi] * K;
+    const CT av = bk * gz[gi - off];
+    sA += av;
+    const CT t = av * u;
+    sB += t;
+    sC = fma(t, u, sC);
+#pragma unroll
+    for (int p = 0; p < 6; ++p) sE[p] = fma(bk, gf[p * fstride + gi - off], sE[p]);
+    K *= r;
+    r *= qr;
+  }
+}
+
 // Kernel sums and their parameter contractions, one (event, lambda) per
 // workgroup, one sample per thread, from the coefficients the bandwidth
-// kernel stored.
+// kernel stored.  The grid factor and its six derivatives over the union of
+// the workgroup's windows are copied to LDS once (when they fit), so that
+// each grid point reads only the sample's catalogue row from memory.
 template <bool F32>
 __global__ __launch_bounds__(kGradBS) void k_event_grad(GradArgs a) {
   int e, b;
@@ -332,6 +388,8 @@ __global__ __launch_bounds__(kGradBS) void k_event_grad(GradArgs a) {
   using CT = typename std::conditional<F32, float, double>::type;
   constexpr int NW = kGradBS / 64 + 1;
   __shared__ double red[(1 + kNG) * NW];
+  __shared__ int redi[2 * (kGradBS / 64)];
+  extern __shared__ __align__(16) unsigned char gsm[];
   const LamParams P = a.P[b];
   double* lnI = a.lnI + (size_t)b * a.E + e;
   double* dlnI = a.dlnI + ((size_t)b * a.E + e) * kNG;
@@ -359,6 +417,31 @@ __global__ __launch_bounds__(kGradBS) void k_event_grad(GradArgs a) {
                       : (const CT*)(a.gf64 + (size_t)b * 6 * a.g.n_z);
   const int nz = a.g.n_z;
   const double* scb = a.sc + (size_t)b * kSC * a.S;
+  // the union of the workgroup's windows
+  int lo_b = 1 << 30, hi_b = -(1 << 30);
+  for (int j = threadIdx.x; j < ns; j += kGradBS) {
+    const int q = s0 + j;
+    if (!(scb[a.S + q] > 0.0)) continue;
+    const double z = scb[q];
+    const double lo_d = fmax(ceil((z - T * h - a.g.z_lo) * a.g.inv_dz), 0.0);
+    const double hi_d = fmin(floor((z + T * h - a.g.z_lo) * a.g.inv_dz), (double)(nz - 1));
+    if (!(lo_d <= hi_d)) continue;
+    lo_b = min(lo_b, (int)lo_d);
+    hi_b = max(hi_b, (int)hi_d);
+  }
+  int mx[2] = {-lo_b, hi_b};
+  block_max_i32<kGradBS, 2>(mx, redi);
+  const int A_lo = max(-mx[0], 0), A_hi = min(mx[1], nz - 1);
+  const int span = A_hi - A_lo + 1;
+  CT* sg = reinterpret_cast<CT*>(gsm);
+  const bool staged = span > 0 && 7 * span <= kGradStageElems;
+  if (staged) {
+    for (int k = threadIdx.x; k < span; k += kGradBS) sg[k] = gzt[A_lo + k];
+    for (int p = 0; p < 6; ++p)
+      for (int k = threadIdx.x; k < span; k += kGradBS)
+        sg[(1 + p) * span + k] = gft[(size_t)p * nz + A_lo + k];
+    __syncthreads();
+  }
   double acc[1 + kNG];
 #pragma unroll
   for (int i = 0; i <= kNG; ++i) acc[i] = 0.0;
@@ -372,51 +455,14 @@ __global__ __launch_bounds__(kGradBS) void k_event_grad(GradArgs a) {
     if (!(lo_d <= hi_d)) continue;
     const int lo = (int)lo_d, hi = (int)hi_d;
     const double u0 = a.g.z_lo + lo_d * dz - z;
-    CT K = (CT)exp(-0.5 * u0 * u0 * inv_h2);
-    CT r = (CT)exp(-(2.0 * u0 * dz + dz * dz) * 0.5 * inv_h2);
+    const CT K = (CT)exp(-0.5 * u0 * u0 * inv_h2);
+    const CT r = (CT)exp(-(2.0 * u0 * dz + dz * dz) * 0.5 * inv_h2);
     const CT* nrow = nzt + (size_t)a.samp_row[q] * nz;
     CT sA = 0, sB = 0, sC = 0, sE[6] = {0, 0, 0, 0, 0, 0};
-    // 4 grid points per iteration: their loads are issued together
-    int gi = lo;
-    for (; gi + 3 <= hi; gi += 4) {
-      CT nv[4], gv[4], fv[6][4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        nv[i] = nrow[gi + i];
-        gv[i] = gzt[gi + i];
-      }
-#pragma unroll
-      for (int p = 0; p < 6; ++p)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) fv[p][i] = gft[(size_t)p * nz + gi + i];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const CT u = (CT)(u0 + (double)(gi + i - lo) * dz);
-        const CT bk = nv[i] * K;
-        const CT av = bk * gv[i];
-        sA += av;
-        const CT t = av * u;
-        sB += t;
-        sC = fma(t, u, sC);
-#pragma unroll
-        for (int p = 0; p < 6; ++p) sE[p] = fma(bk, fv[p][i], sE[p]);
-        K *= r;
-        r *= qr;
-      }
-    }
-    for (; gi <= hi; ++gi) {
-      const CT u = (CT)(u0 + (double)(gi - lo) * dz);
-      const CT bk = nrow[gi] * K;
-      const CT av = bk * gzt[gi];
-      sA += av;
-      const CT t = av * u;
-      sB += t;
-      sC = fma(t, u, sC);
-#pragma unroll
-      for (int p = 0; p < 6; ++p) sE[p] = fma(bk, gft[(size_t)p * nz + gi], sE[p]);
-      K *= r;
-      r *= qr;
-    }
+    if (staged)
+      window_sums<CT>(nrow, sg, sg + span, span, A_lo, lo, hi, u0, dz, K, r, qr, sA, sB, sC, sE);
+    else
+      window_sums<CT>(nrow, gzt, gft, nz, 0, lo, hi, u0, dz, K, r, qr, sA, sB, sC, sE);
     const double A = (double)sA, Bz = (double)sB * inv_h2, Chh = (double)sC * inv_h2;
     acc[0] += cw * A;
     // distance parameters: weight, z-shift, bandwidth, grid factor (H0: g ~ H0)
@@ -576,8 +622,8 @@ hipError_t launch_grad(const GradArgs& a, const SelGradArgs& sa, GradFinalArgs f
   if (a.E > 0) {
     k_event_bandwidth_grad<<<(unsigned)nb, kGradBS, 0, st>>>(a);
     CH_LAUNCH_CHECK();
-    if (f32) k_event_grad<true><<<(unsigned)nb, kGradBS, 0, st>>>(a);
-    else k_event_grad<false><<<(unsigned)nb, kGradBS, 0, st>>>(a);
+    if (f32) k_event_grad<true><<<(unsigned)nb, kGradBS, kGradStageElems * sizeof(float), st>>>(a);
+    else k_event_grad<false><<<(unsigned)nb, kGradBS, kGradStageElems * sizeof(double), st>>>(a);
     CH_LAUNCH_CHECK();
   }
   k_grad_final<<<a.B, kGFinBS, 0, st>>>(fa);
