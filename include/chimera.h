@@ -202,13 +202,14 @@ chimera_status chimera_scratch_bytes(chimera_ctx* ctx, const chimera_events* ev,
  * d ln L / d(H0, Om, Xi0, n, alpha, beta, mu_g, sigma_g, lambda_g, gamma,
  * kappa, z_p); mmin and mmax are edges of the mass support and are not
  * differentiated.  The window edges |z_g - z_j| = T h are held fixed.  prec:
- * CHIMERA_FP64, or CHIMERA_FP32 for the per-sample window sums in FP32 (the
- * sample transform, bandwidth, selection and every sum over samples, events
- * and injections in FP64).  lnl follows chimera_lnl_batch's rules; grad is
- * NaN where lnl is not finite.  The per-lambda layout is the same as above.
- * Device scratch grows with 120 bytes per sample and point; a call whose
- * scratch would exceed 16 GiB runs as consecutive chunks of points on the
- * same stream, with the same results. */
+ * CHIMERA_FP64, or CHIMERA_FP32 for the per-sample window sums and the
+ * stored per-sample derivatives in FP32 (the sample transform, bandwidth,
+ * selection and every sum over samples, events and injections in FP64).  lnl
+ * follows chimera_lnl_batch's rules; grad is NaN where lnl is not finite.
+ * The per-lambda layout is the same as above.  Device scratch grows with 120
+ * bytes per sample and point (68 in FP32); a call whose scratch would exceed
+ * 16 GiB runs as consecutive chunks of points on the same stream, with the
+ * same results. */
 chimera_status chimera_lnl_grad(chimera_ctx* ctx, const chimera_events* ev, const double* lam,
                                 int64_t B, int32_t prec, double* lnl, double* grad, int32_t mem,
                                 void* hip_stream);

@@ -827,11 +827,11 @@ chimera_status chimera_selection_xi(chimera_ctx* ctx, const double* lam, int64_t
 }
 
 // Lambda points per gradient launch sequence: the per-sample coefficients
-// (15 doubles per sample and lambda) stay within 16 GiB.
+// (120 bytes per sample and lambda, 68 in FP32) stay within 16 GiB.
 constexpr double kGradScratchCap = 16.0 * (1ull << 30);
 
-int64_t grad_lambda_chunk(const chimera_events* ev, int64_t B) {
-  const double per = (double)ev->n_samp * 8.0 * kGradSampleFields + 8.0 * ev->E * 23.0;
+int64_t grad_lambda_chunk(const chimera_events* ev, int64_t B, bool f32) {
+  const double per = (double)ev->n_samp * grad_sample_bytes(f32) + 8.0 * ev->E * 23.0;
   const int64_t c = (int64_t)std::max(1.0, std::floor(kGradScratchCap / per));
   return std::min(B, c);
 }
@@ -868,7 +868,9 @@ static chimera_status run_grad_chunk(chimera_ctx* ctx, const chimera_events* ev,
     *fr = cv.take<int>(B);
     sa.partial = cv.take<double>((size_t)B * std::max(nchunk, 1) * (1 + CHIMERA_NGRAD));
     a.hd = cv.take<double>((size_t)B * E * 10);
-    a.sc = cv.take<double>((size_t)B * kGradSampleFields * ev->n_samp);
+    a.sc = cv.take<double>((size_t)B * 2 * ev->n_samp);
+    a.sd = f32 ? (void*)cv.take<float>((size_t)B * kGradDerivFields * ev->n_samp)
+               : (void*)cv.take<double>((size_t)B * kGradDerivFields * ev->n_samp);
     a.lnI = cv.take<double>((size_t)B * E);
     a.dlnI = cv.take<double>((size_t)B * E * CHIMERA_NGRAD);
     *lam_d = host ? cv.take<double>((size_t)B * CHIMERA_NLAM) : nullptr;
@@ -909,7 +911,7 @@ static chimera_status run_grad_chunk(chimera_ctx* ctx, const chimera_events* ev,
   a.ev_samp_off = ev->ev_samp_off; a.samp_row = ev->samp_row; a.samp_c = ev->samp_c;
   a.dl = ev->dl; a.lndl = ev->lndl; a.m1d = ev->m1d; a.m2d = ev->m2d;
   a.lnm1d = ev->lnm1d; a.lnm2d = ev->lnm2d;
-  a.E = E; a.B = (int)B; a.S = ev->n_samp;
+  a.E = E; a.B = (int)B; a.S = ev->n_samp; a.f32 = f32 ? 1 : 0;
   a.trunc = f32 ? ctx->cfg.trunc_fp32 : ctx->cfg.trunc_fp64;
   sa.P = P; sa.Q = a.Q; sa.flag_mono = fm; sa.flag_range = fr;
   sa.chi = chi; sa.chio = chio; sa.inv = inv; sa.dtab = dtab; sa.g = g; sa.ntot = ctx->ntot;
@@ -931,7 +933,7 @@ static chimera_status run_grad_chunk(chimera_ctx* ctx, const chimera_events* ev,
 static chimera_status run_grad(chimera_ctx* ctx, const chimera_events* ev, const double* lam,
                                int64_t B, int32_t prec, double* lnl, double* grad, int32_t mem,
                                void* hip_stream) {
-  const int64_t Bc = grad_lambda_chunk(ev, B);
+  const int64_t Bc = grad_lambda_chunk(ev, B, prec == CHIMERA_FP32);
   for (int64_t c0 = 0; c0 < B; c0 += Bc) {
     const int64_t n = std::min(Bc, B - c0);
     chimera_status s = run_grad_chunk(ctx, ev, lam + c0 * CHIMERA_NLAM, n, prec, lnl + c0,

@@ -40,9 +40,9 @@ namespace {
 constexpr int kNG = CHIMERA_NGRAD;   // 12
 constexpr int kNS = 9;               // parameters a sample depends on: H0, Om, Xi0, n, mass (5)
 constexpr int kGradBS = 256;
-constexpr int kSC = kGradSampleFields;
+constexpr int kSD = kGradDerivFields;
 constexpr int kGradStageElems = 6144;   // LDS copy of g and g dln g/dp: 7 x span values
-static_assert(kSC == 2 + kNS + 4, "per-sample coefficient layout");
+static_assert(kSD == kNS + 4 && kGradSampleFields == 2 + kSD, "per-sample coefficient layout");
 
 __device__ __forceinline__ double phi_std(double t) {
   return 0.39894228040143267794 * exp(-0.5 * t * t);
@@ -221,8 +221,9 @@ __global__ void k_grid_grad(const LamParams* __restrict__ Pv, const double2* __r
 // M1 = sum w (z - s), M2 = sum w (z - s)^2 (s: the event's first redshift)
 // and their derivatives for the parameters a sample depends on.  Writes
 // hd[b][e] = (h, d ln h / dp for those 9 parameters), h < 0 marking W1 = 0,
-// and every sample's coefficients sc[b][field][sample]: z, c w (0: no
-// weight), d ln w / dp (9), dz / dp (4 distance parameters).
+// and every sample's coefficients: sc[b][field][sample] = z, c w (0: no
+// weight); sd[b][field][sample] = d ln w / dp (9), dz / dp (4 distance
+// parameters), in FP32 when the window sums are.
 __global__ __launch_bounds__(kGradBS) void k_event_bandwidth_grad(GradArgs a) {
   int e, b;
   if (!decode_item_lambda(a.E, a.B, e, b)) return;
@@ -269,13 +270,22 @@ __global__ __launch_bounds__(kGradBS) void k_event_bandwidth_grad(GradArgs a) {
 #pragma unroll
     for (int i = 0; i < 6; ++i) cur[i] = nxt[i];
     const double w = sg.w;
-    double* sc = a.sc + (size_t)b * kSC * a.S + q;
+    double* sc = a.sc + (size_t)b * 2 * a.S + q;
     sc[0] = sg.zp1 - 1.0;
     sc[a.S] = w > 0.0 ? a.samp_c[q] * w : 0.0;
+    if (a.f32) {
+      float* sd = (float*)a.sd + (size_t)b * kSD * a.S + q;
 #pragma unroll
-    for (int p = 0; p < kNS; ++p) sc[(size_t)(2 + p) * a.S] = sg.dlw[p];
+      for (int p = 0; p < kNS; ++p) sd[(size_t)p * a.S] = (float)sg.dlw[p];
 #pragma unroll
-    for (int p = 0; p < 4; ++p) sc[(size_t)(2 + kNS + p) * a.S] = sg.zp1 * sg.dx[p];
+      for (int p = 0; p < 4; ++p) sd[(size_t)(kNS + p) * a.S] = (float)(sg.zp1 * sg.dx[p]);
+    } else {
+      double* sd = (double*)a.sd + (size_t)b * kSD * a.S + q;
+#pragma unroll
+      for (int p = 0; p < kNS; ++p) sd[(size_t)p * a.S] = sg.dlw[p];
+#pragma unroll
+      for (int p = 0; p < 4; ++p) sd[(size_t)(kNS + p) * a.S] = sg.zp1 * sg.dx[p];
+    }
     if (!(w > 0.0)) continue;
     const double t = sg.zp1 - 1.0 - zs;
     m[0] += w;
@@ -416,7 +426,8 @@ __global__ __launch_bounds__(kGradBS) void k_event_grad(GradArgs a) {
   const CT* gft = F32 ? (const CT*)(a.gf32 + (size_t)b * 6 * a.g.n_z)
                       : (const CT*)(a.gf64 + (size_t)b * 6 * a.g.n_z);
   const int nz = a.g.n_z;
-  const double* scb = a.sc + (size_t)b * kSC * a.S;
+  const double* scb = a.sc + (size_t)b * 2 * a.S;
+  const CT* sdb = (const CT*)a.sd + (size_t)b * kSD * a.S;
   // the union of the workgroup's windows
   int lo_b = 1 << 30, hi_b = -(1 << 30);
   for (int j = threadIdx.x; j < ns; j += kGradBS) {
@@ -469,11 +480,11 @@ __global__ __launch_bounds__(kGradBS) void k_event_grad(GradArgs a) {
     const double Eg[4] = {A / P.h0, (double)sE[0], (double)sE[1], (double)sE[2]};
 #pragma unroll
     for (int p = 0; p < 4; ++p)
-      acc[1 + p] += cw * (scb[(size_t)(2 + p) * a.S + q] * A +
-                          scb[(size_t)(2 + kNS + p) * a.S + q] * Bz + Chh * hd[1 + p] + Eg[p]);
+      acc[1 + p] += cw * ((double)sdb[(size_t)p * a.S + q] * A +
+                          (double)sdb[(size_t)(kNS + p) * a.S + q] * Bz + Chh * hd[1 + p] + Eg[p]);
 #pragma unroll
     for (int p = 4; p < kNS; ++p)
-      acc[1 + p] += cw * (scb[(size_t)(2 + p) * a.S + q] * A + Chh * hd[1 + p]);
+      acc[1 + p] += cw * ((double)sdb[(size_t)p * a.S + q] * A + Chh * hd[1 + p]);
 #pragma unroll
     for (int p = 0; p < 3; ++p) acc[1 + kNS + p] += cw * (double)sE[3 + p];
   }

@@ -68,8 +68,11 @@ constexpr int kSmFBytes64 = 44 * 1024;
 constexpr int kSmFBytes32 = 36 * 1024;
 constexpr int sm_fbytes(bool f32) { return f32 ? kSmFBytes32 : kSmFBytes64; }
 constexpr int kSmGCap = 512;             // entries of the G_m table
-// per-sample gradient coefficients: z, c w, d ln w / dp (9), dz / dp (4)
+// per-sample gradient coefficients: z and c w (double), then d ln w / dp (9)
+// and dz / dp (4) (double, or float in FP32 mode)
 constexpr int kGradSampleFields = 15;
+constexpr int kGradDerivFields = 13;
+inline double grad_sample_bytes(bool f32) { return 16.0 + kGradDerivFields * (f32 ? 4.0 : 8.0); }
 // every pixel row of an event needs a row of >= 2 slots in the F slice
 static_assert(CHIMERA_MAX_EVENT_PIXELS * 2 * (int)sizeof(double) <= kSmFBytes64, "F slice too small");
 static_assert(CHIMERA_MAX_EVENT_PIXELS * 2 * (int)sizeof(float) <= kSmFBytes32, "F slice too small");
@@ -169,7 +172,9 @@ struct GradArgs {
   int E, B;
   double trunc;
   double* hd;               // [B][E][10] h and d ln h/dp (written by the bandwidth kernel)
-  double* sc;               // [B][kGradSampleFields][S] per-sample coefficients (bandwidth kernel)
+  double* sc;               // [B][2][S] z and c w of each sample (bandwidth kernel)
+  void* sd;                 // [B][13][S] d ln w/dp, dz/dp: double, or float when f32
+  int f32;
   long long S;              // samples of the event set
   double* lnI;              // [B][E]
   double* dlnI;             // [B][E][12]

@@ -87,14 +87,14 @@ def test_chunked_call_equals_its_parts(full):
 
 
 def test_gradient_chunked_call_equals_its_parts(full):
-    """The adjoint stores 15 doubles per sample and point; 160 points at this
-    size pass its 16 GiB cap, so the call runs in two chunks.  Each point's
-    ln L and gradient equal the ones from calls over the two halves."""
+    """The adjoint stores 68 bytes per sample and point in FP32; 240 points at
+    this size pass its 16 GiB cap, so the call runs in two chunks.  Each
+    point's ln L and gradient equal the ones from calls over the two halves."""
     d, chimera, ctx, es = full
-    lam = np.concatenate([d.lam, d.lam[::-1]])[:160]
+    lam = np.concatenate([d.lam, d.lam[::-1]])[:240]
     l_all, g_all = ctx.lnl_grad(es, lam, chimera.CHIMERA_FP32)
-    l_a, g_a = ctx.lnl_grad(es, lam[:80], chimera.CHIMERA_FP32)
-    l_b, g_b = ctx.lnl_grad(es, lam[80:], chimera.CHIMERA_FP32)
+    l_a, g_a = ctx.lnl_grad(es, lam[:120], chimera.CHIMERA_FP32)
+    l_b, g_b = ctx.lnl_grad(es, lam[120:], chimera.CHIMERA_FP32)
     to_np = lambda t: t.cpu().numpy() if hasattr(t, "cpu") else np.asarray(t)
     assert np.array_equal(to_np(l_all), np.concatenate([to_np(l_a), to_np(l_b)]), equal_nan=True)
     assert np.array_equal(to_np(g_all), np.concatenate([to_np(g_a), to_np(g_b)]), equal_nan=True)
