@@ -171,3 +171,61 @@ def test_grad_c4_sampled_events_match_oracle(c4):
     e32 = np.abs(g32[fin] - grad[fin]) / np.maximum(1.0, np.abs(grad[fin]))
     print("worst FP64 rel err vs oracle", worst, "FP32 vs FP64 max", e32.max())
     assert e32.max() <= 1e-2
+
+
+def wide_windows():
+    """Two events on a 1200-point grid: event 0's weighted samples spread over
+    1000..9000 Mpc, so its windows cover the whole grid (more grid points
+    than the window kernel copies to LDS: it reads the grid factor tables in
+    place); event 1 is narrow (copied)."""
+    rng = np.random.default_rng(11)
+    n_z, z_lo, z_hi = 1200, 0.0, 1.6
+    grid = np.linspace(z_lo, z_hi, n_z)
+    rows = np.stack([np.exp(-0.5 * ((grid - mu) / 0.05) ** 2) + 0.05 for mu in (0.4, 0.8, 1.1)])
+    counts = np.array([30, 25, 20])
+    dl = np.concatenate([rng.uniform(1000.0, 9000.0, 55),
+                         3000.0 * (1 + 0.05 * rng.standard_normal(20))])
+    m1 = rng.uniform(20, 60, dl.size)
+    ninj = 3000
+    im1 = rng.uniform(8, 150, ninj)
+    return dict(n_z=n_z, z_lo=z_lo, z_hi=z_hi, grid=grid, rows=rows, nz_tot=rows.mean(axis=0),
+                ev_pix_off=np.array([0, 2, 3]),
+                pix_samp_off=np.concatenate([[0], np.cumsum(counts)]),
+                pix_row=np.array([0, 1, 2]), c_ir=np.array([0.5, 0.3, 0.8]),
+                dl=dl, m1=m1, m2=m1 * rng.uniform(0.4, 1.0, dl.size),
+                idl=rng.uniform(100, 9000, ninj), im1=im1, im2=im1 * rng.uniform(0.2, 1.0, ninj),
+                lnp=np.full(ninj, -12.0), ninj=ninj * 4)
+
+
+def test_grad_wide_windows_match_oracle():
+    import oracle
+    from oracle import gradient as G
+    from paper_2504_02034_amd import chimera
+    h = wide_windows()
+    events, cat, inj = handcrafted_oracle(h)
+    lam = hand_lams()[:3]
+    # event 0's windows span more grid points than the LDS copy holds (7 x 6144 values)
+    L = oracle.likelihood
+    ev0 = events[0]
+    z, w = L.redshift_and_weight(np.concatenate([p.dl for p in ev0.pixels]),
+                                 np.concatenate([p.m1d for p in ev0.pixels]),
+                                 np.concatenate([p.m2d for p in ev0.pixels]), lam[0])
+    dz = h["grid"][1] - h["grid"][0]
+    hb = L.bandwidth(z, w, dz)
+    zw = z[w > 0]
+    lo = max(math.ceil((zw.min() - 8.6 * hb) / dz), 0)
+    hi = min(math.floor((zw.max() + 8.6 * hb) / dz), h["n_z"] - 1)
+    assert 7 * (hi - lo + 1) > 6144
+    ctx = chimera.Context(n_z=h["n_z"], z_lo=h["z_lo"], z_hi=h["z_hi"])
+    ctx.set_catalog(h["rows"], h["nz_tot"])
+    ctx.set_injections(h["idl"], h["im1"], h["im2"], h["lnp"], h["ninj"])
+    es = ctx.add_events(h["ev_pix_off"], h["pix_samp_off"], h["pix_row"], h["c_ir"], h["dl"],
+                        h["m1"], h["m2"])
+    lnl, grad = ctx.lnl_grad(es, lam, chimera.CHIMERA_FP64)
+    for b in range(lam.shape[0]):
+        ref = G.lnl_grad(events, cat, inj, lam[b], T=8.6)
+        print(b, lnl[b], ref["lnl"])
+        assert abs(lnl[b] - ref["lnl"]) <= 1e-10 * abs(ref["lnl"])
+        err = np.abs(grad[b] - ref["grad"]) / np.maximum(1.0, np.abs(ref["grad"]))
+        assert np.all(err <= 1e-8), (b, err)
+    ctx.close()
