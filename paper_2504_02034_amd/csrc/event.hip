@@ -42,11 +42,23 @@ namespace chimera {
 namespace {
 
 // acc_k <- acc_k rho_k + F_g G_(g-c) for g = hi down to lo (all chains inside
-// their windows).
+// their windows), eight grid points per iteration (then four, then one).
 template <class A, int K>
 __device__ __forceinline__ void horner_span(A (&acc)[K], const A (&rho)[K], const A* __restrict__ F,
                                             const A* __restrict__ G, int hi, int lo) {
   int g = hi;
+  for (; g - 7 >= lo; g -= 8) {
+    A av[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) av[i] = F[g - i] * G[g - i];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      A t = acc[k];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) t = fma(t, rho[k], av[i]);
+      acc[k] = t;
+    }
+  }
   for (; g - 3 >= lo; g -= 4) {
     const A a0 = F[g] * G[g];
     const A a1 = F[g - 1] * G[g - 1];
