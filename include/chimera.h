@@ -62,8 +62,10 @@ extern "C" {
 typedef struct chimera_ctx chimera_ctx;
 typedef struct chimera_events chimera_events;
 
-/* Largest number of pixel rows of one event (one row per pixel must fit the
- * kernels' on-chip slice of the catalogue density). */
+/* Largest number of pixel rows of one event.  The FP32 form stages every row
+ * of such an event in the kernels' on-chip slice of the catalogue density;
+ * FP64 does up to 2048 rows (more when the kernel windows are narrow) and
+ * evaluates a larger event by direct sums (equal up to rounding). */
 #define CHIMERA_MAX_EVENT_PIXELS 2560
 
 typedef enum {

@@ -20,6 +20,7 @@ CHIMERA_OK, CHIMERA_EINVAL, CHIMERA_ENOMEM, CHIMERA_EDEVICE, CHIMERA_ERANGE, CHI
     0, -1, -2, -3, -4, -5)
 CHIMERA_FP64, CHIMERA_FP32 = 0, 1
 CHIMERA_HOST, CHIMERA_DEVICE = 0, 1
+CHIMERA_MAX_EVENT_PIXELS = 2560
 NLAM, NGRAD = 14, 12
 
 _STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ERANGE", -5: "ESTATE"}

@@ -25,8 +25,8 @@
 //                       and are masked one bound at a time only on the edge
 //                       points where a sample's window and the group's differ;
 //                     - the unit's partial sum of c_ir w_j A_j goes to scratch.
-//                   FP64 runs three workgroups per CU (registers), FP32 four
-//                   (smaller slice, chain factors formed after the sweep).
+//                   Both run four workgroups per CU (the chain factors are
+//                   formed after the sweep, which keeps the registers low).
 // k_event_final     per (event, lambda): the units' partial sums in a fixed
 //                   order, I_i = sum / (h sqrt(2 pi)), ln I_i.
 #include <math.h>
@@ -298,21 +298,19 @@ __device__ __forceinline__ void event_smooth(const EventArgs& a) {
   const bool horner_ok = ebound < (F32 ? 60.0 : 600.0);
   const double zc = a.g.z_lo + (double)c * dz;
   const double cir = has ? a.grp_c[gi] : 0.0;
-  // c_ir w_k C_k rho_k^(lo_k - c), the factor of chain k: in FP64 computed
-  // here; in FP32 after the sweep from z_k and w_k read again, which keeps the
-  // registers low enough for four waves per SIMD
+  // c_ir w_k C_k rho_k^(lo_k - c), the factor of chain k, formed after the
+  // sweep from z_k and w_k read again, which keeps the registers low enough
+  // for four waves per SIMD
   auto chain_coef = [&](int k, double zkk, double wkk) {
     const double delta = zkk - zc;
     const double x = -0.5 * delta * delta * inv_h2 + (double)(klo[k] - c) * dz * delta * inv_h2;
     return cir * wkk * (F32 ? (double)__expf((float)x) : exp(x));
   };
   CT acc[K], rho[K];
-  double coef[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     const double delta = zk[k] - zc;
     acc[k] = (CT)0;
-    coef[k] = 0.0;
     // a chain without a window (zero weight, or outside the grid) still runs
     // through the shared bulk; rho = 0 keeps it finite (the ratio of a
     // far-away sample would overflow) and it is left out of the sum
@@ -322,7 +320,6 @@ __device__ __forceinline__ void event_smooth(const EventArgs& a) {
       rho[k] = (CT)__expf((float)(dz * delta * inv_h2));
     } else {
       rho[k] = (CT)exp(dz * delta * inv_h2);
-      coef[k] = chain_coef(k, zk[k], wk[k]);
     }
   }
   double total = 0.0, npts = 0.0;
@@ -451,11 +448,11 @@ __device__ __forceinline__ void event_smooth(const EventArgs& a) {
         }
       }
     }
-    if (F32) asm volatile("" ::: "memory");   // read z_k, w_k again
+    asm volatile("" ::: "memory");   // read z_k, w_k again
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       if (klo[k] <= khi[k]) {
-        const double ck = F32 ? chain_coef(k, zb[first + k], (double)wb[first + k]) : coef[k];
+        const double ck = chain_coef(k, zb[first + k], (double)wb[first + k]);
         total += ck * (double)acc[k];
       }
     }
@@ -463,15 +460,17 @@ __device__ __forceinline__ void event_smooth(const EventArgs& a) {
     // fallback (windows too wide for the tables or the chain range): direct sums
     const double* gzb = a.gz64 + (size_t)b * a.g.n_z;
     const size_t row = (size_t)a.slot_row[p0 + a.grp_slot[gi]] * a.g.n_z;
+    asm volatile("" ::: "memory");   // read z_k, w_k again
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       if (klo[k] > khi[k]) continue;
+      const double zkk = zb[first + k];
       double sacc = 0.0;
       for (int g = klo[k]; g <= khi[k]; ++g) {
-        const double x = (a.g.z_lo + (double)g * dz - zk[k]);
+        const double x = (a.g.z_lo + (double)g * dz - zkk);
         sacc += exp(-0.5 * x * x * inv_h2) * a.nz64[row + g] * gzb[g];
       }
-      total += cir * wk[k] * sacc;
+      total += cir * (double)wb[first + k] * sacc;
     }
   }
   double fin[1] = {total};
@@ -493,7 +492,8 @@ __device__ __forceinline__ void event_smooth(const EventArgs& a) {
   }
 }
 
-__global__ __launch_bounds__(kSmBS) void k_event_smooth64(EventArgs a) { event_smooth<false>(a); }
+__global__ __launch_bounds__(kSmBS) __attribute__((amdgpu_waves_per_eu(4)))
+void k_event_smooth64(EventArgs a) { event_smooth<false>(a); }
 
 __global__ __launch_bounds__(kSmBS) __attribute__((amdgpu_waves_per_eu(4)))
 void k_event_smooth32(EventArgs a) { event_smooth<true>(a); }

@@ -62,20 +62,26 @@ constexpr int kZwBS = 256;               // k_event_zw: threads per (event, lamb
 constexpr int kSmBS = 256;               // k_event_smooth: one sample group per thread
 constexpr int kGroupK = 8;               // samples per group (Horner chains per lane)
 constexpr int kUnitGroups = kSmBS;       // groups per work unit (chunk of one event)
-// LDS for the staged F slice: FP64 44 KB (three workgroups per CU, as the
-// registers allow), FP32 36 KB (four workgroups per CU)
-constexpr int kSmFBytes64 = 44 * 1024;
+// LDS for the staged F slice: FP64 35.5 KB, FP32 36 KB; with the G_m table
+// and the kernel's static arrays (< 512 B) four workgroups fit in a CU's
+// 160 KB, as the registers allow
+constexpr int kSmFBytes64 = 35 * 1024 + 512;
 constexpr int kSmFBytes32 = 36 * 1024;
 constexpr int sm_fbytes(bool f32) { return f32 ? kSmFBytes32 : kSmFBytes64; }
 constexpr int kSmGCap = 512;             // entries of the G_m table
+static_assert(4 * (kSmFBytes64 + kSmGCap * (int)sizeof(double) + 512) <= 160 * 1024, "LDS");
+static_assert(4 * (kSmFBytes32 + kSmGCap * (int)sizeof(float) + 512) <= 160 * 1024, "LDS");
 // per-sample gradient coefficients: z and c w (double), then d ln w / dp (9)
 // and dz / dp (4) (double, or float in FP32 mode)
 constexpr int kGradSampleFields = 15;
 constexpr int kGradDerivFields = 13;
 inline double grad_sample_bytes(bool f32) { return 16.0 + kGradDerivFields * (f32 ? 4.0 : 8.0); }
-// every pixel row of an event needs a row of >= 2 slots in the F slice
-static_assert(CHIMERA_MAX_EVENT_PIXELS * 2 * (int)sizeof(double) <= kSmFBytes64, "F slice too small");
+// every pixel row of an event needs a row of >= 2 slots in the F slice (the
+// slice and G share the pool).  FP32 holds every accepted event; FP64 holds
+// 2048 rows with a full G table, and a larger event whose rows and G do not
+// fit takes the direct sums
 static_assert(CHIMERA_MAX_EVENT_PIXELS * 2 * (int)sizeof(float) <= kSmFBytes32, "F slice too small");
+static_assert(2048 * 2 * (int)sizeof(double) <= kSmFBytes64, "F slice too small");
 
 struct EventArgs {
   const LamParams* P;

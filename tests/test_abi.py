@@ -54,3 +54,15 @@ def test_bad_config_rejected_without_device():
     with pytest.raises(chimera.ChimeraError) as e:
         chimera.chimera_create(c)
     assert e.value.status == chimera.CHIMERA_EINVAL
+
+
+def test_constants_match_header():
+    from paper_2504_02034_amd import chimera
+    src = open(os.path.join(ROOT, "include", "chimera.h")).read()
+    defined = dict(re.findall(r"#define\s+(CHIMERA_[A-Z_]+)\s+(-?\d+)", src))
+    assert int(defined["CHIMERA_MAX_EVENT_PIXELS"]) == chimera.CHIMERA_MAX_EVENT_PIXELS
+    enum = dict(re.findall(r"\b(CHIMERA_[A-Z0-9_]+)\s*=\s*(-?\d+)", src))
+    for name in ("CHIMERA_OK", "CHIMERA_EINVAL", "CHIMERA_ENOMEM", "CHIMERA_EDEVICE",
+                 "CHIMERA_ERANGE", "CHIMERA_ESTATE", "CHIMERA_FP64", "CHIMERA_FP32",
+                 "CHIMERA_HOST", "CHIMERA_DEVICE"):
+        assert int(enum[name]) == getattr(chimera, name), name

@@ -9,7 +9,6 @@ from paper_2504_02034_amd import synth
 
 pytestmark = pytest.mark.gpu
 
-MAX_PIX = 2560          # CHIMERA_MAX_EVENT_PIXELS
 N_Z = 200
 
 
@@ -107,7 +106,7 @@ def test_event_set_checks(chimera):
             ctx.add_events(*args)
         assert status(e) == want
     # one event over more pixel rows than an LDS slice can hold
-    n = MAX_PIX + 1
+    n = chimera.CHIMERA_MAX_EVENT_PIXELS + 1
     with pytest.raises(chimera.ChimeraError) as e:
         ctx.add_events(np.array([0, n]), np.arange(n + 1), np.zeros(n, np.int64), np.ones(n),
                        np.full(n, 2000.0), np.full(n, 40.0), np.full(n, 30.0))

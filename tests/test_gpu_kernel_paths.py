@@ -3,7 +3,10 @@
 grid, about 40 000 entries) does not fit the workgroup's LDS, so its units
 take direct sums in both precisions, while the narrow event of the same call
 takes the Horner sweep.  Groups whose windows share no grid point: a
-handmade event whose group spread cap is wide and bandwidth small."""
+handmade event whose group spread cap is wide and bandwidth small.  The
+largest events the library accepts: 2560 pixel rows (FP32 stages them two
+grid points per slice; FP64 takes direct sums) and 2048 rows (FP64 stages
+them one grid point per slice)."""
 import numpy as np
 import pytest
 
@@ -95,4 +98,37 @@ def test_groups_without_a_common_window():
         assert mid.size >= 2 and mid.max() - mid.min() > 2 * 8.6 * hb
     ctx, es = context(chimera, h)
     check(chimera, ctx, es, h, lam, T=8.6)
+    ctx.close()
+
+
+def many_rows_case():
+    """Event 0 over CHIMERA_MAX_EVENT_PIXELS = 2560 pixel rows, event 1 over
+    2048, one to three samples per row, distances around 3000 Mpc."""
+    rng = np.random.default_rng(31)
+    n_z, z_lo, z_hi = 200, 0.0, 1.6
+    grid = np.linspace(z_lo, z_hi, n_z)
+    n_rows = 2560
+    mu = rng.uniform(0.2, 1.2, n_rows)
+    rows = np.exp(-0.5 * ((grid[None, :] - mu[:, None]) / 0.15) ** 2) + 0.02
+    pix_row = np.concatenate([np.arange(n_rows), rng.permutation(n_rows)[:2048]])
+    counts = rng.integers(1, 4, pix_row.size)
+    S = int(counts.sum())
+    dl = 3000.0 * (1 + 0.12 * rng.standard_normal(S))
+    m1 = rng.uniform(20, 60, S)
+    ninj = 3000
+    im1 = rng.uniform(8, 150, ninj)
+    return dict(n_z=n_z, z_lo=z_lo, z_hi=z_hi, grid=grid, rows=rows, nz_tot=rows.mean(axis=0),
+                ev_pix_off=np.array([0, n_rows, pix_row.size]),
+                pix_samp_off=np.concatenate([[0], np.cumsum(counts)]), pix_row=pix_row,
+                c_ir=rng.uniform(0.2, 1.0, pix_row.size), dl=dl, m1=m1,
+                m2=m1 * rng.uniform(0.5, 0.95, S), idl=rng.uniform(100, 9000, ninj), im1=im1,
+                im2=im1 * rng.uniform(0.2, 1.0, ninj), lnp=np.full(ninj, -12.0), ninj=ninj * 4)
+
+
+def test_events_with_the_most_pixel_rows():
+    from paper_2504_02034_amd import chimera
+    h = many_rows_case()
+    assert h["ev_pix_off"][1] == chimera.CHIMERA_MAX_EVENT_PIXELS
+    ctx, es = context(chimera, h)
+    check(chimera, ctx, es, h, hand_lams()[:2], T=8.6)
     ctx.close()
