@@ -268,6 +268,13 @@ __device__ __forceinline__ void event_smooth(const EventArgs& a) {
       }
     }
   }
+  // Horner ratios rho_k = exp(dz (z_k - z_c) / h^2); a chain without a window
+  // (zero weight, or outside the grid) still runs through the shared bulk:
+  // rho = 0 keeps it finite (the ratio of a far-away sample would overflow)
+  // and it is left out of the sum
+  CT rho[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) rho[k] = (CT)0;
   int c = 0;
   double mloc = 0.0, dloc = 0.0;
   if (zn > 0.0) {
@@ -276,8 +283,13 @@ __device__ __forceinline__ void event_smooth(const EventArgs& a) {
     mloc = (double)max(hi_u - c, c - lo_u);
     const double zc0 = a.g.z_lo + cd * dz;
 #pragma unroll
-    for (int k = 0; k < K; ++k)
-      if (klo[k] <= khi[k]) dloc = fmax(dloc, fabs(zk[k] - zc0));
+    for (int k = 0; k < K; ++k) {
+      if (klo[k] <= khi[k]) {
+        const double delta = zk[k] - zc0;
+        dloc = fmax(dloc, fabs(delta));
+        rho[k] = F32 ? (CT)__expf((float)(dz * delta * inv_h2)) : (CT)exp(dz * delta * inv_h2);
+      }
+    }
   }
   // unit bounds, chain range and the largest |z_k - centre| (rounded up to
   // FP32 and compared as its bit pattern, which orders non-negative floats)
@@ -306,22 +318,9 @@ __device__ __forceinline__ void event_smooth(const EventArgs& a) {
     const double x = -0.5 * delta * delta * inv_h2 + (double)(klo[k] - c) * dz * delta * inv_h2;
     return cir * wkk * (F32 ? (double)__expf((float)x) : exp(x));
   };
-  CT acc[K], rho[K];
+  CT acc[K];
 #pragma unroll
-  for (int k = 0; k < K; ++k) {
-    const double delta = zk[k] - zc;
-    acc[k] = (CT)0;
-    // a chain without a window (zero weight, or outside the grid) still runs
-    // through the shared bulk; rho = 0 keeps it finite (the ratio of a
-    // far-away sample would overflow) and it is left out of the sum
-    if (klo[k] > khi[k]) {
-      rho[k] = (CT)0;
-    } else if (F32) {
-      rho[k] = (CT)__expf((float)(dz * delta * inv_h2));
-    } else {
-      rho[k] = (CT)exp(dz * delta * inv_h2);
-    }
-  }
+  for (int k = 0; k < K; ++k) acc[k] = (CT)0;
   double total = 0.0, npts = 0.0;
   if (a.count) {
 #pragma unroll
