@@ -27,7 +27,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}     # MI355X published dense vector peaks
-FLOPS_PER_EVAL = 2.0                            # one multiply-add per kernel evaluation
+# FP32 without packed instructions (the build turns them off): one FMA per lane per cycle
+PEAK_TFLOPS_UNPACKED = {"fp64": 78.6, "fp32": 78.6}
+# algorithmic cost of one (sample, grid point) kernel evaluation: the Gaussian
+# recurrence K_{g+1} = K_g r_g, r_{g+1} = r_g q and the multiply-add of K F
+# into the sum, 4 flops (the kernels' Horner chains spend one FMA per pair)
+FLOPS_PER_EVAL = 4.0
 
 
 def log(msg):
@@ -76,24 +81,41 @@ def time_precision(ctx, es, lam_t, prec, steps, warmup):
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_event_kernels_precision_300ev.json")
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "counters_event_kernels_precision_300ev.json")
 
 
-def measured_traffic(kernel, workload):
-    """HBM bytes per launch of `kernel` from the committed counter summary, or
-    None when the summary is absent, for another workload, or taken on sources
-    that differ from the ones built now."""
+def current_summary(path, workload):
+    """A committed counter summary (JSON), or None when it is absent, for
+    another workload, or taken on sources that differ from the ones built now."""
     import hashlib
-    if workload != "precision_300ev" or not os.path.exists(TRAFFIC_FILE):
+    if workload != "precision_300ev" or not os.path.exists(path):
         return None
-    with open(TRAFFIC_FILE) as f:
+    with open(path) as f:
         t = json.load(f)
     h = hashlib.sha256()
     for src in t["sources"]:
         with open(os.path.join(ROOT, src), "rb") as f:
             h.update(f.read())
-    if h.hexdigest() != t["sources_sha256"] or kernel not in t["kernels"]:
+    return t if h.hexdigest() == t["sources_sha256"] else None
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` from the committed traffic summary (or None)."""
+    t = current_summary(TRAFFIC_FILE, workload)
+    if t is None or kernel not in t["kernels"]:
         return None
     return t["kernels"][kernel]["traffic_bytes"]
+
+
+def measured_counters(kernel, workload):
+    """VALU lane instructions per evaluated pair and the VALU busy fraction of
+    `kernel` from the committed instruction-counter summary (or None)."""
+    t = current_summary(COUNTERS_FILE, workload)
+    if t is None or kernel not in t["kernels"]:
+        return None
+    k = t["kernels"][kernel]
+    return {"valu_lane_instr_per_pair": k["valu_lane_instr_per_pair"],
+            "valu_busy": k["valu_busy"], "source": os.path.relpath(COUNTERS_FILE, ROOT)}
 
 
 def pct(v, q):
@@ -138,11 +160,46 @@ def cpu_baseline(wl, cf, ev, inj, lams, n_events):
                       f"{wl.n_events}/{n_events}; measured {t_all:.1f}s"}
 
 
-def tile_events(p, n_events):
-    """A prepared event set of n_events made by cycling through p's events
-    (same catalogue rows), for serving workloads larger than the generated set."""
-    from paper_2504_02034_amd import prep
-    return prep.subset(p, [i % p.n_events for i in range(n_events)])
+def grad_checks(ctx, es, lam_t, n_points=2):
+    """At the full gradient workload: the FP32 adjoint's error against FP64 over
+    every finite point, and the FP64 adjoint against central differences of
+    the FP64 ln L (step 1e-5 relative, all 12 parameters) at a few points.
+    ln L jumps where a source-frame mass crosses the mass model's hard edges
+    inside the step: a (point, parameter) whose differences at steps h and h/2
+    disagree by more than 10 % is counted as such and left out."""
+    import numpy as np
+
+    from paper_2504_02034_amd import chimera, synth
+    lam = lam_t.cpu().numpy()
+    l64, g64 = ctx.lnl_grad(es, lam, chimera.CHIMERA_FP64)
+    _, g32 = ctx.lnl_grad(es, lam, chimera.CHIMERA_FP32)
+    fin = np.flatnonzero(np.isfinite(l64))
+    rel32 = np.abs(g32[fin] - g64[fin]) / np.maximum(1.0, np.abs(g64[fin]))
+    def central(l, p, st):
+        lp, lm = l.copy(), l.copy()
+        lp[p] += st
+        lm[p] -= st
+        return (ctx.lnl(es, lp[None], chimera.CHIMERA_FP64)[0]
+                - ctx.lnl(es, lm[None], chimera.CHIMERA_FP64)[0]) / (2 * st)
+
+    worst, jumps, n = 0.0, 0, 0
+    for b in fin[:: max(1, fin.size // n_points)][:n_points]:
+        for kk, p in enumerate(synth.GRAD_COLUMNS):
+            st = 1e-5 * abs(lam[b, p])
+            fd, fd2 = central(lam[b], p, st), central(lam[b], p, 0.5 * st)
+            n += 1
+            if abs(fd - fd2) > 0.1 * max(1.0, abs(fd2)):
+                jumps += 1
+                continue
+            worst = max(worst, abs(g64[b, kk] - fd) / max(1.0, abs(fd)))
+    log(f"grad checks: FP32 vs FP64 max rel {rel32.max() if rel32.size else None}, "
+        f"FP64 vs central differences max rel {worst:.2e} ({jumps} of {n} pairs with a jump)")
+    return {"finite_points": int(fin.size),
+            "fp32_vs_fp64_max_rel_err": float(rel32.max()) if rel32.size else None,
+            "fp64_vs_central_difference": {"points": int(min(n_points, fin.size)),
+                                           "step_rel": 1e-5, "pairs": n,
+                                           "pairs_with_a_jump": jumps,
+                                           "max_rel_err": float(worst)}}
 
 
 def time_grad(ctx, es, lam_t, prec, steps):
@@ -156,31 +213,38 @@ def time_grad(ctx, es, lam_t, prec, steps):
     return (time.perf_counter() - t) / steps
 
 
-def serve_bench(ctx, p, n_requests=300, seed=5):
-    """Poisson trace against resident event sets of 50, 300 and 1000 events
-    sharing one catalogue and injection set: request sizes log-uniform in
-    1..512, event set uniform.  First the FP32 server is saturated (every
-    request queued at once) to measure its throughput; the open-loop trace
-    then arrives at 0.7 of that rate.  The FP32 server (continuous batching,
-    4 streams, HBM budget) and plain FP64 launches, one request at a time,
-    replay the same trace."""
+def serve_bench(wl, cf, inj, n_requests=300, seed=5, max_pass_s=0.05):
+    """Serving: resident event sets of 50, 300, 1000 and 3000 distinct events
+    x 4096 samples (nested subsets of one generated set of 3000) sharing the
+    workload's catalogue and injections; a Poisson trace of requests, sizes
+    log-uniform in 1..512, event set uniform.  First the FP32 server is
+    saturated (every request queued at once) to measure its throughput; the
+    open-loop trace then arrives at 0.7 of that rate.  The FP32 server
+    (continuous batching, 4 streams, HBM budget, passing bounded by
+    max_pass_s) and plain FP64 launches, one request at a time, replay the
+    same trace."""
     import numpy as np
 
     from paper_2504_02034_amd import chimera, prep, synth
     from paper_2504_02034_amd.server import HipExecutor, Server
-    sizes = (50, 300, 1000)
-    sets = [ctx.add_prepared(prep.subset(p, list(range(50)))), ctx.add_prepared(p),
-            ctx.add_prepared(tile_events(p, 1000))]
+    sizes = (50, 300, 1000, 3000)
+    t = time.perf_counter()
+    ev = synth.make_events(wl, cf, n_events=sizes[-1], n_samples=4096, child=6)
+    p = prep.prepare(cf[0], ev, wl.n_z, wl.z_lo, wl.z_hi, cred=wl.cred)
+    log(f"serving inputs ready in {time.perf_counter() - t:.1f}s: {p.n_events} events, "
+        f"{p.dl.size} samples, {p.nz.shape[0]} catalogue rows")
+    ctx, full = chimera.context_from_prepared(p, inj, device=0, n_tab=8192)
+    sets = [ctx.add_prepared(prep.subset(p, list(range(n)))) for n in sizes[:-1]] + [full]
     rng = np.random.default_rng(seed)
     B = np.clip(np.floor(np.exp(rng.uniform(0.0, math.log(513.0), n_requests))).astype(int), 1, 512)
-    which = rng.integers(0, 3, n_requests)
+    which = rng.integers(0, len(sets), n_requests)
     base = synth.make_lambdas(synth.WORKLOADS["precision_300ev"])
     lams = [base[rng.integers(0, base.shape[0], b)] for b in B]
     gaps = rng.exponential(1.0, n_requests)
-    ex = HipExecutor(ctx)
+    ex = HipExecutor(ctx, max_fused=512)
     biggest = max(ex.scratch_bytes(sets[w], int(b), chimera.CHIMERA_FP32) for b, w in zip(B, which))
     budget = int(2.5 * biggest)
-    srv = Server(ex, n_workers=4, max_fused=512, hbm_budget=budget)
+    srv = Server(ex, n_workers=4, max_fused=512, hbm_budget=budget, max_pass_s=max_pass_s)
     srv.wait(srv.submit(sets[1], lams[0][:1], chimera.CHIMERA_FP32))      # warm up
     # saturated throughput: the whole trace queued at once
     srv.reset_stats()
@@ -203,6 +267,7 @@ def serve_bench(ctx, p, n_requests=300, seed=5):
         srv.wait(t)
     st = srv.stats()
     srv.close()
+    held = ctx.scratch_held()
     # plain FP64 launches, one request at a time, same trace
     lat = []
     t0 = time.perf_counter()
@@ -214,10 +279,12 @@ def serve_bench(ctx, p, n_requests=300, seed=5):
         lat.append(time.perf_counter() - t0 - arrivals[i])
     span64 = time.perf_counter() - t0
     lat = sorted(lat)
-    for es in sets:
-        es.release()
+    ctx.close()
+    log(f"serving: FP32 server p50 {st['p50_ms']:.1f} ms p99 {st['p99_ms']:.1f} ms, "
+        f"{st['requests_per_launch']:.2f} requests per launch")
     return {
-        "requests": n_requests, "event_sets": list(sizes), "batch": "log-uniform 1..512",
+        "requests": n_requests, "event_sets": list(sizes), "samples_per_event": 4096,
+        "batch": "log-uniform 1..512",
         "saturated_fp32_evals_per_s": round(float(B.sum()) / t_sat, 1),
         "saturated_requests_per_launch": round(sat["requests_per_launch"], 3),
         "arrival_rate_req_s": round(rate, 2),
@@ -225,9 +292,12 @@ def serve_bench(ctx, p, n_requests=300, seed=5):
                         "p50_ms": round(st["p50_ms"], 3), "p99_ms": round(st["p99_ms"], 3),
                         "launches": st["launches"],
                         "requests_per_launch": round(st["requests_per_launch"], 3),
+                        "passed": st["passed"], "scratch_releases": st["releases"],
                         "peak_inflight": st["peak_inflight"],
                         "peak_scratch_gb": round(st["peak_bytes"] / 2**30, 2),
-                        "hbm_budget_gb": round(budget / 2**30, 2)},
+                        "scratch_held_after_gb": round(held / 2**30, 2),
+                        "hbm_budget_gb": round(budget / 2**30, 2),
+                        "max_pass_ms": round(max_pass_s * 1e3, 1)},
         "fp64_plain": {"evals_per_s": round(float(B.sum()) / span64, 1),
                        "p50_ms": round(pct(lat, 50) * 1e3, 3),
                        "p99_ms": round(pct(lat, 99) * 1e3, 3)},
@@ -298,8 +368,9 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-grad", action="store_true")
     ap.add_argument("--no-photo", action="store_true")
-    ap.add_argument("--photo-all", action="store_true",
-                    help="the photometric workload for the three Xi0 truths 0.6, 1.0, 1.8")
+    ap.add_argument("--photo-one", action="store_true",
+                    help="the photometric workload for the Xi0 = 1 truth only (default: the "
+                         "three truths 0.6, 1.0, 1.8)")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="first copy 1 GiB device to device (a kernel of known traffic "
                          "for calibrating the FETCH_SIZE / WRITE_SIZE counters)")
@@ -342,11 +413,15 @@ def main():
 
     def roof(name):
         r = res[name]
+        kern = "chimera::k_event_smooth" + name[2:]
         return {"bound": "alu", "achieved": round(r["achieved"], 3), "peak": PEAK_TFLOPS[name],
                 "unit": "TFLOP/s", "frac": round(r["achieved"] / PEAK_TFLOPS[name], 4),
-                "traffic": measured_traffic("chimera::k_event_smooth" + name[2:], wl.name),
+                "traffic": measured_traffic(kern, wl.name),
                 "kernel": "k_event_smooth" + name[2:],
-                "kernel_ms": round(r["avg_ms"], 4), "evals_per_launch": int(r["evals"])}
+                "kernel_ms": round(r["avg_ms"], 4), "evals_per_launch": int(r["evals"]),
+                "flops_per_eval": FLOPS_PER_EVAL,
+                "frac_of_unpacked_peak": round(r["achieved"] / PEAK_TFLOPS_UNPACKED[name], 4),
+                "counters": measured_counters(kern, wl.name)}
 
     k = args.steps
     w32 = res["fp32"]["wall"]
@@ -382,14 +457,14 @@ def main():
             g[name] = {"ms": round(sec * 1e3, 3), "evals_per_s": round(lam_g.shape[0] / sec, 1),
                        "over_forward": round(sec / (res[name]["wall"] / k * lam_g.shape[0] / B), 2)}
             log(f"grad {name}: {sec * 1e3:.2f} ms for {lam_g.shape[0]} lambda")
+        g.update(grad_checks(ctx, es, lam_g))
         line["grad"] = g
-    if not args.no_serve:
-        log("serving trace")
-        line["serving"] = serve_bench(ctx, p)
     ctx.close()
+    if not args.no_serve:
+        line["serving"] = serve_bench(wl, cf, inj)
     if not args.no_photo:
         log("photometric workload")
-        line["photometric"] = photo_bench((0.6, 1.0, 1.8) if args.photo_all else (1.0,))
+        line["photometric"] = photo_bench((1.0,) if args.photo_one else (0.6, 1.0, 1.8))
     if not args.no_cpu_baseline:
         log("timing the CPU oracle (cpu_baseline)")
         fin_idx = np.flatnonzero(np.isfinite(res["fp64"]["out"]))[:args.cpu_lambdas]

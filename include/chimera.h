@@ -187,15 +187,28 @@ chimera_status chimera_selection_xi(chimera_ctx* ctx, const double* lam, int64_t
 
 /* Device scratch (bytes) that one launch sequence of chimera_lnl_batch uses
  * for B points of event set ev (NULL: the selection alone) in precision prec
- * and memory mode mem, rounded up to a power of two.  The context keeps one
- * scratch block per stream, grown to the largest such size used on that
- * stream and reused by later calls on it (work on a stream runs in order);
- * the blocks are freed by chimera_destroy.  For admission control by an HBM
- * budget: chimera_config's hbm_budget bounds one call; a scheduler of
- * concurrent calls on several streams sums these.  For a chunked call (see
+ * and memory mode mem, rounded up to a power of two (with an event set, the
+ * per-event ln I_i buffer is always counted).  The context keeps one scratch
+ * block per stream, grown to the largest such size used on that stream and
+ * reused by later calls on it (work on a stream runs in order); a call holds
+ * its stream's block until its last launch is enqueued (a host call until its
+ * results are back), so calls from several host threads on one stream run
+ * one after the other.  For admission control by an HBM budget:
+ * chimera_config's hbm_budget bounds one call; a scheduler of concurrent
+ * calls on several streams bounds the sum of the blocks (chimera_scratch_held)
+ * and frees idle ones (chimera_release_scratch).  For a chunked call (see
  * chimera_lnl_batch) this is one chunk's scratch. */
 chimera_status chimera_scratch_bytes(chimera_ctx* ctx, const chimera_events* ev, int64_t B,
                                      int32_t prec, int32_t mem, size_t* bytes);
+
+/* Bytes of the scratch blocks the context holds, summed over its streams. */
+chimera_status chimera_scratch_held(chimera_ctx* ctx, size_t* bytes);
+
+/* Free the scratch block of hip_stream (after the work enqueued on it) and
+ * return the freed memory to the device, keeping in the stream-ordered pool
+ * only what the context's other blocks add up to.  Synchronises hip_stream.
+ * A later call on the stream allocates a new block. */
+chimera_status chimera_release_scratch(chimera_ctx* ctx, void* hip_stream);
 
 /* ln L and its gradient at B points (the adjoint of eq. hyperlike through
  * every step above: the redshift of each sample as an implicit function of

@@ -31,8 +31,8 @@ EXPORTS = ("chimera_default_config", "chimera_create", "chimera_destroy", "chime
            "chimera_set_injections",
            "chimera_add_events",
            "chimera_release_events", "chimera_lnl_batch", "chimera_selection_xi",
-           "chimera_lnl_grad", "chimera_scratch_bytes", "chimera_profile_enable",
-           "chimera_profile_read")
+           "chimera_lnl_grad", "chimera_scratch_bytes", "chimera_scratch_held",
+           "chimera_release_scratch", "chimera_profile_enable", "chimera_profile_read")
 
 
 class ChimeraError(RuntimeError):
@@ -84,6 +84,8 @@ def _load():
         "chimera_lnl_grad": (ctypes.c_int, [_P, _P, _P, _I64, _I32, _P, _P, _I32, _P]),
         "chimera_scratch_bytes": (ctypes.c_int, [_P, _P, _I64, _I32, _I32,
                                                  ctypes.POINTER(ctypes.c_size_t)]),
+        "chimera_scratch_held": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_size_t)]),
+        "chimera_release_scratch": (ctypes.c_int, [_P, _P]),
         "chimera_profile_enable": (ctypes.c_int, [_P, _I32]),
         "chimera_profile_read": (ctypes.c_int, [_P, ctypes.POINTER(_I64),
                                                 ctypes.POINTER(ctypes.c_double),
@@ -256,6 +258,16 @@ def chimera_scratch_bytes(h, ev, B, prec=CHIMERA_FP64, mem=CHIMERA_DEVICE) -> in
     return out.value
 
 
+def chimera_scratch_held(h) -> int:
+    out = ctypes.c_size_t()
+    _check(lib.chimera_scratch_held(h, ctypes.byref(out)))
+    return out.value
+
+
+def chimera_release_scratch(h, stream=None):
+    _check(lib.chimera_release_scratch(h, _stream_ptr(stream)))
+
+
 def chimera_profile_enable(h, on=True):
     _check(lib.chimera_profile_enable(h, 1 if on else 0))
 
@@ -337,6 +349,12 @@ class Context:
     def scratch_bytes(self, ev: EventSet, B, prec=CHIMERA_FP64, mem=CHIMERA_DEVICE) -> int:
         return chimera_scratch_bytes(self.handle, ev.handle if ev is not None else None, B, prec,
                                      mem)
+
+    def scratch_held(self) -> int:
+        return chimera_scratch_held(self.handle)
+
+    def release_scratch(self, stream=None):
+        chimera_release_scratch(self.handle, stream)
 
     def lnl_grad(self, ev: EventSet, lam, prec=CHIMERA_FP64, stream=None):
         """(ln L [B], d ln L / d(GRAD_NAMES) [B, 12])."""

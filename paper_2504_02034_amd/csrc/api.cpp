@@ -6,7 +6,9 @@
 #include <cmath>
 #include <cstring>
 #include <limits>
+#include <atomic>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -110,8 +112,17 @@ struct chimera_ctx {
   double inj_dmin = 0.0, inj_dmax = 0.0;
   bool has_cat = false, has_inj = false;
   std::vector<chimera_events*> events;
-  // per-stream scratch arenas (grow only; freed by chimera_destroy)
-  std::map<hipStream_t, std::pair<void*, size_t>> arenas;
+  // per-stream scratch arenas (grown to the largest call on the stream; freed
+  // by chimera_release_scratch or chimera_destroy).  A call holds its
+  // stream's lock from taking the arena until its last enqueue (for host
+  // calls until its results are back), so calls on one stream from several
+  // host threads cannot interleave their use of the arena.
+  struct Arena {
+    void* p = nullptr;
+    std::atomic<size_t> n{0};
+    std::mutex mu;
+  };
+  std::map<hipStream_t, std::unique_ptr<Arena>> arenas;
   // diagnostics
   bool profile = false;
   unsigned long long* d_count = nullptr;
@@ -279,7 +290,7 @@ void chimera_destroy(chimera_ctx* ctx) {
     (void)hipEventDestroy(m.second);
   }
   dfree(ctx->d_count);
-  for (auto& a : ctx->arenas) dfree(a.second.first);
+  for (auto& a : ctx->arenas) dfree(a.second->p);
   for (auto* e : ctx->events) free_events(e);
   free_catalog(ctx);
   free_injections(ctx);
@@ -651,25 +662,32 @@ int64_t lambda_chunk(const chimera_events* ev, int64_t B, bool f32) {
   return std::min(B, c);
 }
 
-// The scratch block of stream st, at least `bytes` large.  Work on one stream
-// runs in order, so consecutive calls on it can share the block; a block that
-// has to grow is released in stream order (after the work that used it).
-static hipError_t stream_scratch(chimera_ctx* ctx, hipStream_t st, size_t bytes, void** out) {
+// The arena of stream st (created empty on first use).
+static chimera_ctx::Arena* arena_of(chimera_ctx* ctx, hipStream_t st) {
   std::lock_guard<std::mutex> lk(ctx->mu);
   auto& a = ctx->arenas[st];
-  if (a.second < bytes) {
-    if (a.first) {
-      hipError_t e = hipFreeAsync(a.first, st);
+  if (!a) a.reset(new chimera_ctx::Arena());
+  return a.get();
+}
+
+// The arena's block, at least `bytes` large (the caller holds ar->mu).  Work
+// on one stream runs in order, so consecutive calls on it share the block; a
+// block that has to grow is released in stream order (after the work that
+// used it).
+static hipError_t arena_reserve(chimera_ctx::Arena* ar, hipStream_t st, size_t bytes, void** out) {
+  if (ar->n < bytes) {
+    if (ar->p) {
+      hipError_t e = hipFreeAsync(ar->p, st);
       if (e != hipSuccess) return e;
-      a.first = nullptr;
-      a.second = 0;
+      ar->p = nullptr;
+      ar->n = 0;
     }
     const size_t n = pool_size(bytes);
-    hipError_t e = hipMallocAsync(&a.first, n, st);
+    hipError_t e = hipMallocAsync(&ar->p, n, st);
     if (e != hipSuccess) return e;
-    a.second = n;
+    ar->n = n;
   }
-  *out = a.first;
+  *out = ar->p;
   return hipSuccess;
 }
 
@@ -701,7 +719,9 @@ static chimera_status run_chunk(chimera_ctx* ctx, const chimera_events* ev, cons
     return fail(CHIMERA_ENOMEM, "call needs " + std::to_string(bytes) +
                                     " scratch bytes, over the context's hbm_budget");
   void* base = nullptr;
-  HIP_TRY(stream_scratch(ctx, st, bytes, &base));
+  chimera_ctx::Arena* ar = arena_of(ctx, st);
+  std::lock_guard<std::mutex> stream_lock(ar->mu);
+  HIP_TRY(arena_reserve(ar, st, bytes, &base));
   Carve cv;
   cv.base = (char*)base;
   carve(cv, s, g, B, E, nchunk, host, need_lnI, ev != nullptr, host, S_ev, U_ev, f32);
@@ -802,9 +822,53 @@ chimera_status chimera_scratch_bytes(chimera_ctx* ctx, const chimera_events* ev,
   const Geometry g = make_geometry(ctx, dmin, dmax);
   Scratch s;
   Carve probe;
-  *bytes = pool_size(carve(probe, s, g, B, E, selection_chunks(ctx->n_det), host, ev && host,
+  // lnI is counted whenever there is an event set: a device call without an
+  // lnI output keeps it in the scratch
+  *bytes = pool_size(carve(probe, s, g, B, E, selection_chunks(ctx->n_det), host, ev != nullptr,
                            ev != nullptr, host, ev ? ev->n_samp : 0, ev ? ev->U : 0,
                            prec == CHIMERA_FP32));
+  return CHIMERA_OK;
+}
+
+chimera_status chimera_scratch_held(chimera_ctx* ctx, size_t* bytes) {
+  if (!ctx || !bytes) return fail(CHIMERA_EINVAL, "null argument");
+  std::vector<chimera_ctx::Arena*> all;
+  {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    for (auto& a : ctx->arenas) all.push_back(a.second.get());
+  }
+  size_t n = 0;
+  for (auto* ar : all) {
+    std::lock_guard<std::mutex> lk(ar->mu);
+    n += ar->n;
+  }
+  *bytes = n;
+  return CHIMERA_OK;
+}
+
+chimera_status chimera_release_scratch(chimera_ctx* ctx, void* hip_stream) {
+  if (!ctx) return fail(CHIMERA_EINVAL, "null context");
+  hipStream_t st = (hipStream_t)hip_stream;
+  chimera_ctx::Arena* ar = arena_of(ctx, st);
+  std::lock_guard<std::mutex> lk(ar->mu);
+  HIP_TRY(hipSetDevice(ctx->cfg.device));
+  if (ar->p) {
+    HIP_TRY(hipFreeAsync(ar->p, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    ar->p = nullptr;
+    ar->n = 0;
+  }
+  // hand the freed block back to the device: keep only what the other
+  // streams' arenas may still take from the pool
+  size_t keep = 0;
+  {
+    std::lock_guard<std::mutex> lk2(ctx->mu);
+    for (auto& a : ctx->arenas)
+      if (a.second.get() != ar) keep += a.second->n;
+  }
+  hipMemPool_t pool;
+  if (hipDeviceGetDefaultMemPool(&pool, ctx->cfg.device) == hipSuccess)
+    (void)hipMemPoolTrimTo(pool, keep);
   return CHIMERA_OK;
 }
 
@@ -893,7 +957,9 @@ static chimera_status run_grad_chunk(chimera_ctx* ctx, const chimera_events* ev,
     return fail(CHIMERA_ENOMEM, "call needs " + std::to_string(bytes) +
                                     " scratch bytes, over the context's hbm_budget");
   void* base = nullptr;
-  HIP_TRY(stream_scratch(ctx, st, bytes, &base));
+  chimera_ctx::Arena* ar = arena_of(ctx, st);
+  std::lock_guard<std::mutex> stream_lock(ar->mu);
+  HIP_TRY(arena_reserve(ar, st, bytes, &base));
   Carve cv;
   cv.base = (char*)base;
   lay(cv, a, sa, fa, &lam_d, &P, &chi, &inv, &dtab, &chio, &gz64, &gz32, &fm, &fr);

@@ -4,8 +4,8 @@ submit(events, lam [B, 14], prec) -> Ticket; wait(ticket) -> ln L [B];
 stats() -> evals/s, p50 / p99 latency and admission figures.
 
 The event sets, the catalogue and the injections stay resident in the
-library's context.  Worker threads, each with its own HIP stream, take work
-as they free up:
+library's context.  Worker threads, each with its own HIP stream and its own
+preallocated pinned and device buffers, take work as they free up:
 
 * continuous batching: a free worker takes the oldest pending request and,
   with it, every other pending request on the same event set and precision
@@ -13,10 +13,15 @@ as they free up:
   one call; each point's result does not depend on the others in its batch
   (every per-lambda reduction has a fixed order), so a request gets the same
   numbers alone and in any mix;
-* admission by HBM budget: a launch starts only while the device scratch of
-  all launches in flight (chimera_scratch_bytes) stays within `hbm_budget`;
-  the oldest request is never passed over, so a large one waits for memory
-  rather than starving;
+* admission by HBM budget: the library keeps one scratch block per stream,
+  grown to the largest call made on it, so the memory held is the sum of
+  the workers' blocks.  A worker takes a group only while that sum, with its
+  own block grown to the group's need (chimera_scratch_bytes), stays within
+  `hbm_budget`; when it would not, the blocks of idle workers are released
+  (chimera_release_scratch) first;
+* passing: when the oldest request cannot get memory, a later request that
+  can may run first, as long as the oldest has waited less than `max_pass_s`
+  (0: never pass; the oldest then waits for memory);
 * work of different workers overlaps on the device (one stream each).
 
 The executor is pluggable: HipExecutor runs the library; tests of the
@@ -51,57 +56,80 @@ class Ticket:
 
 
 class HipExecutor:
-    """Runs fused requests through chimera_lnl_batch on a per-worker stream."""
+    """Runs fused requests through chimera_lnl_batch on a per-worker stream,
+    with per-worker pinned host and device buffers for lambda and ln L (no
+    allocation per request)."""
 
-    def __init__(self, ctx):
+    class Worker:
+        def __init__(self, torch, max_fused):
+            self.stream = torch.cuda.Stream()
+            self.lam_h = torch.empty((max_fused, 14), dtype=torch.float64, pin_memory=True)
+            self.out_h = torch.empty(max_fused, dtype=torch.float64, pin_memory=True)
+            self.lam_d = torch.empty((max_fused, 14), dtype=torch.float64, device="cuda")
+            self.out_d = torch.empty(max_fused, dtype=torch.float64, device="cuda")
+            self.done = torch.cuda.Event()
+
+    def __init__(self, ctx, max_fused: int = 512):
         import torch
         self.torch = torch
         self.ctx = ctx
+        self.max_fused = max_fused
 
     def new_worker(self):
-        return self.torch.cuda.Stream()
+        return HipExecutor.Worker(self.torch, self.max_fused)
 
     def scratch_bytes(self, events, B, prec) -> int:
         from . import chimera
-        # lambda and ln L device buffers of the call, plus the library's scratch
-        return self.ctx.scratch_bytes(events, B, prec, chimera.CHIMERA_DEVICE) + 15 * 8 * B
+        return self.ctx.scratch_bytes(events, B, prec, chimera.CHIMERA_DEVICE)
 
-    def run(self, stream, events, lam, prec) -> np.ndarray:
+    def release(self, worker):
+        self.ctx.release_scratch(worker.stream)
+
+    def run(self, worker, events, lam, prec) -> np.ndarray:
         torch = self.torch
-        with torch.cuda.stream(stream):
-            lam_d = torch.from_numpy(lam).pin_memory().to("cuda", non_blocking=True)
-            out = self.ctx.lnl(events, lam_d, prec, stream=stream)
-            host = out.to("cpu", non_blocking=True)
-        stream.synchronize()
-        return host.numpy()
+        B = lam.shape[0]
+        worker.lam_h[:B].copy_(torch.from_numpy(lam))
+        with torch.cuda.stream(worker.stream):
+            worker.lam_d[:B].copy_(worker.lam_h[:B], non_blocking=True)
+            self.ctx.lnl(events, worker.lam_d[:B], prec, lnl=worker.out_d[:B],
+                         stream=worker.stream)
+            worker.out_h[:B].copy_(worker.out_d[:B], non_blocking=True)
+            worker.done.record(worker.stream)
+        worker.done.synchronize()
+        return worker.out_h[:B].numpy().copy()
 
 
 class Server:
     def __init__(self, executor, n_workers: int = 4, max_fused: int = 512,
-                 hbm_budget: int = 0):
+                 hbm_budget: int = 0, max_pass_s: float = 0.0):
         if n_workers < 1 or max_fused < 1:
             raise ValueError("n_workers and max_fused must be >= 1")
         self.ex = executor
         self.max_fused = max_fused
         self.budget = int(hbm_budget)          # 0: no limit
+        self.max_pass_s = float(max_pass_s)
         self._mu = threading.Lock()
         self._cv = threading.Condition(self._mu)
         self._pending: collections.deque = collections.deque()
         self._next_id = 0
-        self._in_use = 0
         self._stop = False
+        self._worker_objs = [self.ex.new_worker() for _ in range(n_workers)]
+        self._arena = [0] * n_workers          # scratch block held by each worker's stream
+        self._busy = [False] * n_workers
         # statistics
         self._lat = []
         self._evals = 0
         self._launches = 0
         self._fused_requests = 0
+        self._passed = 0
+        self._releases = 0
         self._peak_bytes = 0
         self._peak_inflight = 0
         self._inflight = 0
         self._t0 = None
         self._t_last = None
-        self._workers = [threading.Thread(target=self._loop, args=(self.ex.new_worker(),),
-                                          daemon=True) for _ in range(n_workers)]
+        self._workers = [threading.Thread(target=self._loop, args=(w,), daemon=True)
+                         for w in range(n_workers)]
         for w in self._workers:
             w.start()
 
@@ -145,6 +173,8 @@ class Server:
                 "p99_ms": float(np.percentile(lat, 99)) if lat.size else float("nan"),
                 "launches": self._launches,
                 "requests_per_launch": self._fused_requests / max(self._launches, 1),
+                "passed": self._passed,
+                "releases": self._releases,
                 "peak_bytes": self._peak_bytes,
                 "peak_inflight": self._peak_inflight,
                 "budget": self.budget,
@@ -154,7 +184,8 @@ class Server:
         """Forget the statistics so far (e.g. after a warm-up request)."""
         with self._mu:
             self._lat, self._evals, self._launches, self._fused_requests = [], 0, 0, 0
-            self._peak_bytes, self._peak_inflight = self._in_use, self._inflight
+            self._passed, self._releases = 0, 0
+            self._peak_bytes, self._peak_inflight = sum(self._arena), self._inflight
             self._t0, self._t_last = None, None
 
     def close(self):
@@ -165,41 +196,77 @@ class Server:
             w.join()
 
     # ------------------------------------------------------------------
-    def _take(self):
-        """Under the lock: the fused group for a free worker, or None."""
-        if not self._pending:
-            return None
-        head = self._pending[0]
+    def _fits(self, w, need) -> bool:
+        """Under the lock: can worker w run a call of `need` scratch bytes,
+        releasing idle workers' blocks if that makes room?"""
+        if not self.budget:
+            return True
+        held = sum(self._arena) - self._arena[w] + max(self._arena[w], need)
+        if held <= self.budget:
+            return True
+        for v in range(len(self._arena)):
+            if held <= self.budget:
+                break
+            if v != w and not self._busy[v] and self._arena[v] > 0:
+                self.ex.release(self._worker_objs[v])
+                held -= self._arena[v]
+                self._arena[v] = 0
+                self._releases += 1
+        return held <= self.budget
+
+    def _group(self, head):
         group, B = [head], head.B
-        for t in list(self._pending)[1:]:
-            if t.events is head.events and t.prec == head.prec and B + t.B <= self.max_fused:
+        for t in self._pending:
+            if t is not head and t.events is head.events and t.prec == head.prec \
+                    and B + t.B <= self.max_fused:
                 group.append(t)
                 B += t.B
-        need = self.ex.scratch_bytes(head.events, B, head.prec)
-        # shrink to what the budget admits; the head alone always fits an idle device
-        while self.budget and self._in_use + need > self.budget and len(group) > 1:
-            B -= group.pop().B
-            need = self.ex.scratch_bytes(head.events, B, head.prec)
-        if self.budget and self._in_use + need > self.budget:
-            return None
-        for t in group:
-            self._pending.remove(t)
-        return group, B, need
+        return group, B
 
-    def _loop(self, worker):
+    def _take(self, w):
+        """Under the lock: the fused group for free worker w, or None."""
+        if not self._pending:
+            return None
+        now = time.perf_counter()
+        oldest = self._pending[0]
+        may_pass = self.max_pass_s > 0 and now - oldest.t_submit < self.max_pass_s
+        seen = set()
+        for head in list(self._pending):
+            key = (id(head.events), head.prec)
+            if key in seen:
+                continue
+            seen.add(key)
+            group, B = self._group(head)
+            need = self.ex.scratch_bytes(head.events, B, head.prec)
+            while len(group) > 1 and not self._fits(w, need):
+                B -= group.pop().B
+                need = self.ex.scratch_bytes(head.events, B, head.prec)
+            if self._fits(w, need):
+                for t in group:
+                    self._pending.remove(t)
+                if head is not oldest:
+                    self._passed += 1
+                return group, B, need
+            if not may_pass:
+                return None
+        return None
+
+    def _loop(self, w):
+        worker = self._worker_objs[w]
         while True:
             with self._cv:
                 while True:
-                    got = self._take()
+                    got = self._take(w)
                     if got is not None or (self._stop and not self._pending):
                         break
-                    self._cv.wait()
+                    self._cv.wait(timeout=self.max_pass_s if self.max_pass_s > 0 else None)
                 if got is None:
                     return
                 group, B, need = got
-                self._in_use += need
+                self._arena[w] = max(self._arena[w], need)
+                self._busy[w] = True
                 self._inflight += 1
-                self._peak_bytes = max(self._peak_bytes, self._in_use)
+                self._peak_bytes = max(self._peak_bytes, sum(self._arena))
                 self._peak_inflight = max(self._peak_inflight, self._inflight)
             t_start = time.perf_counter()
             lam = np.concatenate([t.lam for t in group]) if len(group) > 1 else group[0].lam
@@ -210,7 +277,7 @@ class Server:
                 err = e
             t_done = time.perf_counter()
             with self._cv:
-                self._in_use -= need
+                self._busy[w] = False
                 self._inflight -= 1
                 self._launches += 1
                 self._fused_requests += len(group)

@@ -2,8 +2,14 @@
 host preprocessing on spectroscopic and photometric catalogues, and the
 photometric stress workload (1000 events x 4096 samples, 1e7 photo-z
 galaxies, 2000-point grid to z = 2.4, 5e6 injections, B = 128) built with
-it: sampled events against the oracle over the same catalogue rows, and the
-FP32 form against FP64."""
+it, for each of the three event sets with truth Xi0 = 0.6, 1.0, 1.8 (each
+with its own seeded catalogue, events and injections): sampled events against
+the oracle over the same catalogue rows, and the FP32 form against FP64.
+
+FP32 bar: the stated |Delta ln L| <= 1e-3 is for 300 events; ln L sums one
+ln I_i per event and the FP32 errors of the events are independent, so for
+1000 events the bar is taken as 1e-3 x 1000 / 300 (the measured value is
+printed)."""
 import numpy as np
 import pytest
 
@@ -44,10 +50,15 @@ def test_builder_matches_host_preprocessing(kind):
     assert 0 < used <= cf[0].z_obs.size
 
 
-@pytest.fixture(scope="module")
-def photo():
+#: seeds of the three photometric event sets (Xi0 = 1 is the photo_1000ev workload itself)
+PHOTO_SEEDS = {1.0: 2, 0.6: 3, 1.8: 4}
+
+
+@pytest.fixture(scope="module", params=[1.0, 0.6, 1.8], ids=lambda x: f"xi0_{x}")
+def photo(request):
     from paper_2504_02034_amd import chimera
-    wl = synth.WORKLOADS["photo_1000ev"]
+    xt = request.param
+    wl = synth.WORKLOADS["photo_1000ev"].scaled(xi0_truth=xt, seed_index=PHOTO_SEEDS[xt])
     cf = synth.make_catalog(wl)
     ev = synth.make_events(wl, cf)
     inj = synth.make_injections(wl)
@@ -73,11 +84,15 @@ def test_photometric_workload(photo):
     fin = np.isfinite(l64)
     assert np.array_equal(np.isfinite(l32), fin)
     d = np.abs(l32[fin] - l64[fin])
-    print("photo-z: finite points", fin.sum(), "max |dlnL| FP32 vs FP64", d.max() if d.size else None)
+    print(f"photo-z Xi0={wl.xi0_truth}: finite points", fin.sum(), "max |dlnL| FP32 vs FP64",
+          d.max() if d.size else None)
+    assert fin.sum() >= 1
     assert d.size == 0 or d.max() <= 1e-3 * wl.n_events / 300
-    pick = [3, 480, 997]
+    rng = np.random.default_rng(int(wl.seed_index))
+    pick = [0, 999] + sorted(rng.choice(np.arange(1, 999), 5, replace=False).tolist())
     events, cat, o_inj = oracle_from_prepared(p, nz, nt, inj, pick)
-    for b in (0, 77):
+    fin_b = np.flatnonzero(fin)
+    for b in [0, 77] + [int(fin_b[len(fin_b) // 2])]:
         ref = oracle.likelihood.lnl(events, cat, o_inj, lam[b], T=8.6)
         for k, e in enumerate(pick):
             r, g = ref["lnI"][k], I64[b, e]

@@ -1,7 +1,9 @@
 """The continuous-batching server on the device: requests from concurrent
 clients over two resident event sets and both precisions, fused and
 overlapped on several streams under an HBM budget that binds, each result
-equal (bitwise) to the same request evaluated alone."""
+equal (bitwise) to the same request evaluated alone, and the scratch the
+library holds (and the device memory in use) within the budget.  Also: host
+calls from two threads on one stream, each equal to the same call alone."""
 import threading
 
 import numpy as np
@@ -26,9 +28,24 @@ def test_served_results_equal_the_request_alone():
     part = ctx.add_events(h["ev_pix_off"][:3], h["pix_samp_off"][:h["ev_pix_off"][2] + 1],
                           h["pix_row"][:h["ev_pix_off"][2]], h["c_ir"][:h["ev_pix_off"][2]],
                           h["dl"][:k], h["m1"][:k], h["m2"][:k])
-    ex = HipExecutor(ctx)
+    import torch
+    ex = HipExecutor(ctx, max_fused=48)
     budget = 3 * ex.scratch_bytes(full, 48, chimera.CHIMERA_FP64)
-    srv = Server(ex, n_workers=4, max_fused=48, hbm_budget=budget)
+    torch.cuda.synchronize()
+    free0, _ = torch.cuda.mem_get_info()
+    srv = Server(ex, n_workers=4, max_fused=48, hbm_budget=budget, max_pass_s=0.01)
+    held_max = [0]
+    stop = threading.Event()
+
+    def watch():
+        # device memory in use beyond what the process held before the server
+        while not stop.is_set():
+            free, _ = torch.cuda.mem_get_info()
+            held_max[0] = max(held_max[0], free0 - free)
+            stop.wait(0.002)
+
+    watcher = threading.Thread(target=watch, daemon=True)
+    watcher.start()
     rng0 = np.random.default_rng(11)
     base = synth.LAMBDA_TRUTH
     reqs, lock = [], threading.Lock()
@@ -61,8 +78,58 @@ def test_served_results_equal_the_request_alone():
         assert np.array_equal(got, alone, equal_nan=True), (t.id, got, alone)
     st = srv.stats()
     srv.close()
-    print(st)
+    stop.set()
+    watcher.join()
+    held = ctx.scratch_held()
+    print(st, "held", held, "device peak", held_max[0], "budget", budget)
     assert st["completed"] == len(reqs) == 60
     assert st["peak_bytes"] <= budget
+    assert held <= budget
+    # the workers' pinned and device buffers (4 x 48 x 15 doubles) and the
+    # allocators' rounding aside, device memory in use stays within the budget
+    assert held_max[0] <= budget + (64 << 20)
     assert st["launches"] <= len(reqs)
     ctx.close()
+
+
+def test_host_calls_from_two_threads_on_one_stream():
+    """Host-memory calls run on the null stream; two threads calling at once
+    with different lambda each get what the call alone gives."""
+    from paper_2504_02034_amd import chimera
+    h = handcrafted()
+    ctx = chimera.Context(n_z=h["n_z"], z_lo=h["z_lo"], z_hi=h["z_hi"])
+    ctx.set_catalog(h["rows"], h["nz_tot"])
+    ctx.set_injections(h["idl"], h["im1"], h["im2"], h["lnp"], h["ninj"])
+    es = ctx.add_events(h["ev_pix_off"], h["pix_samp_off"], h["pix_row"], h["c_ir"], h["dl"],
+                        h["m1"], h["m2"])
+    rng = np.random.default_rng(3)
+    lams = []
+    for k in range(2):
+        B = 40 + 23 * k                    # different sizes: the shared block regrows
+        lam = np.tile(synth.LAMBDA_TRUTH, (B, 1))
+        lam[:, 0] = rng.uniform(40, 120, B)
+        lam[:, 2] = rng.uniform(0.5, 2.5, B)
+        lams.append(lam)
+    alone = [[ctx.lnl(es, lam, prec) for prec in (0, 1)] for lam in lams]
+    out = [[None, None], [None, None]]
+    errs = []
+
+    def worker(k):
+        try:
+            for r in range(20):
+                prec = r % 2
+                got = ctx.lnl(es, lams[k], prec)
+                if not np.array_equal(got, alone[k][prec], equal_nan=True):
+                    out[k][prec] = got
+                    return
+        except BaseException as e:  # noqa: BLE001
+            errs.append(e)
+
+    th = [threading.Thread(target=worker, args=(k,)) for k in range(2)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    ctx.close()
+    assert not errs, errs
+    assert all(o is None for row in out for o in row), out

@@ -1,7 +1,9 @@
 """Scheduling logic of the continuous-batching server with a CPU stand-in
 for the device executor: results routed to the right requests whatever the
-fusion, the HBM budget never exceeded, fusion of queued requests on the same
-event set, first-come order under memory pressure, errors isolated to their
+fusion, the memory held (every worker's scratch block) never above the HBM
+budget, idle blocks released to make room, fusion of queued requests on the
+same event set, first-come order under memory pressure unless passing is
+allowed (then bounded by the oldest request's age), errors isolated to their
 requests, drain on close."""
 import threading
 import time
@@ -18,12 +20,16 @@ class Events:
 
 
 class MockExec:
+    """CPU stand-in: each worker's 'stream' keeps a scratch block grown to its
+    largest call, as the library does, until released."""
+
     def __init__(self, per_point_s=2e-4, fail_tag=None):
         self.per_point_s = per_point_s
         self.fail_tag = fail_tag
         self.mu = threading.Lock()
-        self.in_use = 0
+        self.arena = {}
         self.peak = 0
+        self.releases = 0
         self.calls = []
 
     def new_worker(self):
@@ -32,20 +38,21 @@ class MockExec:
     def scratch_bytes(self, events, B, prec):
         return 1000 + 100 * B
 
+    def release(self, worker):
+        with self.mu:
+            self.arena[id(worker)] = 0
+            self.releases += 1
+
     def run(self, worker, events, lam, prec):
         need = self.scratch_bytes(events, lam.shape[0], prec)
         with self.mu:
-            self.in_use += need
-            self.peak = max(self.peak, self.in_use)
+            self.arena[id(worker)] = max(self.arena.get(id(worker), 0), need)
+            self.peak = max(self.peak, sum(self.arena.values()))
             self.calls.append((events.tag, lam.shape[0], prec, time.perf_counter()))
-        try:
-            time.sleep(lam.shape[0] * self.per_point_s)
-            if self.fail_tag is not None and events.tag == self.fail_tag:
-                raise ValueError("executor failure")
-            return value(events, lam, prec)
-        finally:
-            with self.mu:
-                self.in_use -= need
+        time.sleep(lam.shape[0] * self.per_point_s)
+        if self.fail_tag is not None and events.tag == self.fail_tag:
+            raise ValueError("executor failure")
+        return value(events, lam, prec)
 
 
 def value(events, lam, prec):
@@ -172,3 +179,62 @@ def test_close_drains_pending_requests():
     assert all(t.done.is_set() and t.error is None for t in ts)
     with pytest.raises(RuntimeError):
         srv.submit(Events(0), lam_batch(rng, 1), 0)
+
+
+def test_idle_blocks_are_released_to_make_room():
+    """Admission counts the blocks every worker's stream holds: a call that
+    would push the sum over the budget first releases idle workers' blocks
+    (never a busy worker's), and is refused when that does not make room."""
+    ex = MockExec()
+    big = 1000 + 100 * 20
+    srv = Server(ex, n_workers=3, max_fused=20, hbm_budget=big + 1200)
+    w0, w1, w2 = srv._worker_objs
+    with srv._cv:
+        srv._arena[:] = [big, 0, 1100]
+        srv._busy[:] = [False, False, True]
+        assert srv._fits(1, big)                 # worker 0's idle block goes
+        assert srv._arena == [0, 0, 1100] and ex.releases == 1
+        srv._arena[:] = [0, big, 1100]
+        srv._busy[:] = [False, True, True]
+        assert not srv._fits(0, big)             # the busy blocks stay
+        assert srv._arena == [0, big, 1100] and ex.releases == 1
+        srv._arena[:] = [0, 0, 0]
+        srv._busy[:] = [False, False, False]
+    srv.close()
+    # and end to end: large calls one after the other on whichever worker is
+    # free never hold more than the budget
+    ex = MockExec(per_point_s=1e-3)
+    srv = Server(ex, n_workers=2, max_fused=20, hbm_budget=big + 1200)
+    rng = np.random.default_rng(7)
+    ts = [srv.submit(Events(0), lam_batch(rng, 20), 0) for _ in range(6)]
+    for t in ts:
+        srv.wait(t, timeout=30)
+    st = srv.stats()
+    srv.close()
+    assert ex.peak <= big + 1200 and st["peak_bytes"] <= big + 1200
+
+
+def test_passing_the_oldest_is_bounded_by_its_age():
+    """With passing allowed, small requests run while the large oldest one
+    waits for memory, and the large one still runs once its age bound is
+    reached (no starvation under a steady stream of small requests)."""
+    ex = MockExec(per_point_s=4e-3)
+    big = 1000 + 100 * 30
+    srv = Server(ex, n_workers=3, max_fused=30, hbm_budget=big, max_pass_s=0.05)
+    rng = np.random.default_rng(8)
+    first = srv.submit(Events(1), lam_batch(rng, 2), 0)        # holds memory for a while
+    time.sleep(0.002)
+    large = srv.submit(Events(2), lam_batch(rng, 30), 0)
+    small = []
+    t_end = time.perf_counter() + 0.4
+    while time.perf_counter() < t_end:                          # a steady stream of small ones
+        small.append(srv.submit(Events(1), lam_batch(rng, 2), 0))
+        time.sleep(0.004)
+    for t in [first, large] + small:
+        srv.wait(t, timeout=30)
+    st = srv.stats()
+    srv.close()
+    assert st["passed"] >= 1
+    assert any(t.t_start < large.t_start for t in small)        # some passed the large one
+    assert large.t_start - large.t_submit < 0.05 + 0.25          # bounded wait
+    assert ex.peak <= big
