@@ -72,15 +72,15 @@ def test_served_results_equal_the_request_alone():
         t.start()
     for t in th:
         t.join()
-    for t, ev, lam, prec in reqs:
-        got = srv.wait(t, timeout=120)
-        alone = ctx.lnl(ev, lam, prec)
-        assert np.array_equal(got, alone, equal_nan=True), (t.id, got, alone)
+    served = [srv.wait(t, timeout=120) for t, _, _, _ in reqs]
     st = srv.stats()
     srv.close()
     stop.set()
     watcher.join()
     held = ctx.scratch_held()
+    for got, (t, ev, lam, prec) in zip(served, reqs):
+        alone = ctx.lnl(ev, lam, prec)
+        assert np.array_equal(got, alone, equal_nan=True), (t.id, got, alone)
     print(st, "held", held, "device peak", held_max[0], "budget", budget)
     assert st["completed"] == len(reqs) == 60
     assert st["peak_bytes"] <= budget
