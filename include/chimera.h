@@ -180,6 +180,23 @@ chimera_status chimera_lnl_batch(chimera_ctx* ctx, const chimera_events* ev, con
                                  int64_t B, int32_t prec, double* lnl, double* lnI, int32_t mem,
                                  void* hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation):
+ * chimera_lnl_batch in device mode (lam, lnl and lnI are device pointers, the
+ * work is enqueued on hip_stream) with its per-call scratch laid out in a
+ * static array of 256 MiB per device that the library holds from its load
+ * until the process ends, so the call allocates nothing.  Larger batches run
+ * as consecutive launch sequences of the points that fit; results are the
+ * same as chimera_lnl_batch's.  Every call on a device shares that device's
+ * array: calls whose work overlaps on one device (other streams, other
+ * contexts or threads) race and must be serialised by the caller (e.g. one
+ * stream).  ENOMEM, with nothing enqueued, when one point of the event set
+ * needs more scratch than the array holds (about 16 bytes per sample in FP64
+ * and 12 in FP32, plus 0.4 MB); no profiling events are recorded. */
+chimera_status chimera_lnl_batch_static(chimera_ctx* ctx, const chimera_events* ev,
+                                        const double* lam, int64_t B, int32_t prec, double* lnl,
+                                        double* lnI, void* hip_stream);
+
 /* ln xi and the effective injection count N_eff (Sect. 2.2) at B points.
  * n_eff may be NULL. */
 chimera_status chimera_selection_xi(chimera_ctx* ctx, const double* lam, int64_t B, int32_t prec,

@@ -5,7 +5,8 @@ import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SOURCES = ["csrc/kernels.hip", "csrc/event.hip", "csrc/grad.hip", "csrc/catalog.hip", "csrc/api.cpp"]
+SOURCES = ["csrc/kernels.hip", "csrc/event.hip", "csrc/grad.hip", "csrc/catalog.hip",
+           "csrc/noalloc.hip", "csrc/api.cpp"]
 LIB = os.path.join(HERE, "libchimera.so")
 ARCH = "gfx950"
 

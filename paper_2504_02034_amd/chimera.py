@@ -30,7 +30,8 @@ EXPORTS = ("chimera_default_config", "chimera_create", "chimera_destroy", "chime
            "chimera_set_catalog", "chimera_set_catalog_galaxies", "chimera_get_catalog",
            "chimera_set_injections",
            "chimera_add_events",
-           "chimera_release_events", "chimera_lnl_batch", "chimera_selection_xi",
+           "chimera_release_events", "chimera_lnl_batch", "chimera_lnl_batch_static",
+           "chimera_selection_xi",
            "chimera_lnl_grad", "chimera_scratch_bytes", "chimera_scratch_held",
            "chimera_release_scratch", "chimera_profile_enable", "chimera_profile_read")
 
@@ -80,6 +81,7 @@ def _load():
                                               ctypes.POINTER(_P)]),
         "chimera_release_events": (ctypes.c_int, [_P, _P]),
         "chimera_lnl_batch": (ctypes.c_int, [_P, _P, _P, _I64, _I32, _P, _P, _I32, _P]),
+        "chimera_lnl_batch_static": (ctypes.c_int, [_P, _P, _P, _I64, _I32, _P, _P, _P]),
         "chimera_selection_xi": (ctypes.c_int, [_P, _P, _I64, _I32, _P, _P, _I32, _P]),
         "chimera_lnl_grad": (ctypes.c_int, [_P, _P, _P, _I64, _I32, _P, _P, _I32, _P]),
         "chimera_scratch_bytes": (ctypes.c_int, [_P, _P, _I64, _I32, _I32,
@@ -212,6 +214,20 @@ def chimera_lnl_batch(h, ev, lam, prec=CHIMERA_FP64, lnl=None, lnI=None, n_ev=No
                                  lnI_arr.ctypes.data_as(_P) if lnI_arr is not None else None,
                                  CHIMERA_HOST, None))
     return (out, lnI_arr) if n_ev is not None else out
+
+
+def chimera_lnl_batch_static(h, ev, lam, prec=CHIMERA_FP64, lnl=None, lnI=None, stream=None):
+    """Device-mode ln L with the library's static scratch (no allocation in the
+    call): lam, lnl (and lnI) are torch tensors on the device."""
+    import torch
+    assert lam.is_cuda and lam.dtype == torch.float64 and lam.is_contiguous()
+    B = lam.shape[0]
+    if lnl is None:
+        lnl = torch.empty(B, dtype=torch.float64, device=lam.device)
+    _check(lib.chimera_lnl_batch_static(h, ev, _P(lam.data_ptr()), B, prec, _P(lnl.data_ptr()),
+                                        _P(lnI.data_ptr()) if lnI is not None else None,
+                                        _stream_ptr(stream)))
+    return lnl
 
 
 def chimera_selection_xi(h, lam, prec=CHIMERA_FP64, stream=None):

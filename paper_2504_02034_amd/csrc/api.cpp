@@ -22,6 +22,11 @@ namespace {
 
 thread_local std::string g_err;
 
+// Device address of each GPU's copy of the static scratch (noalloc.hip),
+// looked up once per device by chimera_create with that device current.
+std::mutex g_static_mu;
+std::map<int, void*> g_static_ptr;
+
 chimera_status fail(chimera_status s, const std::string& msg) {
   g_err = msg;
   return s;
@@ -270,6 +275,14 @@ chimera_status chimera_create(const chimera_config* cfg, chimera_ctx** out) {
   HIP_TRY(hipGetDeviceCount(&ndev));
   if (cfg->device < 0 || cfg->device >= ndev) return fail(CHIMERA_EINVAL, "no such device");
   HIP_TRY(hipSetDevice(cfg->device));
+  {
+    std::lock_guard<std::mutex> lk(g_static_mu);
+    if (!g_static_ptr.count(cfg->device)) {
+      void* p = nullptr;
+      HIP_TRY(static_scratch_address(&p));
+      g_static_ptr[cfg->device] = p;
+    }
+  }
   hipMemPool_t pool;
   if (hipDeviceGetDefaultMemPool(&pool, cfg->device) == hipSuccess) {
     uint64_t thr = std::numeric_limits<uint64_t>::max();
@@ -691,9 +704,11 @@ static hipError_t arena_reserve(chimera_ctx::Arena* ar, hipStream_t st, size_t b
   return hipSuccess;
 }
 
+// One launch sequence.  ext (the static scratch, or NULL) replaces the
+// stream's arena; then nothing is allocated (and no profiling events made).
 static chimera_status run_chunk(chimera_ctx* ctx, const chimera_events* ev, const double* lam,
                                 int64_t B, int32_t prec, double* lnl, double* lnI, double* ln_xi,
-                                double* n_eff, int32_t mem, void* hip_stream) {
+                                double* n_eff, int32_t mem, void* hip_stream, void* ext = nullptr) {
   hipStream_t st = (hipStream_t)hip_stream;
   HIP_TRY(hipSetDevice(ctx->cfg.device));
   const bool f32 = prec == CHIMERA_FP32;
@@ -718,10 +733,16 @@ static chimera_status run_chunk(chimera_ctx* ctx, const chimera_events* ev, cons
   if (ctx->cfg.hbm_budget && pool_size(bytes) > ctx->cfg.hbm_budget)
     return fail(CHIMERA_ENOMEM, "call needs " + std::to_string(bytes) +
                                     " scratch bytes, over the context's hbm_budget");
-  void* base = nullptr;
-  chimera_ctx::Arena* ar = arena_of(ctx, st);
-  std::lock_guard<std::mutex> stream_lock(ar->mu);
-  HIP_TRY(arena_reserve(ar, st, bytes, &base));
+  void* base = ext;
+  std::unique_lock<std::mutex> stream_lock;
+  if (!ext) {
+    chimera_ctx::Arena* ar = arena_of(ctx, st);
+    stream_lock = std::unique_lock<std::mutex>(ar->mu);
+    HIP_TRY(arena_reserve(ar, st, bytes, &base));
+  } else if (bytes > kStaticScratchBytes) {
+    return fail(CHIMERA_ENOMEM, "launch needs " + std::to_string(bytes) +
+                                    " scratch bytes, over the static scratch");
+  }
   Carve cv;
   cv.base = (char*)base;
   carve(cv, s, g, B, E, nchunk, host, need_lnI, ev != nullptr, host, S_ev, U_ev, f32);
@@ -764,7 +785,7 @@ static chimera_status run_chunk(chimera_ctx* ctx, const chimera_events* ev, cons
     a.count = nullptr;
     a.pcount = s.pcount;
     hipEvent_t t0 = nullptr, t1 = nullptr;
-    if (ctx->profile) {
+    if (ctx->profile && !ext) {
       std::lock_guard<std::mutex> lk(ctx->mu);
       a.count = ctx->d_count;
       HIP_TRY(hipEventCreate(&t0));
@@ -880,6 +901,60 @@ chimera_status chimera_lnl_batch(chimera_ctx* ctx, const chimera_events* ev, con
   if (!ev) return fail(CHIMERA_EINVAL, "null event set");
   if (!lnl) return fail(CHIMERA_EINVAL, "null output");
   return run_batch(ctx, ev, lam, B, prec, lnl, lnI, nullptr, nullptr, mem, hip_stream);
+}
+
+// Scratch bytes of one device-mode launch sequence of B points.
+static size_t device_launch_bytes(chimera_ctx* ctx, const chimera_events* ev, int64_t B,
+                                  bool f32, bool have_lnI) {
+  double dmin = ctx->n_det ? ctx->inj_dmin : std::numeric_limits<double>::infinity();
+  double dmax = ctx->n_det ? ctx->inj_dmax : 0.0;
+  dmin = std::min(dmin, ev->dmin);
+  dmax = std::max(dmax, ev->dmax);
+  if (!(dmax > 0.0)) dmin = dmax = 1.0;
+  const Geometry g = make_geometry(ctx, dmin, dmax);
+  Scratch s;
+  Carve probe;
+  return carve(probe, s, g, B, ev->E, selection_chunks(ctx->n_det), false, !have_lnI, true, false,
+               ev->n_samp, ev->U, f32);
+}
+
+chimera_status chimera_lnl_batch_static(chimera_ctx* ctx, const chimera_events* ev,
+                                        const double* lam, int64_t B, int32_t prec, double* lnl,
+                                        double* lnI, void* hip_stream) {
+  chimera_status s = check_common(ctx, lam, B, prec, CHIMERA_DEVICE);
+  if (s != CHIMERA_OK) return s;
+  if (!ev) return fail(CHIMERA_EINVAL, "null event set");
+  if (!lnl) return fail(CHIMERA_EINVAL, "null output");
+  void* base = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_static_mu);
+    auto it = g_static_ptr.find(ctx->cfg.device);
+    if (it == g_static_ptr.end()) return fail(CHIMERA_ESTATE, "static scratch not set up");
+    base = it->second;
+  }
+  // the most lambda points per launch sequence that the static scratch holds
+  const bool f32 = prec == CHIMERA_FP32;
+  int64_t lo = 0, hi = B;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi + 1) / 2;
+    if (device_launch_bytes(ctx, ev, mid, f32, lnI != nullptr) <= kStaticScratchBytes) lo = mid;
+    else hi = mid - 1;
+  }
+  if (lo < 1)
+    return fail(CHIMERA_ENOMEM,
+                "one lambda point of this event set needs " +
+                    std::to_string(device_launch_bytes(ctx, ev, 1, f32, lnI != nullptr)) +
+                    " scratch bytes, more than the static scratch of " +
+                    std::to_string(kStaticScratchBytes) + " (use chimera_lnl_batch)");
+  const int64_t E = ev->E;
+  for (int64_t c0 = 0; c0 < B; c0 += lo) {
+    const int64_t n = std::min(lo, B - c0);
+    chimera_status r = run_chunk(ctx, ev, lam + c0 * CHIMERA_NLAM, n, prec, lnl + c0,
+                                 lnI ? lnI + c0 * E : nullptr, nullptr, nullptr, CHIMERA_DEVICE,
+                                 hip_stream, base);
+    if (r != CHIMERA_OK) return r;
+  }
+  return CHIMERA_OK;
 }
 
 chimera_status chimera_selection_xi(chimera_ctx* ctx, const double* lam, int64_t B, int32_t prec,

@@ -129,6 +129,11 @@ struct EventArgs {
 hipError_t launch_events(const EventArgs& a, bool f32, hipStream_t st, hipEvent_t t0 = nullptr,
                          hipEvent_t t1 = nullptr);
 
+// static scratch of the allocation-free entry point (noalloc.hip): 256 MiB
+// per device, lambda points run in chunks that fit it
+constexpr size_t kStaticScratchBytes = size_t(256) << 20;
+hipError_t static_scratch_address(void** ptr);
+
 hipError_t launch_tables(const double* lam, int B, const Geometry& g, LamParams* P, double2* chi,
                          double2* inv, double2* dtab, double* gz64, float* gz32, int* flag_mono,
                          int* flag_range, hipStream_t st);
