@@ -17,6 +17,14 @@ Sect. 2.2       xi = (1/N_inj) sum_{detected} s_j,
                 the sky integral of p_cat is n_tot since detection does not
                 depend on the sky), N_eff as printed with sums over detected.
 
+eq. gw-kernel-single1d (the single-1D kernel of Sect. 2.3)
+                one weighted KDE per event over all its in-region samples,
+                KDE(z) = (1/N_i) sum_j w_j N(z; z_j, h_i), times the pixel's
+                2-D sky factor S_ir = c_ir N_ir (c_ir = S_ir / N_ir is the
+                preprocessing's per-pixel factor):
+                I_i = sum_r S_ir sum_g tau_g n_r(z_g) g(z_g) KDE(z_g)
+                (same samples, weights, bandwidth and window as many-1D).
+
 Bandwidth (the paper is silent; reading): one Gaussian bandwidth per
 (event, lambda) from all of the event's in-region samples: Scott's rule with
 the Kish effective size n_eff = W1^2/W2 and the unbiased weighted variance,
@@ -153,6 +161,28 @@ def event_integral(pixels_z, pixels_w, pixels_c, pixels_row, grid, tau, gz, T=No
     return total, h
 
 
+def event_integral_single1d(pixels_z, pixels_w, pixels_c, pixels_row, grid, tau, gz, T=None):
+    """(I_i, h_i) of one event with the single-1D kernel (eq. gw-kernel-single1d):
+    the event's one weighted redshift KDE on the grid, times each pixel's sky
+    factor S_ir = c_ir N_ir and catalogue row, summed over pixels."""
+    dz = grid[1] - grid[0]
+    z_all = np.concatenate(pixels_z)
+    w_all = np.concatenate(pixels_w)
+    h = bandwidth(z_all, w_all, dz)
+    if h is None:
+        return 0.0, float("nan")
+    diff = grid[None, :] - z_all[:, None]
+    k = np.exp(-0.5 * (diff / h) ** 2) / (h * math.sqrt(2.0 * math.pi))
+    if T is not None:
+        k = np.where(np.abs(diff) <= T * h, k, 0.0)
+    kde = (w_all @ k) / z_all.size
+    total = 0.0
+    for zr, c, nr in zip(pixels_z, pixels_c, pixels_row):
+        s_ir = c * zr.size
+        total += s_ir * float(np.sum(tau * nr * gz * kde))
+    return total, h
+
+
 def selection(inj: InjectionSet, cat: Catalog, lam):
     """(xi, N_eff) by the injection estimator of Sect. 2.2."""
     z, w = redshift_and_weight(inj.dl, inj.m1d, inj.m2d, lam)
@@ -181,17 +211,22 @@ def _event_worker(i):
         sl = d["slices"][i][len(zs)]
         zs.append(d["z"][sl]); ws.append(d["w"][sl]); cs.append(px.c)
         rs.append(d["cat"].rows[px.pix])
-    return event_integral(zs, ws, cs, rs, d["cat"].grid, d["tau"], d["gz"], d["T"])
+    f = event_integral_single1d if d["kernel"] == "single1d" else event_integral
+    return f(zs, ws, cs, rs, d["cat"].grid, d["tau"], d["gz"], d["T"])
 
 
 def lnl(events, cat: Catalog, inj: InjectionSet, lam, T=None, workers: int = 1,
-        event_subset=None):
+        event_subset=None, kernel: str = "many1d"):
     """ln L and its parts at one lambda.
 
-    Returns dict(lnl, lnI[E] (NaN for events not in event_subset), h[E], ln_xi, neff).
-    With event_subset, lnl is the partial sum over those events minus
-    len(subset) ln xi (used for sampled parity checks).
+    kernel: "many1d" (eq. gw-kernel-many1d) or "single1d" (eq.
+    gw-kernel-single1d).  Returns dict(lnl, lnI[E] (NaN for events not in
+    event_subset), h[E], ln_xi, neff).  With event_subset, lnl is the partial
+    sum over those events minus len(subset) ln xi (used for sampled parity
+    checks).
     """
+    if kernel not in ("many1d", "single1d"):
+        raise ValueError(f"unknown kernel {kernel!r}")
     lam = np.asarray(lam, dtype=np.float64)
     E = len(events)
     sub = list(range(E)) if event_subset is None else list(event_subset)
@@ -220,7 +255,7 @@ def lnl(events, cat: Catalog, inj: InjectionSet, lam, T=None, workers: int = 1,
         res["lnl"] = np.nan
         return res
     _WORK.update(events=events, slices=slices, z=z, w=w, cat=cat, tau=trapezoid(cat.grid),
-                 gz=grid_factor(cat.grid, lam), T=T)
+                 gz=grid_factor(cat.grid, lam), T=T, kernel=kernel)
     if workers > 1 and len(sub) > 1:
         import multiprocessing as mp
         with mp.get_context("fork").Pool(workers) as pool:

@@ -2,7 +2,8 @@
 20-point grid, 50 injections) evaluated at 30 significant digits with mpmath,
 every step written out here from its definition (eq. dL-em and dL-mg with
 adaptive quadrature and a bracketed root, the PLP mass model of Sect. 3.1,
-the weighted Gaussian KDE of eq. gw-kernel-many1d summed over the grid, the
+the weighted Gaussian KDE of eq. gw-kernel-many1d, or the one per-event KDE
+times the pixels' sky factors of eq. gw-kernel-single1d, summed over the grid, the
 injection estimator of Sect. 2.2, eq. hyperlike); the oracle (dense, T = inf)
 must agree to 1e-13."""
 import mpmath as mp
@@ -14,7 +15,7 @@ import oracle
 C = mp.mpf("299792.458")
 
 
-def mp_lnl(events, grid, rows, n_tot, inj, lam):
+def mp_lnl(events, grid, rows, n_tot, inj, lam, kernel="many1d"):
     mp.mp.dps = 30
     h0, om, xi0, n, alpha, beta, mmin, mmax, mu, sg, lg, gam, kap, zp = [mp.mpf(float(x)) for x in lam]
 
@@ -80,13 +81,23 @@ def mp_lnl(events, grid, rows, n_tot, inj, lam):
         var = mp.fsum(w * (z - mean) ** 2 for w, z in zip(ws, zs)) / (W1 - W2 / W1)
         h = max(mp.sqrt(var) * (W1 * W1 / W2) ** mp.mpf("-0.2"), 2 * dz)
         total = mp.mpf(0)
-        for p, (c, row, *_r) in enumerate(ev):
-            for z, w, q in zip(zs, ws, pix):
-                if q != p:
-                    continue
-                A = mp.fsum(tau[k] * mp.npdf(g[k], z, h) * mp.mpf(float(row[k])) * gfac[k]
-                            for k in range(len(g)))
-                total += mp.mpf(float(c)) * w * A
+        if kernel == "single1d":
+            # eq. gw-kernel-single1d: one KDE over every sample of the event,
+            # times the pixel's sky factor c_r N_r
+            kde = [mp.fsum(w * mp.npdf(g[k], z, h) for z, w in zip(zs, ws)) / len(zs)
+                   for k in range(len(g))]
+            for p, (c, row, *_r) in enumerate(ev):
+                n_p = sum(1 for q in pix if q == p)
+                total += mp.mpf(float(c)) * n_p * mp.fsum(
+                    tau[k] * mp.mpf(float(row[k])) * gfac[k] * kde[k] for k in range(len(g)))
+        else:
+            for p, (c, row, *_r) in enumerate(ev):
+                for z, w, q in zip(zs, ws, pix):
+                    if q != p:
+                        continue
+                    A = mp.fsum(tau[k] * mp.npdf(g[k], z, h) * mp.mpf(float(row[k])) * gfac[k]
+                                for k in range(len(g)))
+                    total += mp.mpf(float(c)) * w * A
         lnI.append(mp.log(total))
     s = []
     nt = [mp.mpf(float(x)) for x in n_tot]
@@ -125,11 +136,12 @@ def tiny_inputs(seed):
     return events, grid, rows, n_tot, inj
 
 
+@pytest.mark.parametrize("kernel", ["many1d", "single1d"])
 @pytest.mark.parametrize("seed,lam", [
     (1, [70.0, 0.3, 1.0, 1.91, 3.4, 1.1, 5.0, 87.0, 34.0, 3.6, 0.04, 2.7, 3.0, 2.0]),
     (2, [62.0, 0.41, 1.6, 2.5, 2.2, -0.4, 6.0, 80.0, 30.0, 5.0, 0.3, 1.9, 2.6, 1.4]),
 ])
-def test_oracle_matches_30_digit_brute_force(seed, lam):
+def test_oracle_matches_30_digit_brute_force(seed, lam, kernel):
     L = oracle.likelihood
     events, grid, rows, n_tot, inj = tiny_inputs(seed)
     o_events = []
@@ -141,9 +153,9 @@ def test_oracle_matches_30_digit_brute_force(seed, lam):
         o_events.append(e)
     cat = L.Catalog(grid=grid, rows={i: r for i, r in enumerate(rows)}, n_tot=n_tot)
     o_inj = L.InjectionSet(inj["dl"], inj["m1d"], inj["m2d"], inj["lnp"], inj["n_total"])
-    ref = L.lnl(o_events, cat, o_inj, np.array(lam))
+    ref = L.lnl(o_events, cat, o_inj, np.array(lam), kernel=kernel)
     if seed == 1:      # this case checks Scott's rule itself, not the 2 dz floor
         assert np.all(ref["h"] > 2.0 * (grid[1] - grid[0]))
-    want, lnI = mp_lnl(events, grid, rows, n_tot, inj, lam)
+    want, lnI = mp_lnl(events, grid, rows, n_tot, inj, lam, kernel=kernel)
     assert np.allclose(ref["lnI"], lnI, rtol=1e-13, atol=0.0)
     assert abs(ref["lnl"] - float(want)) <= 1e-13 * abs(float(want))
