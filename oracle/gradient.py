@@ -316,10 +316,16 @@ def selection_grad(inj: L.InjectionSet, cat: L.Catalog, lam):
     return S1 / inj.n_total, (dls[:, pos] @ s[pos]) / S1
 
 
-def lnl_grad(events, cat: L.Catalog, inj: L.InjectionSet, lam, T=None):
+def lnl_grad(events, cat: L.Catalog, inj: L.InjectionSet, lam, T=None, kernel="many1d"):
     """dict(lnl, grad[12], lnI[E], dlnI[E, 12], ln_xi, dln_xi[12]).
 
+    kernel "single1d" (eq. gw-kernel-single1d): the sum over pixels of S_ir
+    times the grid sum of n_r g KDE is, by linearity, the grid sum of
+    (sum_r S_ir n_r) g KDE, i.e. one pixel holding all N_i samples with
+    c = 1/N_i and that row; event_grad then applies unchanged.
     grad is NaN where lnl is not finite."""
+    if kernel not in ("many1d", "single1d"):
+        raise ValueError(f"unknown kernel {kernel!r}")
     lam = np.asarray(lam, dtype=np.float64)
     E = len(events)
     out = {"lnl": -np.inf, "grad": np.full(NG, np.nan), "lnI": np.full(E, -np.inf),
@@ -335,14 +341,20 @@ def lnl_grad(events, cat: L.Catalog, inj: L.InjectionSet, lam, T=None):
         per_event = []
         for ev in events:
             zs, ws, lws, zzs, cs, rs = [], [], [], [], [], []
-            for px in ev.pixels:
-                z = cosmo.invert_dl(px.dl, lam[0], lam[1], lam[2], lam[3])
+            if kernel == "single1d":
+                dl, m1d, m2d = ev.all_samples()
+                parts = [(dl, m1d, m2d, 1.0 / dl.size,
+                          sum(px.sky() * cat.rows[px.pix] for px in ev.pixels))]
+            else:
+                parts = [(px.dl, px.m1d, px.m2d, px.c, cat.rows[px.pix]) for px in ev.pixels]
+            for dl, m1d, m2d, c, row in parts:
+                z = cosmo.invert_dl(dl, lam[0], lam[1], lam[2], lam[3])
                 if np.any(np.isnan(z)):
                     out["lnl"] = np.nan
                     return out
-                w, lw, zz = sample_log_weight_grad(z, px.m1d, px.m2d, lam)
+                w, lw, zz = sample_log_weight_grad(z, m1d, m2d, lam)
                 zs.append(z); ws.append(w); lws.append(lw); zzs.append(zz)
-                cs.append(px.c); rs.append(cat.rows[px.pix])
+                cs.append(c); rs.append(row)
             per_event.append(event_grad(zs, ws, lws, zzs, cs, rs, grid, tau, gz, dlng, T))
     except cosmo.NonMonotone:
         return out

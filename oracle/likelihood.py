@@ -18,12 +18,12 @@ Sect. 2.2       xi = (1/N_inj) sum_{detected} s_j,
                 depend on the sky), N_eff as printed with sums over detected.
 
 eq. gw-kernel-single1d (the single-1D kernel of Sect. 2.3)
-                one weighted KDE per event over all its in-region samples,
-                KDE(z) = (1/N_i) sum_j w_j N(z; z_j, h_i), times the pixel's
-                2-D sky factor S_ir = c_ir N_ir (c_ir = S_ir / N_ir is the
-                preprocessing's per-pixel factor):
+                one weighted KDE per event over all its N_i samples (those
+                outside the pixels of its region included),
+                KDE(z) = (1/N_i) sum_j w_j N(z; z_j, h_i), h_i from the same
+                N_i samples, times each pixel's 2-D sky factor S_ir:
                 I_i = sum_r S_ir sum_g tau_g n_r(z_g) g(z_g) KDE(z_g)
-                (same samples, weights, bandwidth and window as many-1D).
+                (same weights, bandwidth rule and window as many-1D).
 
 Bandwidth (the paper is silent; reading): one Gaussian bandwidth per
 (event, lambda) from all of the event's in-region samples: Scott's rule with
@@ -64,11 +64,24 @@ class Pixel:
     dl: np.ndarray
     m1d: np.ndarray
     m2d: np.ndarray
+    s: float = None           # sky factor S_ir (None: c x the pixel's sample count)
+
+    def sky(self) -> float:
+        return self.s if self.s is not None else self.c * self.dl.size
 
 
 @dataclass
 class Event:
     pixels: list = field(default_factory=list)
+    # every sample of the event, in and out of its pixels, as (dl, m1d, m2d);
+    # None: the pixels' samples (the single-1D KDE is trained on these)
+    samples: tuple = None
+
+    def all_samples(self):
+        if self.samples is not None:
+            return self.samples
+        return tuple(np.concatenate([getattr(px, a) for px in self.pixels])
+                     for a in ("dl", "m1d", "m2d"))
 
 
 @dataclass
@@ -161,13 +174,12 @@ def event_integral(pixels_z, pixels_w, pixels_c, pixels_row, grid, tau, gz, T=No
     return total, h
 
 
-def event_integral_single1d(pixels_z, pixels_w, pixels_c, pixels_row, grid, tau, gz, T=None):
+def event_integral_single1d(z_all, w_all, pixels_s, pixels_row, grid, tau, gz, T=None):
     """(I_i, h_i) of one event with the single-1D kernel (eq. gw-kernel-single1d):
-    the event's one weighted redshift KDE on the grid, times each pixel's sky
-    factor S_ir = c_ir N_ir and catalogue row, summed over pixels."""
+    the event's one weighted redshift KDE over all its samples z_all (weights
+    w_all) on the grid, times each pixel's sky factor S_ir and catalogue row,
+    summed over pixels."""
     dz = grid[1] - grid[0]
-    z_all = np.concatenate(pixels_z)
-    w_all = np.concatenate(pixels_w)
     h = bandwidth(z_all, w_all, dz)
     if h is None:
         return 0.0, float("nan")
@@ -177,8 +189,7 @@ def event_integral_single1d(pixels_z, pixels_w, pixels_c, pixels_row, grid, tau,
         k = np.where(np.abs(diff) <= T * h, k, 0.0)
     kde = (w_all @ k) / z_all.size
     total = 0.0
-    for zr, c, nr in zip(pixels_z, pixels_c, pixels_row):
-        s_ir = c * zr.size
+    for s_ir, nr in zip(pixels_s, pixels_row):
         total += s_ir * float(np.sum(tau * nr * gz * kde))
     return total, h
 
@@ -206,13 +217,16 @@ _WORK: dict = {}
 def _event_worker(i):
     d = _WORK
     ev = d["events"][i]
-    zs, ws, cs, rs = [], [], [], []
+    rs = [d["cat"].rows[px.pix] for px in ev.pixels]
+    if d["kernel"] == "single1d":
+        sl = d["slices"][i][0]
+        return event_integral_single1d(d["z"][sl], d["w"][sl], [px.sky() for px in ev.pixels], rs,
+                                       d["cat"].grid, d["tau"], d["gz"], d["T"])
+    zs, ws, cs = [], [], []
     for px in ev.pixels:
         sl = d["slices"][i][len(zs)]
         zs.append(d["z"][sl]); ws.append(d["w"][sl]); cs.append(px.c)
-        rs.append(d["cat"].rows[px.pix])
-    f = event_integral_single1d if d["kernel"] == "single1d" else event_integral
-    return f(zs, ws, cs, rs, d["cat"].grid, d["tau"], d["gz"], d["T"])
+    return event_integral(zs, ws, cs, rs, d["cat"].grid, d["tau"], d["gz"], d["T"])
 
 
 def lnl(events, cat: Catalog, inj: InjectionSet, lam, T=None, workers: int = 1,
@@ -239,9 +253,11 @@ def lnl(events, cat: Catalog, inj: InjectionSet, lam, T=None, workers: int = 1,
     off = 0
     for i in sub:
         sl_i = []
-        for px in events[i].pixels:
-            n = px.dl.size
-            dls.append(px.dl); m1s.append(px.m1d); m2s.append(px.m2d)
+        groups = ([events[i].all_samples()] if kernel == "single1d" else
+                  [(px.dl, px.m1d, px.m2d) for px in events[i].pixels])
+        for dl, m1, m2 in groups:
+            n = dl.size
+            dls.append(dl); m1s.append(m1); m2s.append(m2)
             sl_i.append(slice(off, off + n))
             off += n
         slices[i] = sl_i

@@ -187,10 +187,10 @@ def events(offsets, dl, m1d, m2d, theta, phi, pix, centres, area, cred=0.9):
         reg = region(px, cred)
         ct, cp = centres(np.asarray(reg, dtype=np.int64))
         s = sky_factors(theta[sl], phi[sl], ct, cp, area)
-        ev = Event()
+        ev = Event(samples=(dl[sl], m1d[sl], m2d[sl]))
         for r, p in enumerate(reg):
             m = px == p
             ev.pixels.append(Pixel(pix=p, c=s[r] / int(m.sum()), dl=dl[sl][m], m1d=m1d[sl][m],
-                                   m2d=m2d[sl][m]))
+                                   m2d=m2d[sl][m], s=float(s[r])))
         out.append(ev)
     return out

@@ -15,7 +15,7 @@ import oracle
 C = mp.mpf("299792.458")
 
 
-def mp_lnl(events, grid, rows, n_tot, inj, lam, kernel="many1d"):
+def mp_lnl(events, grid, rows, n_tot, inj, lam, kernel="many1d", extra=None):
     mp.mp.dps = 30
     h0, om, xi0, n, alpha, beta, mmin, mmax, mu, sg, lg, gam, kap, zp = [mp.mpf(float(x)) for x in lam]
 
@@ -66,9 +66,12 @@ def mp_lnl(events, grid, rows, n_tot, inj, lam, kernel="many1d"):
     tau = [dz / 2 if k in (0, len(g) - 1) else dz for k in range(len(g))]
     gfac = [psi(zg) / ((1 + zg) ** 3 * Dz(zg)) for zg in g]
     lnI = []
-    for ev in events:
+    for e, ev in enumerate(events):
         zs, ws, pix = [], [], []
-        for p, (c, row, dl, m1d, m2d) in enumerate(ev):
+        groups = list(enumerate((dl, m1d, m2d) for _c, _row, dl, m1d, m2d in ev))
+        if kernel == "single1d" and extra is not None:
+            groups.append((-1, extra[e]))      # samples outside every pixel
+        for p, (dl, m1d, m2d) in groups:
             for d, a, b in zip(dl, m1d, m2d):
                 z = z_of(d)
                 zs.append(z)
@@ -151,11 +154,23 @@ def test_oracle_matches_30_digit_brute_force(seed, lam, kernel):
             e.pixels.append(L.Pixel(pix=next(i for i, r in enumerate(rows) if r is row), c=c,
                                     dl=dl, m1d=m1, m2d=m2))
         o_events.append(e)
+    extra = None
+    if kernel == "single1d":
+        # two samples per event outside its pixels: they enter the single-1D
+        # KDE and bandwidth, not the many-1D sums
+        rng = np.random.default_rng(100 + seed)
+        extra = []
+        for e in o_events:
+            m1 = rng.uniform(15.0, 55.0, 2)
+            x = (rng.uniform(2000.0, 12000.0, 2), m1, m1 * rng.uniform(0.5, 0.95, 2))
+            extra.append(x)
+            e.samples = tuple(np.concatenate([getattr(px, a) for px in e.pixels] + [x[k]])
+                              for k, a in enumerate(("dl", "m1d", "m2d")))
     cat = L.Catalog(grid=grid, rows={i: r for i, r in enumerate(rows)}, n_tot=n_tot)
     o_inj = L.InjectionSet(inj["dl"], inj["m1d"], inj["m2d"], inj["lnp"], inj["n_total"])
     ref = L.lnl(o_events, cat, o_inj, np.array(lam), kernel=kernel)
     if seed == 1:      # this case checks Scott's rule itself, not the 2 dz floor
         assert np.all(ref["h"] > 2.0 * (grid[1] - grid[0]))
-    want, lnI = mp_lnl(events, grid, rows, n_tot, inj, lam, kernel=kernel)
+    want, lnI = mp_lnl(events, grid, rows, n_tot, inj, lam, kernel=kernel, extra=extra)
     assert np.allclose(ref["lnI"], lnI, rtol=1e-13, atol=0.0)
     assert abs(ref["lnl"] - float(want)) <= 1e-13 * abs(float(want))

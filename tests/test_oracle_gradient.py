@@ -106,9 +106,9 @@ def hand():
     return h, handcrafted_oracle(h)
 
 
-def _lnl(structs, T):
+def _lnl(structs, T, kernel="many1d"):
     events, cat, inj = structs
-    return lambda l: L.lnl(events, cat, inj, l, T=T)["lnl"]
+    return lambda l: L.lnl(events, cat, inj, l, T=T, kernel=kernel)["lnl"]
 
 
 def _xi(structs):
@@ -128,15 +128,17 @@ def test_selection_gradient_vs_differences(hand, lam):
         assert abs(dlnxi[k] - fd) <= 1e-6 * max(1.0, abs(fd)), (k, dlnxi[k], fd)
 
 
+@pytest.mark.parametrize("kernel", ["many1d", "single1d"])
 @pytest.mark.parametrize("T", [None, 8.6], ids=["dense", "T8.6"])
 @pytest.mark.parametrize("lam", [TRUTH, OTHER], ids=["truth", "other"])
-def test_lnl_gradient_vs_differences(hand, lam, T):
+def test_lnl_gradient_vs_differences(hand, lam, T, kernel):
     _, structs = hand
     events, cat, inj = structs
-    res = G.lnl_grad(events, cat, inj, lam, T=T)
-    ref = L.lnl(events, cat, inj, lam, T=T)
+    res = G.lnl_grad(events, cat, inj, lam, T=T, kernel=kernel)
+    ref = L.lnl(events, cat, inj, lam, T=T, kernel=kernel)
     assert res["lnl"] == pytest.approx(ref["lnl"], rel=1e-13)
-    f = _lnl(structs, T)
+    assert np.allclose(res["lnI"], ref["lnI"], rtol=1e-13, atol=0)
+    f = _lnl(structs, T, kernel)
     for k, p in enumerate(G.GRAD_INDEX):
         fd = G.richardson(f, lam, p, rel_step=1e-6)
         assert abs(res["grad"][k] - fd) <= 1e-6 * max(1.0, abs(fd)), (k, res["grad"][k], fd)
