@@ -167,6 +167,33 @@ chimera_status chimera_add_events(chimera_ctx* ctx, int32_t n_ev, const int64_t*
                                   const int64_t* pix_samp_off, const int64_t* pix_row,
                                   const double* c_ir, const double* dl, const double* m1d,
                                   const double* m2d, chimera_events** out);
+
+/* One resident event set for the single-1D kernel (eq. gw-kernel-single1d,
+ * Sect. 2.3): each event's redshift KDE is one weighted KDE over all its
+ * samples, KDE_i(z) = (1/N_i) sum_j w_j N(z; z_j, h_i), and its pixels enter
+ * only through their sky factors,
+ *   I_i = sum_r S_ir sum_g tau_g n_r(z_g) g(z_g) KDE_i(z_g).
+ *   ev_samp_off[n_ev+1]   samples of event i are [ev_samp_off[i], ev_samp_off[i+1])
+ *   dl, m1d, m2d[n_samp]  all N_i samples of each event (n_samp = ev_samp_off[n_ev]);
+ *                         any order within an event
+ *   ev_pix_off[n_ev+1]    pixels of event i are [ev_pix_off[i], ev_pix_off[i+1])
+ *   pix_row[P]            catalogue row of each pixel
+ *   s_ir[P]               sky factor S_ir of each pixel (> 0; with the many-1D
+ *                         layout of the same region, S_ir = c_ir x N_ir)
+ * The bandwidth h_i is taken over the same N_i samples.  The library folds
+ * the sky factors into one row per event, sum_r S_ir n_r(z_g) (lambda does
+ * not enter), at this call and again whenever the catalogue is replaced, and
+ * then runs the many-1D kernels with one pseudo-pixel of c = 1/N_i per event:
+ * every evaluation call (ln L, gradient, the allocation-free variant) takes
+ * the returned set.  The set holds n_ev x n_z doubles and floats of rows.
+ * There is no limit on an event's pixel count.  Host arrays; synchronous.
+ * Returns EINVAL on a malformed layout, ERANGE when a pixel refers past the
+ * catalogue, ESTATE before a catalogue is set. */
+chimera_status chimera_add_events_single1d(chimera_ctx* ctx, int32_t n_ev,
+                                           const int64_t* ev_samp_off, const double* dl,
+                                           const double* m1d, const double* m2d,
+                                           const int64_t* ev_pix_off, const int64_t* pix_row,
+                                           const double* s_ir, chimera_events** out);
 chimera_status chimera_release_events(chimera_ctx* ctx, chimera_events* ev);
 
 /* ln L at B points (eq. hyperlike).  prec: CHIMERA_FP64, or CHIMERA_FP32 for

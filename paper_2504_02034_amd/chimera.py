@@ -29,7 +29,7 @@ _STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ERANGE", -5:
 EXPORTS = ("chimera_default_config", "chimera_create", "chimera_destroy", "chimera_last_error",
            "chimera_set_catalog", "chimera_set_catalog_galaxies", "chimera_get_catalog",
            "chimera_set_injections",
-           "chimera_add_events",
+           "chimera_add_events", "chimera_add_events_single1d",
            "chimera_release_events", "chimera_lnl_batch", "chimera_lnl_batch_static",
            "chimera_selection_xi",
            "chimera_lnl_grad", "chimera_scratch_bytes", "chimera_scratch_held",
@@ -79,6 +79,8 @@ def _load():
                                                         ctypes.POINTER(_I64)]),
         "chimera_add_events": (ctypes.c_int, [_P, _I32, _P, _P, _P, _P, _P, _P, _P,
                                               ctypes.POINTER(_P)]),
+        "chimera_add_events_single1d": (ctypes.c_int, [_P, _I32, _P, _P, _P, _P, _P, _P, _P,
+                                                       ctypes.POINTER(_P)]),
         "chimera_release_events": (ctypes.c_int, [_P, _P]),
         "chimera_lnl_batch": (ctypes.c_int, [_P, _P, _P, _I64, _I32, _P, _P, _I32, _P]),
         "chimera_lnl_batch_static": (ctypes.c_int, [_P, _P, _P, _I64, _I32, _P, _P, _P]),
@@ -176,6 +178,20 @@ def chimera_add_events(h, ev_pix_off, pix_samp_off, pix_row, c_ir, dl, m1d, m2d)
     ev = _P()
     _check(lib.chimera_add_events(h, o1.size - 1, p1, p2, p3, *[p for _, p in rest],
                                   ctypes.byref(ev)))
+    return ev
+
+
+def chimera_add_events_single1d(h, ev_samp_off, dl, m1d, m2d, ev_pix_off, pix_row, s_ir):
+    o1, p1 = _host(ev_samp_off, np.int64)
+    samp = [_host(x, np.float64) for x in (dl, m1d, m2d)]
+    o2, p2 = _host(ev_pix_off, np.int64)
+    o3, p3 = _host(pix_row, np.int64)
+    o4, p4 = _host(s_ir, np.float64)
+    if o2.size != o1.size:
+        raise ValueError("ev_samp_off and ev_pix_off must both have n_ev + 1 entries")
+    ev = _P()
+    _check(lib.chimera_add_events_single1d(h, o1.size - 1, p1, *[p for _, p in samp], p2, p3, p4,
+                                           ctypes.byref(ev)))
     return ev
 
 
@@ -350,6 +366,17 @@ class Context:
     def add_prepared(self, p) -> EventSet:
         """Resident event set from prep.Prepared."""
         return self.add_events(p.ev_pix_off, p.pix_samp_off, p.pix_row, p.c_ir, p.dl, p.m1d, p.m2d)
+
+    def add_events_single1d(self, ev_samp_off, dl, m1d, m2d, ev_pix_off, pix_row,
+                            s_ir) -> EventSet:
+        h = chimera_add_events_single1d(self.handle, ev_samp_off, dl, m1d, m2d, ev_pix_off,
+                                        pix_row, s_ir)
+        return EventSet(self, h, len(ev_samp_off) - 1)
+
+    def add_prepared_single1d(self, s) -> EventSet:
+        """Resident single-1D event set from prep.Single1D."""
+        return self.add_events_single1d(s.ev_samp_off, s.dl, s.m1d, s.m2d, s.ev_pix_off,
+                                        s.pix_row, s.s_ir)
 
     def lnl(self, ev: EventSet, lam, prec=CHIMERA_FP64, with_lnI=False, lnl=None, lnI=None,
             stream=None):

@@ -102,6 +102,16 @@ struct chimera_events {
   double* samp_c = nullptr;     // c_ir of each sample's pixel (adjoint)
   double dmin = 0.0, dmax = 0.0;
   int64_t rows_needed = 0;      // 1 + the largest catalogue row the set refers to
+  // single-1D sets (eq. gw-kernel-single1d): one pseudo-pixel per event whose
+  // row is the event's pixels' sky factors folded into the catalogue rows,
+  // sum_p S_p n_{row_p}(z); folded at creation and again whenever the
+  // catalogue is replaced.  slot_row / samp_row index these rows.
+  bool single1d = false;
+  int* fold_pix_off = nullptr;  // [E+1]
+  int* fold_row = nullptr;      // [P] catalogue row of each pixel
+  double* fold_s = nullptr;     // [P] sky factor of each pixel
+  double* own64 = nullptr;      // [E][n_z]
+  float* own32 = nullptr;
 };
 
 struct chimera_ctx {
@@ -142,7 +152,28 @@ void free_events(chimera_events* ev) {
   dfree(ev->grp_first); dfree(ev->grp_cnt); dfree(ev->grp_slot); dfree(ev->grp_c);
   dfree(ev->dl); dfree(ev->lndl); dfree(ev->m1d); dfree(ev->m2d);
   dfree(ev->lnm1d); dfree(ev->lnm2d); dfree(ev->samp_row); dfree(ev->samp_c);
+  dfree(ev->fold_pix_off); dfree(ev->fold_row); dfree(ev->fold_s);
+  dfree(ev->own64); dfree(ev->own32);
   delete ev;
+}
+
+// The rows the kernels read for event set ev: its own folded rows for a
+// single-1D set, else the catalogue's.
+const double* rows64(const chimera_ctx* c, const chimera_events* ev) {
+  return ev && ev->single1d ? ev->own64 : c->nz64;
+}
+const float* rows32(const chimera_ctx* c, const chimera_events* ev) {
+  return ev && ev->single1d ? ev->own32 : c->nz32;
+}
+
+// Fold a single-1D set's rows from the current catalogue (ctx->mu held,
+// device current); synchronous.
+hipError_t fold_rows(const chimera_ctx* c, chimera_events* ev) {
+  FoldArgs f{ev->fold_pix_off, ev->fold_row, ev->fold_s, ev->E, c->cfg.n_z, c->nz64, ev->own64,
+             ev->own32};
+  hipError_t e = launch_fold_rows(f, nullptr);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  return e;
 }
 
 void free_injections(chimera_ctx* c) {
@@ -322,6 +353,18 @@ chimera_status check_resident_rows(const chimera_ctx* ctx, int64_t n_rows) {
   return CHIMERA_OK;
 }
 
+// After a catalogue replacement: fold the rows of every resident single-1D
+// set again (ctx->mu held).
+chimera_status refold_all(chimera_ctx* ctx) {
+  for (auto* e : ctx->events)
+    if (e->single1d) {
+      hipError_t er = fold_rows(ctx, e);
+      if (er != hipSuccess)
+        return fail(CHIMERA_EDEVICE, std::string("folding single-1D rows: ") + hipGetErrorString(er));
+    }
+  return CHIMERA_OK;
+}
+
 }  // namespace
 
 chimera_status chimera_set_catalog(chimera_ctx* ctx, int64_t n_rows, const double* nz,
@@ -346,7 +389,7 @@ chimera_status chimera_set_catalog(chimera_ctx* ctx, int64_t n_rows, const doubl
   HIP_TRY(upload(&ctx->ntot, nz_tot, nzn));
   ctx->n_rows = n_rows;
   ctx->has_cat = true;
-  return CHIMERA_OK;
+  return refold_all(ctx);
 }
 
 chimera_status chimera_set_catalog_galaxies(chimera_ctx* ctx, int64_t n_pix, int64_t n_gal,
@@ -431,7 +474,7 @@ chimera_status chimera_set_catalog_galaxies(chimera_ctx* ctx, int64_t n_pix, int
   ctx->n_rows = n_rows;
   ctx->has_cat = true;
   if (n_used) *n_used = used;
-  return CHIMERA_OK;
+  return refold_all(ctx);
 }
 
 chimera_status chimera_get_catalog(chimera_ctx* ctx, double* nz, double* nz_tot) {
@@ -488,6 +531,22 @@ chimera_status chimera_set_injections(chimera_ctx* ctx, int64_t n_det, int64_t n
   return CHIMERA_OK;
 }
 
+namespace {
+
+// Pixels of a single-1D set, folded into one row per event.
+struct Fold {
+  const int64_t* ev_pix_off;  // [n_ev+1]
+  const int64_t* pix_row;     // [P] catalogue rows
+  const double* s_ir;         // [P] sky factors
+};
+
+chimera_status build_events(chimera_ctx* ctx, int32_t n_ev, const int64_t* ev_pix_off,
+                            const int64_t* pix_samp_off, const int64_t* pix_row,
+                            const double* c_ir, const double* dl, const double* m1d,
+                            const double* m2d, const Fold* fold, chimera_events** out);
+
+}  // namespace
+
 chimera_status chimera_add_events(chimera_ctx* ctx, int32_t n_ev, const int64_t* ev_pix_off,
                                   const int64_t* pix_samp_off, const int64_t* pix_row,
                                   const double* c_ir, const double* dl, const double* m1d,
@@ -518,6 +577,65 @@ chimera_status chimera_add_events(chimera_ctx* ctx, int32_t n_ev, const int64_t*
   if (S > (int64_t)0x7fffffff) return fail(CHIMERA_ERANGE, "too many samples in one set");
   if (!finite_positive(dl, S) || !finite_positive(m1d, S) || !finite_positive(m2d, S))
     return fail(CHIMERA_EINVAL, "sample distances and masses must be finite and > 0");
+  return build_events(ctx, n_ev, ev_pix_off, pix_samp_off, pix_row, c_ir, dl, m1d, m2d, nullptr,
+                      out);
+}
+
+chimera_status chimera_add_events_single1d(chimera_ctx* ctx, int32_t n_ev,
+                                           const int64_t* ev_samp_off, const double* dl,
+                                           const double* m1d, const double* m2d,
+                                           const int64_t* ev_pix_off, const int64_t* pix_row,
+                                           const double* s_ir, chimera_events** out) {
+  if (!ctx || !out || !ev_samp_off || !dl || !m1d || !m2d || !ev_pix_off || !pix_row || !s_ir)
+    return fail(CHIMERA_EINVAL, "null argument");
+  *out = nullptr;
+  if (n_ev < 1) return fail(CHIMERA_EINVAL, "need at least one event");
+  if (!ctx->has_cat) return fail(CHIMERA_ESTATE, "set the catalogue before adding events");
+  if (ev_samp_off[0] != 0 || ev_pix_off[0] != 0)
+    return fail(CHIMERA_EINVAL, "ev_samp_off[0] and ev_pix_off[0] must be 0");
+  for (int i = 0; i < n_ev; ++i) {
+    if (ev_samp_off[i + 1] <= ev_samp_off[i])
+      return fail(CHIMERA_EINVAL, "every event needs at least one sample");
+    if (ev_pix_off[i + 1] <= ev_pix_off[i])
+      return fail(CHIMERA_EINVAL, "every event needs at least one pixel");
+  }
+  const int64_t P = ev_pix_off[n_ev];
+  if (P > (int64_t)0x7fffffff) return fail(CHIMERA_ERANGE, "too many pixels in one set");
+  for (int64_t p = 0; p < P; ++p) {
+    if (pix_row[p] < 0 || pix_row[p] >= ctx->n_rows)
+      return fail(CHIMERA_ERANGE, "pix_row refers past the catalogue");
+    if (!(std::isfinite(s_ir[p]) && s_ir[p] > 0.0))
+      return fail(CHIMERA_EINVAL, "s_ir must be finite and > 0");
+  }
+  const int64_t S = ev_samp_off[n_ev];
+  if (S > (int64_t)0x7fffffff) return fail(CHIMERA_ERANGE, "too many samples in one set");
+  if (!finite_positive(dl, S) || !finite_positive(m1d, S) || !finite_positive(m2d, S))
+    return fail(CHIMERA_EINVAL, "sample distances and masses must be finite and > 0");
+  // one pseudo-pixel per event over all its samples, c = 1/N_i (the KDE's
+  // normalisation), row e = the event's folded row
+  std::vector<int64_t> one(n_ev + 1), own_row(n_ev);
+  std::vector<double> c(n_ev);
+  for (int e = 0; e <= n_ev; ++e) one[e] = e;
+  for (int e = 0; e < n_ev; ++e) {
+    own_row[e] = e;
+    c[e] = 1.0 / (double)(ev_samp_off[e + 1] - ev_samp_off[e]);
+  }
+  Fold f{ev_pix_off, pix_row, s_ir};
+  return build_events(ctx, n_ev, one.data(), ev_samp_off, own_row.data(), c.data(), dl, m1d, m2d,
+                      &f, out);
+}
+
+namespace {
+
+// The groups, work units and device copies of one event set (arguments
+// checked by the caller).  fold != NULL makes a single-1D set: pix_row then
+// indexes the set's own folded rows.
+chimera_status build_events(chimera_ctx* ctx, int32_t n_ev, const int64_t* ev_pix_off,
+                            const int64_t* pix_samp_off, const int64_t* pix_row,
+                            const double* c_ir, const double* dl, const double* m1d,
+                            const double* m2d, const Fold* fold, chimera_events** out) {
+  const int64_t P = ev_pix_off[n_ev];
+  const int64_t S = pix_samp_off[P];
   // Groups: <= kGroupK samples of one pixel, consecutive in distance, spanning
   // at most kGroupSpread times the event's distance spread; the event's groups
   // are then ordered by mean distance (the same order in redshift for every
@@ -610,7 +728,18 @@ chimera_status chimera_add_events(chimera_ctx* ctx, int32_t n_ev, const int64_t*
     dmax = std::max(dmax, odl[j]);
   }
   int64_t rows_needed = 0;
-  for (int64_t p = 0; p < P; ++p) rows_needed = std::max(rows_needed, pix_row[p] + 1);
+  std::vector<int> f_off, f_row;
+  if (fold) {
+    const int64_t FP = fold->ev_pix_off[n_ev];
+    f_off.assign(fold->ev_pix_off, fold->ev_pix_off + n_ev + 1);
+    f_row.resize(FP);
+    for (int64_t p = 0; p < FP; ++p) {
+      f_row[p] = (int)fold->pix_row[p];
+      rows_needed = std::max(rows_needed, fold->pix_row[p] + 1);
+    }
+  } else {
+    for (int64_t p = 0; p < P; ++p) rows_needed = std::max(rows_needed, pix_row[p] + 1);
+  }
   std::lock_guard<std::mutex> lk(ctx->mu);
   if (rows_needed > ctx->n_rows)   // the catalogue changed since the check above
     return fail(CHIMERA_ERANGE, "pix_row refers past the catalogue");
@@ -642,6 +771,16 @@ chimera_status chimera_add_events(chimera_ctx* ctx, int32_t n_ev, const int64_t*
   if (e == hipSuccess) e = upload(&ev->lnm2d, l2.data(), S);
   if (e == hipSuccess) e = upload(&ev->samp_row, orow.data(), S);
   if (e == hipSuccess) e = upload(&ev->samp_c, oc.data(), S);
+  if (fold) {
+    ev->single1d = true;
+    const size_t rows = (size_t)n_ev * ctx->cfg.n_z;
+    if (e == hipSuccess) e = upload(&ev->fold_pix_off, f_off.data(), f_off.size());
+    if (e == hipSuccess) e = upload(&ev->fold_row, f_row.data(), f_row.size());
+    if (e == hipSuccess) e = upload(&ev->fold_s, fold->s_ir, f_row.size());
+    if (e == hipSuccess) e = hipMalloc((void**)&ev->own64, rows * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc((void**)&ev->own32, rows * sizeof(float));
+    if (e == hipSuccess) e = fold_rows(ctx, ev);
+  }
   if (e != hipSuccess) {
     free_events(ev);
     return fail(e == hipErrorOutOfMemory ? CHIMERA_ENOMEM : CHIMERA_EDEVICE,
@@ -651,6 +790,8 @@ chimera_status chimera_add_events(chimera_ctx* ctx, int32_t n_ev, const int64_t*
   *out = ev;
   return CHIMERA_OK;
 }
+
+}  // namespace
 
 chimera_status chimera_release_events(chimera_ctx* ctx, chimera_events* ev) {
   if (!ctx || !ev) return fail(CHIMERA_EINVAL, "null argument");
@@ -771,7 +912,7 @@ static chimera_status run_chunk(chimera_ctx* ctx, const chimera_events* ev, cons
     EventArgs a;
     a.P = s.P; a.flag_mono = s.flag_mono; a.flag_range = s.flag_range;
     a.chi = s.chi; a.inv = s.inv; a.dtab = s.dtab; a.g = g; a.gz64 = s.gz64; a.gz32 = s.gz32;
-    a.nz64 = ctx->nz64; a.nz32 = ctx->nz32;
+    a.nz64 = rows64(ctx, ev); a.nz32 = rows32(ctx, ev);
     a.ev_samp_off = ev->ev_samp_off; a.ev_slot_off = ev->ev_slot_off;
     a.ev_unit_off = ev->ev_unit_off; a.slot_row = ev->slot_row;
     a.grp_first = ev->grp_first; a.grp_cnt = ev->grp_cnt; a.grp_slot = ev->grp_slot;
@@ -1048,7 +1189,7 @@ static chimera_status run_grad_chunk(chimera_ctx* ctx, const chimera_events* ev,
   HIP_TRY(launch_chi_om_table(P, (int)B, g, chio, st));
   a.P = P; a.flag_mono = fm; a.flag_range = fr;
   a.chi = chi; a.chio = chio; a.inv = inv; a.dtab = dtab; a.g = g;
-  a.gz64 = gz64; a.gz32 = gz32; a.nz64 = ctx->nz64; a.nz32 = ctx->nz32;
+  a.gz64 = gz64; a.gz32 = gz32; a.nz64 = rows64(ctx, ev); a.nz32 = rows32(ctx, ev);
   a.ev_samp_off = ev->ev_samp_off; a.samp_row = ev->samp_row; a.samp_c = ev->samp_c;
   a.dl = ev->dl; a.lndl = ev->lndl; a.m1d = ev->m1d; a.m2d = ev->m2d;
   a.lnm1d = ev->lnm1d; a.lnm2d = ev->lnm2d;

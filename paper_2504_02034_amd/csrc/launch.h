@@ -263,4 +263,17 @@ struct CatalogArgs {
 hipError_t launch_catalog(const CatalogArgs& c, hipStream_t st);
 hipError_t launch_catalog_finish(const CatalogArgs& c, long long n_used, hipStream_t st);
 
+// Single-1D event rows from the catalogue rows (catalog.hip).
+struct FoldArgs {
+  const int* pix_off;       // [n_ev+1] pixels of event e: [pix_off[e], pix_off[e+1])
+  const int* row;           // [P] catalogue row of each pixel
+  const double* s;          // [P] sky factor S_ir of each pixel
+  int n_ev, n_z;
+  const double* nz64;       // [n_rows][n_z] catalogue rows
+  double* out64;            // [n_ev][n_z] (written)
+  float* out32;             // [n_ev][n_z] (written)
+};
+
+hipError_t launch_fold_rows(const FoldArgs& f, hipStream_t st);
+
 }  // namespace chimera

@@ -51,10 +51,29 @@ class Prepared:
     dl: np.ndarray            # [S] float64, sorted by (event, pixel, dl)
     m1d: np.ndarray
     m2d: np.ndarray
+    s_ir: np.ndarray = None   # [P] float64 sky factor S_ir of each (event, pixel)
 
     @property
     def n_events(self) -> int:
         return len(self.ev_pix_off) - 1
+
+
+@dataclass
+class Single1D:
+    """Arrays of chimera_add_events_single1d (eq. gw-kernel-single1d): every
+    sample of each event (those outside its region included) and the
+    region's pixels with their sky factors."""
+    ev_samp_off: np.ndarray   # [E+1] int64
+    dl: np.ndarray            # [S] float64, all samples of each event
+    m1d: np.ndarray
+    m2d: np.ndarray
+    ev_pix_off: np.ndarray    # [E+1] int64
+    pix_row: np.ndarray       # [P] int64 catalogue row
+    s_ir: np.ndarray          # [P] float64
+
+    @property
+    def n_events(self) -> int:
+        return len(self.ev_samp_off) - 1
 
 
 def trapezoid_weights(n_z: int, z_lo: float, z_hi: float) -> np.ndarray:
@@ -196,7 +215,7 @@ def prepare(cat: synth.Catalog, ev: synth.Events, n_z: int, z_lo: float, z_hi: f
     area = synth.pixel_area(ev.nside)
     ev_pix_off = [0]
     samp_off = [0]
-    pix_id, c_list, dl_l, m1_l, m2_l = [], [], [], [], []
+    pix_id, c_list, s_list, dl_l, m1_l, m2_l = [], [], [], [], [], []
     for e in range(ev.n_events):
         sl = slice(ev.offsets[e], ev.offsets[e + 1])
         pix = ev.pix[sl]
@@ -214,6 +233,7 @@ def prepare(cat: synth.Catalog, ev: synth.Events, n_z: int, z_lo: float, z_hi: f
             idx = idx[np.argsort(dle[idx], kind="stable")]
             pix_id.append(int(p))
             c_list.append(s_ir[r] / idx.size)
+            s_list.append(s_ir[r])
             dl_l.append(dle[idx]); m1_l.append(m1e[idx]); m2_l.append(m2e[idx])
             samp_off.append(samp_off[-1] + idx.size)
         ev_pix_off.append(len(pix_id))
@@ -227,7 +247,8 @@ def prepare(cat: synth.Catalog, ev: synth.Events, n_z: int, z_lo: float, z_hi: f
                     ev_pix_off=np.asarray(ev_pix_off, dtype=np.int64),
                     pix_samp_off=np.asarray(samp_off, dtype=np.int64),
                     pix_row=pix_row, pix_id=pix_id, c_ir=np.asarray(c_list),
-                    dl=np.concatenate(dl_l), m1d=np.concatenate(m1_l), m2d=np.concatenate(m2_l))
+                    dl=np.concatenate(dl_l), m1d=np.concatenate(m1_l), m2d=np.concatenate(m2_l),
+                    s_ir=np.asarray(s_list))
 
 
 def subset(p: Prepared, events) -> Prepared:
@@ -235,11 +256,12 @@ def subset(p: Prepared, events) -> Prepared:
     catalogue rows."""
     ev_off = [0]
     samp_off = [0]
-    rows, ids, cs, dls, m1s, m2s = [], [], [], [], [], []
+    rows, ids, cs, ss, dls, m1s, m2s = [], [], [], [], [], [], []
     for e in events:
         for q in range(p.ev_pix_off[e], p.ev_pix_off[e + 1]):
             a, b = p.pix_samp_off[q], p.pix_samp_off[q + 1]
             rows.append(p.pix_row[q]); ids.append(p.pix_id[q]); cs.append(p.c_ir[q])
+            ss.append(p.s_ir[q] if p.s_ir is not None else np.nan)
             dls.append(p.dl[a:b]); m1s.append(p.m1d[a:b]); m2s.append(p.m2d[a:b])
             samp_off.append(samp_off[-1] + (b - a))
         ev_off.append(len(rows))
@@ -247,7 +269,26 @@ def subset(p: Prepared, events) -> Prepared:
                     np.asarray(ev_off, np.int64), np.asarray(samp_off, np.int64),
                     np.asarray(rows, np.int64), np.asarray(ids, np.int64),
                     np.asarray(cs, np.float64), np.concatenate(dls), np.concatenate(m1s),
-                    np.concatenate(m2s))
+                    np.concatenate(m2s), None if p.s_ir is None else np.asarray(ss, np.float64))
+
+
+def single1d(p: Prepared, ev: synth.Events, events=None) -> Single1D:
+    """The single-1D arrays of the events p was prepared from (all of them, or
+    the listed ones in that order): the region, rows and sky factors of p,
+    and every raw sample of each event."""
+    events = range(p.n_events) if events is None else list(events)
+    samp_off, pix_off = [0], [0]
+    dls, m1s, m2s, rows, ss = [], [], [], [], []
+    for e in events:
+        a, b = int(ev.offsets[e]), int(ev.offsets[e + 1])
+        dls.append(ev.dl[a:b]); m1s.append(ev.m1d[a:b]); m2s.append(ev.m2d[a:b])
+        samp_off.append(samp_off[-1] + (b - a))
+        q0, q1 = p.ev_pix_off[e], p.ev_pix_off[e + 1]
+        rows.append(p.pix_row[q0:q1]); ss.append(p.s_ir[q0:q1])
+        pix_off.append(pix_off[-1] + (q1 - q0))
+    return Single1D(np.asarray(samp_off, np.int64), np.concatenate(dls), np.concatenate(m1s),
+                    np.concatenate(m2s), np.asarray(pix_off, np.int64),
+                    np.concatenate(rows).astype(np.int64), np.concatenate(ss).astype(np.float64))
 
 
 def galaxy_arrays(cat: synth.Catalog, n_z: int, z_lo: float, z_hi: float):
