@@ -25,6 +25,12 @@ eq. gw-kernel-single1d (the single-1D kernel of Sect. 2.3)
                 I_i = sum_r S_ir sum_g tau_g n_r(z_g) g(z_g) KDE(z_g)
                 (same weights, bandwidth rule and window as many-1D).
 
+Kernel options of Sect. 2.3 (kernel_values, bin_samples): the Epanechnikov
+                kernel in place of the Gaussian (reading: variance h^2, support
+                sqrt(5) h), and binned data sets (reading: n_bins equal-width
+                bins over each KDE's sample range, one point per bin at its
+                centre with the bin's summed weight).
+
 Bandwidth (the paper is silent; reading): one Gaussian bandwidth per
 (event, lambda) from all of the event's in-region samples: Scott's rule with
 the Kish effective size n_eff = W1^2/W2 and the unbiased weighted variance,
@@ -147,47 +153,106 @@ def grid_factor(grid, lam):
         (1.0 + grid) ** 3 * cosmo.ddl_gw_dz(grid, h0, om, xi0, n))
 
 
-def event_integral(pixels_z, pixels_w, pixels_c, pixels_row, grid, tau, gz, T=None):
-    """(I_i, h_i) of one event given its per-pixel (z, w, c, n_r)."""
+EPAN_SCALE = math.sqrt(5.0)
+
+
+def kernel_values(grid, z, h, shape="gaussian", T=None):
+    """[len(z), len(grid)] kernel K(z_g; z_j, h), each integrating to 1 in z.
+
+    "gaussian": N(z_g; z_j, h), kept where |z_g - z_j| <= T h when T is given.
+    "epanechnikov" (the compact option of Sect. 2.3; reading: scaled to the
+    variance h^2 so that the same bandwidth rule applies):
+    3 / (4 a h) max(0, 1 - ((z_g - z_j) / (a h))^2), a = sqrt(5); T is unused
+    (the kernel vanishes outside a h)."""
+    diff = grid[None, :] - np.asarray(z)[:, None]
+    if shape == "gaussian":
+        k = np.exp(-0.5 * (diff / h) ** 2) / (h * math.sqrt(2.0 * math.pi))
+        if T is not None:
+            k = np.where(np.abs(diff) <= T * h, k, 0.0)
+        return k
+    if shape == "epanechnikov":
+        ah = EPAN_SCALE * h
+        return 0.75 / ah * np.maximum(0.0, 1.0 - (diff / ah) ** 2)
+    raise ValueError(f"unknown kernel shape {shape!r}")
+
+
+def support(h, shape, T):
+    """Half-width of the kernel's support (None: the whole grid)."""
+    if shape == "epanechnikov":
+        return EPAN_SCALE * h
+    return None if T is None else T * h
+
+
+def grid_span(grid, z, reach):
+    """The grid points within reach of some z (all points for reach None);
+    only a saving: the kernel values outside are 0."""
+    if reach is None:
+        return slice(None)
+    lo = np.searchsorted(grid, np.min(z) - reach, side="left")
+    hi = np.searchsorted(grid, np.max(z) + reach, side="right")
+    return slice(lo, hi)
+
+
+def bin_samples(z, w, n_bins):
+    """The binned data set of Sect. 2.3 (reading): n_bins equal-width bins
+    spanning [min z, max z] of the samples (the largest in the last bin); each
+    bin becomes one point at its centre carrying the summed weight of its
+    samples (empty bins carry 0).  All samples at one redshift: one bin at
+    that redshift holds the whole weight."""
+    z = np.asarray(z, dtype=np.float64)
+    w = np.asarray(w, dtype=np.float64)
+    lo, hi = float(np.min(z)), float(np.max(z))
+    width = (hi - lo) / n_bins
+    if width > 0.0:
+        idx = np.minimum(np.floor((z - lo) / width).astype(np.int64), n_bins - 1)
+        centres = lo + (np.arange(n_bins) + 0.5) * width
+    else:
+        idx = np.zeros(z.size, dtype=np.int64)
+        centres = np.full(n_bins, lo)
+    weights = np.zeros(n_bins)
+    for b, wj in zip(idx, w):          # in sample order: a plain, ordered sum
+        weights[b] += wj
+    return centres, weights
+
+
+def event_integral(pixels_z, pixels_w, pixels_c, pixels_row, grid, tau, gz, T=None,
+                   shape="gaussian", n_bins=0):
+    """(I_i, h_i) of one event given its per-pixel (z, w, c, n_r).  shape:
+    the 1-D kernel (kernel_values); n_bins > 0 replaces each pixel's samples
+    by its binned data set (bin_samples) in the kernel sums, the bandwidth
+    and the 1/N_r in c staying those of the samples."""
     dz = grid[1] - grid[0]
     z_all = np.concatenate(pixels_z)
     w_all = np.concatenate(pixels_w)
     h = bandwidth(z_all, w_all, dz)
     if h is None:
         return 0.0, float("nan")
+    reach = support(h, shape, T)
     total = 0.0
-    norm = 1.0 / (h * math.sqrt(2.0 * math.pi))
     for zr, wr, c, nr in zip(pixels_z, pixels_w, pixels_c, pixels_row):
+        if n_bins:
+            zr, wr = bin_samples(zr, wr, n_bins)
         f = tau * nr * gz
-        if T is None:
-            g = slice(None)
-        else:
-            lo = np.searchsorted(grid, zr.min() - T * h, side="left")
-            hi = np.searchsorted(grid, zr.max() + T * h, side="right")
-            g = slice(lo, hi)
-        diff = grid[g][None, :] - zr[:, None]
-        k = np.exp(-0.5 * (diff / h) ** 2) * norm
-        if T is not None:
-            k = np.where(np.abs(diff) <= T * h, k, 0.0)
-        a = k @ f[g]
+        g = grid_span(grid, zr, reach)
+        a = kernel_values(grid[g], zr, h, shape, T) @ f[g]
         total += c * float(wr @ a)
     return total, h
 
 
-def event_integral_single1d(z_all, w_all, pixels_s, pixels_row, grid, tau, gz, T=None):
+def event_integral_single1d(z_all, w_all, pixels_s, pixels_row, grid, tau, gz, T=None,
+                            shape="gaussian", n_bins=0):
     """(I_i, h_i) of one event with the single-1D kernel (eq. gw-kernel-single1d):
     the event's one weighted redshift KDE over all its samples z_all (weights
-    w_all) on the grid, times each pixel's sky factor S_ir and catalogue row,
-    summed over pixels."""
+    w_all; binned when n_bins > 0) on the grid, times each pixel's sky factor
+    S_ir and catalogue row, summed over pixels."""
     dz = grid[1] - grid[0]
     h = bandwidth(z_all, w_all, dz)
     if h is None:
         return 0.0, float("nan")
-    diff = grid[None, :] - z_all[:, None]
-    k = np.exp(-0.5 * (diff / h) ** 2) / (h * math.sqrt(2.0 * math.pi))
-    if T is not None:
-        k = np.where(np.abs(diff) <= T * h, k, 0.0)
-    kde = (w_all @ k) / z_all.size
+    zk, wk = bin_samples(z_all, w_all, n_bins) if n_bins else (z_all, w_all)
+    g = grid_span(grid, zk, support(h, shape, T))
+    kde = np.zeros(grid.size)
+    kde[g] = (wk @ kernel_values(grid[g], zk, h, shape, T)) / z_all.size
     total = 0.0
     for s_ir, nr in zip(pixels_s, pixels_row):
         total += s_ir * float(np.sum(tau * nr * gz * kde))
@@ -218,29 +283,36 @@ def _event_worker(i):
     d = _WORK
     ev = d["events"][i]
     rs = [d["cat"].rows[px.pix] for px in ev.pixels]
+    opt = dict(shape=d["shape"], n_bins=d["n_bins"])
     if d["kernel"] == "single1d":
         sl = d["slices"][i][0]
         return event_integral_single1d(d["z"][sl], d["w"][sl], [px.sky() for px in ev.pixels], rs,
-                                       d["cat"].grid, d["tau"], d["gz"], d["T"])
+                                       d["cat"].grid, d["tau"], d["gz"], d["T"], **opt)
     zs, ws, cs = [], [], []
     for px in ev.pixels:
         sl = d["slices"][i][len(zs)]
         zs.append(d["z"][sl]); ws.append(d["w"][sl]); cs.append(px.c)
-    return event_integral(zs, ws, cs, rs, d["cat"].grid, d["tau"], d["gz"], d["T"])
+    return event_integral(zs, ws, cs, rs, d["cat"].grid, d["tau"], d["gz"], d["T"], **opt)
 
 
 def lnl(events, cat: Catalog, inj: InjectionSet, lam, T=None, workers: int = 1,
-        event_subset=None, kernel: str = "many1d"):
+        event_subset=None, kernel: str = "many1d", shape: str = "gaussian", n_bins: int = 0):
     """ln L and its parts at one lambda.
 
     kernel: "many1d" (eq. gw-kernel-many1d) or "single1d" (eq.
-    gw-kernel-single1d).  Returns dict(lnl, lnI[E] (NaN for events not in
-    event_subset), h[E], ln_xi, neff).  With event_subset, lnl is the partial
-    sum over those events minus len(subset) ln xi (used for sampled parity
-    checks).
+    gw-kernel-single1d); shape: the 1-D kernel ("gaussian" or
+    "epanechnikov", kernel_values); n_bins: 0, or the bins of each KDE's
+    binned data set (bin_samples).  Returns dict(lnl, lnI[E] (NaN for events
+    not in event_subset), h[E], ln_xi, neff).  With event_subset, lnl is the
+    partial sum over those events minus len(subset) ln xi (used for sampled
+    parity checks).
     """
     if kernel not in ("many1d", "single1d"):
         raise ValueError(f"unknown kernel {kernel!r}")
+    if shape not in ("gaussian", "epanechnikov"):
+        raise ValueError(f"unknown kernel shape {shape!r}")
+    if n_bins < 0:
+        raise ValueError("n_bins must be >= 0")
     lam = np.asarray(lam, dtype=np.float64)
     E = len(events)
     sub = list(range(E)) if event_subset is None else list(event_subset)
@@ -271,7 +343,7 @@ def lnl(events, cat: Catalog, inj: InjectionSet, lam, T=None, workers: int = 1,
         res["lnl"] = np.nan
         return res
     _WORK.update(events=events, slices=slices, z=z, w=w, cat=cat, tau=trapezoid(cat.grid),
-                 gz=grid_factor(cat.grid, lam), T=T, kernel=kernel)
+                 gz=grid_factor(cat.grid, lam), T=T, kernel=kernel, shape=shape, n_bins=n_bins)
     if workers > 1 and len(sub) > 1:
         import multiprocessing as mp
         with mp.get_context("fork").Pool(workers) as pool:
