@@ -83,6 +83,11 @@ enum { CHIMERA_HOST = 0, CHIMERA_DEVICE = 1 };
 #define CHIMERA_NLAM 14
 #define CHIMERA_NGRAD 12
 
+/* 1-D kernel shapes of an event set (chimera_set_event_kde). */
+enum { CHIMERA_KDE_GAUSSIAN = 0, CHIMERA_KDE_EPANECHNIKOV = 1 };
+/* Largest number of bins per KDE data set. */
+#define CHIMERA_MAX_BINS 4096
+
 typedef struct {
   int32_t n_z;          /* redshift grid points (>= 3)                                */
   double z_lo, z_hi;    /* grid z_g = z_lo + g (z_hi - z_lo)/(n_z - 1)                 */
@@ -196,6 +201,28 @@ chimera_status chimera_add_events_single1d(chimera_ctx* ctx, int32_t n_ev,
                                            const double* s_ir, chimera_events** out);
 chimera_status chimera_release_events(chimera_ctx* ctx, chimera_events* ev);
 
+/* Kernel options of a resident event set (Sect. 2.3: the 1-D KDEs take a
+ * Gaussian or an Epanechnikov kernel, and their data sets may be binned).
+ *   shape   CHIMERA_KDE_GAUSSIAN (the default of every set) or
+ *           CHIMERA_KDE_EPANECHNIKOV: K(z; z_j, h) = 3/(4 a h) (1 - u^2) for
+ *           |u| <= 1, u = (z - z_j)/(a h), a = sqrt(5) (the kernel of
+ *           variance h^2, so the bandwidth rule is unchanged); its support
+ *           replaces the T h window
+ *   n_bins  0 (the samples themselves) or 1..CHIMERA_MAX_BINS: at each
+ *           lambda every KDE data set (a pixel's samples, or for a single-1D
+ *           set the event's) is replaced by n_bins equal-width bins over its
+ *           redshift range, each a point at the bin's centre carrying the
+ *           summed weight of its samples (the largest redshift in the last
+ *           bin; all samples at one redshift: one point there).  The
+ *           bandwidth and the 1/N normalisation stay those of the samples.
+ * Later evaluation calls on the set use the options; chimera_lnl_grad
+ * refuses a set with other than the defaults (EINVAL).  Synchronous; waits
+ * for the device, so no call may be using the set.  EINVAL on a bad shape,
+ * n_bins out of range or an unknown set; ERANGE when the set's pixel slots
+ * times n_bins exceed 2^31 - 1. */
+chimera_status chimera_set_event_kde(chimera_ctx* ctx, chimera_events* ev, int32_t shape,
+                                     int32_t n_bins);
+
 /* ln L at B points (eq. hyperlike).  prec: CHIMERA_FP64, or CHIMERA_FP32 for
  * FP32 bulk arithmetic (mass weights, kernel sums) with the distance tables,
  * the inversion, the bandwidth moments and every per-event and per-lambda sum
@@ -268,7 +295,8 @@ chimera_status chimera_release_scratch(chimera_ctx* ctx, void* hip_stream);
  * The per-lambda layout is the same as above.  Device scratch grows with 120
  * bytes per sample and point (68 in FP32); a call whose scratch would exceed
  * 16 GiB runs as consecutive chunks of points on the same stream, with the
- * same results. */
+ * same results.  EINVAL for a set with kernel options other than the
+ * defaults (chimera_set_event_kde). */
 chimera_status chimera_lnl_grad(chimera_ctx* ctx, const chimera_events* ev, const double* lam,
                                 int64_t B, int32_t prec, double* lnl, double* grad, int32_t mem,
                                 void* hip_stream);

@@ -21,6 +21,8 @@ CHIMERA_OK, CHIMERA_EINVAL, CHIMERA_ENOMEM, CHIMERA_EDEVICE, CHIMERA_ERANGE, CHI
 CHIMERA_FP64, CHIMERA_FP32 = 0, 1
 CHIMERA_HOST, CHIMERA_DEVICE = 0, 1
 CHIMERA_MAX_EVENT_PIXELS = 2560
+CHIMERA_KDE_GAUSSIAN, CHIMERA_KDE_EPANECHNIKOV = 0, 1
+CHIMERA_MAX_BINS = 4096
 NLAM, NGRAD = 14, 12
 
 _STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ERANGE", -5: "ESTATE"}
@@ -29,7 +31,7 @@ _STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ERANGE", -5:
 EXPORTS = ("chimera_default_config", "chimera_create", "chimera_destroy", "chimera_last_error",
            "chimera_set_catalog", "chimera_set_catalog_galaxies", "chimera_get_catalog",
            "chimera_set_injections",
-           "chimera_add_events", "chimera_add_events_single1d",
+           "chimera_add_events", "chimera_add_events_single1d", "chimera_set_event_kde",
            "chimera_release_events", "chimera_lnl_batch", "chimera_lnl_batch_static",
            "chimera_selection_xi",
            "chimera_lnl_grad", "chimera_scratch_bytes", "chimera_scratch_held",
@@ -81,6 +83,7 @@ def _load():
                                               ctypes.POINTER(_P)]),
         "chimera_add_events_single1d": (ctypes.c_int, [_P, _I32, _P, _P, _P, _P, _P, _P, _P,
                                                        ctypes.POINTER(_P)]),
+        "chimera_set_event_kde": (ctypes.c_int, [_P, _P, _I32, _I32]),
         "chimera_release_events": (ctypes.c_int, [_P, _P]),
         "chimera_lnl_batch": (ctypes.c_int, [_P, _P, _P, _I64, _I32, _P, _P, _I32, _P]),
         "chimera_lnl_batch_static": (ctypes.c_int, [_P, _P, _P, _I64, _I32, _P, _P, _P]),
@@ -193,6 +196,10 @@ def chimera_add_events_single1d(h, ev_samp_off, dl, m1d, m2d, ev_pix_off, pix_ro
     _check(lib.chimera_add_events_single1d(h, o1.size - 1, p1, *[p for _, p in samp], p2, p3, p4,
                                            ctypes.byref(ev)))
     return ev
+
+
+def chimera_set_event_kde(h, ev, shape, n_bins):
+    _check(lib.chimera_set_event_kde(h, ev, int(shape), int(n_bins)))
 
 
 def chimera_release_events(h, ev):
@@ -372,6 +379,12 @@ class Context:
         h = chimera_add_events_single1d(self.handle, ev_samp_off, dl, m1d, m2d, ev_pix_off,
                                         pix_row, s_ir)
         return EventSet(self, h, len(ev_samp_off) - 1)
+
+    def set_event_kde(self, ev: EventSet, shape=None, n_bins=0):
+        """Kernel options of an event set: shape CHIMERA_KDE_GAUSSIAN (default)
+        or CHIMERA_KDE_EPANECHNIKOV, n_bins 0 (unbinned) or the bins per KDE."""
+        chimera_set_event_kde(self.handle, ev.handle,
+                              CHIMERA_KDE_GAUSSIAN if shape is None else shape, n_bins)
 
     def add_prepared_single1d(self, s) -> EventSet:
         """Resident single-1D event set from prep.Single1D."""

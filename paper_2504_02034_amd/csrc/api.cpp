@@ -112,6 +112,21 @@ struct chimera_events {
   double* fold_s = nullptr;     // [P] sky factor of each pixel
   double* own64 = nullptr;      // [E][n_z]
   float* own32 = nullptr;
+  // kernel options (chimera_set_event_kde, Sect. 2.3)
+  int P = 0;                    // pixel slots
+  int shape = 0, n_bins = 0;
+  int* pix_off = nullptr;       // [P+1] samples of each slot in pix_idx
+  int* pix_idx = nullptr;       // [n_samp] sample positions of each slot, by distance
+  double* slot_c = nullptr;     // [P] c_ir of each slot
+  int* ev_iota = nullptr;       // [E+1] e: one work unit per event (Epanechnikov)
+  // work layout over the bins: groups of <= kGroupK consecutive bins of a slot
+  std::vector<int> h_slot_off;   // host copies: slots of each event, c_ir of each slot
+  std::vector<double> h_slot_c;
+  int Ub = 0;
+  int *b_ev_unit_off = nullptr, *b_unit_event = nullptr, *b_unit_grp0 = nullptr,
+      *b_unit_ngrp = nullptr, *b_grp_first = nullptr, *b_grp_cnt = nullptr,
+      *b_grp_slot = nullptr;
+  double* b_grp_c = nullptr;
 };
 
 struct chimera_ctx {
@@ -146,6 +161,16 @@ struct chimera_ctx {
 
 namespace {
 
+void free_bin_layout(chimera_events* ev) {
+  dfree(ev->b_ev_unit_off); dfree(ev->b_unit_event); dfree(ev->b_unit_grp0);
+  dfree(ev->b_unit_ngrp); dfree(ev->b_grp_first); dfree(ev->b_grp_cnt); dfree(ev->b_grp_slot);
+  dfree(ev->b_grp_c);
+  ev->b_ev_unit_off = ev->b_unit_event = ev->b_unit_grp0 = ev->b_unit_ngrp = nullptr;
+  ev->b_grp_first = ev->b_grp_cnt = ev->b_grp_slot = nullptr;
+  ev->b_grp_c = nullptr;
+  ev->Ub = 0;
+}
+
 void free_events(chimera_events* ev) {
   dfree(ev->ev_samp_off); dfree(ev->ev_slot_off); dfree(ev->ev_unit_off); dfree(ev->slot_row);
   dfree(ev->unit_event); dfree(ev->unit_grp0); dfree(ev->unit_ngrp);
@@ -154,6 +179,8 @@ void free_events(chimera_events* ev) {
   dfree(ev->lnm1d); dfree(ev->lnm2d); dfree(ev->samp_row); dfree(ev->samp_c);
   dfree(ev->fold_pix_off); dfree(ev->fold_row); dfree(ev->fold_s);
   dfree(ev->own64); dfree(ev->own32);
+  dfree(ev->pix_off); dfree(ev->pix_idx); dfree(ev->slot_c); dfree(ev->ev_iota);
+  free_bin_layout(ev);
   delete ev;
 }
 
@@ -231,12 +258,19 @@ struct Scratch {
   double* hbuf;
   double* part;
   long long* pcount;
+  double* bz;
+  void* bw;
 };
 
 // Lay out (or size, when base is null) the scratch of one call.
-size_t carve(Carve& cv, Scratch& s, const Geometry& g, int64_t B, int E, int nchunk,
-             bool need_lam, bool need_lnI, bool need_grid, bool need_outs, int64_t S = 0,
-             int U = 0, bool f32 = false) {
+size_t carve(Carve& cv, Scratch& s, const Geometry& g, int64_t B, int nchunk, bool need_lam,
+             bool need_lnI, bool need_outs, const chimera_events* ev, bool f32) {
+  const bool need_grid = ev != nullptr;
+  const int E = ev ? ev->E : 0;
+  const int64_t S = ev ? ev->n_samp : 0;
+  // partial sums: one per work unit (samples or bins), or per event
+  const int U = ev ? std::max(std::max(ev->U, ev->Ub), ev->E) : 0;
+  const int64_t NB = ev && ev->n_bins ? (int64_t)ev->P * ev->n_bins : 0;
   s.P = cv.take<LamParams>(B);
   s.chi = cv.take<double2>((size_t)B * g.n_t);
   s.inv = cv.take<double2>((size_t)B * g.n_u);
@@ -257,6 +291,9 @@ size_t carve(Carve& cv, Scratch& s, const Geometry& g, int64_t B, int E, int nch
   s.hbuf = S ? cv.take<double>((size_t)B * E) : nullptr;
   s.part = S ? cv.take<double>((size_t)B * std::max(U, 1)) : nullptr;
   s.pcount = S ? cv.take<long long>((size_t)B * std::max(U, 1)) : nullptr;
+  s.bz = NB ? cv.take<double>((size_t)B * NB) : nullptr;
+  s.bw = NB ? (f32 ? (void*)cv.take<float>((size_t)B * NB) : (void*)cv.take<double>((size_t)B * NB))
+            : nullptr;
   return cv.off;
 }
 
@@ -644,7 +681,7 @@ chimera_status build_events(chimera_ctx* ctx, int32_t n_ev, const int64_t* ev_pi
   const int kSpreadRun = 128;
   std::vector<int> ev_samp(n_ev + 1, 0), ev_slot(n_ev + 1), ev_unit(n_ev + 1, 0), srow(P);
   std::vector<int> u_event, u_grp0, u_ngrp;
-  std::vector<int> gfirst, gcnt, gslot;
+  std::vector<int> gfirst, gcnt, gslot, gabs;
   std::vector<double> gc;
   std::vector<double> odl, om1, om2, oc;
   std::vector<int> orow;
@@ -704,6 +741,7 @@ chimera_status build_events(chimera_ctx* ctx, int32_t n_ev, const int64_t* ev_pi
       }
     }
     for (auto& g : groups) {
+      gabs.push_back((int)(ev_pix_off[e] + g.slot));
       gfirst.push_back((int)odl.size());
       gcnt.push_back((int)g.idx.size());
       gslot.push_back(g.slot);
@@ -718,6 +756,22 @@ chimera_status build_events(chimera_ctx* ctx, int32_t n_ev, const int64_t* ev_pi
     }
     ev_samp[e + 1] = (int)odl.size();
   }
+  // each slot's samples (positions in group order) by distance, for the
+  // binned data sets and the Epanechnikov sums
+  std::vector<int> s_off(P + 1, 0), s_idx(S);
+  for (size_t q = 0; q < gabs.size(); ++q) s_off[gabs[q] + 1] += gcnt[q];
+  for (int64_t p = 0; p < P; ++p) s_off[p + 1] += s_off[p];
+  {
+    std::vector<int> fill(s_off.begin(), s_off.end() - 1);
+    for (size_t q = 0; q < gabs.size(); ++q)
+      for (int k = 0; k < gcnt[q]; ++k) s_idx[fill[gabs[q]]++] = gfirst[q] + k;
+    for (int64_t p = 0; p < P; ++p)
+      std::stable_sort(s_idx.begin() + s_off[p], s_idx.begin() + s_off[p + 1],
+                       [&](int x, int y) { return odl[x] < odl[y]; });
+  }
+  std::vector<double> s_c(c_ir, c_ir + P);
+  std::vector<int> iota(n_ev + 1);
+  for (int i = 0; i <= n_ev; ++i) iota[i] = i;
   std::vector<double> ld(S), l1(S), l2(S);
   double dmin = std::numeric_limits<double>::infinity(), dmax = 0.0;
   for (int64_t j = 0; j < S; ++j) {
@@ -771,6 +825,14 @@ chimera_status build_events(chimera_ctx* ctx, int32_t n_ev, const int64_t* ev_pi
   if (e == hipSuccess) e = upload(&ev->lnm2d, l2.data(), S);
   if (e == hipSuccess) e = upload(&ev->samp_row, orow.data(), S);
   if (e == hipSuccess) e = upload(&ev->samp_c, oc.data(), S);
+  ev->P = (int)P;
+  if (e == hipSuccess) e = upload(&ev->pix_off, s_off.data(), s_off.size());
+  if (e == hipSuccess) e = upload(&ev->pix_idx, s_idx.data(), s_idx.size());
+  if (e == hipSuccess) e = upload(&ev->slot_c, s_c.data(), s_c.size());
+  if (e == hipSuccess) e = upload(&ev->ev_iota, iota.data(), iota.size());
+  // the bin layout of chimera_set_event_kde needs the slots' events
+  ev->h_slot_off.assign(ev_slot.begin(), ev_slot.end());
+  ev->h_slot_c = s_c;
   if (fold) {
     ev->single1d = true;
     const size_t rows = (size_t)n_ev * ctx->cfg.n_z;
@@ -805,13 +867,81 @@ chimera_status chimera_release_events(chimera_ctx* ctx, chimera_events* ev) {
   return CHIMERA_OK;
 }
 
+chimera_status chimera_set_event_kde(chimera_ctx* ctx, chimera_events* ev, int32_t shape,
+                                     int32_t n_bins) {
+  if (!ctx || !ev) return fail(CHIMERA_EINVAL, "null argument");
+  if (shape != CHIMERA_KDE_GAUSSIAN && shape != CHIMERA_KDE_EPANECHNIKOV)
+    return fail(CHIMERA_EINVAL, "unknown kernel shape");
+  if (n_bins < 0 || n_bins > CHIMERA_MAX_BINS)
+    return fail(CHIMERA_EINVAL, "n_bins out of [0, CHIMERA_MAX_BINS]");
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  if (std::find(ctx->events.begin(), ctx->events.end(), ev) == ctx->events.end())
+    return fail(CHIMERA_EINVAL, "unknown event set");
+  if ((int64_t)ev->P * n_bins > (int64_t)0x7fffffff)
+    return fail(CHIMERA_ERANGE, "pixel slots x n_bins exceed 2^31 - 1");
+  HIP_TRY(hipSetDevice(ctx->cfg.device));
+  HIP_TRY(hipDeviceSynchronize());
+  free_bin_layout(ev);
+  ev->shape = CHIMERA_KDE_GAUSSIAN;
+  ev->n_bins = 0;
+  if (n_bins > 0) {
+    // groups of <= kGroupK consecutive bins of one slot; within an event the
+    // groups are ordered by their place in the slots' ranges (every slot's
+    // first group, then every slot's second, ...), so that a work unit spans
+    // a narrow redshift range, and cut into runs of <= kUnitGroups
+    const int gps = (n_bins + kGroupK - 1) / kGroupK;
+    std::vector<int> eu(ev->E + 1, 0), ue, ug0, ung, gf, gn, gs;
+    std::vector<double> gcv;
+    for (int e = 0; e < ev->E; ++e) {
+      const int so = ev->h_slot_off[e], ns = ev->h_slot_off[e + 1] - so;
+      const int gbase = (int)gf.size();
+      for (int q = 0; q < gps; ++q)
+        for (int r = 0; r < ns; ++r) {
+          gf.push_back((so + r) * n_bins + q * kGroupK);
+          gn.push_back(std::min(kGroupK, n_bins - q * kGroupK));
+          gs.push_back(r);
+          gcv.push_back(ev->h_slot_c[so + r]);
+        }
+      const int ng = (int)gf.size() - gbase;
+      const int R = (ng + kUnitGroups - 1) / kUnitGroups;
+      for (int u = 0; u < R; ++u) {
+        const int a = (int)((long long)ng * u / R), z = (int)((long long)ng * (u + 1) / R);
+        ue.push_back(e);
+        ug0.push_back(gbase + a);
+        ung.push_back(z - a);
+      }
+      eu[e + 1] = (int)ue.size();
+    }
+    hipError_t er = hipSuccess;
+    if (er == hipSuccess) er = upload(&ev->b_ev_unit_off, eu.data(), eu.size());
+    if (er == hipSuccess) er = upload(&ev->b_unit_event, ue.data(), ue.size());
+    if (er == hipSuccess) er = upload(&ev->b_unit_grp0, ug0.data(), ug0.size());
+    if (er == hipSuccess) er = upload(&ev->b_unit_ngrp, ung.data(), ung.size());
+    if (er == hipSuccess) er = upload(&ev->b_grp_first, gf.data(), gf.size());
+    if (er == hipSuccess) er = upload(&ev->b_grp_cnt, gn.data(), gn.size());
+    if (er == hipSuccess) er = upload(&ev->b_grp_slot, gs.data(), gs.size());
+    if (er == hipSuccess) er = upload(&ev->b_grp_c, gcv.data(), gcv.size());
+    if (er != hipSuccess) {
+      free_bin_layout(ev);
+      return fail(er == hipErrorOutOfMemory ? CHIMERA_ENOMEM : CHIMERA_EDEVICE,
+                  std::string("uploading the bin layout: ") + hipGetErrorString(er));
+    }
+    ev->Ub = (int)ue.size();
+  }
+  ev->shape = shape;
+  ev->n_bins = n_bins;
+  return CHIMERA_OK;
+}
+
 // Largest per-sample scratch (z_j, w_j for every sample and lambda) of one
 // launch sequence; a call over more lambda points runs in consecutive chunks.
 constexpr double kSampleScratchCap = 8.0 * (1ull << 30);
 
 int64_t lambda_chunk(const chimera_events* ev, int64_t B, bool f32) {
   if (!ev) return B;
-  const double per = (double)ev->n_samp * (f32 ? 12.0 : 16.0) + 8.0 * (ev->E + ev->U);
+  const double nb = ev->n_bins ? (double)ev->P * ev->n_bins : 0.0;
+  const double per = ((double)ev->n_samp + nb) * (f32 ? 12.0 : 16.0) +
+                     8.0 * (ev->E + std::max(std::max(ev->U, ev->Ub), ev->E));
   const int64_t c = (int64_t)std::max(1.0, std::floor(kSampleScratchCap / per));
   return std::min(B, c);
 }
@@ -867,10 +997,7 @@ static chimera_status run_chunk(chimera_ctx* ctx, const chimera_events* ev, cons
   Scratch s;
   Carve probe;
   const bool need_lnI = ev && (host || !lnI);
-  const int64_t S_ev = ev ? ev->n_samp : 0;
-  const int U_ev = ev ? ev->U : 0;
-  const size_t bytes = carve(probe, s, g, B, E, nchunk, host, need_lnI, ev != nullptr, host,
-                             S_ev, U_ev, f32);
+  const size_t bytes = carve(probe, s, g, B, nchunk, host, need_lnI, host, ev, f32);
   if (ctx->cfg.hbm_budget && pool_size(bytes) > ctx->cfg.hbm_budget)
     return fail(CHIMERA_ENOMEM, "call needs " + std::to_string(bytes) +
                                     " scratch bytes, over the context's hbm_budget");
@@ -886,7 +1013,7 @@ static chimera_status run_chunk(chimera_ctx* ctx, const chimera_events* ev, cons
   }
   Carve cv;
   cv.base = (char*)base;
-  carve(cv, s, g, B, E, nchunk, host, need_lnI, ev != nullptr, host, S_ev, U_ev, f32);
+  carve(cv, s, g, B, nchunk, host, need_lnI, host, ev, f32);
   const double* lam_dev = lam;
   if (host) {
     HIP_TRY(hipMemcpyAsync(s.lam, lam, (size_t)B * CHIMERA_NLAM * sizeof(double),
@@ -932,8 +1059,24 @@ static chimera_status run_chunk(chimera_ctx* ctx, const chimera_events* ev, cons
       HIP_TRY(hipEventCreate(&t0));
       HIP_TRY(hipEventCreate(&t1));
     }
-    // t0 / t1 bracket the smoothing kernel (the dominant one) on stream st
-    HIP_TRY(launch_events(a, f32, st, t0, t1));
+    a.shape = ev->shape; a.n_bins = ev->n_bins; a.n_slots = ev->P;
+    a.pix_off = ev->pix_off; a.pix_idx = ev->pix_idx; a.slot_c = ev->slot_c;
+    a.bz = s.bz; a.bw = s.bw;
+    // the kernel-sum launch: over the samples, the bins, or one unit per event
+    EventArgs k = a;
+    if (ev->shape == CHIMERA_KDE_EPANECHNIKOV) {
+      k.U = E;
+      k.ev_unit_off = ev->ev_iota;
+    } else if (ev->n_bins) {
+      k.zbuf = s.bz; k.wbuf = s.bw; k.S = (long long)ev->P * ev->n_bins;
+      k.ev_unit_off = ev->b_ev_unit_off; k.U = ev->Ub;
+      k.grp_first = ev->b_grp_first; k.grp_cnt = ev->b_grp_cnt; k.grp_slot = ev->b_grp_slot;
+      k.grp_c = ev->b_grp_c;
+      k.unit_event = ev->b_unit_event; k.unit_grp0 = ev->b_unit_grp0;
+      k.unit_ngrp = ev->b_unit_ngrp;
+    }
+    // t0 / t1 bracket the kernel sums (the dominant kernel) on stream st
+    HIP_TRY(launch_events(a, k, f32, st, t0, t1));
     if (t0) {
       std::lock_guard<std::mutex> lk(ctx->mu);
       ctx->marks.emplace_back(t0, t1);
@@ -986,9 +1129,8 @@ chimera_status chimera_scratch_bytes(chimera_ctx* ctx, const chimera_events* ev,
   Carve probe;
   // lnI is counted whenever there is an event set: a device call without an
   // lnI output keeps it in the scratch
-  *bytes = pool_size(carve(probe, s, g, B, E, selection_chunks(ctx->n_det), host, ev != nullptr,
-                           ev != nullptr, host, ev ? ev->n_samp : 0, ev ? ev->U : 0,
-                           prec == CHIMERA_FP32));
+  *bytes = pool_size(carve(probe, s, g, B, selection_chunks(ctx->n_det), host, ev != nullptr,
+                           host, ev, prec == CHIMERA_FP32));
   return CHIMERA_OK;
 }
 
@@ -1055,8 +1197,7 @@ static size_t device_launch_bytes(chimera_ctx* ctx, const chimera_events* ev, in
   const Geometry g = make_geometry(ctx, dmin, dmax);
   Scratch s;
   Carve probe;
-  return carve(probe, s, g, B, ev->E, selection_chunks(ctx->n_det), false, !have_lnI, true, false,
-               ev->n_samp, ev->U, f32);
+  return carve(probe, s, g, B, selection_chunks(ctx->n_det), false, !have_lnI, false, ev, f32);
 }
 
 chimera_status chimera_lnl_batch_static(chimera_ctx* ctx, const chimera_events* ev,
@@ -1232,6 +1373,8 @@ chimera_status chimera_lnl_grad(chimera_ctx* ctx, const chimera_events* ev, cons
   if (s != CHIMERA_OK) return s;
   if (!ev) return fail(CHIMERA_EINVAL, "null event set");
   if (!lnl || !grad) return fail(CHIMERA_EINVAL, "null output");
+  if (ev->shape != CHIMERA_KDE_GAUSSIAN || ev->n_bins != 0)
+    return fail(CHIMERA_EINVAL, "the adjoint takes the Gaussian kernel on unbinned samples");
   return run_grad(ctx, ev, lam, B, prec, lnl, grad, mem, hip_stream);
 }
 

@@ -511,6 +511,258 @@ __global__ __launch_bounds__(256) void k_count_sum(const long long* __restrict__
 }
 
 // ---------------------------------------------------------------------------
+// Binned data sets (Sect. 2.3): per pixel slot and lambda, n_bins equal-width
+// bins over the slot's redshift range; a bin's point sits at its centre and
+// carries the summed weight of its samples.  The slot's samples are read in
+// distance order (pix_idx), which is redshift order since d_L^gw increases,
+// so each bin holds a contiguous run: lane q finds its run by two binary
+// searches and sums it in order (a fixed order, no atomics).
+template <bool F32>
+__global__ __launch_bounds__(kBinBS) void k_event_bin(EventArgs a) {
+  using CT = typename std::conditional<F32, float, double>::type;
+  constexpr int SPB = kBinBS / 64;                        // slots per workgroup
+  int it, b;
+  if (!decode_item_lambda((a.n_slots + SPB - 1) / SPB, a.B, it, b)) return;
+  const int p = it * SPB + (int)(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (p >= a.n_slots) return;
+  if (a.P[b].flag | a.flag_mono[b] | a.flag_range[b]) return;
+  const int j0 = a.pix_off[p], n = a.pix_off[p + 1] - j0;
+  const int* idx = a.pix_idx + j0;
+  const double* zb = a.zbuf + (size_t)b * a.S;
+  const CT* wb = (const CT*)a.wbuf + (size_t)b * a.S;
+  const int nb = a.n_bins;
+  const double zlo = zb[idx[0]], zhi = zb[idx[n - 1]];
+  const double width = (zhi - zlo) / (double)nb;
+  auto bin_of = [&](int j) -> int {
+    if (!(width > 0.0)) return 0;
+    const double q = floor((zb[idx[j]] - zlo) / width);
+    return q >= (double)(nb - 1) ? nb - 1 : (int)q;
+  };
+  // first position in [lo, n) whose bin is >= q
+  auto first_at = [&](int lo, int q) {
+    int hi = n;
+    while (lo < hi) {
+      const int m = (lo + hi) >> 1;
+      if (bin_of(m) < q) lo = m + 1;
+      else hi = m;
+    }
+    return lo;
+  };
+  const size_t base = (size_t)b * a.n_slots * nb + (size_t)p * nb;
+  for (int q = lane; q < nb; q += 64) {
+    const int s = first_at(0, q);
+    const int e = first_at(s, q + 1);
+    double wsum = 0.0;
+    for (int j = s; j < e; ++j) wsum += (double)wb[idx[j]];
+    a.bz[base + q] = width > 0.0 ? zlo + ((double)q + 0.5) * width : zlo;
+    ((CT*)a.bw)[base + q] = (CT)wsum;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Epanechnikov kernel sums (Sect. 2.3's compact option): with
+// K = 3/(4 a h) (1 - u^2), u = (z_g - z_j) / (a h), a = sqrt(5), and W = a h / dz,
+//   sum_{|g - x_j| <= W} tau_g F(z_g) (1 - (g - x_j)^2 / W^2)
+//     = S0 - (S2 - 2 d S1 + d^2 S0) / W^2,   S_m = sum tau F (g - m0)^m,
+// d = x_j - m0, over the sample's window: each S_m is a difference of two
+// prefix sums, so a sample costs O(1) whatever its window.  One (event,
+// lambda) per workgroup; each wave takes pixel slots in turn and walks the
+// slot's points (samples, or bins) in redshift order in chunks whose windows
+// fit kEpCap grid points: it stages tau F over the chunk's range in LDS (the
+// grid factor already carries tau),
+// forms the three prefix sums in FP64 (per lane over a contiguous block, then
+// a scan across lanes), and evaluates the chunk's points.  The origin m0 is
+// the chunk's middle point, which keeps (g - m0)^2 small against the window.
+template <bool F32>
+__global__ __launch_bounds__(kEpBS) void k_event_epan(EventArgs a) {
+  using CT = typename std::conditional<F32, float, double>::type;
+  constexpr int NWV = kEpBS / 64;
+  int e, b;
+  if (!decode_item_lambda(a.E, a.B, e, b)) return;
+  __shared__ double q0[NWV][kEpCap], q1[NWV][kEpCap], q2[NWV][kEpCap];
+  __shared__ double wtot[NWV];
+  __shared__ long long wcnt[NWV];
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  double* part = a.part + (size_t)b * a.E + e;
+  const LamParams P = a.P[b];
+  const double h = a.hbuf[(size_t)b * a.E + e];
+  if ((P.flag | a.flag_mono[b] | a.flag_range[b]) || !(h > 0.0)) {
+    if (threadIdx.x == 0) {
+      *part = 0.0;
+      if (a.count) a.pcount[(size_t)b * a.E + e] = 0;
+    }
+    return;
+  }
+  const int nz = a.g.n_z;
+  const double W = kEpanScale * h * a.g.inv_dz;
+  const double inv_W2 = 1.0 / (W * W);
+  const CT* gz = F32 ? (const CT*)(a.gz32 + (size_t)b * nz) : (const CT*)(a.gz64 + (size_t)b * nz);
+  const CT* nzt = F32 ? (const CT*)a.nz32 : (const CT*)a.nz64;
+  const bool binned = a.n_bins > 0;
+  const double* zsrc = binned ? a.bz + (size_t)b * a.n_slots * a.n_bins : a.zbuf + (size_t)b * a.S;
+  const CT* wsrc = binned ? (const CT*)a.bw + (size_t)b * a.n_slots * a.n_bins
+                          : (const CT*)a.wbuf + (size_t)b * a.S;
+  const int s0 = a.ev_slot_off[e], ns = a.ev_slot_off[e + 1] - s0;
+  double* Q0 = q0[wv];
+  double* Q1 = q1[wv];
+  double* Q2 = q2[wv];
+  auto wave_sync = [] {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  };
+  double wave_total = 0.0;
+  long long npts = 0;
+  for (int r = wv; r < ns; r += NWV) {
+    const int p = s0 + r;
+    int j0, n;
+    const int* idx = nullptr;
+    if (binned) {
+      j0 = p * a.n_bins;
+      n = a.n_bins;
+    } else {
+      j0 = a.pix_off[p];
+      n = a.pix_off[p + 1] - j0;
+      idx = a.pix_idx + j0;
+    }
+    auto pos = [&](int j) { return idx ? idx[j] : j0 + j; };
+    auto xat = [&](int j) { return (zsrc[pos(j)] - a.g.z_lo) * a.g.inv_dz; };
+    const CT* row = nzt + (size_t)a.slot_row[p] * nz;
+    double acc = 0.0;
+    int j = 0;
+    while (j < n) {
+      const double lo0 = ceil(xat(j) - W);
+      if (lo0 > (double)(nz - 1)) break;                 // this point and the rest lie above the grid
+      const int glo = (int)fmax(lo0, 0.0);
+      // the chunk: points from j on whose windows end within glo + kEpCap - 1
+      // (the window ends rise with j, so they are a prefix)
+      int j1 = j;
+      for (;;) {
+        const int jj = j1 + lane;
+        bool ok = false;
+        if (jj < n) ok = fmin(floor(xat(jj) + W), (double)(nz - 1)) <= (double)(glo + kEpCap - 1);
+        const unsigned long long m = __ballot(ok);
+        const int lead = (~m == 0ull) ? 64 : __builtin_ctzll(~m);
+        j1 += lead;
+        if (lead < 64 || j1 >= n) break;
+      }
+      if (j1 == j) {
+        // a window wider than a chunk: a direct sum, the wave across its points
+        const double xj = xat(j);
+        const int lo = (int)fmax(ceil(xj - W), 0.0), hi = (int)fmin(floor(xj + W), (double)(nz - 1));
+        double t = 0.0;
+        for (int g = lo + lane; g <= hi; g += 64) {
+          const double u = ((double)g - xj) / W;
+          t += (double)(row[g] * gz[g]) * (1.0 - u * u);
+        }
+        t = wave_sum(t);
+        if (lane == 0) {
+          acc += (double)wsrc[pos(j)] * t;
+          npts += 1;
+        }
+        ++j;
+        continue;
+      }
+      const int ghi = (int)fmin(floor(xat(j1 - 1) + W), (double)(nz - 1));
+      if (ghi < glo) {           // no grid point in any window of the chunk
+        j = j1;
+        continue;
+      }
+      const int L = ghi - glo + 1;                       // <= kEpCap
+      const int mid = glo + (L >> 1);
+      wave_sync();               // the previous chunk's prefix sums are read
+      for (int q = lane; q < L; q += 64) {
+        const int g = glo + q;
+        Q0[q] = (double)(row[g] * gz[g]);                // gz carries tau_g
+      }
+      wave_sync();
+      // per lane: a contiguous block of <= kEpCap / 64 points
+      const int per = (L + 63) >> 6;
+      const int qa = min(lane * per, L), qb = min(qa + per, L);
+      double f[kEpCap / 64];
+      double t0 = 0.0, t1 = 0.0, t2 = 0.0;
+#pragma unroll
+      for (int i = 0; i < kEpCap / 64; ++i) {
+        f[i] = qa + i < qb ? Q0[qa + i] : 0.0;
+        const double t = (double)(qa + i + glo - mid);
+        t0 += f[i];
+        t1 += f[i] * t;
+        t2 += f[i] * t * t;
+      }
+      // exclusive scan of the lane totals across the wave (lane order)
+      double c0 = t0, c1 = t1, c2 = t2;
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const double u0 = __shfl_up(c0, o, 64), u1 = __shfl_up(c1, o, 64), u2 = __shfl_up(c2, o, 64);
+        if (lane >= o) {
+          c0 += u0;
+          c1 += u1;
+          c2 += u2;
+        }
+      }
+      c0 -= t0;
+      c1 -= t1;
+      c2 -= t2;
+      wave_sync();               // every lane has read its block of F
+#pragma unroll
+      for (int i = 0; i < kEpCap / 64; ++i) {
+        if (qa + i < qb) {
+          const double t = (double)(qa + i + glo - mid);
+          c0 += f[i];
+          c1 += f[i] * t;
+          c2 += f[i] * t * t;
+          Q0[qa + i] = c0;
+          Q1[qa + i] = c1;
+          Q2[qa + i] = c2;
+        }
+      }
+      wave_sync();
+      for (int k = j + lane; k < j1; k += 64) {
+        const double wk = (double)wsrc[pos(k)];
+        if (!(wk > 0.0)) continue;
+        const double xk = xat(k);
+        const int lo = (int)fmax(ceil(xk - W), (double)glo);
+        const int hi = (int)fmin(floor(xk + W), (double)ghi);
+        if (lo > hi) continue;
+        const int qh = hi - glo, ql = lo - 1 - glo;
+        const double S0 = Q0[qh] - (ql >= 0 ? Q0[ql] : 0.0);
+        const double S1 = Q1[qh] - (ql >= 0 ? Q1[ql] : 0.0);
+        const double S2 = Q2[qh] - (ql >= 0 ? Q2[ql] : 0.0);
+        const double d = xk - (double)mid;
+        const double A = S0 - (S2 - 2.0 * d * S1 + d * d * S0) * inv_W2;
+        acc += wk * fmax(A, 0.0);
+        npts += 1;
+      }
+      j = j1;
+    }
+    const double st = wave_sum(acc);
+    if (lane == 0) wave_total += a.slot_c[p] * st;
+  }
+  if (a.count) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) npts += __shfl_xor(npts, o, 64);
+  }
+  if (lane == 0) {
+    wtot[wv] = wave_total;
+    wcnt[wv] = npts;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    long long c = 0;
+#pragma unroll
+    for (int k = 0; k < NWV; ++k) {
+      t += wtot[k];
+      c += wcnt[k];
+    }
+    *part = t;
+    if (a.count) a.pcount[(size_t)b * a.E + e] = c;
+  }
+}
+
+// ---------------------------------------------------------------------------
 __global__ void k_event_final(EventArgs a) {
   const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (id >= (long long)a.B * a.E) return;
@@ -523,31 +775,45 @@ __global__ void k_event_final(EventArgs a) {
     const double h = a.hbuf[(size_t)b * a.E + e];
     double s = 0.0;
     for (int u = a.ev_unit_off[e]; u < a.ev_unit_off[e + 1]; ++u) s += a.part[(size_t)b * a.U + u];
-    const double I = h > 0.0 ? s * kInvSqrt2Pi / h : 0.0;
+    const double norm = a.shape == kShapeEpanechnikov ? 0.75 / kEpanScale : kInvSqrt2Pi;
+    const double I = h > 0.0 ? s * norm / h : 0.0;
     out = I > 0.0 ? log(I) : -INFINITY;
   }
   a.lnI[(size_t)b * a.E + e] = out;
 }
 
 // ---------------------------------------------------------------------------
-hipError_t launch_events(const EventArgs& a, bool f32, hipStream_t st, hipEvent_t t0,
-                         hipEvent_t t1) {
+hipError_t launch_events(const EventArgs& a, const EventArgs& kern, bool f32, hipStream_t st,
+                         hipEvent_t t0, hipEvent_t t1) {
   const long long bz = item_lambda_blocks(a.E, a.B);
-  const long long bs = item_lambda_blocks(a.U, a.B);
-  const size_t lds = (size_t)sm_fbytes(f32) + (size_t)kSmGCap * (f32 ? sizeof(float) : sizeof(double));
-  const void* smooth = f32 ? (const void*)k_event_smooth32 : (const void*)k_event_smooth64;
   hipError_t err;
   if (f32) k_event_zw<true><<<(unsigned)bz, kZwBS, 0, st>>>(a);
   else k_event_zw<false><<<(unsigned)bz, kZwBS, 0, st>>>(a);
-  err = hipFuncSetAttribute(smooth, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  if (err != hipSuccess) return err;
-  if (t0 && (err = hipEventRecord(t0, st)) != hipSuccess) return err;
-  if (f32) k_event_smooth32<<<(unsigned)bs, kSmBS, lds, st>>>(a);
-  else k_event_smooth64<<<(unsigned)bs, kSmBS, lds, st>>>(a);
-  if (t1 && (err = hipEventRecord(t1, st)) != hipSuccess) return err;
-  if (a.count) k_count_sum<<<1, 256, 0, st>>>(a.pcount, (long long)a.B * a.U, a.count);
-  const long long nf = (long long)a.B * a.E;
-  k_event_final<<<(unsigned)((nf + 255) / 256), 256, 0, st>>>(a);
+  if (a.n_bins > 0) {
+    const long long bb = item_lambda_blocks((a.n_slots + kBinBS / 64 - 1) / (kBinBS / 64), a.B);
+    if (f32) k_event_bin<true><<<(unsigned)bb, kBinBS, 0, st>>>(a);
+    else k_event_bin<false><<<(unsigned)bb, kBinBS, 0, st>>>(a);
+  }
+  if (kern.shape == kShapeEpanechnikov) {
+    if (t0 && (err = hipEventRecord(t0, st)) != hipSuccess) return err;
+    if (f32) k_event_epan<true><<<(unsigned)bz, kEpBS, 0, st>>>(kern);
+    else k_event_epan<false><<<(unsigned)bz, kEpBS, 0, st>>>(kern);
+    if (t1 && (err = hipEventRecord(t1, st)) != hipSuccess) return err;
+  } else {
+    const long long bs = item_lambda_blocks(kern.U, kern.B);
+    const size_t lds =
+        (size_t)sm_fbytes(f32) + (size_t)kSmGCap * (f32 ? sizeof(float) : sizeof(double));
+    const void* smooth = f32 ? (const void*)k_event_smooth32 : (const void*)k_event_smooth64;
+    err = hipFuncSetAttribute(smooth, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (err != hipSuccess) return err;
+    if (t0 && (err = hipEventRecord(t0, st)) != hipSuccess) return err;
+    if (f32) k_event_smooth32<<<(unsigned)bs, kSmBS, lds, st>>>(kern);
+    else k_event_smooth64<<<(unsigned)bs, kSmBS, lds, st>>>(kern);
+    if (t1 && (err = hipEventRecord(t1, st)) != hipSuccess) return err;
+  }
+  if (kern.count) k_count_sum<<<1, 256, 0, st>>>(kern.pcount, (long long)kern.B * kern.U, kern.count);
+  const long long nf = (long long)kern.B * kern.E;
+  k_event_final<<<(unsigned)((nf + 255) / 256), 256, 0, st>>>(kern);
   return hipGetLastError();
 }
 

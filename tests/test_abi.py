@@ -61,8 +61,10 @@ def test_constants_match_header():
     src = open(os.path.join(ROOT, "include", "chimera.h")).read()
     defined = dict(re.findall(r"#define\s+(CHIMERA_[A-Z_]+)\s+(-?\d+)", src))
     assert int(defined["CHIMERA_MAX_EVENT_PIXELS"]) == chimera.CHIMERA_MAX_EVENT_PIXELS
+    assert int(defined["CHIMERA_MAX_BINS"]) == chimera.CHIMERA_MAX_BINS
     enum = dict(re.findall(r"\b(CHIMERA_[A-Z0-9_]+)\s*=\s*(-?\d+)", src))
     for name in ("CHIMERA_OK", "CHIMERA_EINVAL", "CHIMERA_ENOMEM", "CHIMERA_EDEVICE",
                  "CHIMERA_ERANGE", "CHIMERA_ESTATE", "CHIMERA_FP64", "CHIMERA_FP32",
-                 "CHIMERA_HOST", "CHIMERA_DEVICE"):
+                 "CHIMERA_HOST", "CHIMERA_DEVICE", "CHIMERA_KDE_GAUSSIAN",
+                 "CHIMERA_KDE_EPANECHNIKOV"):
         assert int(enum[name]) == getattr(chimera, name), name
