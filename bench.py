@@ -213,6 +213,59 @@ def time_grad(ctx, es, lam_t, prec, steps):
     return (time.perf_counter() - t) / steps
 
 
+#: the other kernels of Sect. 2.3 timed on the same events: (KDE layout,
+#: 1-D kernel shape, bins per KDE data set)
+VARIANTS = [("single1d", "gaussian", 0), ("many1d", "epanechnikov", 0),
+            ("single1d", "epanechnikov", 0), ("many1d", "gaussian", 16),
+            ("single1d", "gaussian", 64)]
+
+
+def variants_bench(ctx, es, p, ev, lam_t, many, steps, warmup):
+    """Each variant on the bench batch: ms per step in both precisions, the
+    dominant kernel's time (HIP events), FP32 vs FP64 |Delta ln L| and the
+    speedup over the many-1D Gaussian step of the same precision."""
+    import numpy as np
+    from paper_2504_02034_amd import chimera, prep
+    shapes = {"gaussian": chimera.CHIMERA_KDE_GAUSSIAN,
+              "epanechnikov": chimera.CHIMERA_KDE_EPANECHNIKOV}
+    single = ctx.add_prepared_single1d(prep.single1d(p, ev))
+    sets = {"many1d": es, "single1d": single}
+    B = lam_t.shape[0]
+    out = []
+    for kernel, shape, nb in VARIANTS:
+        es_v = sets[kernel]
+        ctx.set_event_kde(es_v, shapes[shape], nb)
+        r = {"kernel": kernel, "shape": shape, "n_bins": nb}
+        vals = {}
+        for name, prec in (("fp64", chimera.CHIMERA_FP64), ("fp32", chimera.CHIMERA_FP32)):
+            o, wall, lat, n, ms, evals = time_precision(ctx, es_v, lam_t, prec, steps, warmup)
+            avg_ms = ms / max(n, 1)
+            dominant = ("k_event_epan" if shape == "epanechnikov" else "k_event_smooth") + name[2:]
+            vals[name] = o
+            r[name] = {"value": round(B * steps / wall, 2), "ms_per_step": round(wall / steps * 1e3, 4),
+                       "kernel": dominant, "kernel_ms": round(avg_ms, 4),
+                       "speedup_over_many1d_gaussian": round(many[name]["wall"] / wall, 3)}
+            if shape == "gaussian":
+                per_launch = evals / max(n, 1)
+                achieved = per_launch * FLOPS_PER_EVAL / (avg_ms * 1e-3) / 1e12
+                r[name].update(evals_per_launch=int(per_launch), achieved_tflops=round(achieved, 3),
+                               frac=round(achieved / PEAK_TFLOPS[name], 4))
+            else:
+                r[name]["points_per_launch"] = int(evals / max(n, 1))
+            log(f"{kernel} {shape} bins={nb} {name}: {wall / steps * 1e3:.2f} ms/step, "
+                f"{dominant} {avg_ms:.2f} ms")
+        fin = np.isfinite(vals["fp64"]) & np.isfinite(vals["fp32"])
+        r["abs_dlnL_fp32_vs_fp64"] = {
+            "max": float(np.max(np.abs(vals["fp32"][fin] - vals["fp64"][fin]))) if fin.any() else None,
+            "same_finite_mask": bool(np.array_equal(np.isfinite(vals["fp32"]),
+                                                    np.isfinite(vals["fp64"]))),
+            "finite_points": int(fin.sum())}
+        ctx.set_event_kde(es_v)
+        out.append(r)
+    single.release()
+    return out
+
+
 def serve_bench(wl, cf, inj, n_requests=300, seed=5, max_pass_s=0.05):
     """Serving: resident event sets of 50, 300, 1000 and 3000 distinct events
     x 4096 samples (nested subsets of one generated set of 3000) sharing the
@@ -368,6 +421,8 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-grad", action="store_true")
     ap.add_argument("--no-photo", action="store_true")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the single-1D, Epanechnikov and binned kernels")
     ap.add_argument("--photo-one", action="store_true",
                     help="the photometric workload for the Xi0 = 1 truth only (default: the "
                          "three truths 0.6, 1.0, 1.8)")
@@ -459,6 +514,9 @@ def main():
             log(f"grad {name}: {sec * 1e3:.2f} ms for {lam_g.shape[0]} lambda")
         g.update(grad_checks(ctx, es, lam_g))
         line["grad"] = g
+    if not args.no_variants:
+        line["kernel_variants"] = variants_bench(ctx, es, p, ev, lam_t, res, args.steps,
+                                                 args.warmup)
     ctx.close()
     if not args.no_serve:
         line["serving"] = serve_bench(wl, cf, inj)

@@ -118,7 +118,7 @@ struct chimera_events {
   int* pix_off = nullptr;       // [P+1] samples of each slot in pix_idx
   int* pix_idx = nullptr;       // [n_samp] sample positions of each slot, by distance
   double* slot_c = nullptr;     // [P] c_ir of each slot
-  int* ev_iota = nullptr;       // [E+1] e: one work unit per event (Epanechnikov)
+  int* slot_event = nullptr;    // [P] event of each slot
   // work layout over the bins: groups of <= kGroupK consecutive bins of a slot
   std::vector<int> h_slot_off;   // host copies: slots of each event, c_ir of each slot
   std::vector<double> h_slot_c;
@@ -179,7 +179,7 @@ void free_events(chimera_events* ev) {
   dfree(ev->lnm1d); dfree(ev->lnm2d); dfree(ev->samp_row); dfree(ev->samp_c);
   dfree(ev->fold_pix_off); dfree(ev->fold_row); dfree(ev->fold_s);
   dfree(ev->own64); dfree(ev->own32);
-  dfree(ev->pix_off); dfree(ev->pix_idx); dfree(ev->slot_c); dfree(ev->ev_iota);
+  dfree(ev->pix_off); dfree(ev->pix_idx); dfree(ev->slot_c); dfree(ev->slot_event);
   free_bin_layout(ev);
   delete ev;
 }
@@ -269,7 +269,7 @@ size_t carve(Carve& cv, Scratch& s, const Geometry& g, int64_t B, int nchunk, bo
   const int E = ev ? ev->E : 0;
   const int64_t S = ev ? ev->n_samp : 0;
   // partial sums: one per work unit (samples or bins), or per event
-  const int U = ev ? std::max(std::max(ev->U, ev->Ub), ev->E) : 0;
+  const int U = ev ? std::max(std::max(ev->U, ev->Ub), ev->P) : 0;
   const int64_t NB = ev && ev->n_bins ? (int64_t)ev->P * ev->n_bins : 0;
   s.P = cv.take<LamParams>(B);
   s.chi = cv.take<double2>((size_t)B * g.n_t);
@@ -770,8 +770,9 @@ chimera_status build_events(chimera_ctx* ctx, int32_t n_ev, const int64_t* ev_pi
                        [&](int x, int y) { return odl[x] < odl[y]; });
   }
   std::vector<double> s_c(c_ir, c_ir + P);
-  std::vector<int> iota(n_ev + 1);
-  for (int i = 0; i <= n_ev; ++i) iota[i] = i;
+  std::vector<int> s_ev(P);
+  for (int i = 0; i < n_ev; ++i)
+    for (int64_t p = ev_pix_off[i]; p < ev_pix_off[i + 1]; ++p) s_ev[p] = i;
   std::vector<double> ld(S), l1(S), l2(S);
   double dmin = std::numeric_limits<double>::infinity(), dmax = 0.0;
   for (int64_t j = 0; j < S; ++j) {
@@ -829,7 +830,7 @@ chimera_status build_events(chimera_ctx* ctx, int32_t n_ev, const int64_t* ev_pi
   if (e == hipSuccess) e = upload(&ev->pix_off, s_off.data(), s_off.size());
   if (e == hipSuccess) e = upload(&ev->pix_idx, s_idx.data(), s_idx.size());
   if (e == hipSuccess) e = upload(&ev->slot_c, s_c.data(), s_c.size());
-  if (e == hipSuccess) e = upload(&ev->ev_iota, iota.data(), iota.size());
+  if (e == hipSuccess) e = upload(&ev->slot_event, s_ev.data(), s_ev.size());
   // the bin layout of chimera_set_event_kde needs the slots' events
   ev->h_slot_off.assign(ev_slot.begin(), ev_slot.end());
   ev->h_slot_c = s_c;
@@ -889,7 +890,11 @@ chimera_status chimera_set_event_kde(chimera_ctx* ctx, chimera_events* ev, int32
     // groups are ordered by their place in the slots' ranges (every slot's
     // first group, then every slot's second, ...), so that a work unit spans
     // a narrow redshift range, and cut into runs of <= kUnitGroups
-    const int gps = (n_bins + kGroupK - 1) / kGroupK;
+    // bins per group: consecutive bins are (range / n_bins) apart, so groups
+    // of n_bins / 4 bins (1..kGroupK) span about a quarter of a slot's range,
+    // which keeps the groups' Horner factors within range in FP32
+    const int bpg = std::max(1, std::min(kGroupK, n_bins / 4));
+    const int gps = (n_bins + bpg - 1) / bpg;
     std::vector<int> eu(ev->E + 1, 0), ue, ug0, ung, gf, gn, gs;
     std::vector<double> gcv;
     for (int e = 0; e < ev->E; ++e) {
@@ -897,8 +902,8 @@ chimera_status chimera_set_event_kde(chimera_ctx* ctx, chimera_events* ev, int32
       const int gbase = (int)gf.size();
       for (int q = 0; q < gps; ++q)
         for (int r = 0; r < ns; ++r) {
-          gf.push_back((so + r) * n_bins + q * kGroupK);
-          gn.push_back(std::min(kGroupK, n_bins - q * kGroupK));
+          gf.push_back((so + r) * n_bins + q * bpg);
+          gn.push_back(std::min(bpg, n_bins - q * bpg));
           gs.push_back(r);
           gcv.push_back(ev->h_slot_c[so + r]);
         }
@@ -941,7 +946,7 @@ int64_t lambda_chunk(const chimera_events* ev, int64_t B, bool f32) {
   if (!ev) return B;
   const double nb = ev->n_bins ? (double)ev->P * ev->n_bins : 0.0;
   const double per = ((double)ev->n_samp + nb) * (f32 ? 12.0 : 16.0) +
-                     8.0 * (ev->E + std::max(std::max(ev->U, ev->Ub), ev->E));
+                     8.0 * (ev->E + std::max(std::max(ev->U, ev->Ub), ev->P));
   const int64_t c = (int64_t)std::max(1.0, std::floor(kSampleScratchCap / per));
   return std::min(B, c);
 }
@@ -1064,9 +1069,11 @@ static chimera_status run_chunk(chimera_ctx* ctx, const chimera_events* ev, cons
     a.bz = s.bz; a.bw = s.bw;
     // the kernel-sum launch: over the samples, the bins, or one unit per event
     EventArgs k = a;
+    a.slot_event = ev->slot_event;
+    k.slot_event = ev->slot_event;
     if (ev->shape == CHIMERA_KDE_EPANECHNIKOV) {
-      k.U = E;
-      k.ev_unit_off = ev->ev_iota;
+      k.U = ev->P;                          // one partial per pixel slot
+      k.ev_unit_off = ev->ev_slot_off;
     } else if (ev->n_bins) {
       k.zbuf = s.bz; k.wbuf = s.bw; k.S = (long long)ev->P * ev->n_bins;
       k.ev_unit_off = ev->b_ev_unit_off; k.U = ev->Ub;

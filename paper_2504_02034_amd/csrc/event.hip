@@ -511,19 +511,39 @@ __global__ __launch_bounds__(256) void k_count_sum(const long long* __restrict__
 }
 
 // ---------------------------------------------------------------------------
+namespace {
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Number of leading lanes (from lane 0) whose flag is set.
+__device__ __forceinline__ int leading_set(bool f) {
+  const unsigned long long m = __ballot(f);
+  return (~m == 0ull) ? 64 : __builtin_ctzll(~m);
+}
+
+}  // namespace
+
 // Binned data sets (Sect. 2.3): per pixel slot and lambda, n_bins equal-width
 // bins over the slot's redshift range; a bin's point sits at its centre and
-// carries the summed weight of its samples.  The slot's samples are read in
-// distance order (pix_idx), which is redshift order since d_L^gw increases,
-// so each bin holds a contiguous run: lane q finds its run by two binary
-// searches and sums it in order (a fixed order, no atomics).
+// carries the summed weight of its samples.  One wave per (slot, lambda)
+// reads the slot's samples in distance order (pix_idx), which is redshift
+// order since d_L^gw increases, 64 at a time: the bins along the lanes never
+// decrease, so a segmented scan over the lanes sums each bin's run and its
+// last lane adds the run to the bin's accumulator in LDS (runs that continue
+// into the next 64 samples add in turn).  A fixed order, no atomics.
 template <bool F32>
 __global__ __launch_bounds__(kBinBS) void k_event_bin(EventArgs a) {
   using CT = typename std::conditional<F32, float, double>::type;
   constexpr int SPB = kBinBS / 64;                        // slots per workgroup
+  extern __shared__ double bacc[];                        // [SPB][n_bins]
   int it, b;
   if (!decode_item_lambda((a.n_slots + SPB - 1) / SPB, a.B, it, b)) return;
-  const int p = it * SPB + (int)(threadIdx.x >> 6);
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int p = it * SPB + wv;
   const int lane = threadIdx.x & 63;
   if (p >= a.n_slots) return;
   if (a.P[b].flag | a.flag_mono[b] | a.flag_range[b]) return;
@@ -532,31 +552,39 @@ __global__ __launch_bounds__(kBinBS) void k_event_bin(EventArgs a) {
   const double* zb = a.zbuf + (size_t)b * a.S;
   const CT* wb = (const CT*)a.wbuf + (size_t)b * a.S;
   const int nb = a.n_bins;
+  double* acc = bacc + (size_t)wv * nb;
+  for (int q = lane; q < nb; q += 64) acc[q] = 0.0;
   const double zlo = zb[idx[0]], zhi = zb[idx[n - 1]];
   const double width = (zhi - zlo) / (double)nb;
-  auto bin_of = [&](int j) -> int {
-    if (!(width > 0.0)) return 0;
-    const double q = floor((zb[idx[j]] - zlo) / width);
-    return q >= (double)(nb - 1) ? nb - 1 : (int)q;
-  };
-  // first position in [lo, n) whose bin is >= q
-  auto first_at = [&](int lo, int q) {
-    int hi = n;
-    while (lo < hi) {
-      const int m = (lo + hi) >> 1;
-      if (bin_of(m) < q) lo = m + 1;
-      else hi = m;
+  wave_sync();
+  for (int c0 = 0; c0 < n; c0 += 64) {
+    const int j = c0 + lane;
+    const bool valid = j < n;
+    int bin = 1 << 30;
+    double s = 0.0;
+    if (valid) {
+      const int q = idx[j];
+      s = (double)wb[q];
+      bin = 0;
+      if (width > 0.0) {
+        const double f = floor((zb[q] - zlo) / width);
+        bin = f >= (double)(nb - 1) ? nb - 1 : (int)f;
+      }
     }
-    return lo;
-  };
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const double u = __shfl_up(s, o, 64);
+      const int bu = __shfl_up(bin, o, 64);
+      if (lane >= o && bu == bin) s += u;
+    }
+    const int bn = __shfl_down(bin, 1, 64);
+    if (valid && (lane == 63 || bn != bin)) acc[bin] += s;
+    wave_sync();
+  }
   const size_t base = (size_t)b * a.n_slots * nb + (size_t)p * nb;
   for (int q = lane; q < nb; q += 64) {
-    const int s = first_at(0, q);
-    const int e = first_at(s, q + 1);
-    double wsum = 0.0;
-    for (int j = s; j < e; ++j) wsum += (double)wb[idx[j]];
     a.bz[base + q] = width > 0.0 ? zlo + ((double)q + 0.5) * width : zlo;
-    ((CT*)a.bw)[base + q] = (CT)wsum;
+    ((CT*)a.bw)[base + q] = (CT)acc[q];
   }
 }
 
@@ -566,32 +594,35 @@ __global__ __launch_bounds__(kBinBS) void k_event_bin(EventArgs a) {
 //   sum_{|g - x_j| <= W} tau_g F(z_g) (1 - (g - x_j)^2 / W^2)
 //     = S0 - (S2 - 2 d S1 + d^2 S0) / W^2,   S_m = sum tau F (g - m0)^m,
 // d = x_j - m0, over the sample's window: each S_m is a difference of two
-// prefix sums, so a sample costs O(1) whatever its window.  One (event,
-// lambda) per workgroup; each wave takes pixel slots in turn and walks the
-// slot's points (samples, or bins) in redshift order in chunks whose windows
-// fit kEpCap grid points: it stages tau F over the chunk's range in LDS (the
-// grid factor already carries tau),
-// forms the three prefix sums in FP64 (per lane over a contiguous block, then
-// a scan across lanes), and evaluates the chunk's points.  The origin m0 is
-// the chunk's middle point, which keeps (g - m0)^2 small against the window.
+// prefix sums, so a point costs O(1) whatever its window.  One wave per
+// (pixel slot, lambda) walks the slot's points (samples, or bins) in redshift
+// order in chunks whose windows fit kEpCap grid points: it stages tau F over
+// the chunk's range in LDS (the grid factor already carries tau), forms the
+// three prefix sums in FP64 (per lane over a contiguous block, then a scan
+// across lanes), and evaluates the chunk's points, loading the next points
+// while it evaluates these.  The origin m0 is the chunk's middle point, which
+// keeps (g - m0)^2 small against the window.  The slot's sum times c_ir is
+// its partial; k_event_final adds an event's slots in order.
 template <bool F32>
 __global__ __launch_bounds__(kEpBS) void k_event_epan(EventArgs a) {
   using CT = typename std::conditional<F32, float, double>::type;
   constexpr int NWV = kEpBS / 64;
-  int e, b;
-  if (!decode_item_lambda(a.E, a.B, e, b)) return;
+  constexpr int PER = kEpCap / 64;
+  int it, b;
+  if (!decode_item_lambda((a.n_slots + NWV - 1) / NWV, a.B, it, b)) return;
   __shared__ double q0[NWV][kEpCap], q1[NWV][kEpCap], q2[NWV][kEpCap];
-  __shared__ double wtot[NWV];
-  __shared__ long long wcnt[NWV];
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  double* part = a.part + (size_t)b * a.E + e;
+  const int p = it * NWV + wv;
+  if (p >= a.n_slots) return;
+  const int e = a.slot_event[p];
+  double* part = a.part + (size_t)b * a.n_slots + p;
   const LamParams P = a.P[b];
   const double h = a.hbuf[(size_t)b * a.E + e];
   if ((P.flag | a.flag_mono[b] | a.flag_range[b]) || !(h > 0.0)) {
-    if (threadIdx.x == 0) {
+    if (lane == 0) {
       *part = 0.0;
-      if (a.count) a.pcount[(size_t)b * a.E + e] = 0;
+      if (a.count) a.pcount[(size_t)b * a.n_slots + p] = 0;
     }
     return;
   }
@@ -599,166 +630,203 @@ __global__ __launch_bounds__(kEpBS) void k_event_epan(EventArgs a) {
   const double W = kEpanScale * h * a.g.inv_dz;
   const double inv_W2 = 1.0 / (W * W);
   const CT* gz = F32 ? (const CT*)(a.gz32 + (size_t)b * nz) : (const CT*)(a.gz64 + (size_t)b * nz);
-  const CT* nzt = F32 ? (const CT*)a.nz32 : (const CT*)a.nz64;
+  const CT* row = (F32 ? (const CT*)a.nz32 : (const CT*)a.nz64) + (size_t)a.slot_row[p] * nz;
   const bool binned = a.n_bins > 0;
   const double* zsrc = binned ? a.bz + (size_t)b * a.n_slots * a.n_bins : a.zbuf + (size_t)b * a.S;
   const CT* wsrc = binned ? (const CT*)a.bw + (size_t)b * a.n_slots * a.n_bins
                           : (const CT*)a.wbuf + (size_t)b * a.S;
-  const int s0 = a.ev_slot_off[e], ns = a.ev_slot_off[e + 1] - s0;
+  int j0, n;
+  const int* idx = nullptr;
+  if (binned) {
+    j0 = p * a.n_bins;
+    n = a.n_bins;
+  } else {
+    j0 = a.pix_off[p];
+    n = a.pix_off[p + 1] - j0;
+    idx = a.pix_idx + j0;
+  }
+  auto pos = [&](int j) { return idx ? idx[j] : j0 + j; };
+  auto xat = [&](int j) { return (zsrc[pos(j)] - a.g.z_lo) * a.g.inv_dz; };
   double* Q0 = q0[wv];
   double* Q1 = q1[wv];
   double* Q2 = q2[wv];
-  auto wave_sync = [] {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  };
-  double wave_total = 0.0;
+  double acc = 0.0;
   long long npts = 0;
-  for (int r = wv; r < ns; r += NWV) {
-    const int p = s0 + r;
-    int j0, n;
-    const int* idx = nullptr;
-    if (binned) {
-      j0 = p * a.n_bins;
-      n = a.n_bins;
-    } else {
-      j0 = a.pix_off[p];
-      n = a.pix_off[p + 1] - j0;
-      idx = a.pix_idx + j0;
+  // tau F over [glo, ghi] (at most kEpCap points) into LDS and its three
+  // prefix sums about mid
+  auto build_prefix = [&](int glo, int ghi, int mid) {
+    const int L = ghi - glo + 1;
+    wave_sync();                 // earlier prefix sums are read
+    for (int q = lane; q < L; q += 64) Q0[q] = (double)(row[glo + q] * gz[glo + q]);
+    wave_sync();
+    // per lane: a contiguous block of <= PER points
+    const int per = (L + 63) >> 6;
+    const int qa = min(lane * per, L), qb = min(qa + per, L);
+    double f[PER];
+    double t0 = 0.0, t1 = 0.0, t2 = 0.0;
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      f[i] = qa + i < qb ? Q0[qa + i] : 0.0;
+      const double t = (double)(qa + i + glo - mid);
+      t0 += f[i];
+      t1 += f[i] * t;
+      t2 += f[i] * t * t;
     }
-    auto pos = [&](int j) { return idx ? idx[j] : j0 + j; };
-    auto xat = [&](int j) { return (zsrc[pos(j)] - a.g.z_lo) * a.g.inv_dz; };
-    const CT* row = nzt + (size_t)a.slot_row[p] * nz;
-    double acc = 0.0;
-    int j = 0;
-    while (j < n) {
-      const double lo0 = ceil(xat(j) - W);
-      if (lo0 > (double)(nz - 1)) break;                 // this point and the rest lie above the grid
-      const int glo = (int)fmax(lo0, 0.0);
-      // the chunk: points from j on whose windows end within glo + kEpCap - 1
-      // (the window ends rise with j, so they are a prefix)
-      int j1 = j;
-      for (;;) {
-        const int jj = j1 + lane;
-        bool ok = false;
-        if (jj < n) ok = fmin(floor(xat(jj) + W), (double)(nz - 1)) <= (double)(glo + kEpCap - 1);
-        const unsigned long long m = __ballot(ok);
-        const int lead = (~m == 0ull) ? 64 : __builtin_ctzll(~m);
-        j1 += lead;
-        if (lead < 64 || j1 >= n) break;
-      }
-      if (j1 == j) {
-        // a window wider than a chunk: a direct sum, the wave across its points
-        const double xj = xat(j);
-        const int lo = (int)fmax(ceil(xj - W), 0.0), hi = (int)fmin(floor(xj + W), (double)(nz - 1));
-        double t = 0.0;
-        for (int g = lo + lane; g <= hi; g += 64) {
-          const double u = ((double)g - xj) / W;
-          t += (double)(row[g] * gz[g]) * (1.0 - u * u);
-        }
-        t = wave_sum(t);
-        if (lane == 0) {
-          acc += (double)wsrc[pos(j)] * t;
-          npts += 1;
-        }
-        ++j;
-        continue;
-      }
-      const int ghi = (int)fmin(floor(xat(j1 - 1) + W), (double)(nz - 1));
-      if (ghi < glo) {           // no grid point in any window of the chunk
-        j = j1;
-        continue;
-      }
-      const int L = ghi - glo + 1;                       // <= kEpCap
-      const int mid = glo + (L >> 1);
-      wave_sync();               // the previous chunk's prefix sums are read
-      for (int q = lane; q < L; q += 64) {
-        const int g = glo + q;
-        Q0[q] = (double)(row[g] * gz[g]);                // gz carries tau_g
-      }
-      wave_sync();
-      // per lane: a contiguous block of <= kEpCap / 64 points
-      const int per = (L + 63) >> 6;
-      const int qa = min(lane * per, L), qb = min(qa + per, L);
-      double f[kEpCap / 64];
-      double t0 = 0.0, t1 = 0.0, t2 = 0.0;
+    // exclusive scan of the lane totals across the wave (lane order)
+    double c0 = t0, c1 = t1, c2 = t2;
 #pragma unroll
-      for (int i = 0; i < kEpCap / 64; ++i) {
-        f[i] = qa + i < qb ? Q0[qa + i] : 0.0;
+    for (int o = 1; o < 64; o <<= 1) {
+      const double u0 = __shfl_up(c0, o, 64), u1 = __shfl_up(c1, o, 64), u2 = __shfl_up(c2, o, 64);
+      if (lane >= o) {
+        c0 += u0;
+        c1 += u1;
+        c2 += u2;
+      }
+    }
+    c0 -= t0;
+    c1 -= t1;
+    c2 -= t2;
+    wave_sync();                 // every lane has read its block of F
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      if (qa + i < qb) {
         const double t = (double)(qa + i + glo - mid);
-        t0 += f[i];
-        t1 += f[i] * t;
-        t2 += f[i] * t * t;
+        c0 += f[i];
+        c1 += f[i] * t;
+        c2 += f[i] * t * t;
+        Q0[qa + i] = c0;
+        Q1[qa + i] = c1;
+        Q2[qa + i] = c2;
       }
-      // exclusive scan of the lane totals across the wave (lane order)
-      double c0 = t0, c1 = t1, c2 = t2;
+    }
+    wave_sync();
+  };
+  // one point's weight times its window sum, from the prefix sums
+  auto eval = [&](double zk, double wk, int glo, int ghi, int mid) {
+    if (!(wk > 0.0)) return;
+    const double xk = (zk - a.g.z_lo) * a.g.inv_dz;
+    const int lk = (int)fmax(ceil(xk - W), (double)glo);
+    const int hk = (int)fmin(floor(xk + W), (double)ghi);
+    if (lk > hk) return;
+    const int qh = hk - glo, ql = lk - 1 - glo;
+    const double S0 = Q0[qh] - (ql >= 0 ? Q0[ql] : 0.0);
+    const double S1 = Q1[qh] - (ql >= 0 ? Q1[ql] : 0.0);
+    const double S2 = Q2[qh] - (ql >= 0 ? Q2[ql] : 0.0);
+    const double d = xk - (double)mid;
+    const double A = S0 - (S2 - 2.0 * d * S1 + d * d * S0) * inv_W2;
+    acc += wk * fmax(A, 0.0);
+    npts += 1;
+  };
+  int j = 0;
+  if (n <= 128) {
+    // the common case: two points per lane in registers, loaded at once, and
+    // (when their windows fit kEpCap points) one chunk
+    double zr[2], wr[2];
 #pragma unroll
-      for (int o = 1; o < 64; o <<= 1) {
-        const double u0 = __shfl_up(c0, o, 64), u1 = __shfl_up(c1, o, 64), u2 = __shfl_up(c2, o, 64);
-        if (lane >= o) {
-          c0 += u0;
-          c1 += u1;
-          c2 += u2;
-        }
+    for (int r = 0; r < 2; ++r) {
+      const int k = lane + 64 * r;
+      zr[r] = 0.0;
+      wr[r] = 0.0;
+      if (k < n) {
+        const int q = pos(k);
+        zr[r] = zsrc[q];
+        wr[r] = (double)wsrc[q];
       }
-      c0 -= t0;
-      c1 -= t1;
-      c2 -= t2;
-      wave_sync();               // every lane has read its block of F
+    }
+    const double zfirst = __shfl(zr[0], 0, 64);
+    const double zlast = __shfl(n > 64 ? zr[1] : zr[0], (n - 1) & 63, 64);
+    const double lo0 = ceil((zfirst - a.g.z_lo) * a.g.inv_dz - W);
+    const int glo = (int)fmax(lo0, 0.0);
+    const int ghi = (int)fmin(floor((zlast - a.g.z_lo) * a.g.inv_dz + W), (double)(nz - 1));
+    if (lo0 > (double)(nz - 1) || ghi < glo) {
+      j = n;                     // no grid point in any window
+    } else if (ghi - glo + 1 <= kEpCap) {
+      const int mid = glo + ((ghi - glo + 1) >> 1);
+      build_prefix(glo, ghi, mid);
 #pragma unroll
-      for (int i = 0; i < kEpCap / 64; ++i) {
-        if (qa + i < qb) {
-          const double t = (double)(qa + i + glo - mid);
-          c0 += f[i];
-          c1 += f[i] * t;
-          c2 += f[i] * t * t;
-          Q0[qa + i] = c0;
-          Q1[qa + i] = c1;
-          Q2[qa + i] = c2;
-        }
+      for (int r = 0; r < 2; ++r)
+        if (lane + 64 * r < n) eval(zr[r], wr[r], glo, ghi, mid);
+      j = n;
+    }
+  }
+  while (j < n) {
+    const double lo0 = ceil(xat(j) - W);
+    if (lo0 > (double)(nz - 1)) break;                   // this point and the rest lie above the grid
+    const int glo = (int)fmax(lo0, 0.0);
+    const double cap_hi = (double)(glo + kEpCap - 1);
+    // the chunk ends at the first point from j on whose window ends past
+    // glo + kEpCap - 1 (the window ends rise with the point): a 64-way search
+    auto fits = [&](int k) { return fmin(floor(xat(k) + W), (double)(nz - 1)) <= cap_hi; };
+    int lo = j, hi = n;                                  // the end lies in [lo, hi]
+    while (hi - lo > 64) {
+      const int step = (hi - lo + 63) / 64;
+      const int k = lo + lane * step;
+      const int cnt = leading_set(k < hi && fits(k));
+      if (cnt == 0) {
+        hi = lo;
+        break;
       }
-      wave_sync();
-      for (int k = j + lane; k < j1; k += 64) {
-        const double wk = (double)wsrc[pos(k)];
-        if (!(wk > 0.0)) continue;
-        const double xk = xat(k);
-        const int lo = (int)fmax(ceil(xk - W), (double)glo);
-        const int hi = (int)fmin(floor(xk + W), (double)ghi);
-        if (lo > hi) continue;
-        const int qh = hi - glo, ql = lo - 1 - glo;
-        const double S0 = Q0[qh] - (ql >= 0 ? Q0[ql] : 0.0);
-        const double S1 = Q1[qh] - (ql >= 0 ? Q1[ql] : 0.0);
-        const double S2 = Q2[qh] - (ql >= 0 ? Q2[ql] : 0.0);
-        const double d = xk - (double)mid;
-        const double A = S0 - (S2 - 2.0 * d * S1 + d * d * S0) * inv_W2;
-        acc += wk * fmax(A, 0.0);
+      const int last_ok = lo + (cnt - 1) * step;
+      hi = min(hi, last_ok + step);
+      lo = last_ok + 1;
+    }
+    int j1 = lo;
+    if (hi > lo) j1 = lo + leading_set(lo + lane < hi && fits(lo + lane));
+    if (j1 == j) {
+      // a window wider than a chunk: a direct sum, the wave across its points
+      const double xj = xat(j);
+      const int g0 = (int)fmax(ceil(xj - W), 0.0), g1 = (int)fmin(floor(xj + W), (double)(nz - 1));
+      double t = 0.0;
+      for (int g = g0 + lane; g <= g1; g += 64) {
+        const double u = ((double)g - xj) / W;
+        t += (double)(row[g] * gz[g]) * (1.0 - u * u);
+      }
+      t = wave_sum(t);
+      if (lane == 0) {
+        acc += (double)wsrc[pos(j)] * t;
         npts += 1;
       }
-      j = j1;
+      ++j;
+      continue;
     }
-    const double st = wave_sum(acc);
-    if (lane == 0) wave_total += a.slot_c[p] * st;
+    const int ghi = (int)fmin(floor(xat(j1 - 1) + W), (double)(nz - 1));
+    if (ghi < glo) {             // no grid point in any window of the chunk
+      j = j1;
+      continue;
+    }
+    const int mid = glo + ((ghi - glo + 1) >> 1);
+    build_prefix(glo, ghi, mid);
+    // the chunk's points, the next point's loads issued before this one's sums
+    int k = j + lane;
+    double zc = 0.0, wc = 0.0;
+    if (k < j1) {
+      const int q = pos(k);
+      zc = zsrc[q];
+      wc = (double)wsrc[q];
+    }
+    while (k < j1) {
+      const int kn = k + 64;
+      double zn = 0.0, wn = 0.0;
+      if (kn < j1) {
+        const int q = pos(kn);
+        zn = zsrc[q];
+        wn = (double)wsrc[q];
+      }
+      eval(zc, wc, glo, ghi, mid);
+      k = kn;
+      zc = zn;
+      wc = wn;
+    }
+    j = j1;
   }
+  const double st = wave_sum(acc);
   if (a.count) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) npts += __shfl_xor(npts, o, 64);
   }
   if (lane == 0) {
-    wtot[wv] = wave_total;
-    wcnt[wv] = npts;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double t = 0.0;
-    long long c = 0;
-#pragma unroll
-    for (int k = 0; k < NWV; ++k) {
-      t += wtot[k];
-      c += wcnt[k];
-    }
-    *part = t;
-    if (a.count) a.pcount[(size_t)b * a.E + e] = c;
+    *part = a.slot_c[p] * st;
+    if (a.count) a.pcount[(size_t)b * a.n_slots + p] = npts;
   }
 }
 
@@ -791,13 +859,18 @@ hipError_t launch_events(const EventArgs& a, const EventArgs& kern, bool f32, hi
   else k_event_zw<false><<<(unsigned)bz, kZwBS, 0, st>>>(a);
   if (a.n_bins > 0) {
     const long long bb = item_lambda_blocks((a.n_slots + kBinBS / 64 - 1) / (kBinBS / 64), a.B);
-    if (f32) k_event_bin<true><<<(unsigned)bb, kBinBS, 0, st>>>(a);
-    else k_event_bin<false><<<(unsigned)bb, kBinBS, 0, st>>>(a);
+    const size_t lds = (size_t)(kBinBS / 64) * a.n_bins * sizeof(double);
+    const void* kb = f32 ? (const void*)k_event_bin<true> : (const void*)k_event_bin<false>;
+    err = hipFuncSetAttribute(kb, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (err != hipSuccess) return err;
+    if (f32) k_event_bin<true><<<(unsigned)bb, kBinBS, lds, st>>>(a);
+    else k_event_bin<false><<<(unsigned)bb, kBinBS, lds, st>>>(a);
   }
   if (kern.shape == kShapeEpanechnikov) {
+    const long long be = item_lambda_blocks((a.n_slots + kEpBS / 64 - 1) / (kEpBS / 64), a.B);
     if (t0 && (err = hipEventRecord(t0, st)) != hipSuccess) return err;
-    if (f32) k_event_epan<true><<<(unsigned)bz, kEpBS, 0, st>>>(kern);
-    else k_event_epan<false><<<(unsigned)bz, kEpBS, 0, st>>>(kern);
+    if (f32) k_event_epan<true><<<(unsigned)be, kEpBS, 0, st>>>(kern);
+    else k_event_epan<false><<<(unsigned)be, kEpBS, 0, st>>>(kern);
     if (t1 && (err = hipEventRecord(t1, st)) != hipSuccess) return err;
   } else {
     const long long bs = item_lambda_blocks(kern.U, kern.B);

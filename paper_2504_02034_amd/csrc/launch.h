@@ -131,20 +131,22 @@ struct EventArgs {
   const int* pix_off;       // [n_slots+1] samples of each slot in pix_idx
   const int* pix_idx;       // sample positions (group order) of each slot, by distance
   const double* slot_c;     // [n_slots] c_ir of each slot
+  const int* slot_event;    // [n_slots] event of each slot
   double* bz;               // [B][n_slots n_bins] bin centres
   void* bw;                 // [B][n_slots n_bins] bin weights (double, or float in FP32 mode)
 };
 
 enum : int { kShapeGaussian = 0, kShapeEpanechnikov = 1 };
 constexpr double kEpanScale = 2.23606797749978969641;   // sqrt(5): support / bandwidth
-constexpr int kEpBS = 256;               // k_event_epan: four waves per (event, lambda)
-constexpr int kEpCap = 512;              // grid points of one staged prefix chunk per wave
+constexpr int kEpBS = 256;               // k_event_epan: one pixel slot per wave, four per group
+constexpr int kEpCap = 256;              // grid points of one staged prefix chunk per wave
 constexpr int kBinBS = 256;              // k_event_bin: one pixel slot per wave
 
 // The forward event kernels in order: k_event_zw on the samples (z, w, h),
 // then with bins k_event_bin, then the smoothing kernel (Gaussian: over the
 // samples, or over the bins with `kern` laid out on them) or k_event_epan
-// (Epanechnikov), then k_event_final.  t0 / t1 bracket the dominant kernel.
+// (Epanechnikov, one partial per pixel slot: `kern` has U = n_slots and the
+// slots as units), then k_event_final.  t0 / t1 bracket the dominant kernel.
 hipError_t launch_events(const EventArgs& a, const EventArgs& kern, bool f32, hipStream_t st,
                          hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
 
