@@ -25,6 +25,14 @@ eq. gw-kernel-single1d (the single-1D kernel of Sect. 2.3)
                 I_i = sum_r S_ir sum_g tau_g n_r(z_g) g(z_g) KDE(z_g)
                 (same weights, bandwidth rule and window as many-1D).
 
+The 3D kernel (Sect. 2.2, kept in Sect. 2.3; event_integral_3d) one Gaussian
+                KDE of the event's N_i samples in (z, u, v), (u, v) a flat sky
+                chart of the event (reading: the gnomonic plane at the samples'
+                mean direction), evaluated at each region pixel's centre and
+                integrated over the pixel as area x value; bandwidth matrix:
+                weighted covariance x n_eff^(-2/7) (reading: Scott's rule in
+                3-D, as scipy's gaussian_kde).
+
 Kernel options of Sect. 2.3 (kernel_values, bin_samples): the Epanechnikov
                 kernel in place of the Gaussian (reading: variance h^2, support
                 sqrt(5) h), and binned data sets (reading: n_bins equal-width
@@ -71,6 +79,8 @@ class Pixel:
     m1d: np.ndarray
     m2d: np.ndarray
     s: float = None           # sky factor S_ir (None: c x the pixel's sample count)
+    uv: tuple = None          # centre in the event's flat sky chart (the 3D kernel)
+    area: float = None        # pixel area [sr] (the 3D kernel)
 
     def sky(self) -> float:
         return self.s if self.s is not None else self.c * self.dl.size
@@ -82,6 +92,9 @@ class Event:
     # every sample of the event, in and out of its pixels, as (dl, m1d, m2d);
     # None: the pixels' samples (the single-1D KDE is trained on these)
     samples: tuple = None
+    # (u, v) of every sample in the event's flat sky chart, in the order of
+    # `samples` (the 3D kernel)
+    sky_uv: tuple = None
 
     def all_samples(self):
         if self.samples is not None:
@@ -259,6 +272,72 @@ def event_integral_single1d(z_all, w_all, pixels_s, pixels_row, grid, tau, gz, T
     return total, h
 
 
+def kde3d_bandwidth(z, u, v, w):
+    """The 3D kernel's bandwidth matrix: the weighted covariance of (z, u, v)
+    (unbiased, W1 - W2/W1 in the denominator) times n_eff^(-2/7), Scott's
+    factor in 3 dimensions with the Kish effective size (reading; the same
+    rule as scipy.stats.gaussian_kde).  None when the weights vanish or the
+    matrix is not positive definite."""
+    W1 = float(np.sum(w))
+    if not W1 > 0:
+        return None
+    W2 = float(np.sum(w * w))
+    if W1 * W1 - W2 <= 1e-12 * W1 * W1:
+        return None
+    x = np.stack([z, u, v], axis=1)
+    d = x - (w @ x) / W1
+    cov = (d.T * w) @ d / (W1 - W2 / W1)
+    H = cov * (W1 * W1 / W2) ** (-2.0 / 7.0)
+    if not (H[0, 0] > 0 and np.linalg.det(H[1:, 1:]) > 0 and np.linalg.det(H) > 0):
+        return None
+    return H
+
+
+def event_integral_3d(z, w, su, sv, pixels_uv, pixels_area, pixels_row, grid, tau, gz, T=None):
+    """(I_i, s_i) of one event with the 3D kernel (the Gaussian KDE of the
+    samples in (z, sky) evaluated at each pixel centre, Sect. 2.2-2.3):
+    I_i = sum_k area_k sum_g tau_g n_k(z_g) g(z_g) (1/N) sum_j w_j N3(r_jgk; H),
+    r = (z_g - z_j, u_k - u_j, v_k - v_j).  The kernel value is the full 3-D
+    Gaussian; with finite T (reading) a pair (j, k) counts where the sky part
+    of the quadratic form, dO^T H_OO^-1 dO, is <= T^2, and a grid point where
+    |z_g - z_j - B dO| <= T s, with B = H_zO H_OO^-1 and s^2 = H_zz - B H_Oz
+    the conditional mean shift and variance of z given the sky offset.  s_i
+    is returned in the bandwidth's place."""
+    H = kde3d_bandwidth(z, su, sv, w)
+    if H is None:
+        return 0.0, float("nan")
+    Hinv = np.linalg.inv(H)
+    norm = 1.0 / ((2.0 * math.pi) ** 1.5 * math.sqrt(np.linalg.det(H)))
+    inv_oo = np.linalg.inv(H[1:, 1:])
+    B = H[0, 1:] @ inv_oo
+    s_cond = math.sqrt(H[0, 0] - B @ H[1:, 0])
+    total = 0.0
+    for (uk, vk), area, nr in zip(pixels_uv, pixels_area, pixels_row):
+        do = np.stack([uk - su, vk - sv], axis=1)
+        zc = z + do @ B
+        keep = np.ones(z.size, dtype=bool)
+        if T is not None:
+            keep = np.einsum("ij,jk,ik->i", do, inv_oo, do) <= T * T
+            if not keep.any():
+                continue
+            lo = np.searchsorted(grid, zc[keep].min() - T * s_cond, side="left")
+            hi = np.searchsorted(grid, zc[keep].max() + T * s_cond, side="right")
+            g = slice(lo, hi)
+        else:
+            g = slice(None)
+        r0 = grid[g][None, :] - z[keep][:, None]
+        r1 = do[keep, 0][:, None]
+        r2 = do[keep, 1][:, None]
+        q = (Hinv[0, 0] * r0 * r0 + Hinv[1, 1] * r1 * r1 + Hinv[2, 2] * r2 * r2
+             + 2.0 * (Hinv[0, 1] * r0 * r1 + Hinv[0, 2] * r0 * r2 + Hinv[1, 2] * r1 * r2))
+        k = norm * np.exp(-0.5 * q)
+        if T is not None:
+            k = np.where(np.abs(grid[g][None, :] - zc[keep][:, None]) <= T * s_cond, k, 0.0)
+        kde = (w[keep] @ k) / z.size
+        total += area * float(np.sum(tau[g] * nr[g] * gz[g] * kde))
+    return total, s_cond
+
+
 def selection(inj: InjectionSet, cat: Catalog, lam):
     """(xi, N_eff) by the injection estimator of Sect. 2.2."""
     z, w = redshift_and_weight(inj.dl, inj.m1d, inj.m2d, lam)
@@ -284,6 +363,12 @@ def _event_worker(i):
     ev = d["events"][i]
     rs = [d["cat"].rows[px.pix] for px in ev.pixels]
     opt = dict(shape=d["shape"], n_bins=d["n_bins"])
+    if d["kernel"] == "3d":
+        sl = d["slices"][i][0]
+        su, sv = ev.sky_uv
+        return event_integral_3d(d["z"][sl], d["w"][sl], su, sv, [px.uv for px in ev.pixels],
+                                 [px.area for px in ev.pixels], rs, d["cat"].grid, d["tau"],
+                                 d["gz"], d["T"])
     if d["kernel"] == "single1d":
         sl = d["slices"][i][0]
         return event_integral_single1d(d["z"][sl], d["w"][sl], [px.sky() for px in ev.pixels], rs,
@@ -299,16 +384,19 @@ def lnl(events, cat: Catalog, inj: InjectionSet, lam, T=None, workers: int = 1,
         event_subset=None, kernel: str = "many1d", shape: str = "gaussian", n_bins: int = 0):
     """ln L and its parts at one lambda.
 
-    kernel: "many1d" (eq. gw-kernel-many1d) or "single1d" (eq.
-    gw-kernel-single1d); shape: the 1-D kernel ("gaussian" or
+    kernel: "many1d" (eq. gw-kernel-many1d), "single1d" (eq.
+    gw-kernel-single1d) or "3d" (event_integral_3d; h is then the
+    conditional width s_i); shape: the 1-D kernel ("gaussian" or
     "epanechnikov", kernel_values); n_bins: 0, or the bins of each KDE's
     binned data set (bin_samples).  Returns dict(lnl, lnI[E] (NaN for events
     not in event_subset), h[E], ln_xi, neff).  With event_subset, lnl is the
     partial sum over those events minus len(subset) ln xi (used for sampled
     parity checks).
     """
-    if kernel not in ("many1d", "single1d"):
+    if kernel not in ("many1d", "single1d", "3d"):
         raise ValueError(f"unknown kernel {kernel!r}")
+    if kernel == "3d" and (shape != "gaussian" or n_bins):
+        raise ValueError("the 3D kernel is Gaussian on the samples")
     if shape not in ("gaussian", "epanechnikov"):
         raise ValueError(f"unknown kernel shape {shape!r}")
     if n_bins < 0:
@@ -325,7 +413,7 @@ def lnl(events, cat: Catalog, inj: InjectionSet, lam, T=None, workers: int = 1,
     off = 0
     for i in sub:
         sl_i = []
-        groups = ([events[i].all_samples()] if kernel == "single1d" else
+        groups = ([events[i].all_samples()] if kernel in ("single1d", "3d") else
                   [(px.dl, px.m1d, px.m2d) for px in events[i].pixels])
         for dl, m1, m2 in groups:
             n = dl.size

@@ -5,6 +5,9 @@ Sect. 2.3, steps a-c, and the many-1D kernel (eq. gw-kernel-many1d):
   reading: pixels ordered by sample count (descending, ties by ascending
   pixel id) are taken until at least `cred` (0.9: the 90% area of Fig. 1)
   of the event's samples are covered; samples outside are dropped;
+* flat sky chart (the 3D kernel): gnomonic coordinates on the plane tangent
+  at the normalised mean of the samples' unit vectors (the plane of the sky
+  factor below);
 * sky factor: the 2-D KDE of all the event's sky samples at the pixel centre,
   times the pixel area (the d^2 Omega of eq. like-integrals over one pixel);
   reading: Gaussian KDE in the gnomonic tangent plane at the samples' mean
@@ -187,10 +190,15 @@ def events(offsets, dl, m1d, m2d, theta, phi, pix, centres, area, cred=0.9):
         reg = region(px, cred)
         ct, cp = centres(np.asarray(reg, dtype=np.int64))
         s = sky_factors(theta[sl], phi[sl], ct, cp, area)
-        ev = Event(samples=(dl[sl], m1d[sl], m2d[sl]))
+        mean = _vec(theta[sl], phi[sl]).sum(axis=0)
+        mean = mean / math.sqrt(float(mean @ mean))
+        suv = tangent_plane(theta[sl], phi[sl], mean)
+        cuv = tangent_plane(ct, cp, mean)
+        ev = Event(samples=(dl[sl], m1d[sl], m2d[sl]), sky_uv=(suv[:, 0], suv[:, 1]))
         for r, p in enumerate(reg):
             m = px == p
             ev.pixels.append(Pixel(pix=p, c=s[r] / int(m.sum()), dl=dl[sl][m], m1d=m1d[sl][m],
-                                   m2d=m2d[sl][m], s=float(s[r])))
+                                   m2d=m2d[sl][m], s=float(s[r]),
+                                   uv=(float(cuv[r, 0]), float(cuv[r, 1])), area=area))
         out.append(ev)
     return out
