@@ -199,6 +199,43 @@ chimera_status chimera_add_events_single1d(chimera_ctx* ctx, int32_t n_ev,
                                            const double* m1d, const double* m2d,
                                            const int64_t* ev_pix_off, const int64_t* pix_row,
                                            const double* s_ir, chimera_events** out);
+
+/* One resident event set for the 3D kernel (Sect. 2.2; kept in Sect. 2.3):
+ * each event's kernel is one Gaussian KDE of its N_i samples in (z, u, v),
+ * (u, v) the sample's position in a flat chart of the event's sky region
+ * (e.g. gnomonic coordinates on the plane tangent at the samples' mean
+ * direction, in radians), evaluated at each pixel centre:
+ *   I_i = sum_k area_k sum_g tau_g n_k(z_g) g(z_g) (1/N_i) sum_j w_j N3(r; H_i),
+ *   r = (z_g - z_j, u_k - u_j, v_k - v_j),
+ * H_i = the weighted covariance of (z, u, v) x n_eff^(-2/7) at each lambda
+ * (Scott's factor in three dimensions, Kish effective size).  The kernel
+ * runs through the many-1D sums: per (pixel, sample) pair a point at
+ * z_j + B dO (B = H_zO H_OO^-1) of weight w_j N2(dO; H_OO), all with the
+ * conditional width s_i (s_i^2 = H_zz - B H_Oz); a pair counts when the sky
+ * part of the quadratic form is <= T^2, a grid point when |z_g - z_j - B dO|
+ * <= T s_i (T: the context's truncation).  An event whose H_i is not
+ * positive definite, or whose weights vanish, has I_i = 0.
+ *   ev_samp_off[n_ev+1]       samples of event i: [ev_samp_off[i], ev_samp_off[i+1])
+ *   dl, m1d, m2d[n_samp]      every sample of each event
+ *   sky_u, sky_v[n_samp]      their chart coordinates
+ *   ev_pix_off[n_ev+1]        pixels of event i: [ev_pix_off[i], ev_pix_off[i+1])
+ *   pix_row[P]                catalogue row of each pixel
+ *   pix_u, pix_v[P]           pixel centres in the event's chart
+ *   pix_area[P]               pixel areas [sr] (> 0)
+ * An event may have at most CHIMERA_MAX_EVENT_PIXELS pixels, and the set
+ * at most 2^31 - 1 (pixel, sample) pairs; the evaluation scratch holds a
+ * redshift and a weight per pair and lambda point (calls run in chunks of
+ * points as for chimera_lnl_batch).  chimera_lnl_grad and
+ * chimera_set_event_kde (other than the defaults) refuse such a set.  Host
+ * arrays; synchronous.  EINVAL on a malformed layout, ERANGE when a pixel
+ * refers past the catalogue or a size limit is exceeded, ESTATE before a
+ * catalogue is set. */
+chimera_status chimera_add_events_3d(chimera_ctx* ctx, int32_t n_ev, const int64_t* ev_samp_off,
+                                    const double* dl, const double* m1d, const double* m2d,
+                                    const double* sky_u, const double* sky_v,
+                                    const int64_t* ev_pix_off, const int64_t* pix_row,
+                                    const double* pix_u, const double* pix_v,
+                                    const double* pix_area, chimera_events** out);
 chimera_status chimera_release_events(chimera_ctx* ctx, chimera_events* ev);
 
 /* Kernel options of a resident event set (Sect. 2.3: the 1-D KDEs take a

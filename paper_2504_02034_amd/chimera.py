@@ -31,7 +31,8 @@ _STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ERANGE", -5:
 EXPORTS = ("chimera_default_config", "chimera_create", "chimera_destroy", "chimera_last_error",
            "chimera_set_catalog", "chimera_set_catalog_galaxies", "chimera_get_catalog",
            "chimera_set_injections",
-           "chimera_add_events", "chimera_add_events_single1d", "chimera_set_event_kde",
+           "chimera_add_events", "chimera_add_events_single1d", "chimera_add_events_3d",
+           "chimera_set_event_kde",
            "chimera_release_events", "chimera_lnl_batch", "chimera_lnl_batch_static",
            "chimera_selection_xi",
            "chimera_lnl_grad", "chimera_scratch_bytes", "chimera_scratch_held",
@@ -83,6 +84,7 @@ def _load():
                                               ctypes.POINTER(_P)]),
         "chimera_add_events_single1d": (ctypes.c_int, [_P, _I32, _P, _P, _P, _P, _P, _P, _P,
                                                        ctypes.POINTER(_P)]),
+        "chimera_add_events_3d": (ctypes.c_int, [_P, _I32] + [_P] * 11 + [ctypes.POINTER(_P)]),
         "chimera_set_event_kde": (ctypes.c_int, [_P, _P, _I32, _I32]),
         "chimera_release_events": (ctypes.c_int, [_P, _P]),
         "chimera_lnl_batch": (ctypes.c_int, [_P, _P, _P, _I64, _I32, _P, _P, _I32, _P]),
@@ -195,6 +197,21 @@ def chimera_add_events_single1d(h, ev_samp_off, dl, m1d, m2d, ev_pix_off, pix_ro
     ev = _P()
     _check(lib.chimera_add_events_single1d(h, o1.size - 1, p1, *[p for _, p in samp], p2, p3, p4,
                                            ctypes.byref(ev)))
+    return ev
+
+
+def chimera_add_events_3d(h, ev_samp_off, dl, m1d, m2d, sky_u, sky_v, ev_pix_off, pix_row,
+                          pix_u, pix_v, pix_area):
+    o1, p1 = _host(ev_samp_off, np.int64)
+    samp = [_host(x, np.float64) for x in (dl, m1d, m2d, sky_u, sky_v)]
+    o2, p2 = _host(ev_pix_off, np.int64)
+    o3, p3 = _host(pix_row, np.int64)
+    pix = [_host(x, np.float64) for x in (pix_u, pix_v, pix_area)]
+    if o2.size != o1.size:
+        raise ValueError("ev_samp_off and ev_pix_off must both have n_ev + 1 entries")
+    ev = _P()
+    _check(lib.chimera_add_events_3d(h, o1.size - 1, p1, *[p for _, p in samp], p2, p3,
+                                     *[p for _, p in pix], ctypes.byref(ev)))
     return ev
 
 
@@ -385,6 +402,17 @@ class Context:
         or CHIMERA_KDE_EPANECHNIKOV, n_bins 0 (unbinned) or the bins per KDE."""
         chimera_set_event_kde(self.handle, ev.handle,
                               CHIMERA_KDE_GAUSSIAN if shape is None else shape, n_bins)
+
+    def add_events_3d(self, ev_samp_off, dl, m1d, m2d, sky_u, sky_v, ev_pix_off, pix_row, pix_u,
+                      pix_v, pix_area) -> EventSet:
+        h = chimera_add_events_3d(self.handle, ev_samp_off, dl, m1d, m2d, sky_u, sky_v, ev_pix_off,
+                                  pix_row, pix_u, pix_v, pix_area)
+        return EventSet(self, h, len(ev_samp_off) - 1)
+
+    def add_prepared_3d(self, t) -> EventSet:
+        """Resident 3D event set from prep.ThreeD."""
+        return self.add_events_3d(t.ev_samp_off, t.dl, t.m1d, t.m2d, t.sky_u, t.sky_v, t.ev_pix_off,
+                                  t.pix_row, t.pix_u, t.pix_v, t.pix_area)
 
     def add_prepared_single1d(self, s) -> EventSet:
         """Resident single-1D event set from prep.Single1D."""

@@ -120,6 +120,19 @@ struct chimera_events {
   double* slot_c = nullptr;     // [P] c_ir of each slot
   int* slot_event = nullptr;    // [P] event of each slot
   // work layout over the bins: groups of <= kGroupK consecutive bins of a slot
+  // the 3D kernel: the unique samples form one slot per event (the sample
+  // transform and the bandwidth moments); the real pixels and the
+  // (pixel, sample) points of the 1-D sums are below
+  int64_t V = 0;                // (pixel, sample) points
+  int Uv = 0;
+  long long* virt_off = nullptr;  // [E+1]
+  double *su = nullptr, *sv = nullptr;  // [n_samp] chart coordinates (group order)
+  double *pu = nullptr, *pv = nullptr;  // [pixels] centres in the chart
+  int *d3_slot_off = nullptr, *d3_slot_row = nullptr;
+  int *v_ev_unit_off = nullptr, *v_unit_event = nullptr, *v_unit_grp0 = nullptr,
+      *v_unit_ngrp = nullptr, *v_grp_first = nullptr, *v_grp_cnt = nullptr,
+      *v_grp_slot = nullptr;
+  double* v_grp_c = nullptr;
   std::vector<int> h_slot_off;   // host copies: slots of each event, c_ir of each slot
   std::vector<double> h_slot_c;
   int Ub = 0;
@@ -180,6 +193,11 @@ void free_events(chimera_events* ev) {
   dfree(ev->fold_pix_off); dfree(ev->fold_row); dfree(ev->fold_s);
   dfree(ev->own64); dfree(ev->own32);
   dfree(ev->pix_off); dfree(ev->pix_idx); dfree(ev->slot_c); dfree(ev->slot_event);
+  dfree(ev->virt_off); dfree(ev->su); dfree(ev->sv); dfree(ev->pu); dfree(ev->pv);
+  dfree(ev->d3_slot_off); dfree(ev->d3_slot_row);
+  dfree(ev->v_ev_unit_off); dfree(ev->v_unit_event); dfree(ev->v_unit_grp0);
+  dfree(ev->v_unit_ngrp); dfree(ev->v_grp_first); dfree(ev->v_grp_cnt); dfree(ev->v_grp_slot);
+  dfree(ev->v_grp_c);
   free_bin_layout(ev);
   delete ev;
 }
@@ -260,6 +278,9 @@ struct Scratch {
   long long* pcount;
   double* bz;
   void* bw;
+  double* p3;
+  double* z3;
+  void* w3;
 };
 
 // Lay out (or size, when base is null) the scratch of one call.
@@ -269,8 +290,9 @@ size_t carve(Carve& cv, Scratch& s, const Geometry& g, int64_t B, int nchunk, bo
   const int E = ev ? ev->E : 0;
   const int64_t S = ev ? ev->n_samp : 0;
   // partial sums: one per work unit (samples or bins), or per event
-  const int U = ev ? std::max(std::max(ev->U, ev->Ub), ev->P) : 0;
+  const int U = ev ? std::max(std::max(ev->U, ev->Ub), std::max(ev->P, ev->Uv)) : 0;
   const int64_t NB = ev && ev->n_bins ? (int64_t)ev->P * ev->n_bins : 0;
+  const int64_t V = ev ? ev->V : 0;
   s.P = cv.take<LamParams>(B);
   s.chi = cv.take<double2>((size_t)B * g.n_t);
   s.inv = cv.take<double2>((size_t)B * g.n_u);
@@ -294,6 +316,10 @@ size_t carve(Carve& cv, Scratch& s, const Geometry& g, int64_t B, int nchunk, bo
   s.bz = NB ? cv.take<double>((size_t)B * NB) : nullptr;
   s.bw = NB ? (f32 ? (void*)cv.take<float>((size_t)B * NB) : (void*)cv.take<double>((size_t)B * NB))
             : nullptr;
+  s.p3 = V ? cv.take<double>((size_t)B * E * 8) : nullptr;
+  s.z3 = V ? cv.take<double>((size_t)B * V) : nullptr;
+  s.w3 = V ? (f32 ? (void*)cv.take<float>((size_t)B * V) : (void*)cv.take<double>((size_t)B * V))
+           : nullptr;
   return cv.off;
 }
 
@@ -577,10 +603,22 @@ struct Fold {
   const double* s_ir;         // [P] sky factors
 };
 
+// Sky data of a 3D set.
+struct Sky3 {
+  const double* sky_u;        // [n_samp] chart coordinates of each sample (input order)
+  const double* sky_v;
+  const int64_t* ev_pix_off;  // [n_ev+1] the events' pixels
+  const int64_t* pix_row;     // [P] catalogue rows
+  const double* pix_u;        // [P] centres in the chart
+  const double* pix_v;
+  const double* pix_area;     // [P] areas
+};
+
 chimera_status build_events(chimera_ctx* ctx, int32_t n_ev, const int64_t* ev_pix_off,
                             const int64_t* pix_samp_off, const int64_t* pix_row,
                             const double* c_ir, const double* dl, const double* m1d,
-                            const double* m2d, const Fold* fold, chimera_events** out);
+                            const double* m2d, const Fold* fold, chimera_events** out,
+                            const Sky3* sky = nullptr);
 
 }  // namespace
 
@@ -662,15 +700,66 @@ chimera_status chimera_add_events_single1d(chimera_ctx* ctx, int32_t n_ev,
                       &f, out);
 }
 
+chimera_status chimera_add_events_3d(chimera_ctx* ctx, int32_t n_ev, const int64_t* ev_samp_off,
+                                    const double* dl, const double* m1d, const double* m2d,
+                                    const double* sky_u, const double* sky_v,
+                                    const int64_t* ev_pix_off, const int64_t* pix_row,
+                                    const double* pix_u, const double* pix_v,
+                                    const double* pix_area, chimera_events** out) {
+  if (!ctx || !out || !ev_samp_off || !dl || !m1d || !m2d || !sky_u || !sky_v || !ev_pix_off ||
+      !pix_row || !pix_u || !pix_v || !pix_area)
+    return fail(CHIMERA_EINVAL, "null argument");
+  *out = nullptr;
+  if (n_ev < 1) return fail(CHIMERA_EINVAL, "need at least one event");
+  if (!ctx->has_cat) return fail(CHIMERA_ESTATE, "set the catalogue before adding events");
+  if (ev_samp_off[0] != 0 || ev_pix_off[0] != 0)
+    return fail(CHIMERA_EINVAL, "ev_samp_off[0] and ev_pix_off[0] must be 0");
+  int64_t V = 0;
+  for (int i = 0; i < n_ev; ++i) {
+    const int64_t ns = ev_samp_off[i + 1] - ev_samp_off[i], np = ev_pix_off[i + 1] - ev_pix_off[i];
+    if (ns < 1) return fail(CHIMERA_EINVAL, "every event needs at least one sample");
+    if (np < 1) return fail(CHIMERA_EINVAL, "every event needs at least one pixel");
+    if (np > CHIMERA_MAX_EVENT_PIXELS)
+      return fail(CHIMERA_ERANGE, "an event has more pixels than CHIMERA_MAX_EVENT_PIXELS");
+    V += ns * np;
+  }
+  if (V > (int64_t)0x7fffffff)
+    return fail(CHIMERA_ERANGE, "samples x pixels of the set exceed 2^31 - 1");
+  const int64_t P = ev_pix_off[n_ev];
+  for (int64_t p = 0; p < P; ++p) {
+    if (pix_row[p] < 0 || pix_row[p] >= ctx->n_rows)
+      return fail(CHIMERA_ERANGE, "pix_row refers past the catalogue");
+    if (!(std::isfinite(pix_u[p]) && std::isfinite(pix_v[p]) && std::isfinite(pix_area[p]) &&
+          pix_area[p] > 0.0))
+      return fail(CHIMERA_EINVAL, "pixel centres must be finite and areas finite and > 0");
+  }
+  const int64_t S = ev_samp_off[n_ev];
+  if (S > (int64_t)0x7fffffff) return fail(CHIMERA_ERANGE, "too many samples in one set");
+  if (!finite_positive(dl, S) || !finite_positive(m1d, S) || !finite_positive(m2d, S))
+    return fail(CHIMERA_EINVAL, "sample distances and masses must be finite and > 0");
+  for (int64_t j = 0; j < S; ++j)
+    if (!(std::isfinite(sky_u[j]) && std::isfinite(sky_v[j])))
+      return fail(CHIMERA_EINVAL, "sample sky coordinates must be finite");
+  // the unique samples: one slot per event (row and c unused by the 3D sums)
+  std::vector<int64_t> one(n_ev + 1), zero_row(n_ev, 0);
+  std::vector<double> c(n_ev, 1.0);
+  for (int e = 0; e <= n_ev; ++e) one[e] = e;
+  Sky3 sky{sky_u, sky_v, ev_pix_off, pix_row, pix_u, pix_v, pix_area};
+  return build_events(ctx, n_ev, one.data(), ev_samp_off, zero_row.data(), c.data(), dl, m1d, m2d,
+                      nullptr, out, &sky);
+}
+
 namespace {
 
 // The groups, work units and device copies of one event set (arguments
 // checked by the caller).  fold != NULL makes a single-1D set: pix_row then
-// indexes the set's own folded rows.
+// indexes the set's own folded rows.  sky != NULL makes a 3D set: the
+// samples form one slot per event and the (pixel, sample) layout is added.
 chimera_status build_events(chimera_ctx* ctx, int32_t n_ev, const int64_t* ev_pix_off,
                             const int64_t* pix_samp_off, const int64_t* pix_row,
                             const double* c_ir, const double* dl, const double* m1d,
-                            const double* m2d, const Fold* fold, chimera_events** out) {
+                            const double* m2d, const Fold* fold, chimera_events** out,
+                            const Sky3* sky) {
   const int64_t P = ev_pix_off[n_ev];
   const int64_t S = pix_samp_off[P];
   // Groups: <= kGroupK samples of one pixel, consecutive in distance, spanning
@@ -681,7 +770,8 @@ chimera_status build_events(chimera_ctx* ctx, int32_t n_ev, const int64_t* ev_pi
   const int kSpreadRun = 128;
   std::vector<int> ev_samp(n_ev + 1, 0), ev_slot(n_ev + 1), ev_unit(n_ev + 1, 0), srow(P);
   std::vector<int> u_event, u_grp0, u_ngrp;
-  std::vector<int> gfirst, gcnt, gslot, gabs;
+  std::vector<int> gfirst, gcnt, gslot, gabs, ev_grp(n_ev + 1, 0);
+  std::vector<int64_t> order;
   std::vector<double> gc;
   std::vector<double> odl, om1, om2, oc;
   std::vector<int> orow;
@@ -747,6 +837,7 @@ chimera_status build_events(chimera_ctx* ctx, int32_t n_ev, const int64_t* ev_pi
       gslot.push_back(g.slot);
       gc.push_back(c_ir[ev_pix_off[e] + g.slot]);
       for (auto j : g.idx) {
+        order.push_back(j);
         odl.push_back(dl[j]);
         om1.push_back(m1d[j]);
         om2.push_back(m2d[j]);
@@ -755,6 +846,7 @@ chimera_status build_events(chimera_ctx* ctx, int32_t n_ev, const int64_t* ev_pi
       }
     }
     ev_samp[e + 1] = (int)odl.size();
+    ev_grp[e + 1] = (int)gfirst.size();
   }
   // each slot's samples (positions in group order) by distance, for the
   // binned data sets and the Epanechnikov sums
@@ -792,8 +884,54 @@ chimera_status build_events(chimera_ctx* ctx, int32_t n_ev, const int64_t* ev_pi
       f_row[p] = (int)fold->pix_row[p];
       rows_needed = std::max(rows_needed, fold->pix_row[p] + 1);
     }
+  } else if (sky) {
+    for (int64_t p = 0; p < sky->ev_pix_off[n_ev]; ++p)
+      rows_needed = std::max(rows_needed, sky->pix_row[p] + 1);
   } else {
     for (int64_t p = 0; p < P; ++p) rows_needed = std::max(rows_needed, pix_row[p] + 1);
+  }
+  // the 3D layout: per event, pixel-major (pixel, sample) points; groups are
+  // the samples' groups repeated for every pixel, ordered group by group
+  std::vector<long long> v_off;
+  std::vector<double> su, sv, pu, pv;
+  std::vector<int> d3_off, d3_row, veu, vue, vug0, vung, vgf, vgn, vgs;
+  std::vector<double> vgc;
+  if (sky) {
+    const int64_t FP = sky->ev_pix_off[n_ev];
+    su.resize(S);
+    sv.resize(S);
+    for (int64_t q = 0; q < S; ++q) {
+      su[q] = sky->sky_u[order[q]];
+      sv[q] = sky->sky_v[order[q]];
+    }
+    pu.assign(sky->pix_u, sky->pix_u + FP);
+    pv.assign(sky->pix_v, sky->pix_v + FP);
+    d3_off.assign(sky->ev_pix_off, sky->ev_pix_off + n_ev + 1);
+    d3_row.assign(sky->pix_row, sky->pix_row + FP);
+    v_off.assign(n_ev + 1, 0);
+    veu.assign(n_ev + 1, 0);
+    for (int e = 0; e < n_ev; ++e) {
+      const int ns = ev_samp[e + 1] - ev_samp[e];
+      const int p0 = d3_off[e], np = d3_off[e + 1] - p0;
+      v_off[e + 1] = v_off[e] + (long long)ns * np;
+      const int gbase = (int)vgf.size();
+      for (int g = ev_grp[e]; g < ev_grp[e + 1]; ++g)
+        for (int k = 0; k < np; ++k) {
+          vgf.push_back((int)(v_off[e] + (long long)k * ns + (gfirst[g] - ev_samp[e])));
+          vgn.push_back(gcnt[g]);
+          vgs.push_back(k);
+          vgc.push_back(sky->pix_area[p0 + k] / (double)ns);
+        }
+      const int ng = (int)vgf.size() - gbase;
+      const int R = (ng + kUnitGroups - 1) / kUnitGroups;
+      for (int u = 0; u < R; ++u) {
+        const int a = (int)((long long)ng * u / R), z = (int)((long long)ng * (u + 1) / R);
+        vue.push_back(e);
+        vug0.push_back(gbase + a);
+        vung.push_back(z - a);
+      }
+      veu[e + 1] = (int)vue.size();
+    }
   }
   std::lock_guard<std::mutex> lk(ctx->mu);
   if (rows_needed > ctx->n_rows)   // the catalogue changed since the check above
@@ -834,6 +972,25 @@ chimera_status build_events(chimera_ctx* ctx, int32_t n_ev, const int64_t* ev_pi
   // the bin layout of chimera_set_event_kde needs the slots' events
   ev->h_slot_off.assign(ev_slot.begin(), ev_slot.end());
   ev->h_slot_c = s_c;
+  if (sky) {
+    ev->V = v_off[n_ev];
+    ev->Uv = (int)vue.size();
+    if (e == hipSuccess) e = upload(&ev->virt_off, v_off.data(), v_off.size());
+    if (e == hipSuccess) e = upload(&ev->su, su.data(), su.size());
+    if (e == hipSuccess) e = upload(&ev->sv, sv.data(), sv.size());
+    if (e == hipSuccess) e = upload(&ev->pu, pu.data(), pu.size());
+    if (e == hipSuccess) e = upload(&ev->pv, pv.data(), pv.size());
+    if (e == hipSuccess) e = upload(&ev->d3_slot_off, d3_off.data(), d3_off.size());
+    if (e == hipSuccess) e = upload(&ev->d3_slot_row, d3_row.data(), d3_row.size());
+    if (e == hipSuccess) e = upload(&ev->v_ev_unit_off, veu.data(), veu.size());
+    if (e == hipSuccess) e = upload(&ev->v_unit_event, vue.data(), vue.size());
+    if (e == hipSuccess) e = upload(&ev->v_unit_grp0, vug0.data(), vug0.size());
+    if (e == hipSuccess) e = upload(&ev->v_unit_ngrp, vung.data(), vung.size());
+    if (e == hipSuccess) e = upload(&ev->v_grp_first, vgf.data(), vgf.size());
+    if (e == hipSuccess) e = upload(&ev->v_grp_cnt, vgn.data(), vgn.size());
+    if (e == hipSuccess) e = upload(&ev->v_grp_slot, vgs.data(), vgs.size());
+    if (e == hipSuccess) e = upload(&ev->v_grp_c, vgc.data(), vgc.size());
+  }
   if (fold) {
     ev->single1d = true;
     const size_t rows = (size_t)n_ev * ctx->cfg.n_z;
@@ -878,6 +1035,8 @@ chimera_status chimera_set_event_kde(chimera_ctx* ctx, chimera_events* ev, int32
   std::lock_guard<std::mutex> lk(ctx->mu);
   if (std::find(ctx->events.begin(), ctx->events.end(), ev) == ctx->events.end())
     return fail(CHIMERA_EINVAL, "unknown event set");
+  if (ev->V && (shape != CHIMERA_KDE_GAUSSIAN || n_bins != 0))
+    return fail(CHIMERA_EINVAL, "the 3D kernel is Gaussian on the samples");
   if ((int64_t)ev->P * n_bins > (int64_t)0x7fffffff)
     return fail(CHIMERA_ERANGE, "pixel slots x n_bins exceed 2^31 - 1");
   HIP_TRY(hipSetDevice(ctx->cfg.device));
@@ -945,8 +1104,8 @@ constexpr double kSampleScratchCap = 8.0 * (1ull << 30);
 int64_t lambda_chunk(const chimera_events* ev, int64_t B, bool f32) {
   if (!ev) return B;
   const double nb = ev->n_bins ? (double)ev->P * ev->n_bins : 0.0;
-  const double per = ((double)ev->n_samp + nb) * (f32 ? 12.0 : 16.0) +
-                     8.0 * (ev->E + std::max(std::max(ev->U, ev->Ub), ev->P));
+  const double per = ((double)ev->n_samp + nb + (double)ev->V) * (f32 ? 12.0 : 16.0) +
+                     8.0 * (9.0 * ev->E + std::max(std::max(ev->U, ev->Ub), std::max(ev->P, ev->Uv)));
   const int64_t c = (int64_t)std::max(1.0, std::floor(kSampleScratchCap / per));
   return std::min(B, c);
 }
@@ -1041,7 +1200,7 @@ static chimera_status run_chunk(chimera_ctx* ctx, const chimera_events* ev, cons
   sa.partial = s.partial;
   HIP_TRY(launch_selection(sa, f32, lnxi_dev, neff_dev, st));
   if (ev) {
-    EventArgs a;
+    EventArgs a{};
     a.P = s.P; a.flag_mono = s.flag_mono; a.flag_range = s.flag_range;
     a.chi = s.chi; a.inv = s.inv; a.dtab = s.dtab; a.g = g; a.gz64 = s.gz64; a.gz32 = s.gz32;
     a.nz64 = rows64(ctx, ev); a.nz32 = rows32(ctx, ev);
@@ -1071,7 +1230,21 @@ static chimera_status run_chunk(chimera_ctx* ctx, const chimera_events* ev, cons
     EventArgs k = a;
     a.slot_event = ev->slot_event;
     k.slot_event = ev->slot_event;
-    if (ev->shape == CHIMERA_KDE_EPANECHNIKOV) {
+    a.V = ev->V;
+    k.V = ev->V;
+    if (ev->V) {
+      // cov3d / expand3d read the real pixels as slots; the sums run over the points
+      a.ev_slot_off = ev->d3_slot_off; a.slot_row = ev->d3_slot_row;
+      a.su = ev->su; a.sv = ev->sv; a.pu = ev->pu; a.pv = ev->pv; a.virt_off = ev->virt_off;
+      a.p3 = s.p3; a.z3 = s.z3; a.w3 = s.w3;
+      k = a;
+      k.zbuf = s.z3; k.wbuf = s.w3; k.S = ev->V;
+      k.ev_unit_off = ev->v_ev_unit_off; k.U = ev->Uv;
+      k.grp_first = ev->v_grp_first; k.grp_cnt = ev->v_grp_cnt; k.grp_slot = ev->v_grp_slot;
+      k.grp_c = ev->v_grp_c;
+      k.unit_event = ev->v_unit_event; k.unit_grp0 = ev->v_unit_grp0;
+      k.unit_ngrp = ev->v_unit_ngrp;
+    } else if (ev->shape == CHIMERA_KDE_EPANECHNIKOV) {
       k.U = ev->P;                          // one partial per pixel slot
       k.ev_unit_off = ev->ev_slot_off;
     } else if (ev->n_bins) {
@@ -1380,8 +1553,9 @@ chimera_status chimera_lnl_grad(chimera_ctx* ctx, const chimera_events* ev, cons
   if (s != CHIMERA_OK) return s;
   if (!ev) return fail(CHIMERA_EINVAL, "null event set");
   if (!lnl || !grad) return fail(CHIMERA_EINVAL, "null output");
-  if (ev->shape != CHIMERA_KDE_GAUSSIAN || ev->n_bins != 0)
-    return fail(CHIMERA_EINVAL, "the adjoint takes the Gaussian kernel on unbinned samples");
+  if (ev->shape != CHIMERA_KDE_GAUSSIAN || ev->n_bins != 0 || ev->V != 0)
+    return fail(CHIMERA_EINVAL,
+                "the adjoint takes the many-1D or single-1D Gaussian kernel on unbinned samples");
   return run_grad(ctx, ev, lam, B, prec, lnl, grad, mem, hip_stream);
 }
 

@@ -831,6 +831,123 @@ __global__ __launch_bounds__(kEpBS) void k_event_epan(EventArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// The 3D kernel (Sect. 2.2): one Gaussian KDE of the event's samples in
+// (z, u, v), (u, v) a flat sky chart, with bandwidth matrix H = weighted
+// covariance x n_eff^(-2/7), evaluated at each pixel centre (u_k, v_k).  For
+// a pixel offset dO = (u_k - u_j, v_k - v_j) the 3-D Gaussian factors as
+//   N3 = N2(dO; H_OO) N(z_g; z_j + B dO, s),  B = H_zO H_OO^-1,
+//   s^2 = H_zz - B H_Oz,
+// so each (pixel, sample) pair is a point at z_j + B dO with weight
+// w_j N2(dO; H_OO) in the pixel's 1-D sum, every point of the event with the
+// one width s: the many-1D smoothing kernel then sums them unchanged.
+//
+// k_event_cov3d: per (event, lambda), the weighted moments of (z, u, v) about
+// the first sample in one pass, then H, B, s and H_OO^-1 (hbuf takes s, or
+// -1 when H is not positive definite or the weights vanish).
+template <bool F32>
+__global__ __launch_bounds__(kZwBS) void k_event_cov3d(EventArgs a) {
+  using CT = typename std::conditional<F32, float, double>::type;
+  constexpr int NW = kZwBS / 64 + 1;
+  __shared__ double red[11 * NW];
+  int e, b;
+  if (!decode_item_lambda(a.E, a.B, e, b)) return;
+  if (a.P[b].flag | a.flag_mono[b] | a.flag_range[b]) return;
+  double* hp = a.hbuf + (size_t)b * a.E + e;
+  if (!(*hp > 0.0)) return;                             // no weight in the event
+  const int s0 = a.ev_samp_off[e], ns = a.ev_samp_off[e + 1] - s0;
+  const double* zb = a.zbuf + (size_t)b * a.S + s0;
+  const CT* wb = (const CT*)a.wbuf + (size_t)b * a.S + s0;
+  const double* su = a.su + s0;
+  const double* sv = a.sv + s0;
+  const double z0 = zb[0], u0 = su[0], v0 = sv[0];
+  double m[11];
+#pragma unroll
+  for (int i = 0; i < 11; ++i) m[i] = 0.0;
+  for (int j = threadIdx.x; j < ns; j += kZwBS) {
+    const double w = (double)wb[j];
+    const double dz = zb[j] - z0, du = su[j] - u0, dv = sv[j] - v0;
+    m[0] += w;
+    m[1] += w * w;
+    m[2] += w * dz;
+    m[3] += w * du;
+    m[4] += w * dv;
+    m[5] += w * dz * dz;
+    m[6] += w * du * du;
+    m[7] += w * dv * dv;
+    m[8] += w * dz * du;
+    m[9] += w * dz * dv;
+    m[10] += w * du * dv;
+  }
+  block_reduce<kZwBS, 11, false>(m, red);
+  if (threadIdx.x != 0) return;
+  const double W1 = m[0], W2 = m[1];
+  double* p3 = a.p3 + ((size_t)b * a.E + e) * 8;
+  if (!(W1 > 0.0) || W1 * W1 - W2 <= 1e-12 * W1 * W1) {
+    *hp = -1.0;
+    return;
+  }
+  const double mz = m[2] / W1, mu = m[3] / W1, mv = m[4] / W1;
+  const double den = W1 - W2 / W1;
+  const double f = pow(W1 * W1 / W2, -2.0 / 7.0) / den;
+  const double Hzz = (m[5] - W1 * mz * mz) * f, Huu = (m[6] - W1 * mu * mu) * f;
+  const double Hvv = (m[7] - W1 * mv * mv) * f, Hzu = (m[8] - W1 * mz * mu) * f;
+  const double Hzv = (m[9] - W1 * mz * mv) * f, Huv = (m[10] - W1 * mu * mv) * f;
+  const double det = Huu * Hvv - Huv * Huv;
+  if (!(Hzz > 0.0 && det > 0.0)) {
+    *hp = -1.0;
+    return;
+  }
+  const double iuu = Hvv / det, iuv = -Huv / det, ivv = Huu / det;
+  const double Bu = Hzu * iuu + Hzv * iuv, Bv = Hzu * iuv + Hzv * ivv;
+  const double s2 = Hzz - (Bu * Hzu + Bv * Hzv);
+  if (!(s2 > 0.0)) {
+    *hp = -1.0;
+    return;
+  }
+  p3[0] = Bu;
+  p3[1] = Bv;
+  p3[2] = iuu;
+  p3[3] = iuv;
+  p3[4] = ivv;
+  p3[5] = -log(2.0 * M_PI * sqrt(det));
+  *hp = sqrt(s2);
+}
+
+// k_event_expand3d: per (event, lambda), every (pixel, sample) point: its
+// redshift z_j + B dO and weight w_j N2(dO; H_OO), 0 where the sky part of the
+// quadratic form exceeds T^2; pixel-major, so each pixel's points follow the
+// samples' group order (the groups of the 1-D sums stay consecutive).
+template <bool F32>
+__global__ __launch_bounds__(kZwBS) void k_event_expand3d(EventArgs a) {
+  using CT = typename std::conditional<F32, float, double>::type;
+  int e, b;
+  if (!decode_item_lambda(a.E, a.B, e, b)) return;
+  if (a.P[b].flag | a.flag_mono[b] | a.flag_range[b]) return;
+  if (!(a.hbuf[(size_t)b * a.E + e] > 0.0)) return;
+  const double* p3 = a.p3 + ((size_t)b * a.E + e) * 8;
+  const double Bu = p3[0], Bv = p3[1], iuu = p3[2], iuv = p3[3], ivv = p3[4], lnn = p3[5];
+  const double T2 = a.trunc * a.trunc;
+  const int s0 = a.ev_samp_off[e], ns = a.ev_samp_off[e + 1] - s0;
+  const int k0 = a.ev_slot_off[e], np = a.ev_slot_off[e + 1] - k0;
+  const double* zb = a.zbuf + (size_t)b * a.S + s0;
+  const CT* wb = (const CT*)a.wbuf + (size_t)b * a.S + s0;
+  const double* su = a.su + s0;
+  const double* sv = a.sv + s0;
+  double* zo = a.z3 + (size_t)b * a.V + a.virt_off[e];
+  CT* wo = (CT*)a.w3 + (size_t)b * a.V + a.virt_off[e];
+  for (int k = 0; k < np; ++k) {
+    const double uk = a.pu[k0 + k], vk = a.pv[k0 + k];
+    for (int j = threadIdx.x; j < ns; j += kZwBS) {
+      const double du = uk - su[j], dv = vk - sv[j];
+      const double q = iuu * du * du + 2.0 * iuv * du * dv + ivv * dv * dv;
+      const double w = q <= T2 ? (double)wb[j] * exp(lnn - 0.5 * q) : 0.0;
+      zo[(size_t)k * ns + j] = zb[j] + Bu * du + Bv * dv;
+      wo[(size_t)k * ns + j] = (CT)w;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 __global__ void k_event_final(EventArgs a) {
   const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (id >= (long long)a.B * a.E) return;
@@ -857,6 +974,15 @@ hipError_t launch_events(const EventArgs& a, const EventArgs& kern, bool f32, hi
   hipError_t err;
   if (f32) k_event_zw<true><<<(unsigned)bz, kZwBS, 0, st>>>(a);
   else k_event_zw<false><<<(unsigned)bz, kZwBS, 0, st>>>(a);
+  if (a.V > 0) {
+    if (f32) {
+      k_event_cov3d<true><<<(unsigned)bz, kZwBS, 0, st>>>(a);
+      k_event_expand3d<true><<<(unsigned)bz, kZwBS, 0, st>>>(a);
+    } else {
+      k_event_cov3d<false><<<(unsigned)bz, kZwBS, 0, st>>>(a);
+      k_event_expand3d<false><<<(unsigned)bz, kZwBS, 0, st>>>(a);
+    }
+  }
   if (a.n_bins > 0) {
     const long long bb = item_lambda_blocks((a.n_slots + kBinBS / 64 - 1) / (kBinBS / 64), a.B);
     const size_t lds = (size_t)(kBinBS / 64) * a.n_bins * sizeof(double);

@@ -132,6 +132,17 @@ struct EventArgs {
   const int* pix_idx;       // sample positions (group order) of each slot, by distance
   const double* slot_c;     // [n_slots] c_ir of each slot
   const int* slot_event;    // [n_slots] event of each slot
+  // the 3D kernel: samples in a flat sky chart, pixel centres and areas, and
+  // the (pixel, sample) points of each event, pixel-major
+  const double* su;         // [S] chart coordinates of each sample (group order)
+  const double* sv;
+  const double* pu;         // [pixels] centre of each pixel in its event's chart
+  const double* pv;
+  const long long* virt_off;  // [E+1] first (pixel, sample) point of each event
+  long long V;              // (pixel, sample) points of the set (0: not a 3D set)
+  double* p3;               // [B][E][8] B_u, B_v, H_OO^-1 (uu, uv, vv), ln N2 norm
+  double* z3;               // [B][V] z_j + B . dO of each point
+  void* w3;                 // [B][V] w_j N2(dO; H_OO) (double, or float in FP32 mode)
   double* bz;               // [B][n_slots n_bins] bin centres
   void* bw;                 // [B][n_slots n_bins] bin weights (double, or float in FP32 mode)
 };
@@ -142,8 +153,10 @@ constexpr int kEpBS = 256;               // k_event_epan: one pixel slot per wav
 constexpr int kEpCap = 256;              // grid points of one staged prefix chunk per wave
 constexpr int kBinBS = 256;              // k_event_bin: one pixel slot per wave
 
-// The forward event kernels in order: k_event_zw on the samples (z, w, h),
-// then with bins k_event_bin, then the smoothing kernel (Gaussian: over the
+// The forward event kernels in order: k_event_zw on the samples (z, w, h);
+// for a 3D set (a.V > 0) k_event_cov3d and k_event_expand3d, with `a`
+// carrying the set's pixels as slots;
+// with bins k_event_bin; then the smoothing kernel (Gaussian: over the
 // samples, or over the bins with `kern` laid out on them) or k_event_epan
 // (Epanechnikov, one partial per pixel slot: `kern` has U = n_slots and the
 // slots as units), then k_event_final.  t0 / t1 bracket the dominant kernel.

@@ -180,8 +180,9 @@ def catalog_density(cat: synth.Catalog, n_z: int, z_lo: float, z_hi: float,
     return nz, nz_tot, n_used
 
 
-def _sky_factors(theta, phi, centres_theta, centres_phi, area):
-    """area x 2-D Scott KDE of (theta, phi) samples at the centres (tangent plane)."""
+def _chart(theta, phi):
+    """The event's flat sky chart: gnomonic coordinates on the plane tangent at
+    the normalised mean of the samples' unit vectors (east, north axes)."""
     v = synth.unit_vectors(theta, phi)
     m = v.sum(axis=0)
     m /= np.linalg.norm(m)
@@ -193,7 +194,12 @@ def _sky_factors(theta, phi, centres_theta, centres_phi, area):
         d = u @ m
         return np.stack([(u @ east) / d, (u @ north) / d], axis=-1)
 
-    x = proj(v)
+    return proj, proj(v)
+
+
+def _sky_factors(theta, phi, centres_theta, centres_phi, area):
+    """area x 2-D Scott KDE of (theta, phi) samples at the centres (tangent plane)."""
+    proj, x = _chart(theta, phi)
     c = proj(synth.unit_vectors(centres_theta, centres_phi))
     n = x.shape[0]
     cov = np.cov(x.T, bias=False) * n ** (-1.0 / 3.0)
@@ -270,6 +276,52 @@ def subset(p: Prepared, events) -> Prepared:
                     np.asarray(rows, np.int64), np.asarray(ids, np.int64),
                     np.asarray(cs, np.float64), np.concatenate(dls), np.concatenate(m1s),
                     np.concatenate(m2s), None if p.s_ir is None else np.asarray(ss, np.float64))
+
+
+@dataclass
+class ThreeD:
+    """Arrays of chimera_add_events_3d: every sample of each event with its
+    position in the event's flat sky chart, and the region's pixels with their
+    centres in that chart and their areas."""
+    ev_samp_off: np.ndarray   # [E+1] int64
+    dl: np.ndarray            # [S]
+    m1d: np.ndarray
+    m2d: np.ndarray
+    sky_u: np.ndarray         # [S] chart coordinates
+    sky_v: np.ndarray
+    ev_pix_off: np.ndarray    # [E+1] int64
+    pix_row: np.ndarray       # [P] int64
+    pix_u: np.ndarray         # [P]
+    pix_v: np.ndarray
+    pix_area: np.ndarray      # [P] sr
+
+    @property
+    def n_events(self) -> int:
+        return len(self.ev_samp_off) - 1
+
+
+def three_d(p: Prepared, ev: synth.Events, events=None) -> ThreeD:
+    """The 3D-kernel arrays of the events p was prepared from (all of them, or
+    the listed ones in that order)."""
+    events = range(p.n_events) if events is None else list(events)
+    area = synth.pixel_area(ev.nside)
+    samp_off, pix_off = [0], [0]
+    cols = {k: [] for k in ("dl", "m1d", "m2d", "su", "sv", "row", "pu", "pv")}
+    for e in events:
+        a, b = int(ev.offsets[e]), int(ev.offsets[e + 1])
+        proj, x = _chart(ev.theta[a:b], ev.phi[a:b])
+        q0, q1 = p.ev_pix_off[e], p.ev_pix_off[e + 1]
+        th, ph = synth.pix2ang_ring(ev.nside, p.pix_id[q0:q1])
+        c = proj(synth.unit_vectors(th, ph))
+        cols["dl"].append(ev.dl[a:b]); cols["m1d"].append(ev.m1d[a:b]); cols["m2d"].append(ev.m2d[a:b])
+        cols["su"].append(x[:, 0]); cols["sv"].append(x[:, 1])
+        cols["row"].append(p.pix_row[q0:q1]); cols["pu"].append(c[:, 0]); cols["pv"].append(c[:, 1])
+        samp_off.append(samp_off[-1] + (b - a))
+        pix_off.append(pix_off[-1] + (q1 - q0))
+    cat = {k: np.concatenate(v) for k, v in cols.items()}
+    return ThreeD(np.asarray(samp_off, np.int64), cat["dl"], cat["m1d"], cat["m2d"], cat["su"],
+                  cat["sv"], np.asarray(pix_off, np.int64), cat["row"].astype(np.int64), cat["pu"],
+                  cat["pv"], np.full(cat["row"].size, area))
 
 
 def single1d(p: Prepared, ev: synth.Events, events=None) -> Single1D:
