@@ -217,7 +217,10 @@ def time_grad(ctx, es, lam_t, prec, steps):
 #: 1-D kernel shape, bins per KDE data set)
 VARIANTS = [("single1d", "gaussian", 0), ("many1d", "epanechnikov", 0),
             ("single1d", "epanechnikov", 0), ("many1d", "gaussian", 16),
-            ("single1d", "gaussian", 64)]
+            ("single1d", "gaussian", 64), ("3d", "gaussian", 0)]
+#: the 3D kernel does about (pixels per event) times the many-1D work per
+#: point: it is timed on the first points of the batch
+BATCH_3D = 16
 
 
 def variants_bench(ctx, es, p, ev, lam_t, many, steps, warmup):
@@ -229,22 +232,27 @@ def variants_bench(ctx, es, p, ev, lam_t, many, steps, warmup):
     shapes = {"gaussian": chimera.CHIMERA_KDE_GAUSSIAN,
               "epanechnikov": chimera.CHIMERA_KDE_EPANECHNIKOV}
     single = ctx.add_prepared_single1d(prep.single1d(p, ev))
-    sets = {"many1d": es, "single1d": single}
-    B = lam_t.shape[0]
+    three = ctx.add_prepared_3d(prep.three_d(p, ev))
+    sets = {"many1d": es, "single1d": single, "3d": three}
     out = []
     for kernel, shape, nb in VARIANTS:
         es_v = sets[kernel]
         ctx.set_event_kde(es_v, shapes[shape], nb)
-        r = {"kernel": kernel, "shape": shape, "n_bins": nb}
+        lam_v = lam_t[:BATCH_3D] if kernel == "3d" else lam_t
+        B = lam_v.shape[0]
+        r = {"kernel": kernel, "shape": shape, "n_bins": nb, "batch": B}
         vals = {}
         for name, prec in (("fp64", chimera.CHIMERA_FP64), ("fp32", chimera.CHIMERA_FP32)):
-            o, wall, lat, n, ms, evals = time_precision(ctx, es_v, lam_t, prec, steps, warmup)
+            o, wall, lat, n, ms, evals = time_precision(ctx, es_v, lam_v, prec, steps, warmup)
             avg_ms = ms / max(n, 1)
             dominant = ("k_event_epan" if shape == "epanechnikov" else "k_event_smooth") + name[2:]
             vals[name] = o
+            # the many-1D step scaled to this batch (its cost is linear in the points)
+            many_wall = many[name]["wall"] * B / lam_t.shape[0]
             r[name] = {"value": round(B * steps / wall, 2), "ms_per_step": round(wall / steps * 1e3, 4),
                        "kernel": dominant, "kernel_ms": round(avg_ms, 4),
-                       "speedup_over_many1d_gaussian": round(many[name]["wall"] / wall, 3)}
+                       "launches_per_step": round(n / steps, 2),
+                       "speedup_over_many1d_gaussian": round(many_wall / wall, 4)}
             if shape == "gaussian":
                 per_launch = evals / max(n, 1)
                 achieved = per_launch * FLOPS_PER_EVAL / (avg_ms * 1e-3) / 1e12
@@ -263,6 +271,7 @@ def variants_bench(ctx, es, p, ev, lam_t, many, steps, warmup):
         ctx.set_event_kde(es_v)
         out.append(r)
     single.release()
+    three.release()
     return out
 
 
