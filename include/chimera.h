@@ -238,6 +238,16 @@ chimera_status chimera_add_events_3d(chimera_ctx* ctx, int32_t n_ev, const int64
                                     const double* pix_area, chimera_events** out);
 chimera_status chimera_release_events(chimera_ctx* ctx, chimera_events* ev);
 
+/* The injection sum's stability check of Sect. 2.2 (reading: the effective
+ * number of injections must exceed factor x the number of events of the
+ * likelihood; the paper uses 5).  Once set, chimera_lnl_batch,
+ * chimera_lnl_batch_static and chimera_lnl_grad give lnl = -inf (and a NaN
+ * gradient) at every point whose ln L would be finite but whose N_eff <=
+ * factor x n_ev of the event set.  factor = 0 (the default) turns the check
+ * off.  EINVAL for a negative or non-finite factor.  Applies to later calls;
+ * do not change it while calls are in flight. */
+chimera_status chimera_set_neff_gate(chimera_ctx* ctx, double factor);
+
 /* Kernel options of a resident event set (Sect. 2.3: the 1-D KDEs take a
  * Gaussian or an Epanechnikov kernel, and their data sets may be binned).
  *   shape   CHIMERA_KDE_GAUSSIAN (the default of every set) or

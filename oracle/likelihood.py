@@ -381,7 +381,8 @@ def _event_worker(i):
 
 
 def lnl(events, cat: Catalog, inj: InjectionSet, lam, T=None, workers: int = 1,
-        event_subset=None, kernel: str = "many1d", shape: str = "gaussian", n_bins: int = 0):
+        event_subset=None, kernel: str = "many1d", shape: str = "gaussian", n_bins: int = 0,
+        neff_gate: float = 0.0):
     """ln L and its parts at one lambda.
 
     kernel: "many1d" (eq. gw-kernel-many1d), "single1d" (eq.
@@ -391,7 +392,9 @@ def lnl(events, cat: Catalog, inj: InjectionSet, lam, T=None, workers: int = 1,
     binned data set (bin_samples).  Returns dict(lnl, lnI[E] (NaN for events
     not in event_subset), h[E], ln_xi, neff).  With event_subset, lnl is the
     partial sum over those events minus len(subset) ln xi (used for sampled
-    parity checks).
+    parity checks).  neff_gate > 0: the stability check of Sect. 2.2 (reading:
+    a finite ln L becomes -inf unless N_eff > neff_gate x the number of events
+    summed).
     """
     if kernel not in ("many1d", "single1d", "3d"):
         raise ValueError(f"unknown kernel {kernel!r}")
@@ -449,4 +452,6 @@ def lnl(events, cat: Catalog, inj: InjectionSet, lam, T=None, workers: int = 1,
         res["lnl"] = -np.inf
     else:
         res["lnl"] = float(np.sum(lnI) - len(sub) * math.log(xi))
+        if neff_gate > 0 and not neff > neff_gate * len(sub):
+            res["lnl"] = -np.inf
     return res

@@ -32,7 +32,7 @@ EXPORTS = ("chimera_default_config", "chimera_create", "chimera_destroy", "chime
            "chimera_set_catalog", "chimera_set_catalog_galaxies", "chimera_get_catalog",
            "chimera_set_injections",
            "chimera_add_events", "chimera_add_events_single1d", "chimera_add_events_3d",
-           "chimera_set_event_kde",
+           "chimera_set_event_kde", "chimera_set_neff_gate",
            "chimera_release_events", "chimera_lnl_batch", "chimera_lnl_batch_static",
            "chimera_selection_xi",
            "chimera_lnl_grad", "chimera_scratch_bytes", "chimera_scratch_held",
@@ -86,6 +86,7 @@ def _load():
                                                        ctypes.POINTER(_P)]),
         "chimera_add_events_3d": (ctypes.c_int, [_P, _I32] + [_P] * 11 + [ctypes.POINTER(_P)]),
         "chimera_set_event_kde": (ctypes.c_int, [_P, _P, _I32, _I32]),
+        "chimera_set_neff_gate": (ctypes.c_int, [_P, ctypes.c_double]),
         "chimera_release_events": (ctypes.c_int, [_P, _P]),
         "chimera_lnl_batch": (ctypes.c_int, [_P, _P, _P, _I64, _I32, _P, _P, _I32, _P]),
         "chimera_lnl_batch_static": (ctypes.c_int, [_P, _P, _P, _I64, _I32, _P, _P, _P]),
@@ -213,6 +214,10 @@ def chimera_add_events_3d(h, ev_samp_off, dl, m1d, m2d, sky_u, sky_v, ev_pix_off
     _check(lib.chimera_add_events_3d(h, o1.size - 1, p1, *[p for _, p in samp], p2, p3,
                                      *[p for _, p in pix], ctypes.byref(ev)))
     return ev
+
+
+def chimera_set_neff_gate(h, factor):
+    _check(lib.chimera_set_neff_gate(h, float(factor)))
 
 
 def chimera_set_event_kde(h, ev, shape, n_bins):
@@ -396,6 +401,10 @@ class Context:
         h = chimera_add_events_single1d(self.handle, ev_samp_off, dl, m1d, m2d, ev_pix_off,
                                         pix_row, s_ir)
         return EventSet(self, h, len(ev_samp_off) - 1)
+
+    def set_neff_gate(self, factor):
+        """ln L = -inf where N_eff <= factor x n_events (0: off)."""
+        chimera_set_neff_gate(self.handle, factor)
 
     def set_event_kde(self, ev: EventSet, shape=None, n_bins=0):
         """Kernel options of an event set: shape CHIMERA_KDE_GAUSSIAN (default)

@@ -154,6 +154,7 @@ struct chimera_ctx {
   double *inj_lnm1d = nullptr, *inj_lnm2d = nullptr, *inj_lnp = nullptr;
   double inj_dmin = 0.0, inj_dmax = 0.0;
   bool has_cat = false, has_inj = false;
+  double neff_gate = 0.0;       // chimera_set_neff_gate
   std::vector<chimera_events*> events;
   // per-stream scratch arenas (grown to the largest call on the stream; freed
   // by chimera_release_scratch or chimera_destroy).  A call holds its
@@ -305,7 +306,7 @@ size_t carve(Carve& cv, Scratch& s, const Geometry& g, int64_t B, int nchunk, bo
   s.lam = need_lam ? cv.take<double>((size_t)B * CHIMERA_NLAM) : nullptr;
   s.lnI = need_lnI ? cv.take<double>((size_t)B * std::max(E, 1)) : nullptr;
   s.ln_xi = cv.take<double>(B);
-  s.neff = need_outs ? cv.take<double>(B) : nullptr;
+  s.neff = cv.take<double>(B);
   s.lnl = need_outs ? cv.take<double>(B) : nullptr;
   s.zbuf = S ? cv.take<double>((size_t)B * S) : nullptr;
   s.wbuf = S ? (f32 ? (void*)cv.take<float>((size_t)B * S) : (void*)cv.take<double>((size_t)B * S))
@@ -1025,6 +1026,15 @@ chimera_status chimera_release_events(chimera_ctx* ctx, chimera_events* ev) {
   return CHIMERA_OK;
 }
 
+chimera_status chimera_set_neff_gate(chimera_ctx* ctx, double factor) {
+  if (!ctx) return fail(CHIMERA_EINVAL, "null context");
+  if (!(std::isfinite(factor) && factor >= 0.0))
+    return fail(CHIMERA_EINVAL, "the gate factor must be finite and >= 0");
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  ctx->neff_gate = factor;
+  return CHIMERA_OK;
+}
+
 chimera_status chimera_set_event_kde(chimera_ctx* ctx, chimera_events* ev, int32_t shape,
                                      int32_t n_bins) {
   if (!ctx || !ev) return fail(CHIMERA_EINVAL, "null argument");
@@ -1186,7 +1196,8 @@ static chimera_status run_chunk(chimera_ctx* ctx, const chimera_events* ev, cons
   }
   double* lnI_dev = need_lnI ? s.lnI : lnI;
   double* lnxi_dev = (host || !ln_xi) ? s.ln_xi : ln_xi;
-  double* neff_dev = host ? (n_eff ? s.neff : nullptr) : n_eff;
+  // N_eff is always formed: the N_eff gate reads it
+  double* neff_dev = host || !n_eff ? s.neff : n_eff;
   double* lnl_dev = host ? s.lnl : lnl;
   HIP_TRY(launch_tables(lam_dev, (int)B, g, s.P, s.chi, s.inv, ev ? s.dtab : nullptr,
                         ev ? s.gz64 : nullptr,
@@ -1261,7 +1272,8 @@ static chimera_status run_chunk(chimera_ctx* ctx, const chimera_events* ev, cons
       std::lock_guard<std::mutex> lk(ctx->mu);
       ctx->marks.emplace_back(t0, t1);
     }
-    HIP_TRY(launch_lnl_final(s.P, s.flag_mono, s.flag_range, lnI_dev, lnxi_dev, E, (int)B,
+    HIP_TRY(launch_lnl_final(s.P, s.flag_mono, s.flag_range, lnI_dev, lnxi_dev, neff_dev,
+                             ctx->neff_gate, E, (int)B,
                              lnl_dev, st));
   }
   if (host) {
@@ -1467,7 +1479,7 @@ static chimera_status run_grad_chunk(chimera_ctx* ctx, const chimera_events* ev,
     a.gf32 = cv.take<float>((size_t)B * 6 * g.n_z);
     *fm = cv.take<int>(B);
     *fr = cv.take<int>(B);
-    sa.partial = cv.take<double>((size_t)B * std::max(nchunk, 1) * (1 + CHIMERA_NGRAD));
+    sa.partial = cv.take<double>((size_t)B * std::max(nchunk, 1) * (2 + CHIMERA_NGRAD));
     a.hd = cv.take<double>((size_t)B * E * 10);
     a.sc = cv.take<double>((size_t)B * 2 * ev->n_samp);
     a.sd = f32 ? (void*)cv.take<float>((size_t)B * kGradDerivFields * ev->n_samp)
@@ -1523,6 +1535,7 @@ static chimera_status run_grad_chunk(chimera_ctx* ctx, const chimera_events* ev,
   sa.n_det = ctx->n_det; sa.B = (int)B; sa.nchunk = nchunk;
   fa.P = P; fa.flag_mono = fm; fa.flag_range = fr; fa.partial = sa.partial; fa.nchunk = nchunk;
   fa.lnI = a.lnI; fa.dlnI = a.dlnI; fa.E = E; fa.n_total = ctx->n_inj_total;
+  fa.neff_gate = ctx->neff_gate;
   HIP_TRY(launch_grad(a, sa, fa, f32, st));
   if (host) {
     HIP_TRY(hipMemcpyAsync(lnl, fa.lnl, B * sizeof(double), hipMemcpyDeviceToHost, st));

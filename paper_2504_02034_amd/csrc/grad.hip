@@ -506,14 +506,16 @@ constexpr int kSelGradBS = 256;
 constexpr int kSelGradPer = 4;
 
 // FP64 in both modes: the selection sums are a small part of the work.
+// Partials per chunk: sum s, the 12 sums s d ln s / dp, sum s^2 (N_eff).
+constexpr int kSelParts = kNG + 2;
 __global__ __launch_bounds__(kSelGradBS) void k_selection_grad(SelGradArgs a) {
   const int chunk = blockIdx.x, b = blockIdx.y;
-  __shared__ double red[(1 + kNG) * (kSelGradBS / 64 + 1)];
-  double* part = a.partial + ((size_t)b * a.nchunk + chunk) * (1 + kNG);
+  __shared__ double red[kSelParts * (kSelGradBS / 64 + 1)];
+  double* part = a.partial + ((size_t)b * a.nchunk + chunk) * kSelParts;
   const LamParams P = a.P[b];
   if (P.flag | a.flag_mono[b] | a.flag_range[b]) {
     if (threadIdx.x == 0)
-      for (int i = 0; i <= kNG; ++i) part[i] = 0.0;
+      for (int i = 0; i < kSelParts; ++i) part[i] = 0.0;
     return;
   }
   const GradParams Q = a.Q[b];
@@ -521,9 +523,9 @@ __global__ __launch_bounds__(kSelGradBS) void k_selection_grad(SelGradArgs a) {
   const double2* chio = a.chio + (size_t)b * a.g.n_t;
   const double2* dtab = a.dtab + (size_t)b * a.g.n_t;
   const double2* inv = a.inv + (size_t)b * a.g.n_u;
-  double acc[1 + kNG];
+  double acc[kSelParts];
 #pragma unroll
-  for (int i = 0; i <= kNG; ++i) acc[i] = 0.0;
+  for (int i = 0; i < kSelParts; ++i) acc[i] = 0.0;
   for (int k = 0; k < kSelGradPer; ++k) {
     const long long j = (long long)chunk * kSelGradBS * kSelGradPer + k * kSelGradBS + threadIdx.x;
     if (j >= a.n_det) break;
@@ -557,6 +559,7 @@ __global__ __launch_bounds__(kSelGradBS) void k_selection_grad(SelGradArgs a) {
     // d ln s / dx at fixed lambda (the weight's own z path is in dlw)
     const double dls_dx = zp1 * slope / nt + dlpsi_dx - 2.0 - Dxx / Dx;
     acc[0] += s;
+    acc[1 + kNG] += s * s;
 #pragma unroll
     for (int p = 0; p < 4; ++p) acc[1 + p] += s * (sg.dlw[p] + dls_dx * sg.dx[p] - dd[p]);
 #pragma unroll
@@ -564,9 +567,9 @@ __global__ __launch_bounds__(kSelGradBS) void k_selection_grad(SelGradArgs a) {
 #pragma unroll
     for (int p = 0; p < 3; ++p) acc[1 + kNS + p] += s * dpsi[p];
   }
-  block_reduce<kSelGradBS, 1 + kNG, false>(acc, red);
+  block_reduce<kSelGradBS, kSelParts, false>(acc, red);
   if (threadIdx.x == 0)
-    for (int i = 0; i <= kNG; ++i) part[i] = acc[i];
+    for (int i = 0; i < kSelParts; ++i) part[i] = acc[i];
 }
 
 // ---------------------------------------------------------------------------
@@ -574,18 +577,18 @@ constexpr int kGFinBS = 256;
 
 __global__ __launch_bounds__(kGFinBS) void k_grad_final(GradFinalArgs a) {
   const int b = blockIdx.x;
-  __shared__ double red[(1 + kNG) * (kGFinBS / 64 + 1)];
+  __shared__ double red[kSelParts * (kGFinBS / 64 + 1)];
   const LamParams P = a.P[b];
   const int flag = P.flag | a.flag_mono[b] | a.flag_range[b];
   // selection: chunks in a fixed order
-  double v[1 + kNG];
+  double v[kSelParts];
 #pragma unroll
-  for (int i = 0; i <= kNG; ++i) v[i] = 0.0;
+  for (int i = 0; i < kSelParts; ++i) v[i] = 0.0;
   for (int c = threadIdx.x; c < a.nchunk; c += kGFinBS)
 #pragma unroll
-    for (int i = 0; i <= kNG; ++i) v[i] += a.partial[((size_t)b * a.nchunk + c) * (1 + kNG) + i];
-  block_reduce<kGFinBS, 1 + kNG, false>(v, red);
-  const double S1 = v[0];
+    for (int i = 0; i < kSelParts; ++i) v[i] += a.partial[((size_t)b * a.nchunk + c) * kSelParts + i];
+  block_reduce<kGFinBS, kSelParts, false>(v, red);
+  const double S1 = v[0], S2 = v[1 + kNG];
   // events
   double u[1 + kNG];
 #pragma unroll
@@ -607,7 +610,10 @@ __global__ __launch_bounds__(kGFinBS) void k_grad_final(GradFinalArgs a) {
       for (int p = 0; p < kNG; ++p) g[p] = NAN;
       return;
     }
-    const double lnl = S1 > 0.0 ? u[0] - (double)a.E * log(S1 / (double)a.n_total) : -INFINITY;
+    double lnl = S1 > 0.0 ? u[0] - (double)a.E * log(S1 / (double)a.n_total) : -INFINITY;
+    if (a.neff_gate > 0.0 && isfinite(lnl) &&
+        !(neff_of(S1, S2, a.n_total) > a.neff_gate * (double)a.E))
+      lnl = -INFINITY;
     a.lnl[b] = lnl;
     const bool ok = isfinite(lnl);
     for (int p = 0; p < kNG; ++p)

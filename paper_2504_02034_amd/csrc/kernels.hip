@@ -314,8 +314,7 @@ __global__ void k_selection_final(SelArgs a, double* __restrict__ ln_xi,
   }
   const double xi = s1 / (double)a.n_total;
   double lx = xi > 0.0 ? log(xi) : -INFINITY;
-  const double dd = s2 - s1 * s1 / (double)a.n_total;
-  double ne = s1 > 0.0 ? (dd > 0.0 ? s1 * s1 / dd : INFINITY) : 0.0;
+  double ne = neff_of(s1, s2, a.n_total);
   if (flag) {
     lx = NAN;
     ne = NAN;
@@ -330,7 +329,9 @@ __global__ __launch_bounds__(kFinBS) void k_lnl_final(const LamParams* __restric
                                                       const int* __restrict__ flag_mono,
                                                       const int* __restrict__ flag_range,
                                                       const double* __restrict__ lnI,
-                                                      const double* __restrict__ ln_xi, int E,
+                                                      const double* __restrict__ ln_xi,
+                                                      const double* __restrict__ neff,
+                                                      double neff_gate, int E,
                                                       double* __restrict__ lnl) {
   const int b = blockIdx.x;
   __shared__ double red[kFinBS / 64 + 1];
@@ -348,6 +349,8 @@ __global__ __launch_bounds__(kFinBS) void k_lnl_final(const LamParams* __restric
     else if (isnan(s) || isnan(lx)) v = NAN;
     else if (s == -INFINITY || lx == -INFINITY) v = -INFINITY;
     else v = s - (double)E * lx;
+    // the injection sum's stability check of Sect. 2.2: N_eff > gate x N_ev
+    if (neff_gate > 0.0 && isfinite(v) && !(neff[b] > neff_gate * (double)E)) v = -INFINITY;
     lnl[b] = v;
   }
 }
@@ -404,9 +407,9 @@ hipError_t launch_selection(const SelArgs& a, bool f32, double* ln_xi, double* n
 }
 
 hipError_t launch_lnl_final(const LamParams* P, const int* flag_mono, const int* flag_range,
-                            const double* lnI, const double* ln_xi, int E, int B, double* lnl,
-                            hipStream_t st) {
-  k_lnl_final<<<B, kFinBS, 0, st>>>(P, flag_mono, flag_range, lnI, ln_xi, E, lnl);
+                            const double* lnI, const double* ln_xi, const double* neff,
+                            double neff_gate, int E, int B, double* lnl, hipStream_t st) {
+  k_lnl_final<<<B, kFinBS, 0, st>>>(P, flag_mono, flag_range, lnI, ln_xi, neff, neff_gate, E, lnl);
   CH_LAUNCH_CHECK();
   return hipSuccess;
 }

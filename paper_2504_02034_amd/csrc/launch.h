@@ -174,8 +174,8 @@ hipError_t launch_tables(const double* lam, int B, const Geometry& g, LamParams*
 hipError_t launch_selection(const SelArgs& a, bool f32, double* ln_xi, double* neff,
                             hipStream_t st);
 hipError_t launch_lnl_final(const LamParams* P, const int* flag_mono, const int* flag_range,
-                            const double* lnI, const double* ln_xi, int E, int B, double* lnl,
-                            hipStream_t st);
+                            const double* lnI, const double* ln_xi, const double* neff,
+                            double neff_gate, int E, int B, double* lnl, hipStream_t st);
 int selection_chunks(long long n_det);
 
 // ---------------------------------------------------------------------------
@@ -259,9 +259,16 @@ struct GradFinalArgs {
   const double* dlnI;
   int E;
   long long n_total;
+  double neff_gate;         // > 0: ln L = -inf where N_eff <= neff_gate x E
   double* lnl;              // [B]
   double* grad;             // [B][12]
 };
+
+// The effective number of injections of Sect. 2.2 from sum s and sum s^2.
+__host__ __device__ inline double neff_of(double s1, double s2, long long n_total) {
+  const double dd = s2 - s1 * s1 / (double)n_total;
+  return s1 > 0.0 ? (dd > 0.0 ? s1 * s1 / dd : INFINITY) : 0.0;
+}
 
 hipError_t launch_chi_om_table(const LamParams* P, int B, const Geometry& g, double2* chio,
                                hipStream_t st);

@@ -168,3 +168,16 @@ def test_selection_unbiased_for_all_detected():
     f = lambda z: np.interp(z, grid, ntot) * psi(z, LAM[11], LAM[12], LAM[13]) / (1 + z)
     ref = quad(f, 0, 1.6, limit=200)[0]
     assert xi == pytest.approx(ref, rel=5.0 / math.sqrt(neff))
+
+
+def test_neff_gate(small_data):
+    """The gate cuts exactly the points whose N_eff is at or below gate x N_ev."""
+    d = small_data
+    r = L.lnl(d.o_events, d.o_cat, d.o_inj, LAM)
+    E = len(d.o_events)
+    assert np.isfinite(r["lnl"]) and r["neff"] > 0
+    just_below = r["neff"] / E * (1 - 1e-9)
+    at = r["neff"] / E * (1 + 1e-12)
+    assert L.lnl(d.o_events, d.o_cat, d.o_inj, LAM, neff_gate=just_below)["lnl"] == r["lnl"]
+    assert L.lnl(d.o_events, d.o_cat, d.o_inj, LAM, neff_gate=at)["lnl"] == -np.inf
+    assert L.lnl(d.o_events, d.o_cat, d.o_inj, LAM, neff_gate=0.0)["lnl"] == r["lnl"]
