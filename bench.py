@@ -283,8 +283,10 @@ def serve_bench(wl, cf, inj, n_requests=300, seed=5, max_pass_s=0.05):
     saturated (every request queued at once) to measure its throughput; the
     open-loop trace then arrives at 0.7 of that rate.  The FP32 server
     (continuous batching, 4 streams, HBM budget, passing bounded by
-    max_pass_s) and plain FP64 launches, one request at a time, replay the
-    same trace."""
+    max_pass_s, short requests first with one worker kept for them) and plain
+    FP64 launches, one request at a time, replay the same trace; each request
+    is then timed alone, and its served latency over that time is its
+    slowdown."""
     import numpy as np
 
     from paper_2504_02034_amd import chimera, prep, synth
@@ -306,7 +308,11 @@ def serve_bench(wl, cf, inj, n_requests=300, seed=5, max_pass_s=0.05):
     ex = HipExecutor(ctx, max_fused=512)
     biggest = max(ex.scratch_bytes(sets[w], int(b), chimera.CHIMERA_FP32) for b, w in zip(B, which))
     budget = int(2.5 * biggest)
-    srv = Server(ex, n_workers=4, max_fused=512, hbm_budget=budget, max_pass_s=max_pass_s)
+    # short requests (up to the scratch of 128 points on the 300-event set) go
+    # first, one worker serving only them
+    small = ex.scratch_bytes(sets[1], 128, chimera.CHIMERA_FP32)
+    srv = Server(ex, n_workers=4, max_fused=512, hbm_budget=budget, max_pass_s=max_pass_s,
+                 small_bytes=small, reserved=1)
     srv.wait(srv.submit(sets[1], lams[0][:1], chimera.CHIMERA_FP32))      # warm up
     # saturated throughput: the whole trace queued at once
     srv.reset_stats()
@@ -330,6 +336,29 @@ def serve_bench(wl, cf, inj, n_requests=300, seed=5, max_pass_s=0.05):
     st = srv.stats()
     srv.close()
     held = ctx.scratch_held()
+    # each request alone on an idle device (same executor path): the server's
+    # latency over this service time is the request's slowdown
+    solo = ex.new_worker()
+    big = int(np.argmax([ex.scratch_bytes(sets[w], int(b), chimera.CHIMERA_FP32)
+                         for b, w in zip(B, which)]))
+    ex.run(solo, sets[which[big]], lams[big], chimera.CHIMERA_FP32)    # the stream's block, once
+    alone = np.empty(n_requests)
+    for i in range(n_requests):
+        t1 = time.perf_counter()
+        ex.run(solo, sets[which[i]], lams[i], chimera.CHIMERA_FP32)
+        alone[i] = time.perf_counter() - t1
+    lat32 = np.array([t.t_done - t.t_submit for t in tickets])
+    is_small = np.array([t.small for t in tickets])
+    wait32 = np.array([t.t_start - t.t_submit for t in tickets])
+    run32 = np.array([t.t_done - t.t_start for t in tickets])
+    slow = lat32 / alone
+    per_set = {}
+    for k, n in enumerate(sizes):
+        m = which == k
+        per_set[str(n)] = {"requests": int(m.sum()),
+                           "p50_ms": round(float(np.percentile(lat32[m], 50)) * 1e3, 3),
+                           "p99_ms": round(float(np.percentile(lat32[m], 99)) * 1e3, 3),
+                           "alone_p99_ms": round(float(np.percentile(alone[m], 99)) * 1e3, 3)}
     # plain FP64 launches, one request at a time, same trace
     lat = []
     t0 = time.perf_counter()
@@ -343,7 +372,8 @@ def serve_bench(wl, cf, inj, n_requests=300, seed=5, max_pass_s=0.05):
     lat = sorted(lat)
     ctx.close()
     log(f"serving: FP32 server p50 {st['p50_ms']:.1f} ms p99 {st['p99_ms']:.1f} ms, "
-        f"{st['requests_per_launch']:.2f} requests per launch")
+        f"{st['requests_per_launch']:.2f} requests per launch, slowdown over alone p50 "
+        f"{np.percentile(slow, 50):.2f} p99 {np.percentile(slow, 99):.2f}")
     return {
         "requests": n_requests, "event_sets": list(sizes), "samples_per_event": 4096,
         "batch": "log-uniform 1..512",
@@ -359,7 +389,17 @@ def serve_bench(wl, cf, inj, n_requests=300, seed=5, max_pass_s=0.05):
                         "peak_scratch_gb": round(st["peak_bytes"] / 2**30, 2),
                         "scratch_held_after_gb": round(held / 2**30, 2),
                         "hbm_budget_gb": round(budget / 2**30, 2),
-                        "max_pass_ms": round(max_pass_s * 1e3, 1)},
+                        "max_pass_ms": round(max_pass_s * 1e3, 1),
+                        "small_request_gb": round(small / 2**30, 3), "reserved_workers": 1,
+                        "small_requests": int(is_small.sum()),
+                        "small_wait_p99_ms": round(float(np.percentile(wait32[is_small], 99)) * 1e3, 3),
+                        "small_run_p99_ms": round(float(np.percentile(run32[is_small], 99)) * 1e3, 3),
+                        "small_latency_p99_ms": round(float(np.percentile(lat32[is_small], 99)) * 1e3, 3),
+                        "slowdown_p50": round(float(np.percentile(slow, 50)), 3),
+                        "slowdown_p99": round(float(np.percentile(slow, 99)), 3),
+                        "alone_p50_ms": round(float(np.percentile(alone, 50)) * 1e3, 3),
+                        "alone_p99_ms": round(float(np.percentile(alone, 99)) * 1e3, 3),
+                        "per_event_set": per_set},
         "fp64_plain": {"evals_per_s": round(float(B.sum()) / span64, 1),
                        "p50_ms": round(pct(lat, 50) * 1e3, 3),
                        "p99_ms": round(pct(lat, 99) * 1e3, 3)},

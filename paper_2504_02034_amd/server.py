@@ -22,6 +22,12 @@ preallocated pinned and device buffers, take work as they free up:
 * passing: when the oldest request cannot get memory, a later request that
   can may run first, as long as the oldest has waited less than `max_pass_s`
   (0: never pass; the oldest then waits for memory);
+* short requests first: with `small_bytes` > 0 a request whose scratch need
+  is at most that is small; a free worker takes the oldest small request
+  before any other (fused only with small ones), and the first `reserved`
+  workers take small requests only, so a short request never waits behind
+  more than the small work in flight, however long the large requests are
+  (a large request that has waited `large_age_s` goes before small ones);
 * work of different workers overlaps on the device (one stream each).
 
 The executor is pluggable: HipExecutor runs the library; tests of the
@@ -44,6 +50,8 @@ class Ticket:
     lam: np.ndarray
     prec: int
     t_submit: float
+    need: int = 0
+    small: bool = False
     t_start: float = 0.0
     t_done: float = 0.0
     result: np.ndarray = None
@@ -101,13 +109,19 @@ class HipExecutor:
 
 class Server:
     def __init__(self, executor, n_workers: int = 4, max_fused: int = 512,
-                 hbm_budget: int = 0, max_pass_s: float = 0.0):
+                 hbm_budget: int = 0, max_pass_s: float = 0.0, small_bytes: int = 0,
+                 reserved: int = 0, large_age_s: float = 1.0):
         if n_workers < 1 or max_fused < 1:
             raise ValueError("n_workers and max_fused must be >= 1")
+        if reserved < 0 or reserved >= n_workers or (reserved and small_bytes <= 0):
+            raise ValueError("reserved workers need small_bytes > 0 and one general worker")
         self.ex = executor
         self.max_fused = max_fused
         self.budget = int(hbm_budget)          # 0: no limit
         self.max_pass_s = float(max_pass_s)
+        self.small_bytes = int(small_bytes)    # 0: no short-first ordering
+        self.reserved = int(reserved)
+        self.large_age_s = float(large_age_s)
         self._mu = threading.Lock()
         self._cv = threading.Condition(self._mu)
         self._pending: collections.deque = collections.deque()
@@ -146,7 +160,8 @@ class Server:
         with self._cv:
             if self._stop:
                 raise RuntimeError("server is closed")
-            t = Ticket(self._next_id, events, lam, prec, time.perf_counter())
+            t = Ticket(self._next_id, events, lam, prec, time.perf_counter(), need=need,
+                       small=0 < need <= self.small_bytes if self.small_bytes else False)
             self._next_id += 1
             if self._t0 is None:
                 self._t0 = t.t_submit
@@ -198,13 +213,16 @@ class Server:
     # ------------------------------------------------------------------
     def _fits(self, w, need) -> bool:
         """Under the lock: can worker w run a call of `need` scratch bytes,
-        releasing idle workers' blocks if that makes room?"""
+        releasing idle workers' blocks if that makes room?  A reserved
+        worker's block counts as at least small_bytes and is never released,
+        so the short requests always have their memory."""
         if not self.budget:
             return True
-        held = sum(self._arena) - self._arena[w] + max(self._arena[w], need)
+        held = sum(self._held(v) for v in range(len(self._arena)) if v != w)
+        held += max(self._held(w), need)
         if held <= self.budget:
             return True
-        for v in range(len(self._arena)):
+        for v in range(self.reserved, len(self._arena)):
             if held <= self.budget:
                 break
             if v != w and not self._busy[v] and self._arena[v] > 0:
@@ -214,11 +232,14 @@ class Server:
                 self._releases += 1
         return held <= self.budget
 
+    def _held(self, v) -> int:
+        return max(self._arena[v], self.small_bytes) if v < self.reserved else self._arena[v]
+
     def _group(self, head):
         group, B = [head], head.B
         for t in self._pending:
             if t is not head and t.events is head.events and t.prec == head.prec \
-                    and B + t.B <= self.max_fused:
+                    and t.small == head.small and B + t.B <= self.max_fused:
                 group.append(t)
                 B += t.B
         return group, B
@@ -230,9 +251,25 @@ class Server:
         now = time.perf_counter()
         oldest = self._pending[0]
         may_pass = self.max_pass_s > 0 and now - oldest.t_submit < self.max_pass_s
+        if self.small_bytes:
+            # small requests first, except large ones that have waited past
+            # large_age_s (so a stream of short requests cannot starve them)
+            aged = [t for t in self._pending
+                    if not t.small and now - t.t_submit > self.large_age_s]
+            order = [] if w < self.reserved else list(aged)
+            order += [t for t in self._pending if t.small]
+            if w >= self.reserved:
+                order += [t for t in self._pending if not t.small and t not in aged]
+            if not order:
+                return None
+            if order[0] is not oldest:          # a small request goes first by rule, not by memory
+                oldest = order[0]
+                may_pass = self.max_pass_s > 0 and now - oldest.t_submit < self.max_pass_s
+        else:
+            order = list(self._pending)
         seen = set()
-        for head in list(self._pending):
-            key = (id(head.events), head.prec)
+        for head in order:
+            key = (id(head.events), head.prec, head.small)
             if key in seen:
                 continue
             seen.add(key)

@@ -1,6 +1,7 @@
 """The continuous-batching server on the device: requests from concurrent
 clients over two resident event sets and both precisions, fused and
-overlapped on several streams under an HBM budget that binds, each result
+overlapped on several streams under an HBM budget that binds, first come
+first served or short requests first, each result
 equal (bitwise) to the same request evaluated alone, and the scratch the
 library holds (and the device memory in use) within the budget.  Also: host
 calls from two threads on one stream, each equal to the same call alone."""
@@ -15,7 +16,8 @@ from tests.datasets import handcrafted
 pytestmark = pytest.mark.gpu
 
 
-def test_served_results_equal_the_request_alone():
+@pytest.mark.parametrize("short_first", [False, True], ids=["fifo", "short_first"])
+def test_served_results_equal_the_request_alone(short_first):
     from paper_2504_02034_amd import chimera
     from paper_2504_02034_amd.server import HipExecutor, Server
     h = handcrafted()
@@ -33,7 +35,10 @@ def test_served_results_equal_the_request_alone():
     budget = 3 * ex.scratch_bytes(full, 48, chimera.CHIMERA_FP64)
     torch.cuda.synchronize()
     free0, _ = torch.cuda.mem_get_info()
-    srv = Server(ex, n_workers=4, max_fused=48, hbm_budget=budget, max_pass_s=0.01)
+    prio = {}
+    if short_first:      # requests up to 8 points on the smaller set go first, one worker kept
+        prio = dict(small_bytes=ex.scratch_bytes(part, 8, chimera.CHIMERA_FP64), reserved=1)
+    srv = Server(ex, n_workers=4, max_fused=48, hbm_budget=budget, max_pass_s=0.01, **prio)
     held_max = [0]
     stop = threading.Event()
 

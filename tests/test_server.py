@@ -238,3 +238,63 @@ def test_passing_the_oldest_is_bounded_by_its_age():
     assert any(t.t_start < large.t_start for t in small)        # some passed the large one
     assert large.t_start - large.t_submit < 0.05 + 0.25          # bounded wait
     assert ex.peak <= big
+
+
+def test_small_requests_overtake_large_ones():
+    """With short-first ordering and one reserved worker, short requests
+    submitted behind a queue of long ones finish long before the long ones,
+    and the reserved worker never runs a long request."""
+    ex = MockExec(per_point_s=2e-3)
+    small_need = ex.scratch_bytes(None, 4, 0)
+    srv = Server(ex, n_workers=2, max_fused=64, small_bytes=small_need, reserved=1,
+                 large_age_s=60.0)
+    big, little = Events(1), Events(2)
+    rng = np.random.default_rng(3)
+    longs = [srv.submit(big, lam_batch(rng, 60)) for _ in range(4)]
+    time.sleep(0.01)
+    shorts = [srv.submit(little, lam_batch(rng, 2)) for _ in range(6)]
+    for t in longs + shorts:
+        srv.wait(t, timeout=30)
+    srv.close()
+    assert max(t.t_done for t in shorts) < max(t.t_done for t in longs)
+    lat_short = max(t.t_done - t.t_submit for t in shorts)
+    assert lat_short < 60 * 2e-3 * 2            # well under two long requests
+    assert all(t.small for t in shorts) and not any(t.small for t in longs)
+
+
+def test_aged_large_requests_are_not_starved():
+    """A long request that has waited past large_age_s goes before newer short
+    ones: one worker, short requests arriving faster than it serves them (so
+    short ones are always pending), and the long one still finishes soon."""
+    ex = MockExec(per_point_s=1e-3)
+    srv = Server(ex, n_workers=1, max_fused=32, small_bytes=ex.scratch_bytes(None, 2, 0),
+                 large_age_s=0.02)
+    big, little = Events(1), Events(2)
+    rng = np.random.default_rng(4)
+    stop = threading.Event()
+
+    def flood():
+        while not stop.is_set():
+            srv.submit(little, lam_batch(rng, 1))
+            time.sleep(0.0005)
+
+    th = threading.Thread(target=flood)
+    th.start()
+    try:
+        time.sleep(0.01)
+        t_long = srv.submit(big, lam_batch(rng, 20))
+        srv.wait(t_long, timeout=5.0)
+    finally:
+        stop.set()
+        th.join()
+        srv.close()
+    assert t_long.t_done - t_long.t_submit < 0.5
+    assert t_long.t_start - t_long.t_submit >= 0.02 * 0.5    # it did wait behind short ones
+
+
+def test_priority_arguments_checked():
+    ex = MockExec()
+    with pytest.raises(ValueError):
+        Server(ex, n_workers=2, reserved=1)           # reserved workers need small_bytes
+    with pytest.raises(ValueError):
+        Server(ex, n_workers=2, small_bytes=10, reserved=2)
