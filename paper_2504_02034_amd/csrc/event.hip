@@ -31,6 +31,7 @@
 //                   order, I_i = sum / (h sqrt(2 pi)), ln I_i.
 #include <math.h>
 
+#include <algorithm>
 #include <type_traits>
 
 #include "common.h"
@@ -501,7 +502,8 @@ void k_event_smooth32(EventArgs a) { event_smooth<true>(a); }
 __global__ __launch_bounds__(256) void k_count_sum(const long long* __restrict__ pc, long long n,
                                                    unsigned long long* __restrict__ count) {
   long long t = 0;
-  for (long long i = threadIdx.x; i < n; i += 256) t += pc[i];
+  for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long long)gridDim.x * 256)
+    t += pc[i];
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
   __shared__ long long r[4];
@@ -1010,7 +1012,11 @@ hipError_t launch_events(const EventArgs& a, const EventArgs& kern, bool f32, hi
     else k_event_smooth64<<<(unsigned)bs, kSmBS, lds, st>>>(kern);
     if (t1 && (err = hipEventRecord(t1, st)) != hipSuccess) return err;
   }
-  if (kern.count) k_count_sum<<<1, 256, 0, st>>>(kern.pcount, (long long)kern.B * kern.U, kern.count);
+  if (kern.count) {
+    const long long nc = (long long)kern.B * kern.U;
+    const unsigned blocks = (unsigned)std::min<long long>((nc + 4095) / 4096 + 1, 1024);
+    k_count_sum<<<blocks, 256, 0, st>>>(kern.pcount, nc, kern.count);
+  }
   const long long nf = (long long)kern.B * kern.E;
   k_event_final<<<(unsigned)((nf + 255) / 256), 256, 0, st>>>(kern);
   return hipGetLastError();
