@@ -326,6 +326,8 @@ def lnl_grad(events, cat: L.Catalog, inj: L.InjectionSet, lam, T=None, kernel="m
     grad is NaN where lnl is not finite."""
     if kernel not in ("many1d", "single1d"):
         raise ValueError(f"unknown kernel {kernel!r}")
+    if cat.p_compl is not None:
+        raise NotImplementedError("the gradient of the incompleteness term is not built")
     lam = np.asarray(lam, dtype=np.float64)
     E = len(events)
     out = {"lnl": -np.inf, "grad": np.full(NG, np.nan), "lnI": np.full(E, -np.inf),

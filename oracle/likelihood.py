@@ -11,6 +11,10 @@ eq. like-integrals + eq. gw-kernel-many1d
                 p_cbc = p_cat psi, complete catalogue f_R = 1)
                 The KDE is (1/N_r) sum_j w_j N(z; z_j, h): not divided by
                 sum w (reading), the 1/N_r sits in c_ir.
+eqs. p-gal, p-miss, f-R (galaxy_density): with a completeness P_compl per
+                pixel the rows and n_tot become those of
+                p_gal = f_R p_cat + (1 - f_R) p_miss, homogeneous completion
+                in comoving volume up to the grid's end (reading).
 Sect. 2.2       xi = (1/N_inj) sum_{detected} s_j,
                 s_j = p(m1,m2) n_tot(z_j) psi(z_j) / [(1+z_j)^3 D'(z_j) p_draw_j]
                 (reading: the 1/p_draw of the cited estimators is restored;
@@ -108,6 +112,34 @@ class Catalog:
     grid: np.ndarray          # z_g, uniform
     rows: dict                # HEALPix id -> n_r(z_g)
     n_tot: np.ndarray
+    # incompleteness (eqs. p-gal, p-miss, f-R); None: a complete catalogue
+    p_compl: dict = None      # HEALPix id -> P_compl(z_g) of the pixel
+    missing: np.ndarray = None  # M(z_g) = sum over all pixels of area x (1 - P_compl) [sr]
+
+
+def completion_density(z, om, z_max):
+    """v(z) = (dV_c/dz per steradian) / V_c(z_max): the homogeneous completion
+    of eq. p-miss as a density in (z, Omega); H0 cancels, so
+    v = chi(z)^2 / (E(z) (4 pi / 3) chi(z_max)^3)."""
+    return (cosmo.chi(z, om) ** 2 / cosmo.efunc(z, om)
+            / (4.0 * math.pi / 3.0 * float(cosmo.chi(z_max, om)) ** 3))
+
+
+def galaxy_density(cat: Catalog, lam):
+    """(rows, n_tot, f_R) of p_gal = f_R p_cat + (1 - f_R) p_miss (eqs. p-gal,
+    p-miss, f-R) on the grid at lambda.  With P_compl per pixel and
+    v = completion_density (z_max = the grid's end):
+      (1 - f_R) p_miss = (1 - P_compl) v,
+      f_R = int dz dOmega P_compl v = sum_g tau_g (4 pi - M(z_g)) v(z_g)
+    (the trapezoid on the grid; reading), so a pixel's row becomes
+    f_R n_r + (1 - P_r) v and the all-sky density f_R n_tot + M v (linear
+    between nodes, as n_tot).  A complete catalogue gives the rows as they are."""
+    if cat.p_compl is None:
+        return cat.rows, cat.n_tot, 1.0
+    v = completion_density(cat.grid, lam[1], cat.grid[-1])
+    f_r = float(np.sum(trapezoid(cat.grid) * (4.0 * math.pi - cat.missing) * v))
+    rows = {p: f_r * r + (1.0 - cat.p_compl[p]) * v for p, r in cat.rows.items()}
+    return rows, f_r * cat.n_tot + cat.missing * v, f_r
 
 
 @dataclass
@@ -341,7 +373,7 @@ def event_integral_3d(z, w, su, sv, pixels_uv, pixels_area, pixels_row, grid, ta
 def selection(inj: InjectionSet, cat: Catalog, lam):
     """(xi, N_eff) by the injection estimator of Sect. 2.2."""
     z, w = redshift_and_weight(inj.dl, inj.m1d, inj.m2d, lam)
-    ntot = np.interp(z, cat.grid, cat.n_tot, left=0.0, right=0.0)
+    ntot = np.interp(z, cat.grid, galaxy_density(cat, lam)[1], left=0.0, right=0.0)
     jac = (1.0 + z) ** 3 * cosmo.ddl_gw_dz(z, lam[0], lam[1], lam[2], lam[3])
     s = w * ntot * psi(z, lam[11], lam[12], lam[13]) / (jac * np.exp(inj.ln_pdraw))
     s1 = float(np.sum(s))
@@ -361,7 +393,7 @@ _WORK: dict = {}
 def _event_worker(i):
     d = _WORK
     ev = d["events"][i]
-    rs = [d["cat"].rows[px.pix] for px in ev.pixels]
+    rs = [d["rows"][px.pix] for px in ev.pixels]
     opt = dict(shape=d["shape"], n_bins=d["n_bins"])
     if d["kernel"] == "3d":
         sl = d["slices"][i][0]
@@ -434,7 +466,8 @@ def lnl(events, cat: Catalog, inj: InjectionSet, lam, T=None, workers: int = 1,
         res["lnl"] = np.nan
         return res
     _WORK.update(events=events, slices=slices, z=z, w=w, cat=cat, tau=trapezoid(cat.grid),
-                 gz=grid_factor(cat.grid, lam), T=T, kernel=kernel, shape=shape, n_bins=n_bins)
+                 gz=grid_factor(cat.grid, lam), T=T, kernel=kernel, shape=shape, n_bins=n_bins,
+                 rows=galaxy_density(cat, lam)[0])
     if workers > 1 and len(sub) > 1:
         import multiprocessing as mp
         with mp.get_context("fork").Pool(workers) as pool:

@@ -448,3 +448,24 @@ def make_lambdas(wl: Workload, batch: int | None = None, child: int = 4) -> np.n
 
 def z_grid(wl: Workload) -> np.ndarray:
     return np.linspace(wl.z_lo, wl.z_hi, wl.n_z)
+
+
+def make_completeness(rows_pix, nside, grid, seed=7):
+    """A synthetic catalogue completeness (input data for the incompleteness
+    term): per HEALPix pixel a falling logistic P(z) = 1 / (1 + e^((z - z_c)/0.08))
+    with z_c drawn in [0.5, 1.3] per pixel (the catalogue's magnitude limit
+    reached at different depths across the sky).  Returns (P rows for
+    rows_pix [n_rows][n_z], M(z) = sum over all 12 nside^2 pixels of
+    area (1 - P) [n_z])."""
+    npix = 12 * nside * nside
+    rng = np.random.default_rng(np.random.SeedSequence([250402034, 99, seed]))
+    zc = rng.uniform(0.5, 1.3, npix)
+    area = pixel_area(nside)
+
+    def p_of(z_c):
+        return 1.0 / (1.0 + np.exp((grid[None, :] - np.asarray(z_c)[:, None]) / 0.08))
+
+    missing = np.zeros(grid.size)
+    for a in range(0, npix, 4096):
+        missing += area * np.sum(1.0 - p_of(zc[a:a + 4096]), axis=0)
+    return p_of(zc[np.asarray(rows_pix)]), missing
