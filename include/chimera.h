@@ -238,6 +238,24 @@ chimera_status chimera_add_events_3d(chimera_ctx* ctx, int32_t n_ev, const int64
                                     const double* pix_area, chimera_events** out);
 chimera_status chimera_release_events(chimera_ctx* ctx, chimera_events* ev);
 
+/* An incomplete catalogue (eqs. p-gal, p-miss, f-R): the galaxy density
+ * becomes p_gal = f_R p_cat + (1 - f_R) p_miss with the missing galaxies
+ * spread homogeneously in comoving volume up to the grid's end z_max:
+ *   row r:   f_R n_r(z) + (1 - P_r(z)) v(z),
+ *   n_tot:   f_R n_tot(z) + M(z) v(z),
+ *   v(z) = (dV_c/dz per sr)(z) / V_c(z_max) = chi(z)^2 / (E(z) (4 pi/3) chi(z_max)^3),
+ *   f_R = sum_g tau_g (4 pi - M(z_g)) v(z_g)   (eq. f-R on the grid),
+ * at every lambda (v and f_R depend on Om).  p_compl[n_rows][n_z]: the
+ * completeness P_compl of each catalogue row's pixel on the grid, in [0, 1];
+ * missing[n_z]: M(z_g) = sum over all sky pixels of area x (1 - P_compl),
+ * in [0, 4 pi] sr.  p_compl = NULL returns to a complete catalogue.  Applies
+ * to later calls; replacing the catalogue clears it; resident single-1D
+ * sets fold it as they fold the rows.  chimera_lnl_grad refuses a context
+ * with it set (EINVAL).  Host arrays; synchronous.  ESTATE before a
+ * catalogue is set, EINVAL for values out of range. */
+chimera_status chimera_set_completeness(chimera_ctx* ctx, const double* p_compl,
+                                       const double* missing);
+
 /* The injection sum's stability check of Sect. 2.2 (reading: the effective
  * number of injections must exceed factor x the number of events of the
  * likelihood; the paper uses 5).  Once set, chimera_lnl_batch,

@@ -32,7 +32,7 @@ EXPORTS = ("chimera_default_config", "chimera_create", "chimera_destroy", "chime
            "chimera_set_catalog", "chimera_set_catalog_galaxies", "chimera_get_catalog",
            "chimera_set_injections",
            "chimera_add_events", "chimera_add_events_single1d", "chimera_add_events_3d",
-           "chimera_set_event_kde", "chimera_set_neff_gate",
+           "chimera_set_event_kde", "chimera_set_neff_gate", "chimera_set_completeness",
            "chimera_release_events", "chimera_lnl_batch", "chimera_lnl_batch_static",
            "chimera_selection_xi",
            "chimera_lnl_grad", "chimera_scratch_bytes", "chimera_scratch_held",
@@ -87,6 +87,7 @@ def _load():
         "chimera_add_events_3d": (ctypes.c_int, [_P, _I32] + [_P] * 11 + [ctypes.POINTER(_P)]),
         "chimera_set_event_kde": (ctypes.c_int, [_P, _P, _I32, _I32]),
         "chimera_set_neff_gate": (ctypes.c_int, [_P, ctypes.c_double]),
+        "chimera_set_completeness": (ctypes.c_int, [_P, _P, _P]),
         "chimera_release_events": (ctypes.c_int, [_P, _P]),
         "chimera_lnl_batch": (ctypes.c_int, [_P, _P, _P, _I64, _I32, _P, _P, _I32, _P]),
         "chimera_lnl_batch_static": (ctypes.c_int, [_P, _P, _P, _I64, _I32, _P, _P, _P]),
@@ -214,6 +215,15 @@ def chimera_add_events_3d(h, ev_samp_off, dl, m1d, m2d, sky_u, sky_v, ev_pix_off
     _check(lib.chimera_add_events_3d(h, o1.size - 1, p1, *[p for _, p in samp], p2, p3,
                                      *[p for _, p in pix], ctypes.byref(ev)))
     return ev
+
+
+def chimera_set_completeness(h, p_compl, missing):
+    if p_compl is None:
+        _check(lib.chimera_set_completeness(h, None, None))
+        return
+    a, pa = _host(p_compl, np.float64)
+    m, pm = _host(missing, np.float64)
+    _check(lib.chimera_set_completeness(h, pa, pm))
 
 
 def chimera_set_neff_gate(h, factor):
@@ -401,6 +411,10 @@ class Context:
         h = chimera_add_events_single1d(self.handle, ev_samp_off, dl, m1d, m2d, ev_pix_off,
                                         pix_row, s_ir)
         return EventSet(self, h, len(ev_samp_off) - 1)
+
+    def set_completeness(self, p_compl, missing=None):
+        """Incomplete catalogue: P_compl [n_rows][n_z] and M(z) [n_z]; None clears it."""
+        chimera_set_completeness(self.handle, p_compl, missing)
 
     def set_neff_gate(self, factor):
         """ln L = -inf where N_eff <= factor x n_events (0: off)."""

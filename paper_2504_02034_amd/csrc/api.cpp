@@ -112,6 +112,8 @@ struct chimera_events {
   double* fold_s = nullptr;     // [P] sky factor of each pixel
   double* own64 = nullptr;      // [E][n_z]
   float* own32 = nullptr;
+  double* ownm64 = nullptr;     // [E][n_z] the same fold of 1 - P_compl
+  float* ownm32 = nullptr;
   // kernel options (chimera_set_event_kde, Sect. 2.3)
   int P = 0;                    // pixel slots
   int shape = 0, n_bins = 0;
@@ -155,6 +157,10 @@ struct chimera_ctx {
   double inj_dmin = 0.0, inj_dmax = 0.0;
   bool has_cat = false, has_inj = false;
   double neff_gate = 0.0;       // chimera_set_neff_gate
+  // incompleteness (chimera_set_completeness): 1 - P_compl per row, M(z)
+  double* miss64 = nullptr;
+  float* miss32 = nullptr;
+  double* missing = nullptr;
   std::vector<chimera_events*> events;
   // per-stream scratch arenas (grown to the largest call on the stream; freed
   // by chimera_release_scratch or chimera_destroy).  A call holds its
@@ -192,7 +198,7 @@ void free_events(chimera_events* ev) {
   dfree(ev->dl); dfree(ev->lndl); dfree(ev->m1d); dfree(ev->m2d);
   dfree(ev->lnm1d); dfree(ev->lnm2d); dfree(ev->samp_row); dfree(ev->samp_c);
   dfree(ev->fold_pix_off); dfree(ev->fold_row); dfree(ev->fold_s);
-  dfree(ev->own64); dfree(ev->own32);
+  dfree(ev->own64); dfree(ev->own32); dfree(ev->ownm64); dfree(ev->ownm32);
   dfree(ev->pix_off); dfree(ev->pix_idx); dfree(ev->slot_c); dfree(ev->slot_event);
   dfree(ev->virt_off); dfree(ev->su); dfree(ev->sv); dfree(ev->pu); dfree(ev->pv);
   dfree(ev->d3_slot_off); dfree(ev->d3_slot_row);
@@ -211,13 +217,29 @@ const double* rows64(const chimera_ctx* c, const chimera_events* ev) {
 const float* rows32(const chimera_ctx* c, const chimera_events* ev) {
   return ev && ev->single1d ? ev->own32 : c->nz32;
 }
+// 1 - P_compl rows for ev (null for a complete catalogue)
+const double* miss64(const chimera_ctx* c, const chimera_events* ev) {
+  if (!c->miss64) return nullptr;
+  return ev && ev->single1d ? ev->ownm64 : c->miss64;
+}
+const float* miss32(const chimera_ctx* c, const chimera_events* ev) {
+  if (!c->miss64) return nullptr;
+  return ev && ev->single1d ? ev->ownm32 : c->miss32;
+}
 
-// Fold a single-1D set's rows from the current catalogue (ctx->mu held,
-// device current); synchronous.
+// Fold a single-1D set's rows from the current catalogue (and its
+// completeness, if any) (ctx->mu held, device current); synchronous.
 hipError_t fold_rows(const chimera_ctx* c, chimera_events* ev) {
+  hipError_t e = hipSuccess;
+  const size_t n = (size_t)ev->E * c->cfg.n_z;
+  if (c->miss64 && !ev->ownm64) {
+    e = hipMalloc((void**)&ev->ownm64, n * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc((void**)&ev->ownm32, n * sizeof(float));
+    if (e != hipSuccess) return e;
+  }
   FoldArgs f{ev->fold_pix_off, ev->fold_row, ev->fold_s, ev->E, c->cfg.n_z, c->nz64, ev->own64,
-             ev->own32};
-  hipError_t e = launch_fold_rows(f, nullptr);
+             ev->own32, c->miss64, ev->ownm64, ev->ownm32};
+  e = launch_fold_rows(f, nullptr);
   if (e == hipSuccess) e = hipDeviceSynchronize();
   return e;
 }
@@ -230,10 +252,16 @@ void free_injections(chimera_ctx* c) {
   c->has_inj = false;
 }
 
+void free_completeness(chimera_ctx* c) {
+  dfree(c->miss64); dfree(c->miss32); dfree(c->missing);
+  c->miss64 = nullptr; c->miss32 = nullptr; c->missing = nullptr;
+}
+
 void free_catalog(chimera_ctx* c) {
   dfree(c->nz64); dfree(c->nz32); dfree(c->ntot);
   c->nz64 = nullptr; c->nz32 = nullptr; c->ntot = nullptr;
   c->has_cat = false;
+  free_completeness(c);    // it belongs to the catalogue's rows
 }
 
 Geometry make_geometry(const chimera_ctx* c, double dmin, double dmax) {
@@ -282,11 +310,15 @@ struct Scratch {
   double* p3;
   double* z3;
   void* w3;
+  double* ntot_eff;
+  double* gzb64;
+  float* gzb32;
 };
 
 // Lay out (or size, when base is null) the scratch of one call.
 size_t carve(Carve& cv, Scratch& s, const Geometry& g, int64_t B, int nchunk, bool need_lam,
-             bool need_lnI, bool need_outs, const chimera_events* ev, bool f32) {
+             bool need_lnI, bool need_outs, const chimera_events* ev, bool f32,
+             bool compl_ = false) {
   const bool need_grid = ev != nullptr;
   const int E = ev ? ev->E : 0;
   const int64_t S = ev ? ev->n_samp : 0;
@@ -317,6 +349,9 @@ size_t carve(Carve& cv, Scratch& s, const Geometry& g, int64_t B, int nchunk, bo
   s.bz = NB ? cv.take<double>((size_t)B * NB) : nullptr;
   s.bw = NB ? (f32 ? (void*)cv.take<float>((size_t)B * NB) : (void*)cv.take<double>((size_t)B * NB))
             : nullptr;
+  s.ntot_eff = compl_ ? cv.take<double>((size_t)B * g.n_z) : nullptr;
+  s.gzb64 = compl_ && need_grid ? cv.take<double>((size_t)B * g.n_z) : nullptr;
+  s.gzb32 = compl_ && need_grid ? cv.take<float>((size_t)B * g.n_z) : nullptr;
   s.p3 = V ? cv.take<double>((size_t)B * E * 8) : nullptr;
   s.z3 = V ? cv.take<double>((size_t)B * V) : nullptr;
   s.w3 = V ? (f32 ? (void*)cv.take<float>((size_t)B * V) : (void*)cv.take<double>((size_t)B * V))
@@ -1026,6 +1061,45 @@ chimera_status chimera_release_events(chimera_ctx* ctx, chimera_events* ev) {
   return CHIMERA_OK;
 }
 
+chimera_status chimera_set_completeness(chimera_ctx* ctx, const double* p_compl,
+                                       const double* missing) {
+  if (!ctx) return fail(CHIMERA_EINVAL, "null context");
+  const size_t nzn = (size_t)ctx->cfg.n_z;
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  if (!ctx->has_cat) return fail(CHIMERA_ESTATE, "set the catalogue first");
+  HIP_TRY(hipSetDevice(ctx->cfg.device));
+  if (!p_compl) {
+    HIP_TRY(hipDeviceSynchronize());
+    free_completeness(ctx);
+    return CHIMERA_OK;
+  }
+  if (!missing) return fail(CHIMERA_EINVAL, "null missing solid angle");
+  const size_t n = (size_t)ctx->n_rows * nzn;
+  for (size_t i = 0; i < n; ++i)
+    if (!(p_compl[i] >= 0.0 && p_compl[i] <= 1.0))
+      return fail(CHIMERA_EINVAL, "p_compl must lie in [0, 1]");
+  for (size_t k = 0; k < nzn; ++k)
+    if (!(missing[k] >= 0.0 && missing[k] <= 4.0 * M_PI))
+      return fail(CHIMERA_EINVAL, "missing must lie in [0, 4 pi]");
+  std::vector<double> m64(std::max<size_t>(n, 1), 0.0);
+  std::vector<float> m32(std::max<size_t>(n, 1), 0.0f);
+  for (size_t i = 0; i < n; ++i) {
+    m64[i] = 1.0 - p_compl[i];
+    m32[i] = (float)m64[i];
+  }
+  HIP_TRY(hipDeviceSynchronize());
+  free_completeness(ctx);
+  hipError_t e = upload(&ctx->miss64, m64.data(), std::max<size_t>(n, 1));
+  if (e == hipSuccess) e = upload(&ctx->miss32, m32.data(), std::max<size_t>(n, 1));
+  if (e == hipSuccess) e = upload(&ctx->missing, missing, nzn);
+  if (e != hipSuccess) {
+    free_completeness(ctx);
+    return fail(e == hipErrorOutOfMemory ? CHIMERA_ENOMEM : CHIMERA_EDEVICE,
+                std::string("uploading the completeness: ") + hipGetErrorString(e));
+  }
+  return refold_all(ctx);
+}
+
 chimera_status chimera_set_neff_gate(chimera_ctx* ctx, double factor) {
   if (!ctx) return fail(CHIMERA_EINVAL, "null context");
   if (!(std::isfinite(factor) && factor >= 0.0))
@@ -1171,7 +1245,8 @@ static chimera_status run_chunk(chimera_ctx* ctx, const chimera_events* ev, cons
   Scratch s;
   Carve probe;
   const bool need_lnI = ev && (host || !lnI);
-  const size_t bytes = carve(probe, s, g, B, nchunk, host, need_lnI, host, ev, f32);
+  const bool compl_ = ctx->miss64 != nullptr;
+  const size_t bytes = carve(probe, s, g, B, nchunk, host, need_lnI, host, ev, f32, compl_);
   if (ctx->cfg.hbm_budget && pool_size(bytes) > ctx->cfg.hbm_budget)
     return fail(CHIMERA_ENOMEM, "call needs " + std::to_string(bytes) +
                                     " scratch bytes, over the context's hbm_budget");
@@ -1187,7 +1262,7 @@ static chimera_status run_chunk(chimera_ctx* ctx, const chimera_events* ev, cons
   }
   Carve cv;
   cv.base = (char*)base;
-  carve(cv, s, g, B, nchunk, host, need_lnI, host, ev, f32);
+  carve(cv, s, g, B, nchunk, host, need_lnI, host, ev, f32, compl_);
   const double* lam_dev = lam;
   if (host) {
     HIP_TRY(hipMemcpyAsync(s.lam, lam, (size_t)B * CHIMERA_NLAM * sizeof(double),
@@ -1204,7 +1279,12 @@ static chimera_status run_chunk(chimera_ctx* ctx, const chimera_events* ev, cons
                         ev ? s.gz32 : nullptr, s.flag_mono, s.flag_range, st));
   SelArgs sa;
   sa.P = s.P; sa.flag_mono = s.flag_mono; sa.flag_range = s.flag_range;
-  sa.chi = s.chi; sa.inv = s.inv; sa.g = g; sa.ntot = ctx->ntot;
+  if (compl_)
+    HIP_TRY(launch_completion(s.P, s.chi, g, (int)B, ctx->ntot, ctx->missing, s.ntot_eff,
+                              ev ? s.gz64 : nullptr, ev ? s.gz32 : nullptr, s.gzb64, s.gzb32, st));
+  sa.chi = s.chi; sa.inv = s.inv; sa.g = g;
+  sa.ntot = compl_ ? s.ntot_eff : ctx->ntot;
+  sa.ntot_stride = compl_ ? g.n_z : 0;
   sa.dl = ctx->inj_dl; sa.lndl = ctx->inj_lndl; sa.m1d = ctx->inj_m1d; sa.m2d = ctx->inj_m2d;
   sa.lnm1d = ctx->inj_lnm1d; sa.lnm2d = ctx->inj_lnm2d; sa.ln_pdraw = ctx->inj_lnp;
   sa.n_det = ctx->n_det; sa.n_total = ctx->n_inj_total; sa.B = (int)B; sa.nchunk = nchunk;
@@ -1215,6 +1295,8 @@ static chimera_status run_chunk(chimera_ctx* ctx, const chimera_events* ev, cons
     a.P = s.P; a.flag_mono = s.flag_mono; a.flag_range = s.flag_range;
     a.chi = s.chi; a.inv = s.inv; a.dtab = s.dtab; a.g = g; a.gz64 = s.gz64; a.gz32 = s.gz32;
     a.nz64 = rows64(ctx, ev); a.nz32 = rows32(ctx, ev);
+    a.mz64 = miss64(ctx, ev); a.mz32 = miss32(ctx, ev);
+    a.gzb64 = s.gzb64; a.gzb32 = s.gzb32;
     a.ev_samp_off = ev->ev_samp_off; a.ev_slot_off = ev->ev_slot_off;
     a.ev_unit_off = ev->ev_unit_off; a.slot_row = ev->slot_row;
     a.grp_first = ev->grp_first; a.grp_cnt = ev->grp_cnt; a.grp_slot = ev->grp_slot;
@@ -1322,7 +1404,7 @@ chimera_status chimera_scratch_bytes(chimera_ctx* ctx, const chimera_events* ev,
   // lnI is counted whenever there is an event set: a device call without an
   // lnI output keeps it in the scratch
   *bytes = pool_size(carve(probe, s, g, B, selection_chunks(ctx->n_det), host, ev != nullptr,
-                           host, ev, prec == CHIMERA_FP32));
+                           host, ev, prec == CHIMERA_FP32, ctx->miss64 != nullptr));
   return CHIMERA_OK;
 }
 
@@ -1389,7 +1471,8 @@ static size_t device_launch_bytes(chimera_ctx* ctx, const chimera_events* ev, in
   const Geometry g = make_geometry(ctx, dmin, dmax);
   Scratch s;
   Carve probe;
-  return carve(probe, s, g, B, selection_chunks(ctx->n_det), false, !have_lnI, false, ev, f32);
+  return carve(probe, s, g, B, selection_chunks(ctx->n_det), false, !have_lnI, false, ev, f32,
+               ctx->miss64 != nullptr);
 }
 
 chimera_status chimera_lnl_batch_static(chimera_ctx* ctx, const chimera_events* ev,
@@ -1569,6 +1652,8 @@ chimera_status chimera_lnl_grad(chimera_ctx* ctx, const chimera_events* ev, cons
   if (ev->shape != CHIMERA_KDE_GAUSSIAN || ev->n_bins != 0 || ev->V != 0)
     return fail(CHIMERA_EINVAL,
                 "the adjoint takes the many-1D or single-1D Gaussian kernel on unbinned samples");
+  if (ctx->miss64)
+    return fail(CHIMERA_EINVAL, "the adjoint takes a complete catalogue (no incompleteness set)");
   return run_grad(ctx, ev, lam, B, prec, lnl, grad, mem, hip_stream);
 }
 

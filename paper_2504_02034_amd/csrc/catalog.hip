@@ -164,21 +164,29 @@ hipError_t launch_catalog_finish(const CatalogArgs& c, long long n_used, hipStre
 
 // Rows of a single-1D event set (eq. gw-kernel-single1d): the pixels' sky
 // factors folded into one row per event, out[e][k] = sum_{p of e} s_p n_{row_p}(z_k),
-// summed in the pixels' given order; a thread per (event, node).
+// summed in the pixels' given order (and the same fold of 1 - P_compl when
+// the catalogue is incomplete); a thread per (event, node).
 __global__ void k_fold_rows(const int* __restrict__ pix_off, const int* __restrict__ row,
                             const double* __restrict__ s, long long n_ev, int n_z,
                             const double* __restrict__ nz64, double* __restrict__ out64,
-                            float* __restrict__ out32) {
+                            float* __restrict__ out32, const double* __restrict__ mz64,
+                            double* __restrict__ mout64, float* __restrict__ mout32) {
   const long long n = n_ev * n_z;
   for (long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x; id < n;
        id += (long long)gridDim.x * blockDim.x) {
     const long long e = id / n_z;
     const int k = (int)(id - e * n_z);
-    double acc = 0.0;
-    for (int p = pix_off[e]; p < pix_off[e + 1]; ++p)
+    double acc = 0.0, macc = 0.0;
+    for (int p = pix_off[e]; p < pix_off[e + 1]; ++p) {
       acc += s[p] * nz64[(long long)row[p] * n_z + k];
+      if (mz64) macc += s[p] * mz64[(long long)row[p] * n_z + k];
+    }
     out64[id] = acc;
     out32[id] = (float)acc;
+    if (mz64) {
+      mout64[id] = macc;
+      mout32[id] = (float)macc;
+    }
   }
 }
 
@@ -187,7 +195,7 @@ hipError_t launch_fold_rows(const FoldArgs& f, hipStream_t st) {
   if (n == 0) return hipSuccess;
   const long long blocks = std::min<long long>((n + 255) / 256, 1 << 16);
   k_fold_rows<<<(unsigned)blocks, 256, 0, st>>>(f.pix_off, f.row, f.s, f.n_ev, f.n_z, f.nz64,
-                                                f.out64, f.out32);
+                                                f.out64, f.out32, f.mz64, f.mout64, f.mout32);
   CH_LAUNCH_CHECK();
   return hipSuccess;
 }

@@ -205,7 +205,7 @@ __global__ __launch_bounds__(kZwBS) void k_event_zw(EventArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-template <bool F32>
+template <bool F32, bool COMPL>
 __device__ __forceinline__ void event_smooth(const EventArgs& a) {
   constexpr int K = kGroupK;
   constexpr int BS = kSmBS;
@@ -367,6 +367,11 @@ __device__ __forceinline__ void event_smooth(const EventArgs& a) {
     const CT* gz = F32 ? (const CT*)(a.gz32 + (size_t)b * a.g.n_z)
                        : (const CT*)(a.gz64 + (size_t)b * a.g.n_z);
     const CT* nzt = F32 ? (const CT*)a.nz32 : (const CT*)a.nz64;
+    // with incompleteness F = n_r gz + (1 - P_r) gzb (gz already carries f_R)
+    const CT* gzc = COMPL ? (F32 ? (const CT*)(a.gzb32 + (size_t)b * a.g.n_z)
+                                 : (const CT*)(a.gzb64 + (size_t)b * a.g.n_z))
+                          : nullptr;
+    const CT* mzt = COMPL ? (F32 ? (const CT*)a.mz32 : (const CT*)a.mz64) : nullptr;
     for (int s_hi = A_hi; s_hi >= A_lo; s_hi -= L) {
       const int s_lo = max(s_hi - L + 1, A_lo);
       const int len = s_hi - s_lo + 1;
@@ -397,10 +402,18 @@ __device__ __forceinline__ void event_smooth(const EventArgs& a) {
             CT v[UR];
 #pragma unroll
             for (int r = 0; r < UR; ++r) v[r] = pb + r * NWV < np ? rp[r][gg] : (CT)0;
+            if (COMPL) {
+              const CT gc = gzc[gg];
+#pragma unroll
+              for (int r = 0; r < UR; ++r)
+                if (pb + r * NWV < np)
+                  v[r] = v[r] * gv +
+                         mzt[(size_t)__builtin_amdgcn_readfirstlane(rr[r]) * a.g.n_z + gg] * gc;
+            }
 #pragma unroll
             for (int r = 0; r < UR; ++r) {
               const int p = pb + r * NWV;
-              if (p < np && qv) ((CT*)smem)[p * Ls + q] = v[r] * gv;
+              if (p < np && qv) ((CT*)smem)[p * Ls + q] = COMPL ? v[r] : v[r] * gv;
             }
           }
         }
@@ -411,6 +424,7 @@ __device__ __forceinline__ void event_smooth(const EventArgs& a) {
         const bool qv = q < len;
         const int gg = s_lo + (qv ? q : 0);
         const CT gv = gz[gg];
+        const CT gc = COMPL ? gzc[gg] : (CT)0;
         for (int pb = wv * RPW + sub; pb < np; pb += NWV * RPW * UR) {
           int rr[UR];
 #pragma unroll
@@ -424,10 +438,17 @@ __device__ __forceinline__ void event_smooth(const EventArgs& a) {
             const int p = pb + r * NWV * RPW;
             v[r] = p < np ? nzt[(size_t)rr[r] * a.g.n_z + gg] : (CT)0;
           }
+          if (COMPL) {
+#pragma unroll
+            for (int r = 0; r < UR; ++r) {
+              const int p = pb + r * NWV * RPW;
+              if (p < np) v[r] = v[r] * gv + mzt[(size_t)rr[r] * a.g.n_z + gg] * gc;
+            }
+          }
 #pragma unroll
           for (int r = 0; r < UR; ++r) {
             const int p = pb + r * NWV * RPW;
-            if (p < np && qv) ((CT*)smem)[p * Ls + q] = v[r] * gv;
+            if (p < np && qv) ((CT*)smem)[p * Ls + q] = COMPL ? v[r] : v[r] * gv;
           }
         }
       }
@@ -459,6 +480,7 @@ __device__ __forceinline__ void event_smooth(const EventArgs& a) {
   } else if (A_lo <= A_hi && has) {
     // fallback (windows too wide for the tables or the chain range): direct sums
     const double* gzb = a.gz64 + (size_t)b * a.g.n_z;
+    const double* gzcb = COMPL ? a.gzb64 + (size_t)b * a.g.n_z : nullptr;
     const size_t row = (size_t)a.slot_row[p0 + a.grp_slot[gi]] * a.g.n_z;
     asm volatile("" ::: "memory");   // read z_k, w_k again
 #pragma unroll
@@ -468,7 +490,9 @@ __device__ __forceinline__ void event_smooth(const EventArgs& a) {
       double sacc = 0.0;
       for (int g = klo[k]; g <= khi[k]; ++g) {
         const double x = (a.g.z_lo + (double)g * dz - zkk);
-        sacc += exp(-0.5 * x * x * inv_h2) * a.nz64[row + g] * gzb[g];
+        const double F = COMPL ? a.nz64[row + g] * gzb[g] + a.mz64[row + g] * gzcb[g]
+                               : a.nz64[row + g] * gzb[g];
+        sacc += exp(-0.5 * x * x * inv_h2) * F;
       }
       total += cir * (double)wb[first + k] * sacc;
     }
@@ -493,10 +517,16 @@ __device__ __forceinline__ void event_smooth(const EventArgs& a) {
 }
 
 __global__ __launch_bounds__(kSmBS) __attribute__((amdgpu_waves_per_eu(4)))
-void k_event_smooth64(EventArgs a) { event_smooth<false>(a); }
+void k_event_smooth64(EventArgs a) { event_smooth<false, false>(a); }
 
 __global__ __launch_bounds__(kSmBS) __attribute__((amdgpu_waves_per_eu(4)))
-void k_event_smooth32(EventArgs a) { event_smooth<true>(a); }
+void k_event_smooth64c(EventArgs a) { event_smooth<false, true>(a); }
+
+__global__ __launch_bounds__(kSmBS) __attribute__((amdgpu_waves_per_eu(4)))
+void k_event_smooth32c(EventArgs a) { event_smooth<true, true>(a); }
+
+__global__ __launch_bounds__(kSmBS) __attribute__((amdgpu_waves_per_eu(4)))
+void k_event_smooth32(EventArgs a) { event_smooth<true, false>(a); }
 
 // profiling: the pair counts of one launch into the context's counter
 __global__ __launch_bounds__(256) void k_count_sum(const long long* __restrict__ pc, long long n,
@@ -633,6 +663,16 @@ __global__ __launch_bounds__(kEpBS) void k_event_epan(EventArgs a) {
   const double inv_W2 = 1.0 / (W * W);
   const CT* gz = F32 ? (const CT*)(a.gz32 + (size_t)b * nz) : (const CT*)(a.gz64 + (size_t)b * nz);
   const CT* row = (F32 ? (const CT*)a.nz32 : (const CT*)a.nz64) + (size_t)a.slot_row[p] * nz;
+  // tau F at node g (the grid factor carries tau; with incompleteness
+  // F = n_r gz + (1 - P_r) gzb)
+  const CT* mrow = a.mz64 ? (F32 ? (const CT*)a.mz32 : (const CT*)a.mz64) + (size_t)a.slot_row[p] * nz
+                          : nullptr;
+  const CT* gzc = a.mz64 ? (F32 ? (const CT*)(a.gzb32 + (size_t)b * nz)
+                                : (const CT*)(a.gzb64 + (size_t)b * nz))
+                         : nullptr;
+  auto stage = [&](int g) {
+    return mrow ? (double)(row[g] * gz[g] + mrow[g] * gzc[g]) : (double)(row[g] * gz[g]);
+  };
   const bool binned = a.n_bins > 0;
   const double* zsrc = binned ? a.bz + (size_t)b * a.n_slots * a.n_bins : a.zbuf + (size_t)b * a.S;
   const CT* wsrc = binned ? (const CT*)a.bw + (size_t)b * a.n_slots * a.n_bins
@@ -659,7 +699,7 @@ __global__ __launch_bounds__(kEpBS) void k_event_epan(EventArgs a) {
   auto build_prefix = [&](int glo, int ghi, int mid) {
     const int L = ghi - glo + 1;
     wave_sync();                 // earlier prefix sums are read
-    for (int q = lane; q < L; q += 64) Q0[q] = (double)(row[glo + q] * gz[glo + q]);
+    for (int q = lane; q < L; q += 64) Q0[q] = stage(glo + q);
     wave_sync();
     // per lane: a contiguous block of <= PER points
     const int per = (L + 63) >> 6;
@@ -781,7 +821,7 @@ __global__ __launch_bounds__(kEpBS) void k_event_epan(EventArgs a) {
       double t = 0.0;
       for (int g = g0 + lane; g <= g1; g += 64) {
         const double u = ((double)g - xj) / W;
-        t += (double)(row[g] * gz[g]) * (1.0 - u * u);
+        t += stage(g) * (1.0 - u * u);
       }
       t = wave_sum(t);
       if (lane == 0) {
@@ -1004,12 +1044,19 @@ hipError_t launch_events(const EventArgs& a, const EventArgs& kern, bool f32, hi
     const long long bs = item_lambda_blocks(kern.U, kern.B);
     const size_t lds =
         (size_t)sm_fbytes(f32) + (size_t)kSmGCap * (f32 ? sizeof(float) : sizeof(double));
-    const void* smooth = f32 ? (const void*)k_event_smooth32 : (const void*)k_event_smooth64;
+    const bool compl_ = kern.mz64 != nullptr;
+    const void* smooth = compl_ ? (f32 ? (const void*)k_event_smooth32c : (const void*)k_event_smooth64c)
+                                : (f32 ? (const void*)k_event_smooth32 : (const void*)k_event_smooth64);
     err = hipFuncSetAttribute(smooth, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (err != hipSuccess) return err;
     if (t0 && (err = hipEventRecord(t0, st)) != hipSuccess) return err;
-    if (f32) k_event_smooth32<<<(unsigned)bs, kSmBS, lds, st>>>(kern);
-    else k_event_smooth64<<<(unsigned)bs, kSmBS, lds, st>>>(kern);
+    if (compl_) {
+      if (f32) k_event_smooth32c<<<(unsigned)bs, kSmBS, lds, st>>>(kern);
+      else k_event_smooth64c<<<(unsigned)bs, kSmBS, lds, st>>>(kern);
+    } else {
+      if (f32) k_event_smooth32<<<(unsigned)bs, kSmBS, lds, st>>>(kern);
+      else k_event_smooth64<<<(unsigned)bs, kSmBS, lds, st>>>(kern);
+    }
     if (t1 && (err = hipEventRecord(t1, st)) != hipSuccess) return err;
   }
   if (kern.count) {

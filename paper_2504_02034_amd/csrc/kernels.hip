@@ -243,6 +243,61 @@ __global__ void k_grid_factor(const LamParams* __restrict__ Pv, const double2* _
 }
 
 // ---------------------------------------------------------------------------
+// incompleteness: the homogeneous completion of eq. p-miss per lambda
+// ---------------------------------------------------------------------------
+constexpr int kCompBS = 256;
+__global__ __launch_bounds__(kCompBS) void k_completion(const LamParams* __restrict__ Pv,
+                                                        const double2* __restrict__ chi, Geometry g,
+                                                        const double* __restrict__ ntot,
+                                                        const double* __restrict__ missing,
+                                                        double* __restrict__ ntot_eff,
+                                                        double* __restrict__ gz64,
+                                                        float* __restrict__ gz32,
+                                                        double* __restrict__ gzb64,
+                                                        float* __restrict__ gzb32) {
+  const int b = blockIdx.x;
+  __shared__ double red[kCompBS / 64 + 1];
+  const LamParams P = Pv[b];
+  const double2* tab = chi + (size_t)b * g.n_t;
+  const double zmax = g.z_lo + (double)(g.n_z - 1) * g.dz;
+  const double cm = chi_at(tab, g, log1p(zmax));
+  const double norm = 1.0 / (4.0 * M_PI / 3.0 * cm * cm * cm);
+  auto vol = [&](int k) {
+    const double z = g.z_lo + (double)k * g.dz;
+    const double c = chi_at(tab, g, log1p(z));
+    return c * c / efunc_of_zp1(P.om, 1.0 + z) * norm;
+  };
+  double t = 0.0;
+  for (int k = threadIdx.x; k < g.n_z; k += kCompBS) {
+    const double tau = (k == 0 || k == g.n_z - 1) ? 0.5 * g.dz : g.dz;
+    t += tau * (4.0 * M_PI - missing[k]) * vol(k);
+  }
+  const double fR = block_sum<kCompBS>(t, red);
+  for (int k = threadIdx.x; k < g.n_z; k += kCompBS) {
+    const double v = vol(k);
+    const size_t i = (size_t)b * g.n_z + k;
+    ntot_eff[i] = fR * ntot[k] + missing[k] * v;
+    if (gz64) {
+      const double gv = gz64[i];
+      gz64[i] = fR * gv;
+      gz32[i] = (float)(fR * gv);
+      gzb64[i] = v * gv;
+      gzb32[i] = (float)(v * gv);
+    }
+  }
+}
+
+hipError_t launch_completion(const LamParams* P, const double2* chi, const Geometry& g, int B,
+                             const double* ntot, const double* missing, double* ntot_eff,
+                             double* gz64, float* gz32, double* gzb64, float* gzb32,
+                             hipStream_t st) {
+  k_completion<<<B, kCompBS, 0, st>>>(P, chi, g, ntot, missing, ntot_eff, gz64, gz32, gzb64,
+                                       gzb32);
+  CH_LAUNCH_CHECK();
+  return hipSuccess;
+}
+
+// ---------------------------------------------------------------------------
 // selection: partial sums of s_j and s_j^2 per (injection chunk, lambda)
 // ---------------------------------------------------------------------------
 constexpr int kSelBS = 256;
@@ -276,15 +331,16 @@ __global__ __launch_bounds__(kSelBS) void k_selection(SelArgs a) {
                          : mass_weight64(P, m1, m2, l1, l2);
     if (w == 0.0) continue;
     // n_tot(z) by linear interpolation on the grid, 0 outside
+    const double* ntot = a.ntot + (size_t)b * a.ntot_stride;
     const double pos = (z - a.g.z_lo) / a.g.dz;
     double nt = 0.0;
     if (pos >= 0.0 && pos <= (double)(a.g.n_z - 1)) {
       int kk = (int)pos;
       if (kk >= a.g.n_z - 1) {
-        nt = a.ntot[a.g.n_z - 1];
+        nt = ntot[a.g.n_z - 1];
       } else {
         const double t = pos - (double)kk;
-        nt = a.ntot[kk] + t * (a.ntot[kk + 1] - a.ntot[kk]);
+        nt = ntot[kk] + t * (ntot[kk + 1] - ntot[kk]);
       }
     }
     if (nt == 0.0) continue;

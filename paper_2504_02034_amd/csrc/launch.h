@@ -42,7 +42,8 @@ struct SelArgs {
   const double2* chi;
   const double2* inv;
   Geometry g;
-  const double* ntot;
+  const double* ntot;       // [n_z], or [B][n_z] when ntot_stride = n_z (incompleteness)
+  long long ntot_stride;
   const double* dl;
   const double* lndl;
   const double* m1d;
@@ -95,6 +96,13 @@ struct EventArgs {
   const float* gz32;
   const double* nz64;
   const float* nz32;
+  // incompleteness (null without it): 1 - P_compl per row, and the grid
+  // factor times the completion density (the grid factor itself is then
+  // scaled by f_R), F = n_r gz + (1 - P_r) gzb
+  const double* mz64;
+  const float* mz32;
+  const double* gzb64;
+  const float* gzb32;
   // event set
   const int* ev_samp_off;   // [E+1] samples of each event (group order)
   const int* ev_slot_off;   // [E+1] pixel slots of each event
@@ -313,7 +321,19 @@ struct FoldArgs {
   const double* nz64;       // [n_rows][n_z] catalogue rows
   double* out64;            // [n_ev][n_z] (written)
   float* out32;             // [n_ev][n_z] (written)
+  const double* mz64;       // [n_rows][n_z] 1 - P_compl (null: none)
+  double* mout64;           // [n_ev][n_z] folded 1 - P_compl (written when mz64)
+  float* mout32;
 };
+
+// Incompleteness (eqs. p-gal, p-miss, f-R) per lambda: the completion density
+// v(z_g) = chi^2 / (E (4 pi / 3) chi(z_max)^3), f_R = sum_g tau_g (4 pi - M_g) v_g,
+// n_tot^eff = f_R n_tot + M v into ntot_eff[B][n_z]; with gz64 (an event call)
+// gzb = v gz and then gz *= f_R (both precisions).  One workgroup per lambda.
+hipError_t launch_completion(const LamParams* P, const double2* chi, const Geometry& g, int B,
+                             const double* ntot, const double* missing, double* ntot_eff,
+                             double* gz64, float* gz32, double* gzb64, float* gzb32,
+                             hipStream_t st);
 
 hipError_t launch_fold_rows(const FoldArgs& f, hipStream_t st);
 
