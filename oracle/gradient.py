@@ -328,6 +328,8 @@ def lnl_grad(events, cat: L.Catalog, inj: L.InjectionSet, lam, T=None, kernel="m
         raise ValueError(f"unknown kernel {kernel!r}")
     if cat.p_compl is not None:
         raise NotImplementedError("the gradient of the incompleteness term is not built")
+    if len(lam) > 14:
+        raise NotImplementedError("the gradient of the smoothed mass model is not built")
     lam = np.asarray(lam, dtype=np.float64)
     E = len(events)
     out = {"lnl": -np.inf, "grad": np.full(NG, np.nan), "lnI": np.full(E, -np.inf),

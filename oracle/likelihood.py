@@ -162,9 +162,11 @@ def lambda_in_domain(lam) -> bool:
     lam = np.asarray(lam, dtype=np.float64)
     if not np.all(np.isfinite(lam)):
         return False
-    h0, om, xi0, _n, _a, _b, mmin, mmax, mu, sg, lg, _g, _k, zp = lam
+    h0, om, xi0, _n, _a, _b, mmin, mmax, mu, sg, lg, _g, _k, zp = lam[:14]
     if not (h0 > 0 and 0 < om <= 1 and xi0 > 0 and 0 < mmin < mmax and sg > 0
             and 0 <= lg <= 1 and zp > -1):
+        return False
+    if lam.size > 14 and not lam[14] >= 0:      # delta_m (the smoothed mass edge)
         return False
     # reading: a Gaussian peak with no mass inside [mmin, mmax] cannot be normalised
     a, b = (mmin - mu) / sg, (mmax - mu) / sg
