@@ -22,6 +22,8 @@
  *   lambda       row-major double [B][14]:
  *                H0, Om, Xi0, n, alpha, beta, mmin, mmax, mu_g, sigma_g,
  *                lambda_g, gamma, kappa, z_p
+ *                ([B][15] with delta_m last once chimera_set_mass_smoothing
+ *                is on; chimera_lambda_width gives the current width)
  *   gradient     row-major double [B][12], the same order without mmin, mmax
  *   ownership    the caller owns every array it passes; the library copies
  *                what it keeps (catalogue, events, injections) to the device
@@ -35,7 +37,8 @@
  *                without waiting.
  *   per-lambda   a lambda outside the domain (non-finite entry, H0 <= 0,
  *   results      Om outside (0,1], Xi0 <= 0, mmin <= 0, mmax <= mmin,
- *                sigma_g <= 0, lambda_g outside [0,1], z_p <= -1), or for
+ *                sigma_g <= 0, lambda_g outside [0,1], z_p <= -1,
+ *                delta_m < 0), or for
  *                which d_L^gw is not increasing on the distance table, gives
  *                lnl = -inf; one for which a resident distance exceeds
  *                d_L^gw(z_tab_max) gives lnl = NaN.  Neither is a call
@@ -265,6 +268,26 @@ chimera_status chimera_set_completeness(chimera_ctx* ctx, const double* p_compl,
  * off.  EINVAL for a negative or non-finite factor.  Applies to later calls;
  * do not change it while calls are in flight. */
 chimera_status chimera_set_neff_gate(chimera_ctx* ctx, double factor);
+
+/* The smoothed lower edge of the mass model (Table 1's delta_m; the paper
+ * takes the model's full form from the population literature).  on = 1:
+ * every later call reads lambda rows of 15 doubles, delta_m >= 0 last; for
+ * delta_m > 0 both p(m1) (power law + peak) and the power law of p(m2|m1)
+ * are multiplied by
+ *   S(m) = 0 for m <= mmin, 1 for m >= mmin + delta_m, and
+ *   1 / (exp(delta_m/m' + delta_m/(m' - delta_m)) + 1) between, m' = m - mmin,
+ * and normalised again on their supports: p(m1) by 1 - int p(m1) (1 - S) dm,
+ * p(m2|m1) by int_mmin^m1 m^beta S dm; both integrals over the smoothed
+ * range come from a per-lambda table of 4096 Gauss-Legendre panels (cubic
+ * Hermite between its nodes; the power law's closed form beyond).  The
+ * masses' smoothing is computed in FP64 in both precisions.  delta_m = 0
+ * gives the unsmoothed model bitwise.  on = 0 returns to 14-entry rows.
+ * chimera_lnl_grad refuses a context with it on (EINVAL).  Applies to later
+ * calls; do not change it while calls are in flight.  EINVAL for on not 0/1. */
+chimera_status chimera_set_mass_smoothing(chimera_ctx* ctx, int32_t on);
+
+/* The number of doubles per lambda row that calls on ctx read (14 or 15). */
+chimera_status chimera_lambda_width(chimera_ctx* ctx, int32_t* width);
 
 /* Kernel options of a resident event set (Sect. 2.3: the 1-D KDEs take a
  * Gaussian or an Epanechnikov kernel, and their data sets may be binned).

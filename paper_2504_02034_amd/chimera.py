@@ -33,6 +33,7 @@ EXPORTS = ("chimera_default_config", "chimera_create", "chimera_destroy", "chime
            "chimera_set_injections",
            "chimera_add_events", "chimera_add_events_single1d", "chimera_add_events_3d",
            "chimera_set_event_kde", "chimera_set_neff_gate", "chimera_set_completeness",
+           "chimera_set_mass_smoothing", "chimera_lambda_width",
            "chimera_release_events", "chimera_lnl_batch", "chimera_lnl_batch_static",
            "chimera_selection_xi",
            "chimera_lnl_grad", "chimera_scratch_bytes", "chimera_scratch_held",
@@ -87,6 +88,8 @@ def _load():
         "chimera_add_events_3d": (ctypes.c_int, [_P, _I32] + [_P] * 11 + [ctypes.POINTER(_P)]),
         "chimera_set_event_kde": (ctypes.c_int, [_P, _P, _I32, _I32]),
         "chimera_set_neff_gate": (ctypes.c_int, [_P, ctypes.c_double]),
+        "chimera_set_mass_smoothing": (ctypes.c_int, [_P, _I32]),
+        "chimera_lambda_width": (ctypes.c_int, [_P, ctypes.POINTER(_I32)]),
         "chimera_set_completeness": (ctypes.c_int, [_P, _P, _P]),
         "chimera_release_events": (ctypes.c_int, [_P, _P]),
         "chimera_lnl_batch": (ctypes.c_int, [_P, _P, _P, _I64, _I32, _P, _P, _I32, _P]),
@@ -230,6 +233,23 @@ def chimera_set_neff_gate(h, factor):
     _check(lib.chimera_set_neff_gate(h, float(factor)))
 
 
+def chimera_set_mass_smoothing(h, on):
+    _check(lib.chimera_set_mass_smoothing(h, 1 if on else 0))
+
+
+def chimera_lambda_width(h) -> int:
+    w = _I32()
+    _check(lib.chimera_lambda_width(h, ctypes.byref(w)))
+    return w.value
+
+
+def _check_lam(h, lam):
+    """The library reads lambda rows of the context's width: refuse others."""
+    w = chimera_lambda_width(h)
+    if len(lam.shape) != 2 or lam.shape[1] != w:
+        raise ValueError(f"lambda must be [B, {w}] for this context, got {tuple(lam.shape)}")
+
+
 def chimera_set_event_kde(h, ev, shape, n_bins):
     _check(lib.chimera_set_event_kde(h, ev, int(shape), int(n_bins)))
 
@@ -248,10 +268,12 @@ def _stream_ptr(stream):
 
 
 def chimera_lnl_batch(h, ev, lam, prec=CHIMERA_FP64, lnl=None, lnI=None, n_ev=None, stream=None):
-    """lam: numpy [B,14] (host call) or a torch tensor on the device (async call)."""
+    """lam: numpy [B, width] (host call) or a torch tensor on the device (async
+    call); width 14, or 15 with the smoothed mass edge."""
     if _is_torch(lam):
         import torch
         assert lam.is_cuda and lam.dtype == torch.float64 and lam.is_contiguous()
+        _check_lam(h, lam)
         B = lam.shape[0]
         if lnl is None:
             lnl = torch.empty(B, dtype=torch.float64, device=lam.device)
@@ -260,6 +282,7 @@ def chimera_lnl_batch(h, ev, lam, prec=CHIMERA_FP64, lnl=None, lnI=None, n_ev=No
                                      CHIMERA_DEVICE, _stream_ptr(stream)))
         return lnl
     lam, pl = _host(np.atleast_2d(lam), np.float64)
+    _check_lam(h, lam)
     B = lam.shape[0]
     out = np.empty(B)
     lnI_arr = None
@@ -276,6 +299,7 @@ def chimera_lnl_batch_static(h, ev, lam, prec=CHIMERA_FP64, lnl=None, lnI=None, 
     call): lam, lnl (and lnI) are torch tensors on the device."""
     import torch
     assert lam.is_cuda and lam.dtype == torch.float64 and lam.is_contiguous()
+    _check_lam(h, lam)
     B = lam.shape[0]
     if lnl is None:
         lnl = torch.empty(B, dtype=torch.float64, device=lam.device)
@@ -288,6 +312,8 @@ def chimera_lnl_batch_static(h, ev, lam, prec=CHIMERA_FP64, lnl=None, lnI=None, 
 def chimera_selection_xi(h, lam, prec=CHIMERA_FP64, stream=None):
     if _is_torch(lam):
         import torch
+        assert lam.is_cuda and lam.dtype == torch.float64 and lam.is_contiguous()
+        _check_lam(h, lam)
         B = lam.shape[0]
         lx = torch.empty(B, dtype=torch.float64, device=lam.device)
         ne = torch.empty(B, dtype=torch.float64, device=lam.device)
@@ -295,6 +321,7 @@ def chimera_selection_xi(h, lam, prec=CHIMERA_FP64, stream=None):
                                         _P(ne.data_ptr()), CHIMERA_DEVICE, _stream_ptr(stream)))
         return lx, ne
     lam, pl = _host(np.atleast_2d(lam), np.float64)
+    _check_lam(h, lam)
     B = lam.shape[0]
     lx, ne = np.empty(B), np.empty(B)
     _check(lib.chimera_selection_xi(h, pl, B, prec, lx.ctypes.data_as(_P), ne.ctypes.data_as(_P),
@@ -307,6 +334,7 @@ def chimera_lnl_grad(h, ev, lam, prec=CHIMERA_FP64, lnl=None, grad=None, stream=
     if _is_torch(lam):
         import torch
         assert lam.is_cuda and lam.dtype == torch.float64 and lam.is_contiguous()
+        _check_lam(h, lam)
         B = lam.shape[0]
         if lnl is None:
             lnl = torch.empty(B, dtype=torch.float64, device=lam.device)
@@ -316,6 +344,7 @@ def chimera_lnl_grad(h, ev, lam, prec=CHIMERA_FP64, lnl=None, grad=None, stream=
                                     _P(grad.data_ptr()), CHIMERA_DEVICE, _stream_ptr(stream)))
         return lnl, grad
     lam, pl = _host(np.atleast_2d(lam), np.float64)
+    _check_lam(h, lam)
     B = lam.shape[0]
     out, g = np.empty(B), np.empty((B, NGRAD))
     _check(lib.chimera_lnl_grad(h, ev, pl, B, prec, out.ctypes.data_as(_P), g.ctypes.data_as(_P),
@@ -419,6 +448,14 @@ class Context:
     def set_neff_gate(self, factor):
         """ln L = -inf where N_eff <= factor x n_events (0: off)."""
         chimera_set_neff_gate(self.handle, factor)
+
+    def set_mass_smoothing(self, on=True):
+        """Lambda rows of 15 entries, delta_m (the smoothed lower mass edge) last."""
+        chimera_set_mass_smoothing(self.handle, on)
+
+    @property
+    def lam_width(self) -> int:
+        return chimera_lambda_width(self.handle)
 
     def set_event_kde(self, ev: EventSet, shape=None, n_bins=0):
         """Kernel options of an event set: shape CHIMERA_KDE_GAUSSIAN (default)

@@ -157,6 +157,7 @@ struct chimera_ctx {
   double inj_dmin = 0.0, inj_dmax = 0.0;
   bool has_cat = false, has_inj = false;
   double neff_gate = 0.0;       // chimera_set_neff_gate
+  std::atomic<int> nlam{CHIMERA_NLAM};  // lambda row width: +1 (delta_m) after chimera_set_mass_smoothing
   // incompleteness (chimera_set_completeness): 1 - P_compl per row, M(z)
   double* miss64 = nullptr;
   float* miss32 = nullptr;
@@ -313,12 +314,13 @@ struct Scratch {
   double* ntot_eff;
   double* gzb64;
   float* gzb32;
+  double2* mtab;
 };
 
 // Lay out (or size, when base is null) the scratch of one call.
 size_t carve(Carve& cv, Scratch& s, const Geometry& g, int64_t B, int nchunk, bool need_lam,
              bool need_lnI, bool need_outs, const chimera_events* ev, bool f32,
-             bool compl_ = false) {
+             bool compl_ = false, int nlam = CHIMERA_NLAM) {
   const bool need_grid = ev != nullptr;
   const int E = ev ? ev->E : 0;
   const int64_t S = ev ? ev->n_samp : 0;
@@ -335,7 +337,8 @@ size_t carve(Carve& cv, Scratch& s, const Geometry& g, int64_t B, int nchunk, bo
   s.flag_mono = cv.take<int>(B);
   s.flag_range = cv.take<int>(B);
   s.partial = cv.take<double>((size_t)B * std::max(nchunk, 1) * 2);
-  s.lam = need_lam ? cv.take<double>((size_t)B * CHIMERA_NLAM) : nullptr;
+  s.lam = need_lam ? cv.take<double>((size_t)B * nlam) : nullptr;
+  s.mtab = nlam > CHIMERA_NLAM ? cv.take<double2>((size_t)B * (kMassPanels + 1)) : nullptr;
   s.lnI = need_lnI ? cv.take<double>((size_t)B * std::max(E, 1)) : nullptr;
   s.ln_xi = cv.take<double>(B);
   s.neff = cv.take<double>(B);
@@ -1100,6 +1103,21 @@ chimera_status chimera_set_completeness(chimera_ctx* ctx, const double* p_compl,
   return refold_all(ctx);
 }
 
+chimera_status chimera_set_mass_smoothing(chimera_ctx* ctx, int32_t on) {
+  if (!ctx) return fail(CHIMERA_EINVAL, "null context");
+  if (on != 0 && on != 1) return fail(CHIMERA_EINVAL, "on must be 0 or 1");
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  ctx->nlam = on ? CHIMERA_NLAM + 1 : CHIMERA_NLAM;
+  return CHIMERA_OK;
+}
+
+chimera_status chimera_lambda_width(chimera_ctx* ctx, int32_t* width) {
+  if (!ctx || !width) return fail(CHIMERA_EINVAL, "null argument");
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  *width = ctx->nlam;
+  return CHIMERA_OK;
+}
+
 chimera_status chimera_set_neff_gate(chimera_ctx* ctx, double factor) {
   if (!ctx) return fail(CHIMERA_EINVAL, "null context");
   if (!(std::isfinite(factor) && factor >= 0.0))
@@ -1227,7 +1245,8 @@ static hipError_t arena_reserve(chimera_ctx::Arena* ar, hipStream_t st, size_t b
 // stream's arena; then nothing is allocated (and no profiling events made).
 static chimera_status run_chunk(chimera_ctx* ctx, const chimera_events* ev, const double* lam,
                                 int64_t B, int32_t prec, double* lnl, double* lnI, double* ln_xi,
-                                double* n_eff, int32_t mem, void* hip_stream, void* ext = nullptr) {
+                                double* n_eff, int32_t mem, int nlam, void* hip_stream,
+                                void* ext = nullptr) {
   hipStream_t st = (hipStream_t)hip_stream;
   HIP_TRY(hipSetDevice(ctx->cfg.device));
   const bool f32 = prec == CHIMERA_FP32;
@@ -1246,7 +1265,8 @@ static chimera_status run_chunk(chimera_ctx* ctx, const chimera_events* ev, cons
   Carve probe;
   const bool need_lnI = ev && (host || !lnI);
   const bool compl_ = ctx->miss64 != nullptr;
-  const size_t bytes = carve(probe, s, g, B, nchunk, host, need_lnI, host, ev, f32, compl_);
+  const size_t bytes =
+      carve(probe, s, g, B, nchunk, host, need_lnI, host, ev, f32, compl_, nlam);
   if (ctx->cfg.hbm_budget && pool_size(bytes) > ctx->cfg.hbm_budget)
     return fail(CHIMERA_ENOMEM, "call needs " + std::to_string(bytes) +
                                     " scratch bytes, over the context's hbm_budget");
@@ -1262,10 +1282,10 @@ static chimera_status run_chunk(chimera_ctx* ctx, const chimera_events* ev, cons
   }
   Carve cv;
   cv.base = (char*)base;
-  carve(cv, s, g, B, nchunk, host, need_lnI, host, ev, f32, compl_);
+  carve(cv, s, g, B, nchunk, host, need_lnI, host, ev, f32, compl_, nlam);
   const double* lam_dev = lam;
   if (host) {
-    HIP_TRY(hipMemcpyAsync(s.lam, lam, (size_t)B * CHIMERA_NLAM * sizeof(double),
+    HIP_TRY(hipMemcpyAsync(s.lam, lam, (size_t)B * nlam * sizeof(double),
                            hipMemcpyHostToDevice, st));
     lam_dev = s.lam;
   }
@@ -1274,7 +1294,8 @@ static chimera_status run_chunk(chimera_ctx* ctx, const chimera_events* ev, cons
   // N_eff is always formed: the N_eff gate reads it
   double* neff_dev = host || !n_eff ? s.neff : n_eff;
   double* lnl_dev = host ? s.lnl : lnl;
-  HIP_TRY(launch_tables(lam_dev, (int)B, g, s.P, s.chi, s.inv, ev ? s.dtab : nullptr,
+  HIP_TRY(launch_tables(lam_dev, nlam, (int)B, g, s.P, s.mtab, s.chi, s.inv,
+                        ev ? s.dtab : nullptr,
                         ev ? s.gz64 : nullptr,
                         ev ? s.gz32 : nullptr, s.flag_mono, s.flag_range, st));
   SelArgs sa;
@@ -1285,6 +1306,7 @@ static chimera_status run_chunk(chimera_ctx* ctx, const chimera_events* ev, cons
   sa.chi = s.chi; sa.inv = s.inv; sa.g = g;
   sa.ntot = compl_ ? s.ntot_eff : ctx->ntot;
   sa.ntot_stride = compl_ ? g.n_z : 0;
+  sa.mtab = s.mtab;
   sa.dl = ctx->inj_dl; sa.lndl = ctx->inj_lndl; sa.m1d = ctx->inj_m1d; sa.m2d = ctx->inj_m2d;
   sa.lnm1d = ctx->inj_lnm1d; sa.lnm2d = ctx->inj_lnm2d; sa.ln_pdraw = ctx->inj_lnp;
   sa.n_det = ctx->n_det; sa.n_total = ctx->n_inj_total; sa.B = (int)B; sa.nchunk = nchunk;
@@ -1294,6 +1316,7 @@ static chimera_status run_chunk(chimera_ctx* ctx, const chimera_events* ev, cons
     EventArgs a{};
     a.P = s.P; a.flag_mono = s.flag_mono; a.flag_range = s.flag_range;
     a.chi = s.chi; a.inv = s.inv; a.dtab = s.dtab; a.g = g; a.gz64 = s.gz64; a.gz32 = s.gz32;
+    a.mtab = s.mtab;
     a.nz64 = rows64(ctx, ev); a.nz32 = rows32(ctx, ev);
     a.mz64 = miss64(ctx, ev); a.mz32 = miss32(ctx, ev);
     a.gzb64 = s.gzb64; a.gzb32 = s.gzb32;
@@ -1377,12 +1400,13 @@ static chimera_status run_batch(chimera_ctx* ctx, const chimera_events* ev, cons
                                 double* n_eff, int32_t mem, void* hip_stream) {
   const int64_t Bc = lambda_chunk(ev, B, prec == CHIMERA_FP32);
   const int64_t E = ev ? ev->E : 0;
+  const int nlam = ctx->nlam;
   for (int64_t c0 = 0; c0 < B; c0 += Bc) {
     const int64_t n = std::min(Bc, B - c0);
     chimera_status s =
-        run_chunk(ctx, ev, lam + c0 * CHIMERA_NLAM, n, prec, lnl ? lnl + c0 : nullptr,
+        run_chunk(ctx, ev, lam + c0 * nlam, n, prec, lnl ? lnl + c0 : nullptr,
                   lnI ? lnI + c0 * E : nullptr, ln_xi ? ln_xi + c0 : nullptr,
-                  n_eff ? n_eff + c0 : nullptr, mem, hip_stream);
+                  n_eff ? n_eff + c0 : nullptr, mem, nlam, hip_stream);
     if (s != CHIMERA_OK) return s;
   }
   return CHIMERA_OK;
@@ -1404,7 +1428,7 @@ chimera_status chimera_scratch_bytes(chimera_ctx* ctx, const chimera_events* ev,
   // lnI is counted whenever there is an event set: a device call without an
   // lnI output keeps it in the scratch
   *bytes = pool_size(carve(probe, s, g, B, selection_chunks(ctx->n_det), host, ev != nullptr,
-                           host, ev, prec == CHIMERA_FP32, ctx->miss64 != nullptr));
+                           host, ev, prec == CHIMERA_FP32, ctx->miss64 != nullptr, ctx->nlam));
   return CHIMERA_OK;
 }
 
@@ -1462,7 +1486,7 @@ chimera_status chimera_lnl_batch(chimera_ctx* ctx, const chimera_events* ev, con
 
 // Scratch bytes of one device-mode launch sequence of B points.
 static size_t device_launch_bytes(chimera_ctx* ctx, const chimera_events* ev, int64_t B,
-                                  bool f32, bool have_lnI) {
+                                  bool f32, bool have_lnI, int nlam) {
   double dmin = ctx->n_det ? ctx->inj_dmin : std::numeric_limits<double>::infinity();
   double dmax = ctx->n_det ? ctx->inj_dmax : 0.0;
   dmin = std::min(dmin, ev->dmin);
@@ -1472,7 +1496,7 @@ static size_t device_launch_bytes(chimera_ctx* ctx, const chimera_events* ev, in
   Scratch s;
   Carve probe;
   return carve(probe, s, g, B, selection_chunks(ctx->n_det), false, !have_lnI, false, ev, f32,
-               ctx->miss64 != nullptr);
+               ctx->miss64 != nullptr, nlam);
 }
 
 chimera_status chimera_lnl_batch_static(chimera_ctx* ctx, const chimera_events* ev,
@@ -1491,24 +1515,26 @@ chimera_status chimera_lnl_batch_static(chimera_ctx* ctx, const chimera_events* 
   }
   // the most lambda points per launch sequence that the static scratch holds
   const bool f32 = prec == CHIMERA_FP32;
+  const int nlam = ctx->nlam;
   int64_t lo = 0, hi = B;
   while (lo < hi) {
     const int64_t mid = (lo + hi + 1) / 2;
-    if (device_launch_bytes(ctx, ev, mid, f32, lnI != nullptr) <= kStaticScratchBytes) lo = mid;
+    if (device_launch_bytes(ctx, ev, mid, f32, lnI != nullptr, nlam) <= kStaticScratchBytes)
+      lo = mid;
     else hi = mid - 1;
   }
   if (lo < 1)
     return fail(CHIMERA_ENOMEM,
                 "one lambda point of this event set needs " +
-                    std::to_string(device_launch_bytes(ctx, ev, 1, f32, lnI != nullptr)) +
+                    std::to_string(device_launch_bytes(ctx, ev, 1, f32, lnI != nullptr, nlam)) +
                     " scratch bytes, more than the static scratch of " +
                     std::to_string(kStaticScratchBytes) + " (use chimera_lnl_batch)");
   const int64_t E = ev->E;
   for (int64_t c0 = 0; c0 < B; c0 += lo) {
     const int64_t n = std::min(lo, B - c0);
-    chimera_status r = run_chunk(ctx, ev, lam + c0 * CHIMERA_NLAM, n, prec, lnl + c0,
+    chimera_status r = run_chunk(ctx, ev, lam + c0 * nlam, n, prec, lnl + c0,
                                  lnI ? lnI + c0 * E : nullptr, nullptr, nullptr, CHIMERA_DEVICE,
-                                 hip_stream, base);
+                                 nlam, hip_stream, base);
     if (r != CHIMERA_OK) return r;
   }
   return CHIMERA_OK;
@@ -1601,7 +1627,8 @@ static chimera_status run_grad_chunk(chimera_ctx* ctx, const chimera_events* ev,
                            hipMemcpyHostToDevice, st));
     lam_dev = lam_d;
   }
-  HIP_TRY(launch_tables(lam_dev, (int)B, g, P, chi, inv, dtab, gz64, gz32, fm, fr, st));
+  HIP_TRY(launch_tables(lam_dev, CHIMERA_NLAM, (int)B, g, P, nullptr, chi, inv, dtab, gz64, gz32,
+                        fm, fr, st));
   HIP_TRY(launch_chi_om_table(P, (int)B, g, chio, st));
   a.P = P; a.flag_mono = fm; a.flag_range = fr;
   a.chi = chi; a.chio = chio; a.inv = inv; a.dtab = dtab; a.g = g;
@@ -1654,6 +1681,8 @@ chimera_status chimera_lnl_grad(chimera_ctx* ctx, const chimera_events* ev, cons
                 "the adjoint takes the many-1D or single-1D Gaussian kernel on unbinned samples");
   if (ctx->miss64)
     return fail(CHIMERA_EINVAL, "the adjoint takes a complete catalogue (no incompleteness set)");
+  if (ctx->nlam != CHIMERA_NLAM)
+    return fail(CHIMERA_EINVAL, "the adjoint takes the unsmoothed mass model (no delta_m)");
   return run_grad(ctx, ev, lam, B, prec, lnl, grad, mem, hip_stream);
 }
 

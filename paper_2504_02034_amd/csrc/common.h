@@ -11,7 +11,7 @@
 namespace chimera {
 
 constexpr double kCkms = 299792.458;   // speed of light [km/s]
-constexpr int kNlam = 14;
+constexpr int kNlam = 14;            // lambda entries (15 with delta_m, chimera_set_mass_smoothing)
 constexpr double kInvSqrt2Pi = 0.39894228040143267794;
 
 // Flags of one lambda (bits).
@@ -28,9 +28,16 @@ struct LamParams {
   double ln_mmin, ln_mmax;
   double ln1zp;     // ln(1 + z_p)
   double inv_sigma;
+  // smoothed lower mass edge (delta_m > 0; 0: none): S(m) multiplies p(m1)
+  // and p(m2|m1), renormalised: 1/N1, Q = int_mmin^top m^beta S dm, the edge
+  // mmin + delta_m and its log, top = min(mmax, edge), the table's node step
+  double dm, sm_n1inv, sm_q, sm_edge, ln_edge, sm_top, sm_h;
   int flag;         // kFlagDomain
   int pad;
 };
+
+// panels of the per-lambda node table of the smoothed edge on [mmin, top]
+constexpr int kMassPanels = 4096;
 
 // Geometry shared by all lambdas of one call.
 struct Geometry {
@@ -122,7 +129,45 @@ template <bool F32>
 __device__ __forceinline__ void sample_zw(const LamParams& P, const double2* __restrict__ dtab,
                                           const double2* __restrict__ inv, const Geometry& g,
                                           double d, double lnd, double m1d, double m2d,
-                                          double lnm1d, double lnm2d, double& z, double& w);
+                                          double lnm1d, double lnm2d, double& z, double& w,
+                                          const double2* __restrict__ mt);
+
+// The smoothing of the lower mass edge: 0 at and below mmin, 1 from
+// mmin + delta_m on, 1 / (exp(dm/m' + dm/(m' - dm)) + 1) between, m' = m - mmin.
+__device__ __forceinline__ double smooth_edge(double m, double mmin, double dm) {
+  const double mp = m - mmin;
+  if (mp >= dm) return 1.0;
+  if (!(mp > 0.0)) return 0.0;
+  return 1.0 / (exp(dm / mp + dm / (mp - dm)) + 1.0);
+}
+
+// p(m1) p(m2|m1) with the smoothed edge (FP64 in both precisions): the
+// unsmoothed mixture times S(m1) / N1, times m2^beta S(m2) over
+// C(m1) = int_mmin^m1 m^beta S dm.  From the edge on, C = Q + the plain power
+// law; below it C = R m1^beta S(m1), whose S(m1) cancels against p(m1)'s, with
+// R(m1) the cubic Hermite of the per-lambda node table (R, dR/dm).
+__device__ __forceinline__ double mass_weight_smoothed(const LamParams& P,
+                                                       const double2* __restrict__ mt, double m1,
+                                                       double m2, double l1, double l2) {
+  if (!(m1 >= P.mmin && m1 <= P.mmax && m2 >= P.mmin && m2 <= m1 && m1 > P.mmin)) return 0.0;
+  const double s2 = smooth_edge(m2, P.mmin, P.dm);
+  if (!(s2 > 0.0)) return 0.0;
+  const double u = (m1 - P.mu) * P.inv_sigma;
+  const double p1 = (P.pl_coef * exp(-P.alpha * l1) + P.tg_coef * exp(-0.5 * u * u)) * P.sm_n1inv;
+  if (m1 >= P.sm_edge) {
+    const double d = l1 - P.ln_edge;
+    const double pl = P.a2 == 0.0 ? d : exp(P.a2 * P.ln_edge) * expm1(P.a2 * d) / P.a2;
+    return p1 * exp(P.beta * l2) * s2 / (P.sm_q + pl);
+  }
+  const double pos = (m1 - P.mmin) / P.sm_h;
+  const int k = (int)fmin(fmax(pos, 0.0), (double)(kMassPanels - 1));
+  const double t = pos - (double)k;
+  const double2 a = mt[k], b = mt[k + 1];
+  const double d = b.x - a.x, s0 = a.y * P.sm_h, s1 = b.y * P.sm_h;
+  const double r = a.x + t * (s0 + t * ((3.0 * d - 2.0 * s0 - s1) + t * (s0 + s1 - 2.0 * d)));
+  if (!(r > 0.0)) return 0.0;
+  return p1 * exp(P.beta * (l2 - l1)) * s2 / r;
+}
 
 // p(m1) p(m2|m1) of the source-frame masses; 0 outside
 // mmin <= m2 <= m1 <= mmax (and m1 > mmin).  l1, l2 = ln m1, ln m2.
@@ -158,7 +203,8 @@ template <bool F32>
 __device__ __forceinline__ void sample_zw(const LamParams& P, const double2* __restrict__ dtab,
                                           const double2* __restrict__ inv, const Geometry& g,
                                           double d, double lnd, double m1d, double m2d,
-                                          double lnm1d, double lnm2d, double& z, double& w) {
+                                          double lnm1d, double lnm2d, double& z, double& w,
+                                          const double2* __restrict__ mt) {
   double x = invert_x(P, nullptr, inv, g, d, lnd, 0);
   double zp1 = exp(x);
   if (!F32) {
@@ -172,6 +218,11 @@ __device__ __forceinline__ void sample_zw(const LamParams& P, const double2* __r
   const double r = 1.0 / zp1;
   const double m1 = m1d * r, m2 = m2d * r;
   const double l1 = lnm1d - x, l2 = lnm2d - x;
+  if (P.dm > 0.0) {
+    const double ws = mass_weight_smoothed(P, mt, m1, m2, l1, l2);
+    w = F32 ? (double)(float)ws : ws;
+    return;
+  }
   w = F32 ? (double)mass_weight32(P, m1, m2, l1, l2) : mass_weight64(P, m1, m2, l1, l2);
 }
 

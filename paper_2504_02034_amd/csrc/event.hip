@@ -155,6 +155,7 @@ __global__ __launch_bounds__(kZwBS) void k_event_zw(EventArgs a) {
   if (P.flag | a.flag_mono[b] | a.flag_range[b]) return;   // the final kernel reports it
   const double2* dtab = a.dtab + (size_t)b * a.g.n_t;
   const double2* inv = a.inv + (size_t)b * a.g.n_u;
+  const double2* mt = a.mtab ? a.mtab + (size_t)b * (kMassPanels + 1) : nullptr;
   const int s0 = a.ev_samp_off[e];
   const int ns = a.ev_samp_off[e + 1] - s0;
   double* zb = a.zbuf + (size_t)b * a.S + s0;
@@ -178,7 +179,8 @@ __global__ __launch_bounds__(kZwBS) void k_event_zw(EventArgs a) {
     double nxt[6];
     in(j + kZwBS, nxt);
     double z, w;
-    sample_zw<F32>(P, dtab, inv, a.g, cur[0], cur[1], cur[2], cur[3], cur[4], cur[5], z, w);
+    sample_zw<F32>(P, dtab, inv, a.g, cur[0], cur[1], cur[2], cur[3], cur[4], cur[5], z, w,
+                   mt);
 #pragma unroll
     for (int i = 0; i < 6; ++i) cur[i] = nxt[i];
     const CT wc = (CT)w;

@@ -1,6 +1,7 @@
 // HIP kernels (gfx950, wave64) of the many-1D standard-siren likelihood.
 //
 //   k_lam_prepare     per-lambda constants and domain checks (Table 1 layout)
+//   k_mass_table      the smoothed lower mass edge's normalisations (Table 1's delta_m)
 //   k_chi_table       chi(x) = int dz/E on x = ln(1+z) nodes, FP64 (eq. dL-em)
 //   k_inverse_table   x(ln d) with d_L^gw(x) = d (eqs. dL-em, dL-mg)
 //   k_grid_factor     tau_g psi(z_g) / [(1+z_g)^3 d d_L^gw/dz]   (eq. jacobian)
@@ -29,10 +30,11 @@ __device__ double ndtr_diff(double a, double b) {
   return a > 0.0 ? 0.5 * (erfc(a * r) - erfc(b * r)) : 0.5 * (erfc(-b * r) - erfc(-a * r));
 }
 
-__global__ void k_lam_prepare(const double* __restrict__ lam, int B, LamParams* __restrict__ out) {
+__global__ void k_lam_prepare(const double* __restrict__ lam, int stride, int B,
+                              LamParams* __restrict__ out) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= B) return;
-  const double* l = lam + (size_t)b * kNlam;
+  const double* l = lam + (size_t)b * stride;
   LamParams P;
   P.h0 = l[0]; P.om = l[1]; P.xi0 = l[2]; P.n = l[3]; P.alpha = l[4]; P.beta = l[5];
   P.mmin = l[6]; P.mmax = l[7]; P.mu = l[8]; P.sigma = l[9]; P.lg = l[10];
@@ -58,8 +60,157 @@ __global__ void k_lam_prepare(const double* __restrict__ lam, int B, LamParams* 
   P.tg_coef = P.lg / (P.sigma * 2.50662827463100050242 * zg);
   P.a2 = 1.0 + P.beta;
   P.mmin_a2 = exp(P.a2 * P.ln_mmin);
+  // the smoothed lower edge (its constants come from k_mass_table)
+  P.dm = stride > kNlam ? l[kNlam] : 0.0;
+  ok = ok && isfinite(P.dm) && P.dm >= 0.0;
+  P.sm_n1inv = 1.0; P.sm_q = 0.0; P.sm_h = 0.0;
+  P.sm_top = fmin(P.mmax, P.mmin + P.dm);
+  P.sm_edge = P.mmin + P.dm;
+  P.ln_edge = log(P.sm_edge);
   if (!ok) P.flag = kFlagDomain;
   out[b] = P;
+}
+
+// ---------------------------------------------------------------------------
+// smoothed-edge constants: one workgroup per lambda.  With f(m) = m^beta S(m)
+// and C(m) = int_mmin^m f, the table holds R = C / f and dR/dm = 1 - R g'
+// (g' = d ln f/dm) on kMassPanels + 1 equal nodes of [mmin, top],
+// top = min(mmax, mmin + delta_m).  R stays smooth and representable where
+// C and f underflow near mmin, so the weights keep their relative accuracy
+// there.  Across a panel R(b) = R(a) f(a)/f(b) + int_a^b f/f(b): pass 1 (one
+// panel per thread in turn, so the steep panels near mmin spread over the
+// block) forms each panel's affine map with 8-point Gauss-Legendre on
+// sub-panels sized to the steepness; pass 2 scans the maps in order.  It also
+// gives Q = C(top) and N1 = int_mmin^top p(m1) S + int_top^mmax p(m1).
+// ---------------------------------------------------------------------------
+constexpr int kMassBS = 256;
+
+// ln S(m) for 0 < m' = m - mmin < delta_m: -softplus(dm/m' + dm/(m' - dm))
+__device__ __forceinline__ double ln_smooth(double mp, double dm) {
+  const double y = dm / mp + dm / (mp - dm);
+  return -(fmax(y, 0.0) + log1p(exp(-fabs(y))));
+}
+
+// ln f(m) = beta ln m + ln S(m), for m > mmin
+__device__ __forceinline__ double ln_fm(const LamParams& P, double m) {
+  const double mp = m - P.mmin;
+  return P.beta * log(m) + (mp >= P.dm ? 0.0 : ln_smooth(mp, P.dm));
+}
+
+// g'(m) = d ln f/dm = beta/m + (1 - S) (dm/m'^2 + dm/(m' - dm)^2), for m > mmin
+__device__ __forceinline__ double dln_fm(const LamParams& P, double m) {
+  const double mp = m - P.mmin;
+  if (mp >= P.dm) return P.beta / m;
+  const double y = P.dm / mp + P.dm / (mp - P.dm);
+  const double oms = 1.0 / (1.0 + exp(-y));
+  const double q = mp - P.dm;
+  return P.beta / m + (oms > 0.0 ? oms * (P.dm / (mp * mp) + P.dm / (q * q)) : 0.0);
+}
+
+__global__ __launch_bounds__(kMassBS) void k_mass_table(LamParams* __restrict__ Pv,
+                                                        double2* __restrict__ mtab) {
+  const int b = blockIdx.x;
+  LamParams P = Pv[b];
+  if (!(P.dm > 0.0) || P.flag) return;
+  double2* tab = mtab + (size_t)b * (kMassPanels + 1);
+  const double h = (P.sm_top - P.mmin) / (double)kMassPanels;
+  const double gx[4] = {0.18343464249564980494, 0.52553240991632898582, 0.79666647741362673959,
+                        0.96028985649753623168};
+  const double gw[4] = {0.36268378337836198297, 0.31370664587788728734, 0.22238103445337447054,
+                        0.10122853629037625915};
+  auto node = [&](int k) { return k == kMassPanels ? P.sm_top : P.mmin + (double)k * h; };
+  // pass 1: tab[k + 1] = (f(a)/f(b), int_a^b f/f(b)) of panel k = [a, b];
+  // and the smoothed primary's mass below top
+  double n1 = 0.0;
+  for (int k = threadIdx.x; k < kMassPanels; k += kMassBS) {
+    const double a = node(k), e = node(k + 1);
+    const double lb = ln_fm(P, e);
+    const double ratio = k == 0 ? 0.0 : exp(ln_fm(P, a) - lb);
+    const double steep = k == 0 ? 1e300 : dln_fm(P, a) * (e - a);
+    const int nsub = (int)fmin(fmax(ceil(steep * 0.25), 1.0), 32.0);
+    const double w = (e - a) / (double)nsub, half = 0.5 * w;
+    double acc = 0.0;
+    for (int j = 0; j < nsub; ++j) {
+      const double mid = a + ((double)j + 0.5) * w;
+      double sj = 0.0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        sj += gw[q] * (exp(ln_fm(P, mid - half * gx[q]) - lb) + exp(ln_fm(P, mid + half * gx[q]) - lb));
+      acc += sj * half;
+    }
+    tab[k + 1] = make_double2(ratio, acc);
+    const double mid = 0.5 * (a + e), hp = 0.5 * (e - a);
+    double sp = 0.0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const double x0 = mid - hp * gx[q], x1 = mid + hp * gx[q];
+      const double u0 = (x0 - P.mu) * P.inv_sigma, u1 = (x1 - P.mu) * P.inv_sigma;
+      const double p0 = P.pl_coef * exp(-P.alpha * log(x0)) + P.tg_coef * exp(-0.5 * u0 * u0);
+      const double p1 = P.pl_coef * exp(-P.alpha * log(x1)) + P.tg_coef * exp(-0.5 * u1 * u1);
+      sp += gw[q] * (p0 * smooth_edge(x0, P.mmin, P.dm) + p1 * smooth_edge(x1, P.mmin, P.dm));
+    }
+    n1 += sp * hp;
+  }
+  __syncthreads();
+  // pass 2: compose the maps of this thread's panels, in order
+  constexpr int per = kMassPanels / kMassBS;
+  const int k0 = threadIdx.x * per;
+  double A = 1.0, Bv = 0.0;          // R_end = A R_start + Bv
+#pragma unroll
+  for (int i = 0; i < per; ++i) {
+    const double2 m = tab[k0 + i + 1];
+    A *= m.x;
+    Bv = m.x * Bv + m.y;
+  }
+  // inclusive scan of the maps (earlier threads first), then this thread's start
+  __shared__ double sA[kMassBS / 64], sB[kMassBS / 64], sN[kMassBS / 64];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  double iA = A, iB = Bv;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const double pA = __shfl_up(iA, o, 64), pB = __shfl_up(iB, o, 64);
+    if (lane >= o) {
+      iB = iA * pB + iB;
+      iA = iA * pA;
+    }
+  }
+  const double n1w = wave_sum(n1);
+  if (lane == 63) { sA[wv] = iA; sB[wv] = iB; }
+  if (lane == 0) sN[wv] = n1w;
+  __syncthreads();
+  // R at this thread's first node: the scan of all earlier maps applied to R(mmin) = 0
+  double r0 = 0.0;
+  for (int i = 0; i < wv; ++i) r0 = sA[i] * r0 + sB[i];
+  const double eB = __shfl_up(iB, 1, 64), eA = __shfl_up(iA, 1, 64);
+  if (lane > 0) r0 = eA * r0 + eB;
+  double r = r0;
+  if (threadIdx.x == 0) tab[0] = make_double2(0.0, 0.0);
+#pragma unroll
+  for (int i = 0; i < per; ++i) {
+    const double2 m = tab[k0 + i + 1];
+    r = m.x * r + m.y;
+    const int k = k0 + i + 1;
+    tab[k] = make_double2(r, 1.0 - r * dln_fm(P, node(k)));
+  }
+  if (threadIdx.x == kMassBS - 1) {
+    double nb = 0.0;
+    for (int i = 0; i < kMassBS / 64; ++i) nb += sN[i];
+    // the unsmoothed mixture's mass on [top, mmax] in closed form
+    double tail = 0.0;
+    if (P.sm_top < P.mmax) {
+      const double a1 = 1.0 - P.alpha, lt = log(P.sm_top), lr = P.ln_mmax - lt;
+      const double pl = a1 == 0.0 ? lr : exp(a1 * lt) * expm1(a1 * lr) / a1;
+      const double z = ndtr_diff((P.mmin - P.mu) / P.sigma, (P.mmax - P.mu) / P.sigma);
+      tail = P.pl_coef * pl +
+             P.lg * ndtr_diff((P.sm_top - P.mu) / P.sigma, (P.mmax - P.mu) / P.sigma) / z;
+    }
+    const double n1v = nb + tail;
+    P.sm_h = h;
+    P.sm_q = r * exp(ln_fm(P, P.sm_top));
+    P.sm_n1inv = 1.0 / n1v;
+    if (!(P.sm_q > 0.0) || !(n1v > 0.0) || !isfinite(P.sm_q)) P.flag = kFlagDomain;
+    Pv[b] = P;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -327,8 +478,13 @@ __global__ __launch_bounds__(kSelBS) void k_selection(SelArgs a) {
     const double z = expm1(x);
     const double m1 = a.m1d[j] / zp1, m2 = a.m2d[j] / zp1;
     const double l1 = a.lnm1d[j] - x, l2 = a.lnm2d[j] - x;
-    const double w = F32 ? (double)mass_weight32(P, m1, m2, l1, l2)
-                         : mass_weight64(P, m1, m2, l1, l2);
+    double w;
+    if (P.dm > 0.0) {
+      w = mass_weight_smoothed(P, a.mtab + (size_t)b * (kMassPanels + 1), m1, m2, l1, l2);
+      if (F32) w = (double)(float)w;
+    } else {
+      w = F32 ? (double)mass_weight32(P, m1, m2, l1, l2) : mass_weight64(P, m1, m2, l1, l2);
+    }
     if (w == 0.0) continue;
     // n_tot(z) by linear interpolation on the grid, 0 outside
     const double* ntot = a.ntot + (size_t)b * a.ntot_stride;
@@ -414,11 +570,15 @@ __global__ __launch_bounds__(kFinBS) void k_lnl_final(const LamParams* __restric
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-hipError_t launch_tables(const double* lam, int B, const Geometry& g, LamParams* P,
-                         double2* chi, double2* inv, double2* dtab, double* gz64, float* gz32,
-                         int* flag_mono, int* flag_range, hipStream_t st) {
-  k_lam_prepare<<<(B + 63) / 64, 64, 0, st>>>(lam, B, P);
+hipError_t launch_tables(const double* lam, int stride, int B, const Geometry& g, LamParams* P,
+                         double2* mtab, double2* chi, double2* inv, double2* dtab, double* gz64,
+                         float* gz32, int* flag_mono, int* flag_range, hipStream_t st) {
+  k_lam_prepare<<<(B + 63) / 64, 64, 0, st>>>(lam, stride, B, P);
   CH_LAUNCH_CHECK();
+  if (mtab) {
+    k_mass_table<<<B, kMassBS, 0, st>>>(P, mtab);
+    CH_LAUNCH_CHECK();
+  }
   k_x_table<0><<<B, kTabBS, 0, st>>>(P, g, chi, flag_mono);
   CH_LAUNCH_CHECK();
   const long long ni = (long long)B * g.n_u;

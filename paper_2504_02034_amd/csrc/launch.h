@@ -44,6 +44,7 @@ struct SelArgs {
   Geometry g;
   const double* ntot;       // [n_z], or [B][n_z] when ntot_stride = n_z (incompleteness)
   long long ntot_stride;
+  const double2* mtab;      // [B][kMassPanels + 1] smoothed-edge tables (delta_m > 0)
   const double* dl;
   const double* lndl;
   const double* m1d;
@@ -91,6 +92,7 @@ struct EventArgs {
   const double2* chi;
   const double2* inv;
   const double2* dtab;      // [B][n_t] (d_L^gw, dd_L^gw/dx) on the x nodes
+  const double2* mtab;      // [B][kMassPanels + 1] smoothed-edge tables (delta_m > 0)
   Geometry g;
   const double* gz64;
   const float* gz32;
@@ -176,9 +178,11 @@ hipError_t launch_events(const EventArgs& a, const EventArgs& kern, bool f32, hi
 constexpr size_t kStaticScratchBytes = size_t(256) << 20;
 hipError_t static_scratch_address(void** ptr);
 
-hipError_t launch_tables(const double* lam, int B, const Geometry& g, LamParams* P, double2* chi,
-                         double2* inv, double2* dtab, double* gz64, float* gz32, int* flag_mono,
-                         int* flag_range, hipStream_t st);
+// lam rows of `stride` entries (kNlam, or kNlam + 1 with delta_m); mtab
+// [B][kMassPanels + 1] when any point may carry delta_m > 0, else null
+hipError_t launch_tables(const double* lam, int stride, int B, const Geometry& g, LamParams* P,
+                         double2* mtab, double2* chi, double2* inv, double2* dtab, double* gz64,
+                         float* gz32, int* flag_mono, int* flag_range, hipStream_t st);
 hipError_t launch_selection(const SelArgs& a, bool f32, double* ln_xi, double* neff,
                             hipStream_t st);
 hipError_t launch_lnl_final(const LamParams* P, const int* flag_mono, const int* flag_range,

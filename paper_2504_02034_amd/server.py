@@ -1,6 +1,6 @@
 """Continuous-batching server for ln L requests from many concurrent samplers.
 
-submit(events, lam [B, 14], prec) -> Ticket; wait(ticket) -> ln L [B];
+submit(events, lam [B, width], prec) -> Ticket; wait(ticket) -> ln L [B];
 stats() -> evals/s, p50 / p99 latency and admission figures.
 
 The event sets, the catalogue and the injections stay resident in the
@@ -71,9 +71,10 @@ class HipExecutor:
     class Worker:
         def __init__(self, torch, max_fused):
             self.stream = torch.cuda.Stream()
-            self.lam_h = torch.empty((max_fused, 14), dtype=torch.float64, pin_memory=True)
+            # flat, so that [B, width] views are contiguous for either lambda width
+            self.lam_h = torch.empty(max_fused * 15, dtype=torch.float64, pin_memory=True)
             self.out_h = torch.empty(max_fused, dtype=torch.float64, pin_memory=True)
-            self.lam_d = torch.empty((max_fused, 14), dtype=torch.float64, device="cuda")
+            self.lam_d = torch.empty(max_fused * 15, dtype=torch.float64, device="cuda")
             self.out_d = torch.empty(max_fused, dtype=torch.float64, device="cuda")
             self.done = torch.cuda.Event()
 
@@ -82,6 +83,11 @@ class HipExecutor:
         self.torch = torch
         self.ctx = ctx
         self.max_fused = max_fused
+
+    @property
+    def lam_width(self) -> int:
+        """Entries per lambda row (14, or 15 with the smoothed mass edge)."""
+        return self.ctx.lam_width
 
     def new_worker(self):
         return HipExecutor.Worker(self.torch, self.max_fused)
@@ -95,12 +101,13 @@ class HipExecutor:
 
     def run(self, worker, events, lam, prec) -> np.ndarray:
         torch = self.torch
-        B = lam.shape[0]
-        worker.lam_h[:B].copy_(torch.from_numpy(lam))
+        B, W = lam.shape
+        lam_h = worker.lam_h[:B * W].view(B, W)
+        lam_d = worker.lam_d[:B * W].view(B, W)
+        lam_h.copy_(torch.from_numpy(lam))
         with torch.cuda.stream(worker.stream):
-            worker.lam_d[:B].copy_(worker.lam_h[:B], non_blocking=True)
-            self.ctx.lnl(events, worker.lam_d[:B], prec, lnl=worker.out_d[:B],
-                         stream=worker.stream)
+            lam_d.copy_(lam_h, non_blocking=True)
+            self.ctx.lnl(events, lam_d, prec, lnl=worker.out_d[:B], stream=worker.stream)
             worker.out_h[:B].copy_(worker.out_d[:B], non_blocking=True)
             worker.done.record(worker.stream)
         worker.done.synchronize()
@@ -150,8 +157,9 @@ class Server:
     # ------------------------------------------------------------------
     def submit(self, events, lam, prec: int = 0) -> Ticket:
         lam = np.ascontiguousarray(np.atleast_2d(lam), dtype=np.float64)
-        if lam.ndim != 2 or lam.shape[1] != 14 or lam.shape[0] < 1:
-            raise ValueError("lam must be [B, 14] with B >= 1")
+        width = getattr(self.ex, "lam_width", 14)
+        if lam.ndim != 2 or lam.shape[1] != width or lam.shape[0] < 1:
+            raise ValueError(f"lam must be [B, {width}] with B >= 1")
         if lam.shape[0] > self.max_fused:
             raise ValueError(f"B = {lam.shape[0]} exceeds max_fused = {self.max_fused}")
         need = self.ex.scratch_bytes(events, lam.shape[0], prec)

@@ -1,0 +1,140 @@
+"""The smoothed lower mass edge (Table 1's delta_m) through the C-ABI
+(chimera_set_mass_smoothing) against the oracle: ln L, ln I_i and ln xi at
+1e-10 (FP64) with delta_m from a narrow edge to one wider than [mmin, mmax],
+FP32 within 1e-3, delta_m = 0 bitwise equal to the 14-entry path, the
+allocation-free entry point, the lambda-width check and the refusals."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2504_02034_amd import synth
+
+pytestmark = pytest.mark.gpu
+REL64 = 1e-10
+
+
+def close(a, b, rel):
+    if math.isnan(b):
+        return math.isnan(a)
+    if math.isinf(b):
+        return a == b
+    return abs(a - b) <= rel * max(1.0, abs(b))
+
+
+@pytest.fixture(scope="module")
+def setup(small_data):
+    from paper_2504_02034_amd import chimera, prep
+    d = small_data
+    ctx, many = chimera.context_from_prepared(d.prep, d.inj)
+    s1d = ctx.add_prepared_single1d(prep.single1d(d.prep, d.ev))
+    lam = synth.make_lambdas(synth.WORKLOADS["precision_300ev"], batch=6, child=321)
+    lam[0] = synth.LAMBDA_TRUTH
+    lam[4] = synth.LAMBDA_TRUTH
+    lam[5] = synth.LAMBDA_TRUTH
+    lam[5, 7] = 40.0                     # mmax inside mmin + delta_m
+    lam15 = np.column_stack([lam, [4.8, 2.0, 0.0, 10.0, 0.0, 60.0]])
+    plain = {k: ctx.lnl(ev, lam, chimera.CHIMERA_FP64, with_lnI=True)
+             for k, ev in (("many1d", many), ("single1d", s1d))}
+    plain_xi = ctx.selection(lam, chimera.CHIMERA_FP64)
+    ctx.set_mass_smoothing(True)
+    yield d, chimera, ctx, {"many1d": many, "single1d": s1d}, lam, lam15, plain, plain_xi
+    ctx.close()
+
+
+@pytest.mark.parametrize("kernel", ["many1d", "single1d"])
+def test_matches_oracle(setup, kernel):
+    import oracle
+    d, chimera, ctx, sets, lam, lam15, plain, plain_xi = setup
+    assert ctx.lam_width == 15
+    lnl, lnI = ctx.lnl(sets[kernel], lam15, chimera.CHIMERA_FP64, with_lnI=True)
+    l32 = ctx.lnl(sets[kernel], lam15, chimera.CHIMERA_FP32)
+    fin = np.isfinite(lnl)
+    assert fin.sum() >= 4 and np.array_equal(np.isfinite(l32), fin)
+    assert np.max(np.abs(l32[fin] - lnl[fin])) <= 1e-3
+    # the smoothing changes the values where delta_m > 0
+    sm = (lam15[:, 14] > 0) & fin
+    assert np.all(np.abs(lnl[sm] - plain[kernel][0][sm]) > 1e-3)
+    for b in range(lam15.shape[0]):
+        ref = oracle.likelihood.lnl(d.o_events, d.o_cat, d.o_inj, lam15[b], T=8.6, kernel=kernel)
+        assert close(lnl[b], ref["lnl"], REL64), (b, lnl[b], ref["lnl"])
+        for i in range(lnI.shape[1]):
+            assert close(lnI[b, i], ref["lnI"][i], REL64), (b, i, lnI[b, i], ref["lnI"][i])
+
+
+def test_selection_matches_oracle(setup):
+    import oracle
+    d, chimera, ctx, sets, lam, lam15, plain, plain_xi = setup
+    lx, ne = ctx.selection(lam15, chimera.CHIMERA_FP64)
+    for b in range(lam15.shape[0]):
+        xi, neff, _ = oracle.likelihood.selection(d.o_inj, d.o_cat, lam15[b])
+        if xi > 0 and np.isfinite(lx[b]):
+            assert abs(lx[b] - math.log(xi)) <= 1e-11 * max(1.0, abs(math.log(xi))), b
+            assert abs(ne[b] - neff) <= 1e-9 * neff, b
+        else:
+            assert not np.isfinite(lx[b]) or not xi > 0, b
+
+
+def test_zero_delta_m_is_the_unsmoothed_path_bitwise(setup):
+    d, chimera, ctx, sets, lam, lam15, plain, plain_xi = setup
+    zero = lam15[:, 14] == 0.0
+    assert zero.sum() >= 2
+    for k, ev in sets.items():
+        lnl, lnI = ctx.lnl(ev, lam15, chimera.CHIMERA_FP64, with_lnI=True)
+        assert np.array_equal(lnl[zero], plain[k][0][zero], equal_nan=True), k
+        assert np.array_equal(lnI[zero], plain[k][1][zero], equal_nan=True), k
+    lx, ne = ctx.selection(lam15, chimera.CHIMERA_FP64)
+    assert np.array_equal(lx[zero], plain_xi[0][zero], equal_nan=True)
+
+
+def test_static_entry_point_and_device_batch(setup):
+    import torch
+    d, chimera, ctx, sets, lam, lam15, plain, plain_xi = setup
+    t = torch.from_numpy(lam15).cuda()
+    for prec in (chimera.CHIMERA_FP32, chimera.CHIMERA_FP64):
+        want = ctx.lnl(sets["many1d"], lam15, prec)
+        dev = chimera.chimera_lnl_batch(ctx.handle, sets["many1d"].handle, t, prec)
+        got = chimera.chimera_lnl_batch_static(ctx.handle, sets["many1d"].handle, t, prec)
+        torch.cuda.synchronize()
+        assert np.array_equal(dev.cpu().numpy(), want, equal_nan=True)
+        assert np.array_equal(got.cpu().numpy(), want, equal_nan=True)
+
+
+def test_domain_width_and_refusals(setup):
+    d, chimera, ctx, sets, lam, lam15, plain, plain_xi = setup
+    bad = lam15[:2].copy()
+    bad[0, 14] = -1.0
+    bad[1, 14] = np.nan
+    assert np.all(ctx.lnl(sets["many1d"], bad, chimera.CHIMERA_FP64) == -np.inf)
+    with pytest.raises(ValueError):
+        ctx.lnl(sets["many1d"], lam, chimera.CHIMERA_FP64)      # 14 entries on a 15-wide context
+    with pytest.raises(chimera.ChimeraError) as ex:
+        ctx.lnl_grad(sets["many1d"], lam15[:2], chimera.CHIMERA_FP64)
+    assert ex.value.status == chimera.CHIMERA_EINVAL
+    with pytest.raises(chimera.ChimeraError) as ex:
+        chimera._check(chimera.lib.chimera_set_mass_smoothing(ctx.handle, 2))
+    assert ex.value.status == chimera.CHIMERA_EINVAL
+    assert ctx.lam_width == 15
+    ctx.set_mass_smoothing(False)
+    try:
+        assert ctx.lam_width == 14
+        lnl = ctx.lnl(sets["many1d"], lam, chimera.CHIMERA_FP64)
+        assert np.array_equal(lnl, plain["many1d"][0], equal_nan=True)
+        ctx.lnl_grad(sets["many1d"], lam[:2], chimera.CHIMERA_FP64)
+    finally:
+        ctx.set_mass_smoothing(True)
+
+
+def test_wide_edge_deep_in_the_smoothed_range(setup):
+    """delta_m = 95 (wider than [mmin, mmax]): every sample sits inside the
+    smoothed range, and the lightest event's ln I_i is about -137, carried by
+    samples whose S(m) is ~1e-40; FP64 still matches the oracle per event."""
+    import oracle
+    d, chimera, ctx, sets, lam, lam15, plain, plain_xi = setup
+    row = np.append(synth.LAMBDA_TRUTH, 95.0)[None, :]
+    lnl, lnI = ctx.lnl(sets["many1d"], row, chimera.CHIMERA_FP64, with_lnI=True)
+    ref = oracle.likelihood.lnl(d.o_events, d.o_cat, d.o_inj, row[0], T=8.6)
+    assert np.isfinite(ref["lnl"]) and min(ref["lnI"]) < -100.0
+    assert close(lnl[0], ref["lnl"], REL64), (lnl[0], ref["lnl"])
+    for i in range(lnI.shape[1]):
+        assert close(lnI[0, i], ref["lnI"][i], REL64), (i, lnI[0, i], ref["lnI"][i])
