@@ -275,6 +275,54 @@ def variants_bench(ctx, es, p, ev, lam_t, many, steps, warmup):
     return out
 
 
+def population_bench(ctx, es, wl, p, lam_t, many, steps, warmup):
+    """The many-1D Gaussian step with the paper-complete population and
+    catalogue options on the bench batch: an incomplete catalogue (the
+    generator's synthetic completeness), the smoothed lower mass edge with
+    delta_m per point drawn from Table 1's prior U(0.01, 10), and both; ms per
+    step and the main kernels' times in both precisions, FP32 vs FP64
+    |Delta ln L|, and the cost over the plain step."""
+    import numpy as np
+    import torch
+
+    from paper_2504_02034_amd import chimera, synth
+    grid = np.linspace(wl.z_lo, wl.z_hi, wl.n_z)
+    p_rows, missing = synth.make_completeness(p.row_pix, wl.nside, grid)
+    rng = np.random.default_rng(np.random.SeedSequence([250402034, 77]))
+    dm = torch.from_numpy(rng.uniform(0.01, 10.0, lam_t.shape[0])).to(lam_t.device)
+    lam15 = torch.cat([lam_t, dm[:, None]], dim=1).contiguous()
+    out = []
+    for name in ("completeness", "mass_smoothing", "both"):
+        if name != "mass_smoothing":
+            ctx.set_completeness(p_rows, missing)
+        if name != "completeness":
+            ctx.set_mass_smoothing(True)
+        lam_v = lam15 if name != "completeness" else lam_t
+        r = {"option": name, "batch": int(lam_v.shape[0])}
+        vals = {}
+        try:
+            for prec_name, prec in (("fp64", chimera.CHIMERA_FP64), ("fp32", chimera.CHIMERA_FP32)):
+                o, wall, lat, n, ms, evals = time_precision(ctx, es, lam_v, prec, steps, warmup)
+                vals[prec_name] = o
+                r[prec_name] = {"value": round(lam_v.shape[0] * steps / wall, 2),
+                                "ms_per_step": round(wall / steps * 1e3, 4),
+                                "smooth_kernel_ms": round(ms / max(n, 1), 4),
+                                "over_plain": round(wall / many[prec_name]["wall"], 4)}
+                log(f"{name} {prec_name}: {wall / steps * 1e3:.2f} ms/step "
+                    f"({wall / many[prec_name]['wall']:.3f} x plain)")
+        finally:
+            ctx.set_completeness(None)
+            ctx.set_mass_smoothing(False)
+        fin = np.isfinite(vals["fp64"]) & np.isfinite(vals["fp32"])
+        r["abs_dlnL_fp32_vs_fp64"] = {
+            "max": float(np.max(np.abs(vals["fp32"][fin] - vals["fp64"][fin]))) if fin.any() else None,
+            "same_finite_mask": bool(np.array_equal(np.isfinite(vals["fp32"]),
+                                                    np.isfinite(vals["fp64"]))),
+            "finite_points": int(fin.sum())}
+        out.append(r)
+    return out
+
+
 def serve_bench(wl, cf, inj, n_requests=300, seed=5, max_pass_s=0.05):
     """Serving: resident event sets of 50, 300, 1000 and 3000 distinct events
     x 4096 samples (nested subsets of one generated set of 3000) sharing the
@@ -470,6 +518,8 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-grad", action="store_true")
     ap.add_argument("--no-photo", action="store_true")
+    ap.add_argument("--no-population", action="store_true",
+                    help="skip the incomplete-catalogue and smoothed-mass-edge steps")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the single-1D, Epanechnikov and binned kernels")
     ap.add_argument("--photo-one", action="store_true",
@@ -566,6 +616,9 @@ def main():
     if not args.no_variants:
         line["kernel_variants"] = variants_bench(ctx, es, p, ev, lam_t, res, args.steps,
                                                  args.warmup)
+    if not args.no_population:
+        line["population_variants"] = population_bench(ctx, es, wl, p, lam_t, res, args.steps,
+                                                       args.warmup)
     ctx.close()
     if not args.no_serve:
         line["serving"] = serve_bench(wl, cf, inj)

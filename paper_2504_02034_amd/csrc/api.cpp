@@ -315,6 +315,7 @@ struct Scratch {
   double* gzb64;
   float* gzb32;
   double2* mtab;
+  double* wscale;
 };
 
 // Lay out (or size, when base is null) the scratch of one call.
@@ -339,6 +340,8 @@ size_t carve(Carve& cv, Scratch& s, const Geometry& g, int64_t B, int nchunk, bo
   s.partial = cv.take<double>((size_t)B * std::max(nchunk, 1) * 2);
   s.lam = need_lam ? cv.take<double>((size_t)B * nlam) : nullptr;
   s.mtab = nlam > CHIMERA_NLAM ? cv.take<double2>((size_t)B * (kMassPanels + 1)) : nullptr;
+  s.wscale = nlam > CHIMERA_NLAM && f32 && S ? cv.take<double>((size_t)B * std::max(E, 1))
+                                             : nullptr;
   s.lnI = need_lnI ? cv.take<double>((size_t)B * std::max(E, 1)) : nullptr;
   s.ln_xi = cv.take<double>(B);
   s.neff = cv.take<double>(B);
@@ -1317,6 +1320,7 @@ static chimera_status run_chunk(chimera_ctx* ctx, const chimera_events* ev, cons
     a.P = s.P; a.flag_mono = s.flag_mono; a.flag_range = s.flag_range;
     a.chi = s.chi; a.inv = s.inv; a.dtab = s.dtab; a.g = g; a.gz64 = s.gz64; a.gz32 = s.gz32;
     a.mtab = s.mtab;
+    a.wscale = s.wscale;
     a.nz64 = rows64(ctx, ev); a.nz32 = rows32(ctx, ev);
     a.mz64 = miss64(ctx, ev); a.mz32 = miss32(ctx, ev);
     a.gzb64 = s.gzb64; a.gzb32 = s.gzb32;

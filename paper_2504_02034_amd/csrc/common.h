@@ -8,6 +8,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace chimera {
 
 constexpr double kCkms = 299792.458;   // speed of light [km/s]
@@ -32,6 +34,8 @@ struct LamParams {
   // and p(m2|m1), renormalised: 1/N1, Q = int_mmin^top m^beta S dm, the edge
   // mmin + delta_m and its log, top = min(mmax, edge), the table's node step
   double dm, sm_n1inv, sm_q, sm_edge, ln_edge, sm_top, sm_h;
+  double sm_pl;     // edge^(1+beta) / (1+beta) (1 at beta = -1): the power law past the edge
+  double sm_lnq, sm_lnn1inv;   // ln Q, ln(1/N1)
   int flag;         // kFlagDomain
   int pad;
 };
@@ -125,7 +129,7 @@ __device__ __forceinline__ double invert_x(const LamParams& P, const double2* __
 // p(m1) p(m2|m1) with uniform PE priors).  FP64 path: inverse table + one
 // Newton step on the d_L^gw node table, whose e^x update reuses the
 // exponential; FP32 path: inverse table only and the mass model in FP32.
-template <bool F32>
+template <bool F32, bool SM = false, bool LOGW = false>
 __device__ __forceinline__ void sample_zw(const LamParams& P, const double2* __restrict__ dtab,
                                           const double2* __restrict__ inv, const Geometry& g,
                                           double d, double lnd, double m1d, double m2d,
@@ -141,32 +145,89 @@ __device__ __forceinline__ double smooth_edge(double m, double mmin, double dm) 
   return 1.0 / (exp(dm / mp + dm / (mp - dm)) + 1.0);
 }
 
-// p(m1) p(m2|m1) with the smoothed edge (FP64 in both precisions): the
-// unsmoothed mixture times S(m1) / N1, times m2^beta S(m2) over
-// C(m1) = int_mmin^m1 m^beta S dm.  From the edge on, C = Q + the plain power
-// law; below it C = R m1^beta S(m1), whose S(m1) cancels against p(m1)'s, with
-// R(m1) the cubic Hermite of the per-lambda node table (R, dR/dm).
+// p(m1) p(m2|m1) with the smoothed edge: the unsmoothed mixture times
+// S(m1) / N1, times m2^beta S(m2) over C(m1) = int_mmin^m1 m^beta S dm.  From
+// the edge on, C = Q + the plain power law; below it C = R m1^beta S(m1), whose
+// S(m1) cancels against p(m1)'s, with R(m1) the cubic Hermite of the
+// per-lambda node table (R, dR/dm).  S(m2) = 1 / (1 + e^y) enters through one
+// final division.  The masses, the exponent y and the table in FP64; in FP32
+// mode the exponentials and the last products in FP32 (a weight whose e^y
+// overflows FP32 is below FP32's range and gives 0).
+template <bool F32>
 __device__ __forceinline__ double mass_weight_smoothed(const LamParams& P,
                                                        const double2* __restrict__ mt, double m1,
                                                        double m2, double l1, double l2) {
   if (!(m1 >= P.mmin && m1 <= P.mmax && m2 >= P.mmin && m2 <= m1 && m1 > P.mmin)) return 0.0;
-  const double s2 = smooth_edge(m2, P.mmin, P.dm);
-  if (!(s2 > 0.0)) return 0.0;
-  const double u = (m1 - P.mu) * P.inv_sigma;
-  const double p1 = (P.pl_coef * exp(-P.alpha * l1) + P.tg_coef * exp(-0.5 * u * u)) * P.sm_n1inv;
-  if (m1 >= P.sm_edge) {
-    const double d = l1 - P.ln_edge;
-    const double pl = P.a2 == 0.0 ? d : exp(P.a2 * P.ln_edge) * expm1(P.a2 * d) / P.a2;
-    return p1 * exp(P.beta * l2) * s2 / (P.sm_q + pl);
+  using T = typename std::conditional<F32, float, double>::type;
+  const double mp = m2 - P.mmin;
+  T ey = (T)0;                                  // e^y of S(m2) = 1 / (1 + e^y)
+  if (mp < P.dm) {
+    if (!(mp > 0.0)) return 0.0;
+    const double y = P.dm * (2.0 * mp - P.dm) / (mp * (mp - P.dm));
+    ey = F32 ? __expf((float)y) : (T)exp(y);
+    if (!(ey < (T)INFINITY)) return 0.0;
   }
-  const double pos = (m1 - P.mmin) / P.sm_h;
-  const int k = (int)fmin(fmax(pos, 0.0), (double)(kMassPanels - 1));
-  const double t = pos - (double)k;
-  const double2 a = mt[k], b = mt[k + 1];
-  const double d = b.x - a.x, s0 = a.y * P.sm_h, s1 = b.y * P.sm_h;
-  const double r = a.x + t * (s0 + t * ((3.0 * d - 2.0 * s0 - s1) + t * (s0 + s1 - 2.0 * d)));
-  if (!(r > 0.0)) return 0.0;
-  return p1 * exp(P.beta * (l2 - l1)) * s2 / r;
+  const bool past = m1 >= P.sm_edge;
+  const T lead = (T)(past ? P.beta * l2 : P.beta * (l2 - l1));
+  const T u = (T)((m1 - P.mu) * P.inv_sigma);
+  const T al1 = (T)(P.alpha * l1);
+  T num;
+  if (F32)
+    num = (T)P.pl_coef * __expf(lead - al1) + (T)P.tg_coef * __expf(lead - (T)0.5 * u * u);
+  else
+    num = (T)P.pl_coef * exp(lead - al1) + (T)P.tg_coef * exp(lead - (T)0.5 * u * u);
+  T c;
+  if (past) {
+    const double d = l1 - P.ln_edge;
+    c = (T)P.sm_q + (P.a2 == 0.0 ? (T)d
+                                  : (T)P.sm_pl * (F32 ? expm1f((float)(P.a2 * d)) : (T)expm1(P.a2 * d)));
+  } else {
+    const double pos = (m1 - P.mmin) / P.sm_h;
+    const int k = (int)fmin(fmax(pos, 0.0), (double)(kMassPanels - 1));
+    const double t = pos - (double)k;
+    const double2 a = mt[k], b = mt[k + 1];
+    const double dd = b.x - a.x, s0 = a.y * P.sm_h, s1 = b.y * P.sm_h;
+    const double r = a.x + t * (s0 + t * ((3.0 * dd - 2.0 * s0 - s1) + t * (s0 + s1 - 2.0 * dd)));
+    if (!(r > 0.0)) return 0.0;
+    c = (T)r;
+    if (!(c > (T)0)) return 0.0;
+  }
+  return (double)(num * (T)P.sm_n1inv / (((T)1 + ey) * c));
+}
+
+// ln of the smoothed weight in FP32 (-inf for 0), so that an FP32 caller can
+// scale an event's weights before they leave FP32's range.  Past the edge
+// both the numerator and C carry the factor m1^-(1+beta), which keeps C near
+// 1/(1+beta): C m1^-(1+beta) = Q m1^-(1+beta) - expm1(-(1+beta) d)/(1+beta).
+__device__ __forceinline__ float lnw_smoothed32(const LamParams& P, const double2* __restrict__ mt,
+                                                double m1, double m2, double l1, double l2) {
+  if (!(m1 >= P.mmin && m1 <= P.mmax && m2 >= P.mmin && m2 <= m1 && m1 > P.mmin)) return -INFINITY;
+  const double mp = m2 - P.mmin;
+  float sp = 0.0f;                              // ln(1 + e^y) = -ln S(m2)
+  if (mp < P.dm) {
+    if (!(mp > 0.0)) return -INFINITY;
+    const float y = (float)(P.dm * (2.0 * mp - P.dm) / (mp * (mp - P.dm)));
+    sp = fmaxf(y, 0.0f) + log1pf(__expf(-fabsf(y)));
+  }
+  const bool past = m1 >= P.sm_edge;
+  const float lead = (float)(past ? P.beta * l2 - P.a2 * l1 : P.beta * (l2 - l1));
+  const float u = (float)((m1 - P.mu) * P.inv_sigma);
+  const float al1 = (float)(P.alpha * l1);
+  const float num = (float)P.pl_coef * __expf(lead - al1) + (float)P.tg_coef * __expf(lead - 0.5f * u * u);
+  float c;
+  if (past) {
+    const float d = (float)(l1 - P.ln_edge), a2 = (float)P.a2;
+    c = __expf((float)(P.sm_lnq - P.a2 * l1)) + (P.a2 == 0.0 ? d : -expm1f(-a2 * d) / a2);
+  } else {
+    const double pos = (m1 - P.mmin) / P.sm_h;
+    const int k = (int)fmin(fmax(pos, 0.0), (double)(kMassPanels - 1));
+    const double t = pos - (double)k;
+    const double2 a = mt[k], b = mt[k + 1];
+    const double dd = b.x - a.x, s0 = a.y * P.sm_h, s1 = b.y * P.sm_h;
+    c = (float)(a.x + t * (s0 + t * ((3.0 * dd - 2.0 * s0 - s1) + t * (s0 + s1 - 2.0 * dd))));
+  }
+  if (!(num > 0.0f && c > 0.0f)) return -INFINITY;
+  return __logf(num) - __logf(c) - sp + (float)P.sm_lnn1inv;
 }
 
 // p(m1) p(m2|m1) of the source-frame masses; 0 outside
@@ -199,7 +260,9 @@ __device__ __forceinline__ float mass_weight32(const LamParams& P, double m1, do
   return a2 * num / -expm1f(a2 * ((float)P.ln_mmin - l1));
 }
 
-template <bool F32>
+// SM: the point may carry the smoothed mass edge; LOGW (FP32, delta_m > 0):
+// w is the weight's log from lnw_smoothed32
+template <bool F32, bool SM, bool LOGW>
 __device__ __forceinline__ void sample_zw(const LamParams& P, const double2* __restrict__ dtab,
                                           const double2* __restrict__ inv, const Geometry& g,
                                           double d, double lnd, double m1d, double m2d,
@@ -218,9 +281,12 @@ __device__ __forceinline__ void sample_zw(const LamParams& P, const double2* __r
   const double r = 1.0 / zp1;
   const double m1 = m1d * r, m2 = m2d * r;
   const double l1 = lnm1d - x, l2 = lnm2d - x;
-  if (P.dm > 0.0) {
-    const double ws = mass_weight_smoothed(P, mt, m1, m2, l1, l2);
-    w = F32 ? (double)(float)ws : ws;
+  if (LOGW) {
+    w = (double)lnw_smoothed32(P, mt, m1, m2, l1, l2);
+    return;
+  }
+  if (SM && P.dm > 0.0) {
+    w = mass_weight_smoothed<F32>(P, mt, m1, m2, l1, l2);
     return;
   }
   w = F32 ? (double)mass_weight32(P, m1, m2, l1, l2) : mass_weight64(P, m1, m2, l1, l2);

@@ -144,7 +144,20 @@ __device__ __forceinline__ void horner_masked(A (&acc)[K], const A (&rho)[K], co
 }  // namespace
 
 // ---------------------------------------------------------------------------
-template <bool F32>
+// SM: the batch may carry the smoothed mass edge (a separate instance keeps
+// the plain one's registers).  The smoothed edge can put an event's weights,
+// or its sums, below FP32's range.  So in FP32 mode with delta_m > 0 the
+// weights are formed as logs and stored as e^(ln w - L), L per (event,
+// lambda): kLogHead32 above the largest log-weight L0 of the threads' first
+// samples, so that weights up to e^(80 + kLogHead32) times those fit and
+// ones more than e^(87 - kLogHead32) below them leave (they count only if
+// every heavier sample's kernel sum is 0).  If a weight comes within e^18 of
+// FP32's top, or all lie more than e^kLogHead32 below L0 (no first sample
+// had weight), the event is transformed again with its largest weight at 1.
+// L goes to wscale for k_event_final (0 elsewhere).
+constexpr float kLogHead32 = 10.0f;
+
+template <bool F32, bool SM>
 __global__ __launch_bounds__(kZwBS) void k_event_zw(EventArgs a) {
   int e, b;
   if (!decode_item_lambda(a.E, a.B, e, b)) return;
@@ -173,17 +186,7 @@ __global__ __launch_bounds__(kZwBS) void k_event_zw(EventArgs a) {
     v[1] = a.lndl[q]; v[2] = a.m1d[q];
     v[3] = a.m2d[q]; v[4] = a.lnm1d[q]; v[5] = a.lnm2d[q];
   };
-  double cur[6];
-  in(threadIdx.x, cur);
-  for (int j = threadIdx.x; j < ns; j += kZwBS) {
-    double nxt[6];
-    in(j + kZwBS, nxt);
-    double z, w;
-    sample_zw<F32>(P, dtab, inv, a.g, cur[0], cur[1], cur[2], cur[3], cur[4], cur[5], z, w,
-                   mt);
-#pragma unroll
-    for (int i = 0; i < 6; ++i) cur[i] = nxt[i];
-    const CT wc = (CT)w;
+  auto put = [&](int j, double z, CT wc) {
     zb[j] = z;
     wb[j] = wc;
     const double wd = (double)wc, t = z - s;
@@ -191,6 +194,65 @@ __global__ __launch_bounds__(kZwBS) void k_event_zw(EventArgs a) {
     m[1] += wd * wd;
     m[2] += wd * t;
     m[3] += wd * t * t;
+  };
+  double cur[6];
+  in(threadIdx.x, cur);
+  if constexpr (F32 && SM) {
+    if (P.dm > 0.0) {
+      auto lw_of = [&](const double (&v)[6], double& z) {
+        double lw;
+        sample_zw<true, true, true>(P, dtab, inv, a.g, v[0], v[1], v[2], v[3], v[4], v[5], z, lw,
+                                    mt);
+        return (float)lw;
+      };
+      double z0 = 0.0;
+      const float l0 = threadIdx.x < ns ? lw_of(cur, z0) : -INFINITY;
+      float L0 = (float)block_max<kZwBS>((double)l0, red);
+      if (!(L0 > -INFINITY)) L0 = 0.0f;
+      float L = L0 + kLogHead32;
+      float top = l0 - L0;                      // the largest ln w - L0 seen
+      if (threadIdx.x < ns) put(threadIdx.x, z0, __expf(fminf(l0 - L, 80.0f)));
+      in(threadIdx.x + kZwBS, cur);
+      for (int j = threadIdx.x + kZwBS; j < ns; j += kZwBS) {
+        double nxt[6];
+        in(j + kZwBS, nxt);
+        double z;
+        const float lw = lw_of(cur, z);
+#pragma unroll
+        for (int i = 0; i < 6; ++i) cur[i] = nxt[i];
+        top = fmaxf(top, lw - L0);
+        put(j, z, __expf(fminf(lw - L, 80.0f)));
+      }
+      const float M = (float)block_max<kZwBS>((double)top, red);
+      if (M > -INFINITY && (M > 70.0f + kLogHead32 || M < -kLogHead32)) {
+        // a weight near FP32's top, or all far below the first samples': again
+        // with the largest weight at 1
+        L = L0 + M;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) m[i] = 0.0;
+        for (int j = threadIdx.x; j < ns; j += kZwBS) {
+          double v[6], z;
+          in(j, v);
+          const float lw = lw_of(v, z);
+          put(j, z, __expf(lw - L));
+        }
+      }
+      if (threadIdx.x == 0) a.wscale[(size_t)b * a.E + e] = (double)L;
+    } else {
+      if (threadIdx.x == 0) a.wscale[(size_t)b * a.E + e] = 0.0;
+    }
+  }
+  if (!(F32 && SM) || !(P.dm > 0.0)) {
+    for (int j = threadIdx.x; j < ns; j += kZwBS) {
+      double nxt[6];
+      in(j + kZwBS, nxt);
+      double z, w;
+      sample_zw<F32, SM>(P, dtab, inv, a.g, cur[0], cur[1], cur[2], cur[3], cur[4], cur[5], z, w,
+                         mt);
+#pragma unroll
+      for (int i = 0; i < 6; ++i) cur[i] = nxt[i];
+      put(j, z, (CT)w);
+    }
   }
   block_reduce<kZwBS, 4, false>(m, red);
   const double W1 = m[0], W2 = m[1];
@@ -381,7 +443,7 @@ __device__ __forceinline__ void event_smooth(const EventArgs& a) {
       // F_r(z_g) = n_r(z_g) g(z_g); UR independent loads in flight per thread.
       // The batch's row indices are read first (one wait), then its UR row
       // segments are loaded together.
-      constexpr int UR = 8;
+      constexpr int UR = (COMPL && !F32) ? 4 : 8;   // FP64 with the completion rows: 2 x 4 loads
       if (lgW == 6) {
         // a wave takes UR rows (uniform row index: scalar base address) and
         // sweeps the slice 64 points at a time
@@ -393,24 +455,30 @@ __device__ __forceinline__ void event_smooth(const EventArgs& a) {
             rr[r] = p < np ? a.slot_row[p0 + p] : 0;
           }
           const CT* rp[UR];
+          const CT* mp[UR];
 #pragma unroll
-          for (int r = 0; r < UR; ++r)
-            rp[r] = nzt + (size_t)__builtin_amdgcn_readfirstlane(rr[r]) * a.g.n_z;
+          for (int r = 0; r < UR; ++r) {
+            const size_t off = (size_t)__builtin_amdgcn_readfirstlane(rr[r]) * a.g.n_z;
+            rp[r] = nzt + off;
+            mp[r] = COMPL ? mzt + off : nullptr;
+          }
           for (int q0 = 0; q0 < len; q0 += 64) {
             const int q = q0 + lane;
             const bool qv = q < len;
             const int gg = s_lo + (qv ? q : 0);
             const CT gv = gz[gg];
-            CT v[UR];
+            CT v[UR], mv[UR];
+            // both rows' segments are loaded together (one wait)
 #pragma unroll
-            for (int r = 0; r < UR; ++r) v[r] = pb + r * NWV < np ? rp[r][gg] : (CT)0;
+            for (int r = 0; r < UR; ++r) {
+              const bool ok = pb + r * NWV < np;
+              v[r] = ok ? rp[r][gg] : (CT)0;
+              if (COMPL) mv[r] = ok ? mp[r][gg] : (CT)0;
+            }
             if (COMPL) {
               const CT gc = gzc[gg];
 #pragma unroll
-              for (int r = 0; r < UR; ++r)
-                if (pb + r * NWV < np)
-                  v[r] = v[r] * gv +
-                         mzt[(size_t)__builtin_amdgcn_readfirstlane(rr[r]) * a.g.n_z + gg] * gc;
+              for (int r = 0; r < UR; ++r) v[r] = v[r] * gv + mv[r] * gc;
             }
 #pragma unroll
             for (int r = 0; r < UR; ++r) {
@@ -434,18 +502,16 @@ __device__ __forceinline__ void event_smooth(const EventArgs& a) {
             const int p = pb + r * NWV * RPW;
             rr[r] = p < np ? a.slot_row[p0 + p] : 0;
           }
-          CT v[UR];
+          CT v[UR], mv[UR];
 #pragma unroll
           for (int r = 0; r < UR; ++r) {
             const int p = pb + r * NWV * RPW;
             v[r] = p < np ? nzt[(size_t)rr[r] * a.g.n_z + gg] : (CT)0;
+            if (COMPL) mv[r] = p < np ? mzt[(size_t)rr[r] * a.g.n_z + gg] : (CT)0;
           }
           if (COMPL) {
 #pragma unroll
-            for (int r = 0; r < UR; ++r) {
-              const int p = pb + r * NWV * RPW;
-              if (p < np) v[r] = v[r] * gv + mzt[(size_t)rr[r] * a.g.n_z + gg] * gc;
-            }
+            for (int r = 0; r < UR; ++r) v[r] = v[r] * gv + mv[r] * gc;
           }
 #pragma unroll
           for (int r = 0; r < UR; ++r) {
@@ -1006,7 +1072,7 @@ __global__ void k_event_final(EventArgs a) {
     for (int u = a.ev_unit_off[e]; u < a.ev_unit_off[e + 1]; ++u) s += a.part[(size_t)b * a.U + u];
     const double norm = a.shape == kShapeEpanechnikov ? 0.75 / kEpanScale : kInvSqrt2Pi;
     const double I = h > 0.0 ? s * norm / h : 0.0;
-    out = I > 0.0 ? log(I) : -INFINITY;
+    out = I > 0.0 ? log(I) + (a.wscale ? a.wscale[(size_t)b * a.E + e] : 0.0) : -INFINITY;
   }
   a.lnI[(size_t)b * a.E + e] = out;
 }
@@ -1016,8 +1082,13 @@ hipError_t launch_events(const EventArgs& a, const EventArgs& kern, bool f32, hi
                          hipEvent_t t0, hipEvent_t t1) {
   const long long bz = item_lambda_blocks(a.E, a.B);
   hipError_t err;
-  if (f32) k_event_zw<true><<<(unsigned)bz, kZwBS, 0, st>>>(a);
-  else k_event_zw<false><<<(unsigned)bz, kZwBS, 0, st>>>(a);
+  if (a.mtab) {
+    if (f32) k_event_zw<true, true><<<(unsigned)bz, kZwBS, 0, st>>>(a);
+    else k_event_zw<false, true><<<(unsigned)bz, kZwBS, 0, st>>>(a);
+  } else {
+    if (f32) k_event_zw<true, false><<<(unsigned)bz, kZwBS, 0, st>>>(a);
+    else k_event_zw<false, false><<<(unsigned)bz, kZwBS, 0, st>>>(a);
+  }
   if (a.V > 0) {
     if (f32) {
       k_event_cov3d<true><<<(unsigned)bz, kZwBS, 0, st>>>(a);

@@ -67,6 +67,7 @@ __global__ void k_lam_prepare(const double* __restrict__ lam, int stride, int B,
   P.sm_top = fmin(P.mmax, P.mmin + P.dm);
   P.sm_edge = P.mmin + P.dm;
   P.ln_edge = log(P.sm_edge);
+  P.sm_pl = P.a2 == 0.0 ? 1.0 : exp(P.a2 * P.ln_edge) / P.a2;
   if (!ok) P.flag = kFlagDomain;
   out[b] = P;
 }
@@ -83,11 +84,22 @@ __global__ void k_lam_prepare(const double* __restrict__ lam, int stride, int B,
 // sub-panels sized to the steepness; pass 2 scans the maps in order.  It also
 // gives Q = C(top) and N1 = int_mmin^top p(m1) S + int_top^mmax p(m1).
 // ---------------------------------------------------------------------------
-constexpr int kMassBS = 256;
+constexpr int kMassBS = 1024;
 
-// ln S(m) for 0 < m' = m - mmin < delta_m: -softplus(dm/m' + dm/(m' - dm))
+// 8-point Gauss-Legendre on [-1, 1]: the positive nodes and their weights
+__constant__ double kGLx[4] = {0.18343464249564980494, 0.52553240991632898582,
+                               0.79666647741362673959, 0.96028985649753623168};
+__constant__ double kGLw[4] = {0.36268378337836198297, 0.31370664587788728734,
+                               0.22238103445337447054, 0.10122853629037625915};
+
+// y = dm/m' + dm/(m' - dm) of S = 1 / (1 + e^y), for 0 < m' < dm
+__device__ __forceinline__ double smooth_exponent(double mp, double dm) {
+  return dm * (2.0 * mp - dm) / (mp * (mp - dm));
+}
+
+// ln S(m) for 0 < m' = m - mmin < delta_m: -softplus(y)
 __device__ __forceinline__ double ln_smooth(double mp, double dm) {
-  const double y = dm / mp + dm / (mp - dm);
+  const double y = smooth_exponent(mp, dm);
   return -(fmax(y, 0.0) + log1p(exp(-fabs(y))));
 }
 
@@ -101,7 +113,7 @@ __device__ __forceinline__ double ln_fm(const LamParams& P, double m) {
 __device__ __forceinline__ double dln_fm(const LamParams& P, double m) {
   const double mp = m - P.mmin;
   if (mp >= P.dm) return P.beta / m;
-  const double y = P.dm / mp + P.dm / (mp - P.dm);
+  const double y = smooth_exponent(mp, P.dm);
   const double oms = 1.0 / (1.0 + exp(-y));
   const double q = mp - P.dm;
   return P.beta / m + (oms > 0.0 ? oms * (P.dm / (mp * mp) + P.dm / (q * q)) : 0.0);
@@ -114,42 +126,68 @@ __global__ __launch_bounds__(kMassBS) void k_mass_table(LamParams* __restrict__ 
   if (!(P.dm > 0.0) || P.flag) return;
   double2* tab = mtab + (size_t)b * (kMassPanels + 1);
   const double h = (P.sm_top - P.mmin) / (double)kMassPanels;
-  const double gx[4] = {0.18343464249564980494, 0.52553240991632898582, 0.79666647741362673959,
-                        0.96028985649753623168};
-  const double gw[4] = {0.36268378337836198297, 0.31370664587788728734, 0.22238103445337447054,
-                        0.10122853629037625915};
+  const double* gx = kGLx;
+  const double* gw = kGLw;
   auto node = [&](int k) { return k == kMassPanels ? P.sm_top : P.mmin + (double)k * h; };
+  // the unsmoothed mixture p(m1) at m, ln m given
+  auto mix = [&](double m, double lm) {
+    const double u = (m - P.mu) * P.inv_sigma;
+    return P.pl_coef * exp(-P.alpha * lm) + P.tg_coef * exp(-0.5 * u * u);
+  };
   // pass 1: tab[k + 1] = (f(a)/f(b), int_a^b f/f(b)) of panel k = [a, b];
   // and the smoothed primary's mass below top
   double n1 = 0.0;
   for (int k = threadIdx.x; k < kMassPanels; k += kMassBS) {
     const double a = node(k), e = node(k + 1);
-    const double lb = ln_fm(P, e);
+    const double lsb = e - P.mmin >= P.dm ? 0.0 : ln_smooth(e - P.mmin, P.dm);
+    const double lb = P.beta * log(e) + lsb;
     const double ratio = k == 0 ? 0.0 : exp(ln_fm(P, a) - lb);
+    // sub-panels resolve f's steep rise near mmin.  Where S(b) < 1e-100 no
+    // weight that matters can use the node, and the recursion's factor
+    // f(a)/f(b) < e^-14 there forgets the error within a panel or two, so
+    // two sub-panels do.
     const double steep = k == 0 ? 1e300 : dln_fm(P, a) * (e - a);
-    const int nsub = (int)fmin(fmax(ceil(steep * 0.25), 1.0), 32.0);
-    const double w = (e - a) / (double)nsub, half = 0.5 * w;
-    double acc = 0.0;
-    for (int j = 0; j < nsub; ++j) {
-      const double mid = a + ((double)j + 0.5) * w;
-      double sj = 0.0;
+    const double cap = lsb < -230.0 ? 2.0 : 32.0;
+    const int nsub = (int)fmin(fmax(ceil(steep * 0.25), 1.0), cap);
+    const double mid = 0.5 * (a + e), hp = 0.5 * (e - a);
+    double acc = 0.0, sp = 0.0;
+    if (nsub == 1) {
+      // one set of nodes serves both integrals
+#pragma unroll 2
+      for (int q = 0; q < 8; ++q) {
+        const double x = mid + (q & 1 ? hp : -hp) * gx[q >> 1];
+        const double lx = log(x), mp = x - P.mmin;
+        double ls = 0.0, sv = 1.0;
+        if (mp < P.dm) {
+          const double y = smooth_exponent(mp, P.dm);
+          const double ex = exp(-fabs(y));
+          ls = -(fmax(y, 0.0) + log1p(ex));
+          sv = (y >= 0.0 ? ex : 1.0) / (1.0 + ex);
+        }
+        acc += gw[q >> 1] * exp(P.beta * lx + ls - lb);
+        sp += gw[q >> 1] * mix(x, lx) * sv;
+      }
+      acc *= hp;
+      sp *= hp;
+    } else {
+      const double w = (e - a) / (double)nsub, half = 0.5 * w;
+      for (int j = 0; j < nsub; ++j) {
+        const double mj = a + ((double)j + 0.5) * w;
+        double sj = 0.0;
 #pragma unroll
-      for (int q = 0; q < 4; ++q)
-        sj += gw[q] * (exp(ln_fm(P, mid - half * gx[q]) - lb) + exp(ln_fm(P, mid + half * gx[q]) - lb));
-      acc += sj * half;
+        for (int q = 0; q < 4; ++q)
+          sj += gw[q] * (exp(ln_fm(P, mj - half * gx[q]) - lb) + exp(ln_fm(P, mj + half * gx[q]) - lb));
+        acc += sj * half;
+      }
+#pragma unroll 2
+      for (int q = 0; q < 8; ++q) {
+        const double x = mid + (q & 1 ? hp : -hp) * gx[q >> 1];
+        sp += gw[q >> 1] * mix(x, log(x)) * smooth_edge(x, P.mmin, P.dm);
+      }
+      sp *= hp;
     }
     tab[k + 1] = make_double2(ratio, acc);
-    const double mid = 0.5 * (a + e), hp = 0.5 * (e - a);
-    double sp = 0.0;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const double x0 = mid - hp * gx[q], x1 = mid + hp * gx[q];
-      const double u0 = (x0 - P.mu) * P.inv_sigma, u1 = (x1 - P.mu) * P.inv_sigma;
-      const double p0 = P.pl_coef * exp(-P.alpha * log(x0)) + P.tg_coef * exp(-0.5 * u0 * u0);
-      const double p1 = P.pl_coef * exp(-P.alpha * log(x1)) + P.tg_coef * exp(-0.5 * u1 * u1);
-      sp += gw[q] * (p0 * smooth_edge(x0, P.mmin, P.dm) + p1 * smooth_edge(x1, P.mmin, P.dm));
-    }
-    n1 += sp * hp;
+    n1 += sp;
   }
   __syncthreads();
   // pass 2: compose the maps of this thread's panels, in order
@@ -163,7 +201,8 @@ __global__ __launch_bounds__(kMassBS) void k_mass_table(LamParams* __restrict__ 
     Bv = m.x * Bv + m.y;
   }
   // inclusive scan of the maps (earlier threads first), then this thread's start
-  __shared__ double sA[kMassBS / 64], sB[kMassBS / 64], sN[kMassBS / 64];
+  constexpr int NW = kMassBS / 64;
+  __shared__ double sA[NW], sB[NW], sN[NW];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   double iA = A, iB = Bv;
 #pragma unroll
@@ -194,7 +233,7 @@ __global__ __launch_bounds__(kMassBS) void k_mass_table(LamParams* __restrict__ 
   }
   if (threadIdx.x == kMassBS - 1) {
     double nb = 0.0;
-    for (int i = 0; i < kMassBS / 64; ++i) nb += sN[i];
+    for (int i = 0; i < NW; ++i) nb += sN[i];
     // the unsmoothed mixture's mass on [top, mmax] in closed form
     double tail = 0.0;
     if (P.sm_top < P.mmax) {
@@ -208,6 +247,8 @@ __global__ __launch_bounds__(kMassBS) void k_mass_table(LamParams* __restrict__ 
     P.sm_h = h;
     P.sm_q = r * exp(ln_fm(P, P.sm_top));
     P.sm_n1inv = 1.0 / n1v;
+    P.sm_lnq = log(P.sm_q);
+    P.sm_lnn1inv = -log(n1v);
     if (!(P.sm_q > 0.0) || !(n1v > 0.0) || !isfinite(P.sm_q)) P.flag = kFlagDomain;
     Pv[b] = P;
   }
@@ -454,7 +495,9 @@ hipError_t launch_completion(const LamParams* P, const double2* chi, const Geome
 constexpr int kSelBS = 256;
 constexpr int kSelPer = 4;
 
-template <bool F32>
+// SM: the batch may carry the smoothed mass edge (a separate instance keeps
+// the plain one's registers)
+template <bool F32, bool SM>
 __global__ __launch_bounds__(kSelBS) void k_selection(SelArgs a) {
   const int chunk = blockIdx.x, b = blockIdx.y;
   __shared__ double red[kSelBS / 64 + 1];
@@ -479,9 +522,8 @@ __global__ __launch_bounds__(kSelBS) void k_selection(SelArgs a) {
     const double m1 = a.m1d[j] / zp1, m2 = a.m2d[j] / zp1;
     const double l1 = a.lnm1d[j] - x, l2 = a.lnm2d[j] - x;
     double w;
-    if (P.dm > 0.0) {
-      w = mass_weight_smoothed(P, a.mtab + (size_t)b * (kMassPanels + 1), m1, m2, l1, l2);
-      if (F32) w = (double)(float)w;
+    if (SM && P.dm > 0.0) {
+      w = mass_weight_smoothed<F32>(P, a.mtab + (size_t)b * (kMassPanels + 1), m1, m2, l1, l2);
     } else {
       w = F32 ? (double)mass_weight32(P, m1, m2, l1, l2) : mass_weight64(P, m1, m2, l1, l2);
     }
@@ -613,8 +655,13 @@ hipError_t launch_selection(const SelArgs& a, bool f32, double* ln_xi, double* n
                             hipStream_t st) {
   if (a.nchunk > 0) {
     dim3 grid(a.nchunk, a.B);
-    if (f32) k_selection<true><<<grid, kSelBS, 0, st>>>(a);
-    else k_selection<false><<<grid, kSelBS, 0, st>>>(a);
+    if (a.mtab) {
+      if (f32) k_selection<true, true><<<grid, kSelBS, 0, st>>>(a);
+      else k_selection<false, true><<<grid, kSelBS, 0, st>>>(a);
+    } else {
+      if (f32) k_selection<true, false><<<grid, kSelBS, 0, st>>>(a);
+      else k_selection<false, false><<<grid, kSelBS, 0, st>>>(a);
+    }
     CH_LAUNCH_CHECK();
   }
   k_selection_final<<<(a.B + 63) / 64, 64, 0, st>>>(a, ln_xi, neff);

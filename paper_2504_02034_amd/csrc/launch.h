@@ -93,6 +93,7 @@ struct EventArgs {
   const double2* inv;
   const double2* dtab;      // [B][n_t] (d_L^gw, dd_L^gw/dx) on the x nodes
   const double2* mtab;      // [B][kMassPanels + 1] smoothed-edge tables (delta_m > 0)
+  double* wscale;           // [B][E] ln of the FP32 weights' scale (FP32 with delta_m), or null
   Geometry g;
   const double* gz64;
   const float* gz32;
