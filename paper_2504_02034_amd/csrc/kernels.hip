@@ -495,10 +495,10 @@ hipError_t launch_completion(const LamParams* P, const double2* chi, const Geome
 constexpr int kSelBS = 256;
 constexpr int kSelPer = 4;
 
-// SM: the batch may carry the smoothed mass edge (a separate instance keeps
+// SM: the batch may carry the smoothed mass edge (a separate kernel keeps
 // the plain one's registers)
 template <bool F32, bool SM>
-__global__ __launch_bounds__(kSelBS) void k_selection(SelArgs a) {
+__device__ __forceinline__ void selection_sums(const SelArgs& a) {
   const int chunk = blockIdx.x, b = blockIdx.y;
   __shared__ double red[kSelBS / 64 + 1];
   const LamParams P = a.P[b];
@@ -555,6 +555,17 @@ __global__ __launch_bounds__(kSelBS) void k_selection(SelArgs a) {
     a.partial[((size_t)b * a.nchunk + chunk) * 2 + 1] = s2;
   }
 }
+
+// Without a register target the compiler keeps ~40 copies of per-lambda
+// constants in VGPRs (130 in FP32: 3 waves per SIMD); at 5 waves it
+// rematerialises them without spilling.
+template <bool F32>
+__global__ __launch_bounds__(kSelBS) __attribute__((amdgpu_waves_per_eu(5)))
+void k_selection(SelArgs a) { selection_sums<F32, false>(a); }
+
+template <bool F32>
+__global__ __launch_bounds__(kSelBS) __attribute__((amdgpu_waves_per_eu(4)))
+void k_selection_sm(SelArgs a) { selection_sums<F32, true>(a); }
 
 __global__ void k_selection_final(SelArgs a, double* __restrict__ ln_xi,
                                   double* __restrict__ neff) {
@@ -656,11 +667,11 @@ hipError_t launch_selection(const SelArgs& a, bool f32, double* ln_xi, double* n
   if (a.nchunk > 0) {
     dim3 grid(a.nchunk, a.B);
     if (a.mtab) {
-      if (f32) k_selection<true, true><<<grid, kSelBS, 0, st>>>(a);
-      else k_selection<false, true><<<grid, kSelBS, 0, st>>>(a);
+      if (f32) k_selection_sm<true><<<grid, kSelBS, 0, st>>>(a);
+      else k_selection_sm<false><<<grid, kSelBS, 0, st>>>(a);
     } else {
-      if (f32) k_selection<true, false><<<grid, kSelBS, 0, st>>>(a);
-      else k_selection<false, false><<<grid, kSelBS, 0, st>>>(a);
+      if (f32) k_selection<true><<<grid, kSelBS, 0, st>>>(a);
+      else k_selection<false><<<grid, kSelBS, 0, st>>>(a);
     }
     CH_LAUNCH_CHECK();
   }
