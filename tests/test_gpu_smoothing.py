@@ -145,3 +145,38 @@ def test_wide_edge_deep_in_the_smoothed_range(setup):
             assert close(lnl[0], ref["lnl"], REL64), (lnl[0], ref["lnl"])
             for i in range(lnI.shape[1]):
                 assert close(lnI[0, i], ref["lnI"][i], REL64), (i, lnI[0, i], ref["lnI"][i])
+
+
+@pytest.mark.parametrize("kernel,shape,n_bins", [("many1d", "epanechnikov", 0),
+                                                 ("single1d", "gaussian", 64),
+                                                 ("3d", "gaussian", 0)])
+def test_other_kernels_with_the_smoothed_edge(setup, kernel, shape, n_bins):
+    """The smoothed weights feed every kernel option: Epanechnikov, binned
+    and 3D sums against the oracle (FP64, 1e-10), and FP32 within 1e-3 of
+    FP64 also at delta_m = 95, where the lightest event's FP32 weights are
+    rescaled."""
+    import oracle
+    from paper_2504_02034_amd import prep
+    d, chimera, ctx, sets, lam, lam15, plain, plain_xi = setup
+    if kernel == "3d":
+        ev = ctx.add_prepared_3d(prep.three_d(d.prep, d.ev))
+    else:
+        ev = sets[kernel]
+        ctx.set_event_kde(ev, chimera.CHIMERA_KDE_EPANECHNIKOV if shape == "epanechnikov"
+                          else chimera.CHIMERA_KDE_GAUSSIAN, n_bins)
+    rows = np.stack([np.append(synth.LAMBDA_TRUTH, 4.8), np.append(synth.LAMBDA_TRUTH, 95.0)])
+    try:
+        lnl, lnI = ctx.lnl(ev, rows, chimera.CHIMERA_FP64, with_lnI=True)
+        l32, I32 = ctx.lnl(ev, rows, chimera.CHIMERA_FP32, with_lnI=True)
+    finally:
+        if kernel == "3d":
+            ev.release()
+        else:
+            ctx.set_event_kde(ev)
+    assert np.all(np.isfinite(lnI)) and np.all(np.isfinite(I32))
+    assert np.max(np.abs(I32 - lnI)) <= 1e-3, np.max(np.abs(I32 - lnI))
+    ref = oracle.likelihood.lnl(d.o_events, d.o_cat, d.o_inj, rows[0], T=8.6, kernel=kernel,
+                                shape=shape, n_bins=n_bins)
+    assert close(lnl[0], ref["lnl"], REL64), (lnl[0], ref["lnl"])
+    for i in range(lnI.shape[1]):
+        assert close(lnI[0, i], ref["lnI"][i], REL64), (i, lnI[0, i], ref["lnI"][i])
