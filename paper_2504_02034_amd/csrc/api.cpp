@@ -1423,7 +1423,6 @@ chimera_status chimera_scratch_bytes(chimera_ctx* ctx, const chimera_events* ev,
   if (prec != CHIMERA_FP64 && prec != CHIMERA_FP32) return fail(CHIMERA_EINVAL, "bad precision");
   if (mem != CHIMERA_HOST && mem != CHIMERA_DEVICE) return fail(CHIMERA_EINVAL, "bad mem");
   const bool host = mem == CHIMERA_HOST;
-  const int E = ev ? ev->E : 0;
   B = lambda_chunk(ev, B, prec == CHIMERA_FP32);
   double dmin = ev ? ev->dmin : 1.0, dmax = ev ? ev->dmax : 1.0;
   const Geometry g = make_geometry(ctx, dmin, dmax);

@@ -556,12 +556,15 @@ __device__ __forceinline__ void selection_sums(const SelArgs& a) {
   }
 }
 
-// Without a register target the compiler keeps ~40 copies of per-lambda
-// constants in VGPRs (130 in FP32: 3 waves per SIMD); at 5 waves it
-// rematerialises them without spilling.
-template <bool F32>
+// Without a register target the FP32 kernel keeps ~40 copies of per-lambda
+// constants in VGPRs (130: 3 waves per SIMD); at 5 waves it rematerialises
+// them without spilling (-8 %; the FP64 kernel is faster at its own 4).
 __global__ __launch_bounds__(kSelBS) __attribute__((amdgpu_waves_per_eu(5)))
-void k_selection(SelArgs a) { selection_sums<F32, false>(a); }
+void k_selection32(SelArgs a) { selection_sums<true, false>(a); }
+
+__global__ __launch_bounds__(kSelBS) void k_selection64(SelArgs a) {
+  selection_sums<false, false>(a);
+}
 
 template <bool F32>
 __global__ __launch_bounds__(kSelBS) __attribute__((amdgpu_waves_per_eu(4)))
@@ -670,8 +673,8 @@ hipError_t launch_selection(const SelArgs& a, bool f32, double* ln_xi, double* n
       if (f32) k_selection_sm<true><<<grid, kSelBS, 0, st>>>(a);
       else k_selection_sm<false><<<grid, kSelBS, 0, st>>>(a);
     } else {
-      if (f32) k_selection<true><<<grid, kSelBS, 0, st>>>(a);
-      else k_selection<false><<<grid, kSelBS, 0, st>>>(a);
+      if (f32) k_selection32<<<grid, kSelBS, 0, st>>>(a);
+      else k_selection64<<<grid, kSelBS, 0, st>>>(a);
     }
     CH_LAUNCH_CHECK();
   }
