@@ -23,7 +23,12 @@ crosses them) and are held fixed.  Pieces:
   the window edges |z_g - z_j| = T h are not differentiated (their terms
   carry the kernel's value e^(-T^2/2) at the edge);
 * selection: s_j = w n_tot psi / ((1+z)^3 D' p_draw) along the same chain,
-  with n_tot linear between grid nodes.
+  with n_tot linear between grid nodes;
+* incomplete catalogue (eqs. p-gal, p-miss, f-R): the rows f_R n_r +
+  (1 - P_r) v and n_tot^eff = f_R n_tot + M v depend on Om through the
+  completion density v = chi^2 / (E (4 pi/3) chi(z_max)^3) and through
+  f_R = sum_g tau_g (4 pi - M) v; d ln v / d Om = 2 chi'/chi - E'/E -
+  3 chi'(z_max)/chi(z_max) with chi' = d chi / d Om and E' = ((1+z)^3 - 1)/(2E).
 
 The lambda-only normalisation derivatives of the mass model: the power
 law's by quadrature (scipy quad) of the differentiated density, the
@@ -31,8 +36,9 @@ truncated Gaussian's from d Phi / dt = phi.
 
 Pins (tests/test_oracle_gradient.py): each piece against Richardson central
 differences of the oracle function it differentiates; the whole gradient
-against Richardson differences of likelihood.lnl on small inputs; dlnL/dn = 0
-exactly at Xi0 = 1 and dlnL/dXi0 = 0 exactly at n = 0.
+against Richardson differences of likelihood.lnl on small inputs, also with
+an incomplete catalogue; dlnL/dn = 0 exactly at Xi0 = 1 and dlnL/dXi0 = 0
+exactly at n = 0.
 """
 from __future__ import annotations
 
@@ -229,6 +235,28 @@ def grid_factor_log_derivs(grid, lam):
     return out
 
 
+def completion_density_dom(z, om, z_max):
+    """d v / d Om of likelihood.completion_density (0 at z = 0, where v = 0)."""
+    z = np.asarray(z, dtype=np.float64)
+    v = L.completion_density(z, om, z_max)
+    ch = cosmo.chi(z, om)
+    e = cosmo.efunc(z, om)
+    dlv = (2.0 * dchi_dom(z, om) / np.where(ch > 0.0, ch, 1.0)
+           - ((1.0 + z) ** 3 - 1.0) / (2.0 * e * e)
+           - 3.0 * float(dchi_dom(np.array([z_max]), om)[0]) / float(cosmo.chi(z_max, om)))
+    return np.where(ch > 0.0, v * dlv, 0.0)
+
+
+def galaxy_density_dom(cat: L.Catalog, lam):
+    """(d rows / d Om, d n_tot / d Om) of likelihood.galaxy_density with an
+    incomplete catalogue: f_R' n_r + (1 - P_r) v' and f_R' n_tot + M v',
+    f_R' = sum_g tau_g (4 pi - M) v'."""
+    dv = completion_density_dom(cat.grid, lam[1], cat.grid[-1])
+    df = float(np.sum(L.trapezoid(cat.grid) * (4.0 * math.pi - cat.missing) * dv))
+    drows = {p: df * r + (1.0 - cat.p_compl[p]) * dv for p, r in cat.rows.items()}
+    return drows, df * cat.n_tot + cat.missing * dv
+
+
 # ---------------------------------------------------------------------------
 # bandwidth
 # ---------------------------------------------------------------------------
@@ -260,8 +288,10 @@ def bandwidth_grad(z, w, dlw, dz_p, dz_grid):
 # ---------------------------------------------------------------------------
 # one event, selection, ln L
 # ---------------------------------------------------------------------------
-def event_grad(pix_z, pix_w, pix_dlw, pix_dz, pix_c, pix_rows, grid, tau, gz, dlng, T=None):
-    """(I_i, d ln I_i / dp [12])."""
+def event_grad(pix_z, pix_w, pix_dlw, pix_dz, pix_c, pix_rows, grid, tau, gz, dlng, T=None,
+               pix_drows=None):
+    """(I_i, d ln I_i / dp [12]); pix_drows: d row / d Om of each pixel's row
+    (an incomplete catalogue), or None."""
     dzg = grid[1] - grid[0]
     z = np.concatenate(pix_z)
     w = np.concatenate(pix_w)
@@ -272,7 +302,8 @@ def event_grad(pix_z, pix_w, pix_dlw, pix_dz, pix_c, pix_rows, grid, tau, gz, dl
         return 0.0, np.full(NG, np.nan)
     S = 0.0
     G = np.zeros(NG)
-    for zr, wr, lw, zz, c, nr in zip(pix_z, pix_w, pix_dlw, pix_dz, pix_c, pix_rows):
+    drs = pix_drows if pix_drows is not None else [None] * len(pix_rows)
+    for zr, wr, lw, zz, c, nr, dnr in zip(pix_z, pix_w, pix_dlw, pix_dz, pix_c, pix_rows, drs):
         f = tau * nr * gz
         u = grid[None, :] - zr[:, None]
         k = np.exp(-0.5 * (u / h) ** 2)
@@ -285,6 +316,8 @@ def event_grad(pix_z, pix_w, pix_dlw, pix_dz, pix_c, pix_rows, grid, tau, gz, dl
         Eg = fk @ dlng.T                            # [n_j, 12]: sum F K dln g/dp
         S += c * float(wr @ A)
         G += c * (lw @ (wr * A) + zz @ (wr * B) + float(wr @ C) * h * dlnh + Eg.T @ wr)
+        if dnr is not None:          # the row's own Om dependence
+            G[_OM] += c * float(wr @ (k @ (tau * dnr * gz)))
     if not S > 0:
         return 0.0, np.full(NG, np.nan)
     I = S / (h * math.sqrt(2.0 * math.pi))
@@ -296,10 +329,11 @@ def selection_grad(inj: L.InjectionSet, cat: L.Catalog, lam):
     z = cosmo.invert_dl(inj.dl, lam[0], lam[1], lam[2], lam[3])
     w, dlw, dzp = sample_log_weight_grad(z, inj.m1d, inj.m2d, lam)
     grid = cat.grid
-    ntot = np.interp(z, grid, cat.n_tot, left=0.0, right=0.0)
+    _, n_tot, _ = L.galaxy_density(cat, lam)
+    ntot = np.interp(z, grid, n_tot, left=0.0, right=0.0)
     # slope of the linear interpolation on the segment that holds z
     k = np.clip(np.searchsorted(grid, z, side="right") - 1, 0, grid.size - 2)
-    slope = (cat.n_tot[k + 1] - cat.n_tot[k]) / (grid[k + 1] - grid[k])
+    slope = (n_tot[k + 1] - n_tot[k]) / (grid[k + 1] - grid[k])
     _, Dz, Dzz, _, dDz = distance_parts(z, lam)
     ps = psi(z, lam[11], lam[12], lam[13])
     s = w * ntot * ps / ((1.0 + z) ** 3 * Dz * np.exp(inj.ln_pdraw))
@@ -313,6 +347,10 @@ def selection_grad(inj: L.InjectionSet, cat: L.Catalog, lam):
     dls = dlw + dls_dz[None, :] * dzp
     dls[:4] -= dDz / Dz
     dls[_GAM:] += dpsi
+    if cat.p_compl is not None:        # n_tot^eff's own Om dependence
+        _, dnt = galaxy_density_dom(cat, lam)
+        dls[_OM] += np.where(pos, np.interp(z, grid, dnt, left=0.0, right=0.0)
+                             / np.where(pos, ntot, 1.0), 0.0)
     return S1 / inj.n_total, (dls[:, pos] @ s[pos]) / S1
 
 
@@ -326,8 +364,6 @@ def lnl_grad(events, cat: L.Catalog, inj: L.InjectionSet, lam, T=None, kernel="m
     grad is NaN where lnl is not finite."""
     if kernel not in ("many1d", "single1d"):
         raise ValueError(f"unknown kernel {kernel!r}")
-    if cat.p_compl is not None:
-        raise NotImplementedError("the gradient of the incompleteness term is not built")
     if len(lam) > 14:
         raise NotImplementedError("the gradient of the smoothed mass model is not built")
     lam = np.asarray(lam, dtype=np.float64)
@@ -338,28 +374,34 @@ def lnl_grad(events, cat: L.Catalog, inj: L.InjectionSet, lam, T=None, kernel="m
         return out
     grid = cat.grid
     tau = L.trapezoid(grid)
+    rows, _, _ = L.galaxy_density(cat, lam)
+    drows = galaxy_density_dom(cat, lam)[0] if cat.p_compl is not None else None
     try:
         gz = L.grid_factor(grid, lam)
         dlng = grid_factor_log_derivs(grid, lam)
         xi, dlnxi = selection_grad(inj, cat, lam)
         per_event = []
         for ev in events:
-            zs, ws, lws, zzs, cs, rs = [], [], [], [], [], []
+            zs, ws, lws, zzs, cs, rs, drs = [], [], [], [], [], [], []
             if kernel == "single1d":
                 dl, m1d, m2d = ev.all_samples()
                 parts = [(dl, m1d, m2d, 1.0 / dl.size,
-                          sum(px.sky() * cat.rows[px.pix] for px in ev.pixels))]
+                          sum(px.sky() * rows[px.pix] for px in ev.pixels),
+                          None if drows is None else
+                          sum(px.sky() * drows[px.pix] for px in ev.pixels))]
             else:
-                parts = [(px.dl, px.m1d, px.m2d, px.c, cat.rows[px.pix]) for px in ev.pixels]
-            for dl, m1d, m2d, c, row in parts:
+                parts = [(px.dl, px.m1d, px.m2d, px.c, rows[px.pix],
+                          None if drows is None else drows[px.pix]) for px in ev.pixels]
+            for dl, m1d, m2d, c, row, drow in parts:
                 z = cosmo.invert_dl(dl, lam[0], lam[1], lam[2], lam[3])
                 if np.any(np.isnan(z)):
                     out["lnl"] = np.nan
                     return out
                 w, lw, zz = sample_log_weight_grad(z, m1d, m2d, lam)
                 zs.append(z); ws.append(w); lws.append(lw); zzs.append(zz)
-                cs.append(c); rs.append(row)
-            per_event.append(event_grad(zs, ws, lws, zzs, cs, rs, grid, tau, gz, dlng, T))
+                cs.append(c); rs.append(row); drs.append(drow)
+            per_event.append(event_grad(zs, ws, lws, zzs, cs, rs, grid, tau, gz, dlng, T,
+                                        drs if drows is not None else None))
     except cosmo.NonMonotone:
         return out
     out["ln_xi"] = math.log(xi) if xi > 0 else -np.inf

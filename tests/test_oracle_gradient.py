@@ -162,3 +162,64 @@ def test_gradient_nan_outside_domain(hand):
     bad[1] = 1.5
     r = G.lnl_grad(events, cat, inj, bad)
     assert r["lnl"] == -np.inf and np.all(np.isnan(r["grad"]))
+
+
+# ---------------------------------------------------------------------------
+# incomplete catalogue (eqs. p-gal, p-miss, f-R): the rows and n_tot depend on
+# Om through the completion density and f_R
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("om", [0.12, 0.3, 0.8])
+def test_completion_density_dom(om):
+    z = np.array([0.0, 0.02, 0.4, 1.1, 1.6])
+    an = G.completion_density_dom(z, om, 1.6)
+    for i, zz in enumerate(z):
+        fd = G.richardson(lambda l: float(L.completion_density(np.array([zz]), l[1], 1.6)[0]),
+                          np.array([70.0, om]), 1)
+        assert abs(an[i] - fd) <= 1e-8 * max(1e-3, abs(fd)), (zz, an[i], fd)
+
+
+@pytest.fixture(scope="module")
+def hand_incomplete(hand):
+    """The handcrafted structures with a smooth per-row completeness and M(z)."""
+    import copy
+    _, (events, cat, inj) = hand
+    grid = cat.grid
+    c = copy.copy(cat)
+    c.p_compl = {r: 1.0 / (1.0 + np.exp((grid - (0.5 + 0.15 * r)) / 0.1)) for r in cat.rows}
+    c.missing = 4.0 * np.pi * (0.2 + 0.6 / (1.0 + np.exp(-(grid - 0.8) / 0.2)))
+    return events, c, inj
+
+
+@pytest.mark.parametrize("lam", [TRUTH, OTHER], ids=["truth", "other"])
+def test_selection_gradient_with_incompleteness(hand_incomplete, lam):
+    events, cat, inj = hand_incomplete
+    xi, dlnxi = G.selection_grad(inj, cat, lam)
+    assert xi == pytest.approx(L.selection(inj, cat, lam)[0], rel=1e-14)
+    f = _xi(hand_incomplete)
+    for k, p in enumerate(G.GRAD_INDEX):
+        fd = G.richardson(f, lam, p, rel_step=1e-6)
+        assert abs(dlnxi[k] - fd) <= 1e-6 * max(1.0, abs(fd)), (k, dlnxi[k], fd)
+
+
+@pytest.mark.parametrize("kernel", ["many1d", "single1d"])
+@pytest.mark.parametrize("lam", [TRUTH, OTHER], ids=["truth", "other"])
+def test_lnl_gradient_with_incompleteness(hand_incomplete, lam, kernel):
+    events, cat, inj = hand_incomplete
+    res = G.lnl_grad(events, cat, inj, lam, T=8.6, kernel=kernel)
+    ref = L.lnl(events, cat, inj, lam, T=8.6, kernel=kernel)
+    assert res["lnl"] == pytest.approx(ref["lnl"], rel=1e-13)
+    f = _lnl(hand_incomplete, 8.6, kernel)
+    for k, p in enumerate(G.GRAD_INDEX):
+        fd = G.richardson(f, lam, p, rel_step=1e-6)
+        assert abs(res["grad"][k] - fd) <= 1e-6 * max(1.0, abs(fd)), (k, res["grad"][k], fd)
+    # the incompleteness moves d ln L / d Om
+    plain = G.lnl_grad(events, hand_incomplete_plain(cat), inj, lam, T=8.6, kernel=kernel)
+    assert abs(plain["grad"][1] - res["grad"][1]) > 1e-3
+
+
+def hand_incomplete_plain(cat):
+    import copy
+    c = copy.copy(cat)
+    c.p_compl = None
+    c.missing = None
+    return c
