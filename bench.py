@@ -281,7 +281,9 @@ def population_bench(ctx, es, wl, p, lam_t, many, steps, warmup):
     generator's synthetic completeness), the smoothed lower mass edge with
     delta_m per point drawn from Table 1's prior U(0.01, 10), and both; ms per
     step and the main kernels' times in both precisions, FP32 vs FP64
-    |Delta ln L|, and the cost over the plain step."""
+    |Delta ln L|, and the cost over the plain step; with the incomplete
+    catalogue also the gradient of the first 64 points against the plain
+    gradient of the same points."""
     import numpy as np
     import torch
 
@@ -291,6 +293,9 @@ def population_bench(ctx, es, wl, p, lam_t, many, steps, warmup):
     rng = np.random.default_rng(np.random.SeedSequence([250402034, 77]))
     dm = torch.from_numpy(rng.uniform(0.01, 10.0, lam_t.shape[0])).to(lam_t.device)
     lam15 = torch.cat([lam_t, dm[:, None]], dim=1).contiguous()
+    lam_g = lam_t[:64].contiguous()
+    grad_plain = {n: time_grad(ctx, es, lam_g, p_, 3) for n, p_ in
+                  (("fp64", chimera.CHIMERA_FP64), ("fp32", chimera.CHIMERA_FP32))}
     out = []
     for name in ("completeness", "mass_smoothing", "both"):
         if name != "mass_smoothing":
@@ -310,6 +315,12 @@ def population_bench(ctx, es, wl, p, lam_t, many, steps, warmup):
                                 "over_plain": round(wall / many[prec_name]["wall"], 4)}
                 log(f"{name} {prec_name}: {wall / steps * 1e3:.2f} ms/step "
                     f"({wall / many[prec_name]['wall']:.3f} x plain)")
+                if name == "completeness":
+                    sec = time_grad(ctx, es, lam_g, prec, 3)
+                    r[prec_name].update(grad_ms_64=round(sec * 1e3, 3),
+                                        grad_over_plain=round(sec / grad_plain[prec_name], 4))
+                    log(f"{name} {prec_name} gradient: {sec * 1e3:.2f} ms for 64 lambda "
+                        f"({sec / grad_plain[prec_name]:.3f} x plain)")
         finally:
             ctx.set_completeness(None)
             ctx.set_mass_smoothing(False)

@@ -253,8 +253,8 @@ chimera_status chimera_release_events(chimera_ctx* ctx, chimera_events* ev);
  * missing[n_z]: M(z_g) = sum over all sky pixels of area x (1 - P_compl),
  * in [0, 4 pi] sr.  p_compl = NULL returns to a complete catalogue.  Applies
  * to later calls; replacing the catalogue clears it; resident single-1D
- * sets fold it as they fold the rows.  chimera_lnl_grad refuses a context
- * with it set (EINVAL).  Host arrays; synchronous.  ESTATE before a
+ * sets fold it as they fold the rows.  chimera_lnl_grad differentiates it
+ * (f_R and v depend on Om).  Host arrays; synchronous.  ESTATE before a
  * catalogue is set, EINVAL for values out of range. */
 chimera_status chimera_set_completeness(chimera_ctx* ctx, const double* p_compl,
                                        const double* missing);
@@ -383,8 +383,12 @@ chimera_status chimera_release_scratch(chimera_ctx* ctx, void* hip_stream);
  * The per-lambda layout is the same as above.  Device scratch grows with 120
  * bytes per sample and point (68 in FP32); a call whose scratch would exceed
  * 16 GiB runs as consecutive chunks of points on the same stream, with the
- * same results.  EINVAL for a set with kernel options other than the
- * defaults (chimera_set_event_kde). */
+ * same results.  With an incomplete catalogue (chimera_set_completeness) the
+ * rows f_R n_r + (1 - P_r) v and n_tot^eff add their Om derivatives
+ * (f_R' n_r + (1 - P_r) v', f_R' n_tot + M v', with d ln v / d Om =
+ * 2 chi'/chi - E'/E - 3 chi'(z_max)/chi(z_max)).  EINVAL for a set with
+ * kernel options other than the defaults (chimera_set_event_kde), a 3D set,
+ * or a context with the smoothed mass edge on. */
 chimera_status chimera_lnl_grad(chimera_ctx* ctx, const chimera_events* ev, const double* lam,
                                 int64_t B, int32_t prec, double* lnl, double* grad, int32_t mem,
                                 void* hip_stream);

@@ -1576,6 +1576,8 @@ static chimera_status run_grad_chunk(chimera_ctx* ctx, const chimera_events* ev,
   }
   const Geometry g = make_geometry(ctx, dmin, dmax);
   const int nchunk = selection_grad_chunks(ctx->n_det);
+  const bool compl_ = ctx->miss64 != nullptr;
+  double *ntot_eff = nullptr, *dntot = nullptr;
   auto lay = [&](Carve& cv, GradArgs& a, SelGradArgs& sa, GradFinalArgs& fa, double** lam_d,
                  LamParams** P, double2** chi, double2** inv, double2** dtab, double2** chio,
                  double** gz64, float** gz32, int** fm, int** fr) {
@@ -1601,6 +1603,13 @@ static chimera_status run_grad_chunk(chimera_ctx* ctx, const chimera_events* ev,
     *lam_d = host ? cv.take<double>((size_t)B * CHIMERA_NLAM) : nullptr;
     fa.lnl = host ? cv.take<double>(B) : lnl;
     fa.grad = host ? cv.take<double>((size_t)B * CHIMERA_NGRAD) : grad;
+    if (compl_) {
+      a.cv64 = cv.take<double>((size_t)B * 2 * g.n_z);
+      a.cv32 = cv.take<float>((size_t)B * 2 * g.n_z);
+      a.cf = cv.take<double>((size_t)B * 2);
+      ntot_eff = cv.take<double>((size_t)B * g.n_z);
+      dntot = cv.take<double>((size_t)B * g.n_z);
+    }
   };
   GradArgs a{};
   SelGradArgs sa{};
@@ -1636,20 +1645,25 @@ static chimera_status run_grad_chunk(chimera_ctx* ctx, const chimera_events* ev,
   a.P = P; a.flag_mono = fm; a.flag_range = fr;
   a.chi = chi; a.chio = chio; a.inv = inv; a.dtab = dtab; a.g = g;
   a.gz64 = gz64; a.gz32 = gz32; a.nz64 = rows64(ctx, ev); a.nz32 = rows32(ctx, ev);
+  a.mz64 = compl_ ? miss64(ctx, ev) : nullptr;
+  a.mz32 = compl_ ? miss32(ctx, ev) : nullptr;
   a.ev_samp_off = ev->ev_samp_off; a.samp_row = ev->samp_row; a.samp_c = ev->samp_c;
   a.dl = ev->dl; a.lndl = ev->lndl; a.m1d = ev->m1d; a.m2d = ev->m2d;
   a.lnm1d = ev->lnm1d; a.lnm2d = ev->lnm2d;
   a.E = E; a.B = (int)B; a.S = ev->n_samp; a.f32 = f32 ? 1 : 0;
   a.trunc = f32 ? ctx->cfg.trunc_fp32 : ctx->cfg.trunc_fp64;
   sa.P = P; sa.Q = a.Q; sa.flag_mono = fm; sa.flag_range = fr;
-  sa.chi = chi; sa.chio = chio; sa.inv = inv; sa.dtab = dtab; sa.g = g; sa.ntot = ctx->ntot;
+  sa.chi = chi; sa.chio = chio; sa.inv = inv; sa.dtab = dtab; sa.g = g;
+  sa.ntot = compl_ ? ntot_eff : ctx->ntot;
+  sa.ntot_stride = compl_ ? g.n_z : 0;
+  sa.dntot_om = compl_ ? dntot : nullptr;
   sa.dl = ctx->inj_dl; sa.lndl = ctx->inj_lndl; sa.m1d = ctx->inj_m1d; sa.m2d = ctx->inj_m2d;
   sa.lnm1d = ctx->inj_lnm1d; sa.lnm2d = ctx->inj_lnm2d; sa.ln_pdraw = ctx->inj_lnp;
   sa.n_det = ctx->n_det; sa.B = (int)B; sa.nchunk = nchunk;
   fa.P = P; fa.flag_mono = fm; fa.flag_range = fr; fa.partial = sa.partial; fa.nchunk = nchunk;
   fa.lnI = a.lnI; fa.dlnI = a.dlnI; fa.E = E; fa.n_total = ctx->n_inj_total;
   fa.neff_gate = ctx->neff_gate;
-  HIP_TRY(launch_grad(a, sa, fa, f32, st));
+  HIP_TRY(launch_grad(a, sa, fa, f32, st, ctx->ntot, ctx->missing));
   if (host) {
     HIP_TRY(hipMemcpyAsync(lnl, fa.lnl, B * sizeof(double), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipMemcpyAsync(grad, fa.grad, (size_t)B * CHIMERA_NGRAD * sizeof(double),
@@ -1682,8 +1696,6 @@ chimera_status chimera_lnl_grad(chimera_ctx* ctx, const chimera_events* ev, cons
   if (ev->shape != CHIMERA_KDE_GAUSSIAN || ev->n_bins != 0 || ev->V != 0)
     return fail(CHIMERA_EINVAL,
                 "the adjoint takes the many-1D or single-1D Gaussian kernel on unbinned samples");
-  if (ctx->miss64)
-    return fail(CHIMERA_EINVAL, "the adjoint takes a complete catalogue (no incompleteness set)");
   if (ctx->nlam != CHIMERA_NLAM)
     return fail(CHIMERA_EINVAL, "the adjoint takes the unsmoothed mass model (no delta_m)");
   return run_grad(ctx, ev, lam, B, prec, lnl, grad, mem, hip_stream);

@@ -216,6 +216,69 @@ __global__ void k_grid_grad(const LamParams* __restrict__ Pv, const double2* __r
   }
 }
 
+// Incomplete catalogue (eqs. p-gal, p-miss, f-R): one workgroup per lambda.
+// v = chi^2 / (E (4 pi/3) chi(z_max)^3) with d ln v / d Om = 2 chi'/chi -
+// E'/E - 3 chi'(z_max)/chi(z_max), chi' = d chi / d Om (the chio table),
+// E' = ((1+z)^3 - 1) / (2E); f_R = sum_g tau_g (4 pi - M) v and f_R' the same
+// sum of v'.  Writes v and v' g on the grid, (f_R, f_R'), and n_tot^eff =
+// f_R n_tot + M v with its Om derivative f_R' n_tot + M v'.
+constexpr int kCompGradBS = 256;
+__global__ __launch_bounds__(kCompGradBS) void k_completion_grad(GradArgs a,
+                                                                 const double* __restrict__ ntot,
+                                                                 const double* __restrict__ missing,
+                                                                 double* __restrict__ ntot_eff,
+                                                                 double* __restrict__ dntot) {
+  const int b = blockIdx.x;
+  __shared__ double red[kCompGradBS / 64 + 1];
+  const LamParams P = a.P[b];
+  const Geometry& g = a.g;
+  const double2* chi = a.chi + (size_t)b * g.n_t;
+  const double2* chio = a.chio + (size_t)b * g.n_t;
+  const double zmax = g.z_lo + (double)(g.n_z - 1) * g.dz;
+  const double xm = log1p(zmax);
+  const double cm = chi_at(chi, g, xm), dcm = chi_at(chio, g, xm);
+  const double norm = 1.0 / (4.0 * M_PI / 3.0 * cm * cm * cm);
+  // v and v' at node k
+  auto vol = [&](int k, double& dv) {
+    const double z = g.z_lo + (double)k * g.dz;
+    const double x = log1p(z);
+    const double c = chi_at(chi, g, x);
+    const double e = efunc_of_zp1(P.om, 1.0 + z);
+    const double v = c * c / e * norm;
+    const double zp3 = (1.0 + z) * (1.0 + z) * (1.0 + z);
+    dv = c > 0.0 ? v * (2.0 * chi_at(chio, g, x) / c - (zp3 - 1.0) / (2.0 * e * e) - 3.0 * dcm / cm)
+                 : 0.0;
+    return v;
+  };
+  double t0 = 0.0, t1 = 0.0;
+  for (int k = threadIdx.x; k < g.n_z; k += kCompGradBS) {
+    const double tau = (k == 0 || k == g.n_z - 1) ? 0.5 * g.dz : g.dz;
+    double dv;
+    const double v = vol(k, dv);
+    t0 += tau * (4.0 * M_PI - missing[k]) * v;
+    t1 += tau * (4.0 * M_PI - missing[k]) * dv;
+  }
+  const double fR = block_sum<kCompGradBS>(t0, red);
+  const double dfR = block_sum<kCompGradBS>(t1, red);
+  if (threadIdx.x == 0) {
+    a.cf[2 * b] = fR;
+    a.cf[2 * b + 1] = dfR;
+  }
+  for (int k = threadIdx.x; k < g.n_z; k += kCompGradBS) {
+    double dv;
+    const double v = vol(k, dv);
+    const size_t i = (size_t)b * g.n_z + k;
+    ntot_eff[i] = fR * ntot[k] + missing[k] * v;
+    dntot[i] = dfR * ntot[k] + missing[k] * dv;
+    const size_t c0 = (size_t)b * 2 * g.n_z + k, c1 = c0 + g.n_z;
+    const double dvg = dv * a.gz64[i];
+    a.cv64[c0] = v;
+    a.cv64[c1] = dvg;
+    a.cv32[c0] = (float)v;
+    a.cv32[c1] = (float)dvg;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Bandwidth and its derivatives, one (event, lambda) per workgroup: W1, W2,
 // M1 = sum w (z - s), M2 = sum w (z - s)^2 (s: the event's first redshift)
@@ -386,12 +449,66 @@ __device__ __forceinline__ void window_sums(const CT* __restrict__ nrow,
   }
 }
 
+// The same sums with an incomplete catalogue: the row is f_R n_r + (1 - P_r) v
+// (mrow = 1 - P_r, vz = v on the grid), so a and the six derivative sums take
+// that row in place of n_r, and d/dOm adds the row's own derivative
+// f_R' n_r g + (1 - P_r) v' g (dvg = v' g).  A separate function keeps the
+// plain one's registers.
+template <class CT>
+__device__ __forceinline__ void window_sums_c(const CT* __restrict__ nrow,
+                                              const CT* __restrict__ mrow,
+                                              const CT* __restrict__ gz, const CT* __restrict__ gf,
+                                              const CT* __restrict__ vz,
+                                              const CT* __restrict__ dvg, CT fR, CT dfR,
+                                              int fstride, int off, int lo, int hi, double u0,
+                                              double dz, CT K, CT r, CT qr, CT& sA, CT& sB,
+                                              CT& sC, CT (&sE)[6]) {
+  auto step = [&](CT n, CT m, CT gv, const CT (&fv)[6], CT v, CT dv, CT u) {
+    const CT kn = n * K, km = m * K;
+    const CT bk = fma(km, v, kn * fR);
+    const CT av = bk * gv;
+    sA += av;
+    const CT t = av * u;
+    sB += t;
+    sC = fma(t, u, sC);
+#pragma unroll
+    for (int p = 0; p < 6; ++p) sE[p] = fma(bk, fv[p], sE[p]);
+    sE[0] = fma(kn, dfR * gv, fma(km, dv, sE[0]));
+    K *= r;
+    r *= qr;
+  };
+  int gi = lo;
+  for (; gi + 1 <= hi; gi += 2) {
+    CT nv[2], mv[2], gv[2], fv[2][6], vv[2], dv[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      nv[i] = nrow[gi + i];
+      mv[i] = mrow[gi + i];
+      gv[i] = gz[gi + i - off];
+      vv[i] = vz[gi + i - off];
+      dv[i] = dvg[gi + i - off];
+#pragma unroll
+      for (int p = 0; p < 6; ++p) fv[i][p] = gf[p * fstride + gi + i - off];
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+      step(nv[i], mv[i], gv[i], fv[i], vv[i], dv[i], (CT)(u0 + (double)(gi + i - lo) * dz));
+  }
+  for (; gi <= hi; ++gi) {
+    CT fv[6];
+#pragma unroll
+    for (int p = 0; p < 6; ++p) fv[p] = gf[p * fstride + gi - off];
+    step(nrow[gi], mrow[gi], gz[gi - off], fv, vz[gi - off], dvg[gi - off],
+         (CT)(u0 + (double)(gi - lo) * dz));
+  }
+}
+
 // Kernel sums and their parameter contractions, one (event, lambda) per
 // workgroup, one sample per thread, from the coefficients the bandwidth
 // kernel stored.  The grid factor and its six derivatives over the union of
 // the workgroup's windows are copied to LDS once (when they fit), so that
 // each grid point reads only the sample's catalogue row from memory.
-template <bool F32>
+template <bool F32, bool COMPL>
 __global__ __launch_bounds__(kGradBS) void k_event_grad(GradArgs a) {
   int e, b;
   if (!decode_item_lambda(a.E, a.B, e, b)) return;
@@ -425,6 +542,12 @@ __global__ __launch_bounds__(kGradBS) void k_event_grad(GradArgs a) {
                       : (const CT*)(a.gz64 + (size_t)b * a.g.n_z);
   const CT* gft = F32 ? (const CT*)(a.gf32 + (size_t)b * 6 * a.g.n_z)
                       : (const CT*)(a.gf64 + (size_t)b * 6 * a.g.n_z);
+  // the completion parts (incomplete catalogue): v and v' g, f_R and f_R'
+  const CT* mzt = COMPL ? (F32 ? (const CT*)a.mz32 : (const CT*)a.mz64) : nullptr;
+  const CT* cvt = COMPL ? (F32 ? (const CT*)(a.cv32 + (size_t)b * 2 * a.g.n_z)
+                               : (const CT*)(a.cv64 + (size_t)b * 2 * a.g.n_z))
+                        : nullptr;
+  const CT fR = COMPL ? (CT)a.cf[2 * b] : (CT)1, dfR = COMPL ? (CT)a.cf[2 * b + 1] : (CT)0;
   const int nz = a.g.n_z;
   const double* scb = a.sc + (size_t)b * 2 * a.S;
   const CT* sdb = (const CT*)a.sd + (size_t)b * kSD * a.S;
@@ -445,12 +568,17 @@ __global__ __launch_bounds__(kGradBS) void k_event_grad(GradArgs a) {
   const int A_lo = max(-mx[0], 0), A_hi = min(mx[1], nz - 1);
   const int span = A_hi - A_lo + 1;
   CT* sg = reinterpret_cast<CT*>(gsm);
-  const bool staged = span > 0 && 7 * span <= kGradStageElems;
+  CT* sgb = sg + 7 * span;                     // v and v' g after g and its derivatives
+  const bool staged = span > 0 && (COMPL ? 9 : 7) * span <= kGradStageElems;
   if (staged) {
     for (int k = threadIdx.x; k < span; k += kGradBS) sg[k] = gzt[A_lo + k];
     for (int p = 0; p < 6; ++p)
       for (int k = threadIdx.x; k < span; k += kGradBS)
         sg[(1 + p) * span + k] = gft[(size_t)p * nz + A_lo + k];
+    if (COMPL)
+      for (int p = 0; p < 2; ++p)
+        for (int k = threadIdx.x; k < span; k += kGradBS)
+          sgb[p * span + k] = cvt[(size_t)p * nz + A_lo + k];
     __syncthreads();
   }
   double acc[1 + kNG];
@@ -469,11 +597,20 @@ __global__ __launch_bounds__(kGradBS) void k_event_grad(GradArgs a) {
     const CT K = (CT)exp(-0.5 * u0 * u0 * inv_h2);
     const CT r = (CT)exp(-(2.0 * u0 * dz + dz * dz) * 0.5 * inv_h2);
     const CT* nrow = nzt + (size_t)a.samp_row[q] * nz;
+    const CT* mrow = COMPL ? mzt + (size_t)a.samp_row[q] * nz : nullptr;
     CT sA = 0, sB = 0, sC = 0, sE[6] = {0, 0, 0, 0, 0, 0};
-    if (staged)
+    if (COMPL) {
+      if (staged)
+        window_sums_c<CT>(nrow, mrow, sg, sg + span, sgb, sgb + span, fR, dfR, span, A_lo, lo, hi,
+                          u0, dz, K, r, qr, sA, sB, sC, sE);
+      else
+        window_sums_c<CT>(nrow, mrow, gzt, gft, cvt, cvt + nz, fR, dfR, nz, 0, lo, hi, u0, dz, K,
+                          r, qr, sA, sB, sC, sE);
+    } else if (staged) {
       window_sums<CT>(nrow, sg, sg + span, span, A_lo, lo, hi, u0, dz, K, r, qr, sA, sB, sC, sE);
-    else
+    } else {
       window_sums<CT>(nrow, gzt, gft, nz, 0, lo, hi, u0, dz, K, r, qr, sA, sB, sC, sE);
+    }
     const double A = (double)sA, Bz = (double)sB * inv_h2, Chh = (double)sC * inv_h2;
     acc[0] += cw * A;
     // distance parameters: weight, z-shift, bandwidth, grid factor (H0: g ~ H0)
@@ -541,9 +678,10 @@ __global__ __launch_bounds__(kSelGradBS) void k_selection_grad(SelGradArgs a) {
     int kk = (int)pos;
     kk = kk > a.g.n_z - 2 ? a.g.n_z - 2 : kk;
     const double t = pos - (double)kk;
-    const double nt = a.ntot[kk] + t * (a.ntot[kk + 1] - a.ntot[kk]);
+    const double* ntot = a.ntot + (size_t)b * a.ntot_stride;
+    const double nt = ntot[kk] + t * (ntot[kk + 1] - ntot[kk]);
     if (!(nt > 0.0)) continue;
-    const double slope = (a.ntot[kk + 1] - a.ntot[kk]) * a.g.inv_dz;   // dn_tot/dz
+    const double slope = (ntot[kk + 1] - ntot[kk]) * a.g.inv_dz;   // dn_tot/dz
     const double x = sg.x, zp1 = sg.zp1;
     const double Dx = P.dh * zp1 * (d.q + d.qp);
     // second x-derivative of d_L^gw: dh e^x (q + 2 q' + q'')
@@ -562,6 +700,10 @@ __global__ __launch_bounds__(kSelGradBS) void k_selection_grad(SelGradArgs a) {
     acc[1 + kNG] += s * s;
 #pragma unroll
     for (int p = 0; p < 4; ++p) acc[1 + p] += s * (sg.dlw[p] + dls_dx * sg.dx[p] - dd[p]);
+    if (a.dntot_om) {          // n_tot^eff's own Om dependence (incompleteness)
+      const double* dn = a.dntot_om + (size_t)b * a.g.n_z;
+      acc[2] += s * (dn[kk] + t * (dn[kk + 1] - dn[kk])) / nt;
+    }
 #pragma unroll
     for (int p = 4; p < kNS; ++p) acc[1 + p] += s * sg.dlw[p];
 #pragma unroll
@@ -623,13 +765,18 @@ __global__ __launch_bounds__(kGFinBS) void k_grad_final(GradFinalArgs a) {
 
 // ---------------------------------------------------------------------------
 hipError_t launch_grad(const GradArgs& a, const SelGradArgs& sa, GradFinalArgs fa, bool f32,
-                       hipStream_t st) {
+                       hipStream_t st, const double* ntot, const double* missing) {
   k_lam_grad_prepare<<<(a.B + 63) / 64, 64, 0, st>>>(a.P, a.B, a.Q);
   CH_LAUNCH_CHECK();
   const long long ng = (long long)a.B * a.g.n_z;
   k_grid_grad<<<(unsigned)((ng + 255) / 256), 256, 0, st>>>(a.P, a.chi, a.chio, a.gz64, a.g,
                                                              a.B, a.gf64, a.gf32);
   CH_LAUNCH_CHECK();
+  if (a.mz64) {
+    k_completion_grad<<<a.B, kCompGradBS, 0, st>>>(a, ntot, missing, const_cast<double*>(sa.ntot),
+                                                   const_cast<double*>(sa.dntot_om));
+    CH_LAUNCH_CHECK();
+  }
   if (sa.nchunk > 0) {
     dim3 grid(sa.nchunk, sa.B);
     k_selection_grad<<<grid, kSelGradBS, 0, st>>>(sa);
@@ -639,8 +786,14 @@ hipError_t launch_grad(const GradArgs& a, const SelGradArgs& sa, GradFinalArgs f
   if (a.E > 0) {
     k_event_bandwidth_grad<<<(unsigned)nb, kGradBS, 0, st>>>(a);
     CH_LAUNCH_CHECK();
-    if (f32) k_event_grad<true><<<(unsigned)nb, kGradBS, kGradStageElems * sizeof(float), st>>>(a);
-    else k_event_grad<false><<<(unsigned)nb, kGradBS, kGradStageElems * sizeof(double), st>>>(a);
+    const size_t lds32 = kGradStageElems * sizeof(float), lds64 = kGradStageElems * sizeof(double);
+    if (a.mz64) {
+      if (f32) k_event_grad<true, true><<<(unsigned)nb, kGradBS, lds32, st>>>(a);
+      else k_event_grad<false, true><<<(unsigned)nb, kGradBS, lds64, st>>>(a);
+    } else {
+      if (f32) k_event_grad<true, false><<<(unsigned)nb, kGradBS, lds32, st>>>(a);
+      else k_event_grad<false, false><<<(unsigned)nb, kGradBS, lds64, st>>>(a);
+    }
     CH_LAUNCH_CHECK();
   }
   k_grad_final<<<a.B, kGFinBS, 0, st>>>(fa);

@@ -218,6 +218,13 @@ struct GradArgs {
   float* gf32;
   const double* nz64;
   const float* nz32;
+  // incomplete catalogue (null otherwise): the rows' 1 - P_compl and, per
+  // lambda, the completion density v and (dv/dOm) g on the grid, f_R, df_R/dOm
+  const double* mz64;
+  const float* mz32;
+  double* cv64;             // [B][2][n_z]
+  float* cv32;
+  double* cf;               // [B][2]
   const int* ev_samp_off;
   const int* samp_row;      // catalogue row of each sample
   const double* samp_c;     // c_ir of each sample's pixel
@@ -248,7 +255,9 @@ struct SelGradArgs {
   const double2* inv;
   const double2* dtab;
   Geometry g;
-  const double* ntot;
+  const double* ntot;       // [n_z], or [B][n_z] when ntot_stride = n_z (incompleteness)
+  long long ntot_stride;
+  const double* dntot_om;   // [B][n_z] d n_tot / d Om (incompleteness), or null
   const double* dl;
   const double* lndl;
   const double* m1d;
@@ -285,8 +294,12 @@ __host__ __device__ inline double neff_of(double s1, double s2, long long n_tota
 
 hipError_t launch_chi_om_table(const LamParams* P, int B, const Geometry& g, double2* chio,
                                hipStream_t st);
+// With an incomplete catalogue (a.mz64 set) ntot / missing are the catalogue's
+// n_tot and M(z), and sa.ntot / sa.dntot_om receive the per-lambda n_tot^eff
+// and its Om derivative.
 hipError_t launch_grad(const GradArgs& a, const SelGradArgs& sa, GradFinalArgs fa, bool f32,
-                       hipStream_t st);
+                       hipStream_t st, const double* ntot = nullptr,
+                       const double* missing = nullptr);
 int selection_grad_chunks(long long n_det);
 
 // ---------------------------------------------------------------------------
