@@ -276,12 +276,17 @@ chimera_status chimera_set_neff_gate(chimera_ctx* ctx, double factor);
  * are multiplied by
  *   S(m) = 0 for m <= mmin, 1 for m >= mmin + delta_m, and
  *   1 / (exp(delta_m/m' + delta_m/(m' - delta_m)) + 1) between, m' = m - mmin,
- * and normalised again on their supports: p(m1) by 1 - int p(m1) (1 - S) dm,
- * p(m2|m1) by int_mmin^m1 m^beta S dm; both integrals over the smoothed
- * range come from a per-lambda table of 4096 Gauss-Legendre panels (cubic
- * Hermite between its nodes; the power law's closed form beyond).  The
- * masses' smoothing is computed in FP64 in both precisions.  delta_m = 0
- * gives the unsmoothed model bitwise.  on = 0 returns to 14-entry rows.
+ * and normalised again on their supports: p(m1) by N1 = int p(m1) S dm,
+ * p(m2|m1) by C(m1) = int_mmin^m1 m^beta S dm.  Per lambda a table on 4097
+ * equal nodes of [mmin, min(mmax, mmin + delta_m)] holds C / (m^beta S) and
+ * its derivative (Gauss-Legendre panels, sub-divided where S rises steeply;
+ * cubic Hermite between the nodes), so the weights keep their relative
+ * accuracy far down the edge; past the edge C is the table's end plus the
+ * power law's closed form.  In FP32 mode an event's weights are formed as
+ * logs and scaled by a per-(event, lambda) factor that ln I_i takes back,
+ * so events whose weights all lie below FP32's range keep a finite ln I_i.
+ * delta_m = 0 gives the unsmoothed model bitwise.  on = 0 returns to
+ * 14-entry rows.
  * chimera_lnl_grad refuses a context with it on (EINVAL).  Applies to later
  * calls; do not change it while calls are in flight.  EINVAL for on not 0/1. */
 chimera_status chimera_set_mass_smoothing(chimera_ctx* ctx, int32_t on);
