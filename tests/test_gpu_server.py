@@ -138,3 +138,53 @@ def test_host_calls_from_two_threads_on_one_stream():
     ctx.close()
     assert not errs, errs
     assert all(o is None for row in out for o in row), out
+
+
+def test_served_results_with_the_population_options():
+    """With an incomplete catalogue and the smoothed mass edge the server takes
+    lambda rows of 15 (delta_m last), refuses rows of 14, and each served
+    result equals the request alone bitwise."""
+    from paper_2504_02034_amd import chimera
+    from paper_2504_02034_amd.server import HipExecutor, Server
+    h = handcrafted()
+    ctx = chimera.Context(n_z=h["n_z"], z_lo=h["z_lo"], z_hi=h["z_hi"])
+    ctx.set_catalog(h["rows"], h["nz_tot"])
+    ctx.set_injections(h["idl"], h["im1"], h["im2"], h["lnp"], h["ninj"])
+    es = ctx.add_events(h["ev_pix_off"], h["pix_samp_off"], h["pix_row"], h["c_ir"], h["dl"],
+                        h["m1"], h["m2"])
+    grid = np.linspace(h["z_lo"], h["z_hi"], h["n_z"])
+    p_rows = np.stack([1.0 / (1.0 + np.exp((grid - (0.5 + 0.15 * r)) / 0.1))
+                       for r in range(h["rows"].shape[0])])
+    ctx.set_completeness(p_rows, 4.0 * np.pi * (0.2 + 0.6 / (1.0 + np.exp(-(grid - 0.8) / 0.2))))
+    ctx.set_mass_smoothing(True)
+    srv = Server(HipExecutor(ctx, max_fused=32), n_workers=3, max_fused=32)
+    try:
+        with pytest.raises(ValueError):
+            srv.submit(es, np.tile(synth.LAMBDA_TRUTH, (2, 1)), 0)
+        reqs, lock = [], threading.Lock()
+
+        def client(seed):
+            rng = np.random.default_rng(seed)
+            for _ in range(8):
+                B = int(rng.integers(1, 12))
+                lam = np.tile(np.append(synth.LAMBDA_TRUTH, 4.8), (B, 1))
+                lam[:, 0] = rng.uniform(40, 120, B)
+                lam[:, 14] = rng.uniform(0.01, 10.0, B)
+                prec = int(rng.integers(2))
+                t = srv.submit(es, lam, prec)
+                with lock:
+                    reqs.append((t, lam, prec))
+
+        th = [threading.Thread(target=client, args=(s,)) for s in range(3)]
+        for t in th:
+            t.start()
+        for t in th:
+            t.join()
+        served = [srv.wait(t, timeout=120) for t, _, _ in reqs]
+    finally:
+        srv.close()
+    for got, (t, lam, prec) in zip(served, reqs):
+        alone = ctx.lnl(es, lam, prec)
+        assert np.array_equal(got, alone, equal_nan=True)
+    assert np.isfinite(np.concatenate(served)).any()
+    ctx.close()
