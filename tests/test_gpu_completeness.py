@@ -113,3 +113,29 @@ def test_cleared_gives_the_complete_catalogue_bitwise_and_refusals(setup):
         ctx.lnl_grad(sets["many1d"], lam[:2], chimera.CHIMERA_FP64)
     finally:
         ctx.set_completeness(p_rows, missing)
+
+
+def test_empty_and_full_completeness_limits(setup):
+    """P_compl = 0 everywhere (every row is the completion density alone) and
+    P_compl = 1 (the catalogue rows times f_R) against the oracle (1e-10)."""
+    import oracle
+    d, chimera, ctx, sets, o_cat, lam, plain, p_rows, missing = setup
+    area = synth.pixel_area(d.wl.nside)
+    npix = 12 * d.wl.nside ** 2
+    try:
+        for val in (0.0, 1.0):
+            pr = np.full_like(p_rows, val)
+            ms = np.full(missing.shape, 4.0 * math.pi * (1.0 - val))
+            ctx.set_completeness(pr, ms)
+            lnl, lnI = ctx.lnl(sets["many1d"], lam[:2], chimera.CHIMERA_FP64, with_lnI=True)
+            c = copy.copy(o_cat)
+            c.p_compl = {k: np.full(d.grid.size, val) for k in o_cat.p_compl}
+            c.missing = ms
+            for b in range(2):
+                ref = oracle.likelihood.lnl(d.o_events, c, d.o_inj, lam[b], T=8.6)
+                assert close(lnl[b], ref["lnl"], REL64), (val, b, lnl[b], ref["lnl"])
+                for i in range(lnI.shape[1]):
+                    assert close(lnI[b, i], ref["lnI"][i], REL64), (val, b, i)
+    finally:
+        ctx.set_completeness(p_rows, missing)
+    assert area * npix == pytest.approx(4.0 * math.pi, rel=1e-12)

@@ -180,3 +180,19 @@ def test_other_kernels_with_the_smoothed_edge(setup, kernel, shape, n_bins):
     assert close(lnl[0], ref["lnl"], REL64), (lnl[0], ref["lnl"])
     for i in range(lnI.shape[1]):
         assert close(lnI[0, i], ref["lnI"][i], REL64), (i, lnI[0, i], ref["lnI"][i])
+
+
+def test_narrow_edges_at_the_prior_bound(setup):
+    """delta_m at and near the lower bound of Table 1's prior (0.01): the
+    table's panels are 2.4e-6 wide and S rises within a few of them."""
+    import oracle
+    d, chimera, ctx, sets, lam, lam15, plain, plain_xi = setup
+    rows = np.stack([np.append(synth.LAMBDA_TRUTH, dm) for dm in (0.01, 0.05, 0.3)])
+    lnl, lnI = ctx.lnl(sets["many1d"], rows, chimera.CHIMERA_FP64, with_lnI=True)
+    l32 = ctx.lnl(sets["many1d"], rows, chimera.CHIMERA_FP32)
+    assert np.all(np.isfinite(lnl)) and np.max(np.abs(l32 - lnl)) <= 1e-3
+    for b in range(rows.shape[0]):
+        ref = oracle.likelihood.lnl(d.o_events, d.o_cat, d.o_inj, rows[b], T=8.6)
+        assert close(lnl[b], ref["lnl"], REL64), (b, lnl[b], ref["lnl"])
+        for i in range(lnI.shape[1]):
+            assert close(lnI[b, i], ref["lnI"][i], REL64), (b, i, lnI[b, i], ref["lnI"][i])
