@@ -156,3 +156,42 @@ def test_hbm_budget_bounds_a_call(chimera):
         ctx.lnl_grad(es, synth.LAMBDA_TRUTH[None, :])
     assert status(e) == chimera.CHIMERA_ENOMEM
     ctx.close()
+
+
+def test_population_option_arguments(chimera):
+    """chimera_set_completeness, chimera_set_mass_smoothing and
+    chimera_lambda_width: null and out-of-range arguments, call order, and a
+    replaced catalogue dropping the completeness."""
+    import ctypes
+    lib = chimera.lib
+    assert lib.chimera_set_mass_smoothing(None, 1) == chimera.CHIMERA_EINVAL
+    ctx0 = chimera.Context(n_z=N_Z, z_lo=0.0, z_hi=1.6)
+    with pytest.raises(chimera.ChimeraError) as e:
+        ctx0.set_completeness(np.full((3, N_Z), 0.5), np.zeros(N_Z))
+    assert status(e) == chimera.CHIMERA_ESTATE
+    assert lib.chimera_lambda_width(ctx0.handle, None) == chimera.CHIMERA_EINVAL
+    w = ctypes.c_int32()
+    assert lib.chimera_lambda_width(ctx0.handle, ctypes.byref(w)) == 0 and w.value == 14
+    ctx0.close()
+    ctx = context(chimera)
+    es = ctx.add_events(*events())
+    lam = synth.LAMBDA_TRUTH[None, :]
+    plain = ctx.lnl(es, lam)
+    p = np.full((3, N_Z), 0.5)
+    for bad_p, bad_m in ((p, None), (p, np.full(N_Z, 13.0)), (p, np.full(N_Z, -0.1)),
+                         (np.full((3, N_Z), -0.2), np.zeros(N_Z))):
+        with pytest.raises(chimera.ChimeraError) as e:
+            ctx.set_completeness(bad_p, bad_m)
+        assert status(e) == chimera.CHIMERA_EINVAL
+    assert np.array_equal(ctx.lnl(es, lam), plain)        # refused calls change nothing
+    ctx.set_completeness(p, np.full(N_Z, 2.0 * np.pi))
+    assert not np.array_equal(ctx.lnl(es, lam), plain)
+    rows, tot = catalog(3)
+    ctx.set_catalog(rows, tot)                             # a new catalogue is complete
+    assert np.array_equal(ctx.lnl(es, lam), plain)
+    ctx.set_mass_smoothing(True)
+    assert ctx.lam_width == 15
+    with pytest.raises(ValueError):
+        ctx.lnl(es, lam)
+    assert np.isfinite(ctx.lnl(es, np.append(synth.LAMBDA_TRUTH, 4.8)[None, :])[0])
+    ctx.close()
