@@ -334,7 +334,7 @@ def population_bench(ctx, es, wl, p, lam_t, many, steps, warmup):
     return out
 
 
-def serve_bench(wl, cf, inj, n_requests=300, seed=5, max_pass_s=0.05):
+def serve_bench(wl, cf, inj, n_requests=300, seed=5, max_pass_s=0.05, chunk_gb=4.0):
     """Serving: resident event sets of 50, 300, 1000 and 3000 distinct events
     x 4096 samples (nested subsets of one generated set of 3000) sharing the
     workload's catalogue and injections; a Poisson trace of requests, sizes
@@ -364,7 +364,7 @@ def serve_bench(wl, cf, inj, n_requests=300, seed=5, max_pass_s=0.05):
     base = synth.make_lambdas(synth.WORKLOADS["precision_300ev"])
     lams = [base[rng.integers(0, base.shape[0], b)] for b in B]
     gaps = rng.exponential(1.0, n_requests)
-    ex = HipExecutor(ctx, max_fused=512)
+    ex = HipExecutor(ctx, max_fused=512, chunk_bytes=int(chunk_gb * (1 << 30)))
     biggest = max(ex.scratch_bytes(sets[w], int(b), chimera.CHIMERA_FP32) for b, w in zip(B, which))
     budget = int(2.5 * biggest)
     # short requests (up to the scratch of 128 points on the 300-event set) go
@@ -449,6 +449,7 @@ def serve_bench(wl, cf, inj, n_requests=300, seed=5, max_pass_s=0.05):
                         "scratch_held_after_gb": round(held / 2**30, 2),
                         "hbm_budget_gb": round(budget / 2**30, 2),
                         "max_pass_ms": round(max_pass_s * 1e3, 1),
+                        "launch_chunk_gb": chunk_gb,
                         "small_request_gb": round(small / 2**30, 3), "reserved_workers": 1,
                         "small_requests": int(is_small.sum()),
                         "small_wait_p99_ms": round(float(np.percentile(wait32[is_small], 99)) * 1e3, 3),
@@ -529,6 +530,9 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-grad", action="store_true")
     ap.add_argument("--no-photo", action="store_true")
+    ap.add_argument("--serve-chunk-gb", type=float, default=4.0,
+                    help="the server's launch sequences of at most this much per-point scratch "
+                         "(0: one per fused batch)")
     ap.add_argument("--no-population", action="store_true",
                     help="skip the incomplete-catalogue and smoothed-mass-edge steps")
     ap.add_argument("--no-variants", action="store_true",
@@ -632,7 +636,7 @@ def main():
                                                        args.warmup)
     ctx.close()
     if not args.no_serve:
-        line["serving"] = serve_bench(wl, cf, inj)
+        line["serving"] = serve_bench(wl, cf, inj, chunk_gb=args.serve_chunk_gb)
     if not args.no_photo:
         log("photometric workload")
         line["photometric"] = photo_bench((1.0,) if args.photo_one else (0.6, 1.0, 1.8))

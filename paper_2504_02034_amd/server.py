@@ -66,7 +66,12 @@ class Ticket:
 class HipExecutor:
     """Runs fused requests through chimera_lnl_batch on a per-worker stream,
     with per-worker pinned host and device buffers for lambda and ln L (no
-    allocation per request)."""
+    allocation per request).  chunk_bytes > 0 cuts a batch into launch
+    sequences of at most that much per-point scratch (about that much work),
+    enqueued back to back on the worker's stream: the device then interleaves
+    other streams' kernels between them, so a short request does not wait for
+    a whole large batch's kernels.  Each point's result does not depend on the
+    chunking."""
 
     class Worker:
         def __init__(self, torch, max_fused):
@@ -78,11 +83,12 @@ class HipExecutor:
             self.out_d = torch.empty(max_fused, dtype=torch.float64, device="cuda")
             self.done = torch.cuda.Event()
 
-    def __init__(self, ctx, max_fused: int = 512):
+    def __init__(self, ctx, max_fused: int = 512, chunk_bytes: int = 0):
         import torch
         self.torch = torch
         self.ctx = ctx
         self.max_fused = max_fused
+        self.chunk_bytes = chunk_bytes
 
     @property
     def lam_width(self) -> int:
@@ -105,9 +111,16 @@ class HipExecutor:
         lam_h = worker.lam_h[:B * W].view(B, W)
         lam_d = worker.lam_d[:B * W].view(B, W)
         lam_h.copy_(torch.from_numpy(lam))
+        step = B
+        if self.chunk_bytes > 0 and B > 1:
+            one = self.scratch_bytes(events, 1, prec)
+            per = max(self.scratch_bytes(events, 2, prec) - one, 1)
+            step = max(1, min(B, int(self.chunk_bytes // per)))
         with torch.cuda.stream(worker.stream):
             lam_d.copy_(lam_h, non_blocking=True)
-            self.ctx.lnl(events, lam_d, prec, lnl=worker.out_d[:B], stream=worker.stream)
+            for i in range(0, B, step):
+                self.ctx.lnl(events, lam_d[i:i + step], prec, lnl=worker.out_d[i:i + step],
+                             stream=worker.stream)
             worker.out_h[:B].copy_(worker.out_d[:B], non_blocking=True)
             worker.done.record(worker.stream)
         worker.done.synchronize()

@@ -1,8 +1,9 @@
 """The continuous-batching server on the device: requests from concurrent
 clients over two resident event sets and both precisions, fused and
 overlapped on several streams under an HBM budget that binds, first come
-first served or short requests first, each result
-equal (bitwise) to the same request evaluated alone, and the scratch the
+first served or short requests first (then with batches cut into launch
+sequences of a few points), each result equal (bitwise) to the same request
+evaluated alone, and the scratch the
 library holds (and the device memory in use) within the budget.  Also: host
 calls from two threads on one stream, each equal to the same call alone."""
 import threading
@@ -32,6 +33,9 @@ def test_served_results_equal_the_request_alone(short_first):
                           h["dl"][:k], h["m1"][:k], h["m2"][:k])
     import torch
     ex = HipExecutor(ctx, max_fused=48)
+    if short_first:      # launch sequences of about 5 points: the results must not change
+        ex.chunk_bytes = 5 * (ex.scratch_bytes(full, 2, chimera.CHIMERA_FP64)
+                              - ex.scratch_bytes(full, 1, chimera.CHIMERA_FP64))
     budget = 3 * ex.scratch_bytes(full, 48, chimera.CHIMERA_FP64)
     torch.cuda.synchronize()
     free0, _ = torch.cuda.mem_get_info()
