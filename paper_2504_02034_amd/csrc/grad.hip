@@ -396,23 +396,40 @@ __global__ __launch_bounds__(kGradBS) void k_event_bandwidth_grad(GradArgs a) {
   }
 }
 
-// A sample's window sums: A = sum a, sum a u, sum a u^2 (a = n_r g K) and six
-// sum n_r K g dln g/dp, by the Gaussian ratio recurrence.  Grid point g of
-// the grid factor is gz[g - off], of derivative p gf[p fstride + g - off]
-// (the workgroup's LDS copy or the tables themselves); 4 points per
-// iteration keep their loads in flight together.
+// A sample's window sums: A = sum a, sum a m, sum a m^2 (a = n_r g K, m the
+// grid offset from the grid point nearest the sample, exact in either
+// precision, so u = m dz + delta) and six sum n_r K g dln g/dp, by the
+// Gaussian ratio recurrence.  Grid point g of the grid factor is gz[g - off],
+// of derivative p gf[p fstride + g - off] (the workgroup's LDS copy or the
+// tables themselves); 4 points per iteration keep their loads in flight
+// together.
 template <class CT>
 __device__ __forceinline__ void window_sums(const CT* __restrict__ nrow,
                                             const CT* __restrict__ gz,
                                             const CT* __restrict__ gf, int fstride, int off,
-                                            int lo, int hi, double u0, double dz, CT K, CT r,
-                                            CT qr, CT& sA, CT& sB, CT& sC, CT (&sE)[6]) {
+                                            int lo, int hi, CT m0, CT K, CT r, CT qr, CT& sA,
+                                            CT& sB, CT& sC, CT (&sE)[6]) {
   int gi = lo;
+  // FP32: the catalogue row one block ahead (the last block's start is read
+  // again at the end, so every read stays inside [lo, hi]); FP64 has no
+  // registers to spare for it
+  constexpr bool PF = sizeof(CT) == 4;
+  CT nx[4];
+  if (PF && gi + 3 <= hi) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) nx[i] = nrow[gi + i];
+  }
   for (; gi + 3 <= hi; gi += 4) {
     CT nv[4], gv[4], fv[6][4];
+    const int gn = min(gi + 4, hi - 3);
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      nv[i] = nrow[gi + i];
+      if (PF) {
+        nv[i] = nx[i];
+        nx[i] = nrow[gn + i];
+      } else {
+        nv[i] = nrow[gi + i];
+      }
       gv[i] = gz[gi + i - off];
     }
 #pragma unroll
@@ -421,7 +438,7 @@ __device__ __forceinline__ void window_sums(const CT* __restrict__ nrow,
       for (int i = 0; i < 4; ++i) fv[p][i] = gf[p * fstride + gi + i - off];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const CT u = (CT)(u0 + (double)(gi + i - lo) * dz);
+      const CT u = m0 + (CT)i;
       const CT bk = nv[i] * K;
       const CT av = bk * gv[i];
       sA += av;
@@ -433,9 +450,11 @@ __device__ __forceinline__ void window_sums(const CT* __restrict__ nrow,
       K *= r;
       r *= qr;
     }
+    m0 += (CT)4;
   }
   for (; gi <= hi; ++gi) {
-    const CT u = (CT)(u0 + (double)(gi - lo) * dz);
+    const CT u = m0;
+    m0 += (CT)1;
     const CT bk = nrow[gi] * K;
     const CT av = bk * gz[gi - off];
     sA += av;
@@ -460,9 +479,9 @@ __device__ __forceinline__ void window_sums_c(const CT* __restrict__ nrow,
                                               const CT* __restrict__ gz, const CT* __restrict__ gf,
                                               const CT* __restrict__ vz,
                                               const CT* __restrict__ dvg, CT fR, CT dfR,
-                                              int fstride, int off, int lo, int hi, double u0,
-                                              double dz, CT K, CT r, CT qr, CT& sA, CT& sB,
-                                              CT& sC, CT (&sE)[6]) {
+                                              int fstride, int off, int lo, int hi, CT m0,
+                                              CT K, CT r, CT qr, CT& sA, CT& sB, CT& sC,
+                                              CT (&sE)[6]) {
   auto step = [&](CT n, CT m, CT gv, const CT (&fv)[6], CT v, CT dv, CT u) {
     const CT kn = n * K, km = m * K;
     const CT bk = fma(km, v, kn * fR);
@@ -492,14 +511,15 @@ __device__ __forceinline__ void window_sums_c(const CT* __restrict__ nrow,
     }
 #pragma unroll
     for (int i = 0; i < 2; ++i)
-      step(nv[i], mv[i], gv[i], fv[i], vv[i], dv[i], (CT)(u0 + (double)(gi + i - lo) * dz));
+      step(nv[i], mv[i], gv[i], fv[i], vv[i], dv[i], m0 + (CT)i);
+    m0 += (CT)2;
   }
   for (; gi <= hi; ++gi) {
     CT fv[6];
 #pragma unroll
     for (int p = 0; p < 6; ++p) fv[p] = gf[p * fstride + gi - off];
-    step(nrow[gi], mrow[gi], gz[gi - off], fv, vz[gi - off], dvg[gi - off],
-         (CT)(u0 + (double)(gi - lo) * dz));
+    step(nrow[gi], mrow[gi], gz[gi - off], fv, vz[gi - off], dvg[gi - off], m0);
+    m0 += (CT)1;
   }
 }
 
@@ -596,22 +616,28 @@ __global__ __launch_bounds__(kGradBS) void k_event_grad(GradArgs a) {
     const double u0 = a.g.z_lo + lo_d * dz - z;
     const CT K = (CT)exp(-0.5 * u0 * u0 * inv_h2);
     const CT r = (CT)exp(-(2.0 * u0 * dz + dz * dz) * 0.5 * inv_h2);
+    // offsets from the grid point nearest the sample: u = m dz + delta
+    const double gcd = rint((z - a.g.z_lo) * a.g.inv_dz);
+    const double delta = a.g.z_lo + gcd * dz - z;
+    const CT m0 = (CT)(lo_d - gcd);
     const CT* nrow = nzt + (size_t)a.samp_row[q] * nz;
     const CT* mrow = COMPL ? mzt + (size_t)a.samp_row[q] * nz : nullptr;
     CT sA = 0, sB = 0, sC = 0, sE[6] = {0, 0, 0, 0, 0, 0};
     if (COMPL) {
       if (staged)
         window_sums_c<CT>(nrow, mrow, sg, sg + span, sgb, sgb + span, fR, dfR, span, A_lo, lo, hi,
-                          u0, dz, K, r, qr, sA, sB, sC, sE);
+                          m0, K, r, qr, sA, sB, sC, sE);
       else
-        window_sums_c<CT>(nrow, mrow, gzt, gft, cvt, cvt + nz, fR, dfR, nz, 0, lo, hi, u0, dz, K,
-                          r, qr, sA, sB, sC, sE);
+        window_sums_c<CT>(nrow, mrow, gzt, gft, cvt, cvt + nz, fR, dfR, nz, 0, lo, hi, m0, K, r,
+                          qr, sA, sB, sC, sE);
     } else if (staged) {
-      window_sums<CT>(nrow, sg, sg + span, span, A_lo, lo, hi, u0, dz, K, r, qr, sA, sB, sC, sE);
+      window_sums<CT>(nrow, sg, sg + span, span, A_lo, lo, hi, m0, K, r, qr, sA, sB, sC, sE);
     } else {
-      window_sums<CT>(nrow, gzt, gft, nz, 0, lo, hi, u0, dz, K, r, qr, sA, sB, sC, sE);
+      window_sums<CT>(nrow, gzt, gft, nz, 0, lo, hi, m0, K, r, qr, sA, sB, sC, sE);
     }
-    const double A = (double)sA, Bz = (double)sB * inv_h2, Chh = (double)sC * inv_h2;
+    const double A = (double)sA, sm = (double)sB;
+    const double Bz = (dz * sm + delta * A) * inv_h2;
+    const double Chh = (dz * (dz * (double)sC + 2.0 * delta * sm) + delta * delta * A) * inv_h2;
     acc[0] += cw * A;
     // distance parameters: weight, z-shift, bandwidth, grid factor (H0: g ~ H0)
     const double Eg[4] = {A / P.h0, (double)sE[0], (double)sE[1], (double)sE[2]};
