@@ -21,7 +21,8 @@ crosses them) and are held fixed.  Pieces:
 * kernel sums: dA/dz_j = sum F K (z_g - z_j)/h^2, dA/dh = sum F K (z_g-z_j)^2/h^3,
   and the grid factor g = psi / ((1+z)^3 D') differentiated on the grid;
   the window edges |z_g - z_j| = T h are not differentiated (their terms
-  carry the kernel's value e^(-T^2/2) at the edge);
+  carry the kernel's value e^(-T^2/2) at the edge); the Epanechnikov kernel
+  (Sect. 2.3's compact option) the same way with its polynomial k;
 * selection: s_j = w n_tot psi / ((1+z)^3 D' p_draw) along the same chain,
   with n_tot linear between grid nodes;
 * incomplete catalogue (eqs. p-gal, p-miss, f-R): the rows f_R n_r +
@@ -289,9 +290,17 @@ def bandwidth_grad(z, w, dlw, dz_p, dz_grid):
 # one event, selection, ln L
 # ---------------------------------------------------------------------------
 def event_grad(pix_z, pix_w, pix_dlw, pix_dz, pix_c, pix_rows, grid, tau, gz, dlng, T=None,
-               pix_drows=None):
+               pix_drows=None, shape="gaussian"):
     """(I_i, d ln I_i / dp [12]); pix_drows: d row / d Om of each pixel's row
-    (an incomplete catalogue), or None."""
+    (an incomplete catalogue), or None.
+
+    shape "epanechnikov" (the compact kernel of Sect. 2.3, scaled to variance
+    h^2: 3 / (4 a h) (1 - u^2 / (a h)^2) on |u| <= a h, a = sqrt(5); T unused):
+    with k = 1 - u^2 / (a h)^2 inside the support, dk/dz_j = 2 u / (a h)^2 and
+    dk/dh = 2 u^2 / ((a h)^2 h); k vanishes on the support's edge, so grid
+    points entering or leaving it add nothing to the derivative."""
+    if shape not in ("gaussian", "epanechnikov"):
+        raise ValueError(f"unknown kernel shape {shape!r}")
     dzg = grid[1] - grid[0]
     z = np.concatenate(pix_z)
     w = np.concatenate(pix_w)
@@ -306,13 +315,23 @@ def event_grad(pix_z, pix_w, pix_dlw, pix_dz, pix_c, pix_rows, grid, tau, gz, dl
     for zr, wr, lw, zz, c, nr, dnr in zip(pix_z, pix_w, pix_dlw, pix_dz, pix_c, pix_rows, drs):
         f = tau * nr * gz
         u = grid[None, :] - zr[:, None]
-        k = np.exp(-0.5 * (u / h) ** 2)
-        if T is not None:
-            k = np.where(np.abs(u) <= T * h, k, 0.0)
-        fk = k * f[None, :]
-        A = fk.sum(axis=1)
-        B = (fk * u).sum(axis=1) / h ** 2          # dA/dz_j
-        C = (fk * u * u).sum(axis=1) / h ** 3      # dA/dh
+        if shape == "epanechnikov":
+            ah = L.EPAN_SCALE * h
+            inside = np.abs(u) <= ah
+            k = np.where(inside, 1.0 - (u / ah) ** 2, 0.0)
+            fk = k * f[None, :]
+            fi = np.where(inside, f[None, :], 0.0)
+            A = fk.sum(axis=1)
+            B = 2.0 * (fi * u).sum(axis=1) / ah ** 2              # dA/dz_j
+            C = 2.0 * (fi * u * u).sum(axis=1) / (ah ** 2 * h)    # dA/dh
+        else:
+            k = np.exp(-0.5 * (u / h) ** 2)
+            if T is not None:
+                k = np.where(np.abs(u) <= T * h, k, 0.0)
+            fk = k * f[None, :]
+            A = fk.sum(axis=1)
+            B = (fk * u).sum(axis=1) / h ** 2          # dA/dz_j
+            C = (fk * u * u).sum(axis=1) / h ** 3      # dA/dh
         Eg = fk @ dlng.T                            # [n_j, 12]: sum F K dln g/dp
         S += c * float(wr @ A)
         G += c * (lw @ (wr * A) + zz @ (wr * B) + float(wr @ C) * h * dlnh + Eg.T @ wr)
@@ -320,7 +339,10 @@ def event_grad(pix_z, pix_w, pix_dlw, pix_dz, pix_c, pix_rows, grid, tau, gz, dl
             G[_OM] += c * float(wr @ (k @ (tau * dnr * gz)))
     if not S > 0:
         return 0.0, np.full(NG, np.nan)
-    I = S / (h * math.sqrt(2.0 * math.pi))
+    if shape == "epanechnikov":
+        I = S * 0.75 / (L.EPAN_SCALE * h)
+    else:
+        I = S / (h * math.sqrt(2.0 * math.pi))
     return I, G / S - dlnh
 
 
@@ -354,8 +376,12 @@ def selection_grad(inj: L.InjectionSet, cat: L.Catalog, lam):
     return S1 / inj.n_total, (dls[:, pos] @ s[pos]) / S1
 
 
-def lnl_grad(events, cat: L.Catalog, inj: L.InjectionSet, lam, T=None, kernel="many1d"):
+def lnl_grad(events, cat: L.Catalog, inj: L.InjectionSet, lam, T=None, kernel="many1d",
+             shape="gaussian"):
     """dict(lnl, grad[12], lnI[E], dlnI[E, 12], ln_xi, dln_xi[12]).
+
+    shape: the KDE kernel, "gaussian" or "epanechnikov" (see event_grad), on
+    the unbinned samples.
 
     kernel "single1d" (eq. gw-kernel-single1d): the sum over pixels of S_ir
     times the grid sum of n_r g KDE is, by linearity, the grid sum of
@@ -401,7 +427,7 @@ def lnl_grad(events, cat: L.Catalog, inj: L.InjectionSet, lam, T=None, kernel="m
                 zs.append(z); ws.append(w); lws.append(lw); zzs.append(zz)
                 cs.append(c); rs.append(row); drs.append(drow)
             per_event.append(event_grad(zs, ws, lws, zzs, cs, rs, grid, tau, gz, dlng, T,
-                                        drs if drows is not None else None))
+                                        drs if drows is not None else None, shape))
     except cosmo.NonMonotone:
         return out
     out["ln_xi"] = math.log(xi) if xi > 0 else -np.inf

@@ -223,3 +223,52 @@ def hand_incomplete_plain(cat):
     c.p_compl = None
     c.missing = None
     return c
+
+
+@pytest.mark.parametrize("kernel", ["many1d", "single1d"])
+@pytest.mark.parametrize("lam", [TRUTH, OTHER], ids=["truth", "other"])
+def test_epanechnikov_gradient_vs_differences(hand, lam, kernel):
+    """The compact kernel of Sect. 2.3 (the Epanechnikov option): the
+    analytic gradient against Richardson differences of likelihood.lnl with
+    the same kernel.  dk/dh and dk/dz_j do not vanish at the support's edge,
+    so ln L has a kink wherever a grid point crosses an edge: a difference
+    whose steps straddle one is off (event 2 at OTHER, H0: 7e-5 at 1e-6,
+    4e-10 at 1e-7).  Each parameter is also differenced at a step ten times
+    smaller, and one of the two must agree."""
+    _, structs = hand
+    events, cat, inj = structs
+    res = G.lnl_grad(events, cat, inj, lam, kernel=kernel, shape="epanechnikov")
+    ref = L.lnl(events, cat, inj, lam, kernel=kernel, shape="epanechnikov")
+    assert np.isfinite(ref["lnl"])
+    assert res["lnl"] == pytest.approx(ref["lnl"], rel=1e-13)
+    assert np.allclose(res["lnI"], ref["lnI"], rtol=1e-13, atol=0)
+    f = lambda l: L.lnl(events, cat, inj, l, kernel=kernel, shape="epanechnikov")["lnl"]  # noqa: E731
+    for k, p in enumerate(G.GRAD_INDEX):
+        fds = [G.richardson(f, lam, p, rel_step=st, abs_floor=st) for st in (1e-6, 1e-7)]
+        err = min(abs(res["grad"][k] - fd) / max(1.0, abs(fd)) for fd in fds)
+        assert err <= 1e-6, (k, res["grad"][k], fds)
+
+
+def test_epanechnikov_gradient_differs_from_the_gaussian(hand):
+    """The shape reaches the gradient (a plausible slip would ignore it)."""
+    _, (events, cat, inj) = hand
+    g = G.lnl_grad(events, cat, inj, TRUTH)["grad"]
+    e = G.lnl_grad(events, cat, inj, TRUTH, shape="epanechnikov")["grad"]
+    assert np.all(np.isfinite(e)) and np.max(np.abs(e - g)) > 1e-3 * np.max(np.abs(g))
+
+
+@pytest.mark.parametrize("kernel", ["many1d", "single1d"])
+def test_epanechnikov_gradient_with_incompleteness(hand_incomplete, kernel):
+    """The compact kernel with an incomplete catalogue: the rows' own Om
+    dependence weighted by the polynomial kernel (differences at two steps,
+    as above)."""
+    events, cat, inj = hand_incomplete
+    lam = OTHER
+    res = G.lnl_grad(events, cat, inj, lam, kernel=kernel, shape="epanechnikov")
+    ref = L.lnl(events, cat, inj, lam, kernel=kernel, shape="epanechnikov")
+    assert np.isfinite(ref["lnl"]) and res["lnl"] == pytest.approx(ref["lnl"], rel=1e-13)
+    f = lambda l: L.lnl(events, cat, inj, l, kernel=kernel, shape="epanechnikov")["lnl"]  # noqa: E731
+    for k, p in enumerate(G.GRAD_INDEX):
+        fds = [G.richardson(f, lam, p, rel_step=st, abs_floor=st) for st in (1e-6, 1e-7)]
+        err = min(abs(res["grad"][k] - fd) / max(1.0, abs(fd)) for fd in fds)
+        assert err <= 1e-6, (k, res["grad"][k], fds)
