@@ -391,9 +391,12 @@ chimera_status chimera_release_scratch(chimera_ctx* ctx, void* hip_stream);
  * same results.  With an incomplete catalogue (chimera_set_completeness) the
  * rows f_R n_r + (1 - P_r) v and n_tot^eff add their Om derivatives
  * (f_R' n_r + (1 - P_r) v', f_R' n_tot + M v', with d ln v / d Om =
- * 2 chi'/chi - E'/E - 3 chi'(z_max)/chi(z_max)).  EINVAL for a set with
- * kernel options other than the defaults (chimera_set_event_kde), a 3D set,
- * or a context with the smoothed mass edge on. */
+ * 2 chi'/chi - E'/E - 3 chi'(z_max)/chi(z_max)).  A set with the
+ * Epanechnikov kernel (chimera_set_event_kde, Sect. 2.3's compact option,
+ * unbinned) is differentiated with k = 1 - u^2/W^2 on its support
+ * |u| <= W = sqrt(5) h (dk/dz_j = 2u/W^2, h dk/dh = 2u^2/W^2; k vanishes on
+ * the support's edge).  EINVAL for a binned set (n_bins > 0), a 3D set, or a
+ * context with the smoothed mass edge on. */
 chimera_status chimera_lnl_grad(chimera_ctx* ctx, const chimera_events* ev, const double* lam,
                                 int64_t B, int32_t prec, double* lnl, double* grad, int32_t mem,
                                 void* hip_stream);

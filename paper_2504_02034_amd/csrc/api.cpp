@@ -1652,6 +1652,7 @@ static chimera_status run_grad_chunk(chimera_ctx* ctx, const chimera_events* ev,
   a.lnm1d = ev->lnm1d; a.lnm2d = ev->lnm2d;
   a.E = E; a.B = (int)B; a.S = ev->n_samp; a.f32 = f32 ? 1 : 0;
   a.trunc = f32 ? ctx->cfg.trunc_fp32 : ctx->cfg.trunc_fp64;
+  a.shape = ev->shape;
   sa.P = P; sa.Q = a.Q; sa.flag_mono = fm; sa.flag_range = fr;
   sa.chi = chi; sa.chio = chio; sa.inv = inv; sa.dtab = dtab; sa.g = g;
   sa.ntot = compl_ ? ntot_eff : ctx->ntot;
@@ -1693,9 +1694,9 @@ chimera_status chimera_lnl_grad(chimera_ctx* ctx, const chimera_events* ev, cons
   if (s != CHIMERA_OK) return s;
   if (!ev) return fail(CHIMERA_EINVAL, "null event set");
   if (!lnl || !grad) return fail(CHIMERA_EINVAL, "null output");
-  if (ev->shape != CHIMERA_KDE_GAUSSIAN || ev->n_bins != 0 || ev->V != 0)
+  if (ev->n_bins != 0 || ev->V != 0)
     return fail(CHIMERA_EINVAL,
-                "the adjoint takes the many-1D or single-1D Gaussian kernel on unbinned samples");
+                "the adjoint takes the many-1D or single-1D kernels on unbinned samples");
   if (ctx->nlam != CHIMERA_NLAM)
     return fail(CHIMERA_EINVAL, "the adjoint takes the unsmoothed mass model (no delta_m)");
   return run_grad(ctx, ev, lam, B, prec, lnl, grad, mem, hip_stream);

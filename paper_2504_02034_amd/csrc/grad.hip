@@ -523,12 +523,59 @@ __device__ __forceinline__ void window_sums_c(const CT* __restrict__ nrow,
   }
 }
 
+// The window sums of the Epanechnikov kernel (Sect. 2.3's compact option,
+// k = 1 - u^2 / W^2 on |u| <= W, W = sqrt(5) h): sA = sum a k, sB = sum a u,
+// sC = sum a u^2 (a = r g with r the sample's row, n_r or, with COMPL, the
+// completed row f_R n_r + (1 - P_r) v) and the six sum r k g dln g/dp (plus
+// k (f_R' n_r g + (1 - P_r) v' g) for Om with COMPL), so that
+// dA/dz_j = 2 sB / W^2 and h dA/dh = 2 sC / W^2.  u = m dz + delta with m
+// exact; two points per iteration.
+template <class CT, bool COMPL>
+__device__ __forceinline__ void window_sums_epan(const CT* __restrict__ nrow,
+                                                 const CT* __restrict__ mrow,
+                                                 const CT* __restrict__ gz,
+                                                 const CT* __restrict__ gf,
+                                                 const CT* __restrict__ vz,
+                                                 const CT* __restrict__ dvg, CT fR, CT dfR,
+                                                 int fstride, int off, int lo, int hi, CT m0,
+                                                 CT dzc, CT delta, CT invW2, CT& sA, CT& sB,
+                                                 CT& sC, CT (&sE)[6]) {
+  auto step = [&](int g, CT m) {
+    const CT n = nrow[g];
+    const CT gv = gz[g - off];
+    CT rv = n;
+    CT mr = (CT)0;
+    if (COMPL) {
+      mr = mrow[g];
+      rv = fma(mr, vz[g - off], n * fR);
+    }
+    const CT u = fma(m, dzc, delta);
+    const CT k = fma(-u * invW2, u, (CT)1);
+    const CT av = rv * gv;
+    sA = fma(av, k, sA);
+    const CT t = av * u;
+    sB += t;
+    sC = fma(t, u, sC);
+    const CT bk = rv * k;
+#pragma unroll
+    for (int p = 0; p < 6; ++p) sE[p] = fma(bk, gf[p * fstride + g - off], sE[p]);
+    if (COMPL) sE[0] = fma(k, fma(n, dfR * gv, mr * dvg[g - off]), sE[0]);
+  };
+  int gi = lo;
+  for (; gi + 1 <= hi; gi += 2) {
+    step(gi, m0);
+    step(gi + 1, m0 + (CT)1);
+    m0 += (CT)2;
+  }
+  if (gi <= hi) step(gi, m0);
+}
+
 // Kernel sums and their parameter contractions, one (event, lambda) per
 // workgroup, one sample per thread, from the coefficients the bandwidth
 // kernel stored.  The grid factor and its six derivatives over the union of
 // the workgroup's windows are copied to LDS once (when they fit), so that
 // each grid point reads only the sample's catalogue row from memory.
-template <bool F32, bool COMPL>
+template <bool F32, bool COMPL, bool EPAN>
 __global__ __launch_bounds__(kGradBS) void k_event_grad(GradArgs a) {
   int e, b;
   if (!decode_item_lambda(a.E, a.B, e, b)) return;
@@ -555,7 +602,11 @@ __global__ __launch_bounds__(kGradBS) void k_event_grad(GradArgs a) {
   }
   const int s0 = a.ev_samp_off[e];
   const int ns = a.ev_samp_off[e + 1] - s0;
-  const double dz = a.g.dz, inv_h2 = 1.0 / (h * h), T = a.trunc;
+  const double dz = a.g.dz, inv_h2 = 1.0 / (h * h);
+  // the window's half-width in units of h: the Gaussian's truncation, or the
+  // Epanechnikov kernel's support
+  const double T = EPAN ? kEpanScale : a.trunc;
+  const double W = kEpanScale * h;
   const CT qr = (CT)exp(-dz * dz * inv_h2);
   const CT* nzt = F32 ? (const CT*)a.nz32 : (const CT*)a.nz64;
   const CT* gzt = F32 ? (const CT*)(a.gz32 + (size_t)b * a.g.n_z)
@@ -614,8 +665,8 @@ __global__ __launch_bounds__(kGradBS) void k_event_grad(GradArgs a) {
     if (!(lo_d <= hi_d)) continue;
     const int lo = (int)lo_d, hi = (int)hi_d;
     const double u0 = a.g.z_lo + lo_d * dz - z;
-    const CT K = (CT)exp(-0.5 * u0 * u0 * inv_h2);
-    const CT r = (CT)exp(-(2.0 * u0 * dz + dz * dz) * 0.5 * inv_h2);
+    const CT K = EPAN ? (CT)0 : (CT)exp(-0.5 * u0 * u0 * inv_h2);
+    const CT r = EPAN ? (CT)0 : (CT)exp(-(2.0 * u0 * dz + dz * dz) * 0.5 * inv_h2);
     // offsets from the grid point nearest the sample: u = m dz + delta
     const double gcd = rint((z - a.g.z_lo) * a.g.inv_dz);
     const double delta = a.g.z_lo + gcd * dz - z;
@@ -623,7 +674,16 @@ __global__ __launch_bounds__(kGradBS) void k_event_grad(GradArgs a) {
     const CT* nrow = nzt + (size_t)a.samp_row[q] * nz;
     const CT* mrow = COMPL ? mzt + (size_t)a.samp_row[q] * nz : nullptr;
     CT sA = 0, sB = 0, sC = 0, sE[6] = {0, 0, 0, 0, 0, 0};
-    if (COMPL) {
+    if (EPAN) {
+      const CT invW2 = (CT)(1.0 / (W * W));
+      if (staged)
+        window_sums_epan<CT, COMPL>(nrow, mrow, sg, sg + span, sgb, sgb + span, fR, dfR, span,
+                                    A_lo, lo, hi, m0, (CT)dz, (CT)delta, invW2, sA, sB, sC, sE);
+      else
+        window_sums_epan<CT, COMPL>(nrow, mrow, gzt, gft, cvt, COMPL ? cvt + nz : nullptr, fR,
+                                    dfR, nz, 0, lo, hi, m0, (CT)dz, (CT)delta, invW2, sA, sB, sC,
+                                    sE);
+    } else if (COMPL) {
       if (staged)
         window_sums_c<CT>(nrow, mrow, sg, sg + span, sgb, sgb + span, fR, dfR, span, A_lo, lo, hi,
                           m0, K, r, qr, sA, sB, sC, sE);
@@ -635,9 +695,19 @@ __global__ __launch_bounds__(kGradBS) void k_event_grad(GradArgs a) {
     } else {
       window_sums<CT>(nrow, gzt, gft, nz, 0, lo, hi, m0, K, r, qr, sA, sB, sC, sE);
     }
-    const double A = (double)sA, sm = (double)sB;
-    const double Bz = (dz * sm + delta * A) * inv_h2;
-    const double Chh = (dz * (dz * (double)sC + 2.0 * delta * sm) + delta * delta * A) * inv_h2;
+    double A, Bz, Chh;
+    if (EPAN) {
+      // dA/dz_j = 2 sum a u / W^2, h dA/dh = 2 sum a u^2 / W^2
+      const double iw2 = 2.0 / (W * W);
+      A = (double)sA;
+      Bz = (double)sB * iw2;
+      Chh = (double)sC * iw2;
+    } else {
+      const double sm = (double)sB;
+      A = (double)sA;
+      Bz = (dz * sm + delta * A) * inv_h2;
+      Chh = (dz * (dz * (double)sC + 2.0 * delta * sm) + delta * delta * A) * inv_h2;
+    }
     acc[0] += cw * A;
     // distance parameters: weight, z-shift, bandwidth, grid factor (H0: g ~ H0)
     const double Eg[4] = {A / P.h0, (double)sE[0], (double)sE[1], (double)sE[2]};
@@ -658,7 +728,7 @@ __global__ __launch_bounds__(kGradBS) void k_event_grad(GradArgs a) {
       *lnI = -INFINITY;
       for (int p = 0; p < kNG; ++p) dlnI[p] = NAN;
     } else {
-      *lnI = log(S * kInvSqrt2Pi / h);
+      *lnI = log(S * (EPAN ? 0.75 / kEpanScale : kInvSqrt2Pi) / h);
       for (int p = 0; p < kNG; ++p) dlnI[p] = acc[1 + p] / S - (p < kNS ? hd[1 + p] : 0.0);
     }
   }
@@ -813,12 +883,23 @@ hipError_t launch_grad(const GradArgs& a, const SelGradArgs& sa, GradFinalArgs f
     k_event_bandwidth_grad<<<(unsigned)nb, kGradBS, 0, st>>>(a);
     CH_LAUNCH_CHECK();
     const size_t lds32 = kGradStageElems * sizeof(float), lds64 = kGradStageElems * sizeof(double);
+    const bool ep = a.shape == kShapeEpanechnikov;
     if (a.mz64) {
-      if (f32) k_event_grad<true, true><<<(unsigned)nb, kGradBS, lds32, st>>>(a);
-      else k_event_grad<false, true><<<(unsigned)nb, kGradBS, lds64, st>>>(a);
+      if (ep) {
+        if (f32) k_event_grad<true, true, true><<<(unsigned)nb, kGradBS, lds32, st>>>(a);
+        else k_event_grad<false, true, true><<<(unsigned)nb, kGradBS, lds64, st>>>(a);
+      } else {
+        if (f32) k_event_grad<true, true, false><<<(unsigned)nb, kGradBS, lds32, st>>>(a);
+        else k_event_grad<false, true, false><<<(unsigned)nb, kGradBS, lds64, st>>>(a);
+      }
     } else {
-      if (f32) k_event_grad<true, false><<<(unsigned)nb, kGradBS, lds32, st>>>(a);
-      else k_event_grad<false, false><<<(unsigned)nb, kGradBS, lds64, st>>>(a);
+      if (ep) {
+        if (f32) k_event_grad<true, false, true><<<(unsigned)nb, kGradBS, lds32, st>>>(a);
+        else k_event_grad<false, false, true><<<(unsigned)nb, kGradBS, lds64, st>>>(a);
+      } else {
+        if (f32) k_event_grad<true, false, false><<<(unsigned)nb, kGradBS, lds32, st>>>(a);
+        else k_event_grad<false, false, false><<<(unsigned)nb, kGradBS, lds64, st>>>(a);
+      }
     }
     CH_LAUNCH_CHECK();
   }

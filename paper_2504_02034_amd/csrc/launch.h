@@ -236,6 +236,7 @@ struct GradArgs {
   const double* lnm2d;
   int E, B;
   double trunc;
+  int shape;                // kShapeGaussian / kShapeEpanechnikov (unbinned samples)
   double* hd;               // [B][E][10] h and d ln h/dp (written by the bandwidth kernel)
   double* sc;               // [B][2][S] z and c w of each sample (bandwidth kernel)
   void* sd;                 // [B][13][S] d ln w/dp, dz/dp: double, or float when f32
