@@ -24,7 +24,9 @@
 // k_event_grad        one (event, lambda) per workgroup, one sample per
 //                     thread, from the stored coefficients: its window by the
 //                     Gaussian ratio recurrence K_(g+1) = K_g r_g,
-//                     r_(g+1) = r_g exp(-dz^2/h^2)
+//                     r_(g+1) = r_g exp(-dz^2/h^2), or (EPAN) the
+//                     Epanechnikov kernel's support with its polynomial
+//                     k = 1 - u^2/W^2 per point
 // k_selection_grad    per (injection chunk, lambda) partial sums
 // k_grad_final        ln L and d ln L / dp per lambda, fixed order
 #include <math.h>
