@@ -365,6 +365,13 @@ chimera_status chimera_selection_xi(chimera_ctx* ctx, const double* lam, int64_t
 chimera_status chimera_scratch_bytes(chimera_ctx* ctx, const chimera_events* ev, int64_t B,
                                      int32_t prec, int32_t mem, size_t* bytes);
 
+/* The same for chimera_lnl_grad: the stream's scratch block that a gradient
+ * call over B points needs (one chunk's, for a chunked call: see
+ * chimera_lnl_grad).  EINVAL for a null argument, B outside [1, 2^20], an
+ * unknown precision or mem. */
+chimera_status chimera_grad_scratch_bytes(chimera_ctx* ctx, const chimera_events* ev, int64_t B,
+                                          int32_t prec, int32_t mem, size_t* bytes);
+
 /* Bytes of the scratch blocks the context holds, summed over its streams. */
 chimera_status chimera_scratch_held(chimera_ctx* ctx, size_t* bytes);
 

@@ -36,7 +36,8 @@ EXPORTS = ("chimera_default_config", "chimera_create", "chimera_destroy", "chime
            "chimera_set_mass_smoothing", "chimera_lambda_width",
            "chimera_release_events", "chimera_lnl_batch", "chimera_lnl_batch_static",
            "chimera_selection_xi",
-           "chimera_lnl_grad", "chimera_scratch_bytes", "chimera_scratch_held",
+           "chimera_lnl_grad", "chimera_scratch_bytes", "chimera_grad_scratch_bytes",
+           "chimera_scratch_held",
            "chimera_release_scratch", "chimera_profile_enable", "chimera_profile_read")
 
 
@@ -98,6 +99,8 @@ def _load():
         "chimera_lnl_grad": (ctypes.c_int, [_P, _P, _P, _I64, _I32, _P, _P, _I32, _P]),
         "chimera_scratch_bytes": (ctypes.c_int, [_P, _P, _I64, _I32, _I32,
                                                  ctypes.POINTER(ctypes.c_size_t)]),
+        "chimera_grad_scratch_bytes": (ctypes.c_int, [_P, _P, _I64, _I32, _I32,
+                                                      ctypes.POINTER(ctypes.c_size_t)]),
         "chimera_scratch_held": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_size_t)]),
         "chimera_release_scratch": (ctypes.c_int, [_P, _P]),
         "chimera_profile_enable": (ctypes.c_int, [_P, _I32]),
@@ -358,6 +361,12 @@ def chimera_scratch_bytes(h, ev, B, prec=CHIMERA_FP64, mem=CHIMERA_DEVICE) -> in
     return out.value
 
 
+def chimera_grad_scratch_bytes(h, ev, B, prec=CHIMERA_FP64, mem=CHIMERA_DEVICE) -> int:
+    out = ctypes.c_size_t(0)
+    _check(lib.chimera_grad_scratch_bytes(h, ev, int(B), prec, mem, ctypes.byref(out)))
+    return out.value
+
+
 def chimera_scratch_held(h) -> int:
     out = ctypes.c_size_t()
     _check(lib.chimera_scratch_held(h, ctypes.byref(out)))
@@ -493,6 +502,9 @@ class Context:
     def scratch_bytes(self, ev: EventSet, B, prec=CHIMERA_FP64, mem=CHIMERA_DEVICE) -> int:
         return chimera_scratch_bytes(self.handle, ev.handle if ev is not None else None, B, prec,
                                      mem)
+
+    def grad_scratch_bytes(self, ev: EventSet, B, prec=CHIMERA_FP64, mem=CHIMERA_DEVICE) -> int:
+        return chimera_grad_scratch_bytes(self.handle, ev.handle, B, prec, mem)
 
     def scratch_held(self) -> int:
         return chimera_scratch_held(self.handle)

@@ -1561,9 +1561,12 @@ int64_t grad_lambda_chunk(const chimera_events* ev, int64_t B, bool f32) {
   return std::min(B, c);
 }
 
+// probe_bytes: only size the call's scratch (pool_size of its layout) and
+// return, with no device work.
 static chimera_status run_grad_chunk(chimera_ctx* ctx, const chimera_events* ev,
                                      const double* lam, int64_t B, int32_t prec, double* lnl,
-                                     double* grad, int32_t mem, void* hip_stream) {
+                                     double* grad, int32_t mem, void* hip_stream,
+                                     size_t* probe_bytes = nullptr) {
   hipStream_t st = (hipStream_t)hip_stream;
   HIP_TRY(hipSetDevice(ctx->cfg.device));
   const bool f32 = prec == CHIMERA_FP32;
@@ -1623,6 +1626,10 @@ static chimera_status run_grad_chunk(chimera_ctx* ctx, const chimera_events* ev,
   Carve probe;
   lay(probe, a, sa, fa, &lam_d, &P, &chi, &inv, &dtab, &chio, &gz64, &gz32, &fm, &fr);
   const size_t bytes = probe.off;
+  if (probe_bytes) {
+    *probe_bytes = pool_size(bytes);
+    return CHIMERA_OK;
+  }
   if (ctx->cfg.hbm_budget && pool_size(bytes) > ctx->cfg.hbm_budget)
     return fail(CHIMERA_ENOMEM, "call needs " + std::to_string(bytes) +
                                     " scratch bytes, over the context's hbm_budget");
@@ -1700,6 +1707,16 @@ chimera_status chimera_lnl_grad(chimera_ctx* ctx, const chimera_events* ev, cons
   if (ctx->nlam != CHIMERA_NLAM)
     return fail(CHIMERA_EINVAL, "the adjoint takes the unsmoothed mass model (no delta_m)");
   return run_grad(ctx, ev, lam, B, prec, lnl, grad, mem, hip_stream);
+}
+
+chimera_status chimera_grad_scratch_bytes(chimera_ctx* ctx, const chimera_events* ev, int64_t B,
+                                          int32_t prec, int32_t mem, size_t* bytes) {
+  if (!ctx || !ev || !bytes) return fail(CHIMERA_EINVAL, "null argument");
+  if (B < 1 || B > (1 << 20)) return fail(CHIMERA_EINVAL, "batch size out of [1, 2^20]");
+  if (prec != CHIMERA_FP64 && prec != CHIMERA_FP32) return fail(CHIMERA_EINVAL, "bad precision");
+  if (mem != CHIMERA_HOST && mem != CHIMERA_DEVICE) return fail(CHIMERA_EINVAL, "bad mem");
+  B = grad_lambda_chunk(ev, B, prec == CHIMERA_FP32);
+  return run_grad_chunk(ctx, ev, nullptr, B, prec, nullptr, nullptr, mem, nullptr, bytes);
 }
 
 chimera_status chimera_profile_enable(chimera_ctx* ctx, int32_t on) {

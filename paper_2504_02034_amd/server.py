@@ -1,7 +1,10 @@
 """Continuous-batching server for ln L requests from many concurrent samplers.
 
 submit(events, lam [B, width], prec) -> Ticket; wait(ticket) -> ln L [B];
-stats() -> evals/s, p50 / p99 latency and admission figures.
+submit(..., grad=True) -> a gradient request; wait -> (ln L [B], d ln L [B, 12])
+(the adjoint, for gradient-based samplers); stats() -> evals/s, p50 / p99
+latency and admission figures.  Gradient requests are fused only with
+gradient requests, and admitted by the gradient call's scratch.
 
 The event sets, the catalogue and the injections stay resident in the
 library's context.  Worker threads, each with its own HIP stream and its own
@@ -54,7 +57,8 @@ class Ticket:
     small: bool = False
     t_start: float = 0.0
     t_done: float = 0.0
-    result: np.ndarray = None
+    grad: bool = False
+    result: object = None
     error: BaseException = None
     done: threading.Event = field(default_factory=threading.Event)
 
@@ -81,6 +85,9 @@ class HipExecutor:
             self.out_h = torch.empty(max_fused, dtype=torch.float64, pin_memory=True)
             self.lam_d = torch.empty(max_fused * 15, dtype=torch.float64, device="cuda")
             self.out_d = torch.empty(max_fused, dtype=torch.float64, device="cuda")
+            # gradient requests: d ln L per point (12 parameters)
+            self.grad_h = torch.empty(max_fused, 12, dtype=torch.float64, pin_memory=True)
+            self.grad_d = torch.empty(max_fused, 12, dtype=torch.float64, device="cuda")
             self.done = torch.cuda.Event()
 
     def __init__(self, ctx, max_fused: int = 512, chunk_bytes: int = 0):
@@ -98,14 +105,18 @@ class HipExecutor:
     def new_worker(self):
         return HipExecutor.Worker(self.torch, self.max_fused)
 
-    def scratch_bytes(self, events, B, prec) -> int:
+    def scratch_bytes(self, events, B, prec, grad: bool = False) -> int:
         from . import chimera
+        if grad:
+            return self.ctx.grad_scratch_bytes(events, B, prec, chimera.CHIMERA_DEVICE)
         return self.ctx.scratch_bytes(events, B, prec, chimera.CHIMERA_DEVICE)
 
     def release(self, worker):
         self.ctx.release_scratch(worker.stream)
 
-    def run(self, worker, events, lam, prec) -> np.ndarray:
+    def run(self, worker, events, lam, prec, grad: bool = False):
+        """ln L [B], or (ln L [B], gradient [B, 12]) for a gradient request."""
+        from . import chimera
         torch = self.torch
         B, W = lam.shape
         lam_h = worker.lam_h[:B * W].view(B, W)
@@ -113,17 +124,26 @@ class HipExecutor:
         lam_h.copy_(torch.from_numpy(lam))
         step = B
         if self.chunk_bytes > 0 and B > 1:
-            one = self.scratch_bytes(events, 1, prec)
-            per = max(self.scratch_bytes(events, 2, prec) - one, 1)
+            one = self.scratch_bytes(events, 1, prec, grad)
+            per = max(self.scratch_bytes(events, 2, prec, grad) - one, 1)
             step = max(1, min(B, int(self.chunk_bytes // per)))
         with torch.cuda.stream(worker.stream):
             lam_d.copy_(lam_h, non_blocking=True)
             for i in range(0, B, step):
-                self.ctx.lnl(events, lam_d[i:i + step], prec, lnl=worker.out_d[i:i + step],
-                             stream=worker.stream)
+                if grad:
+                    chimera.chimera_lnl_grad(self.ctx.handle, events.handle, lam_d[i:i + step],
+                                             prec, lnl=worker.out_d[i:i + step],
+                                             grad=worker.grad_d[i:i + step], stream=worker.stream)
+                else:
+                    self.ctx.lnl(events, lam_d[i:i + step], prec, lnl=worker.out_d[i:i + step],
+                                 stream=worker.stream)
             worker.out_h[:B].copy_(worker.out_d[:B], non_blocking=True)
+            if grad:
+                worker.grad_h[:B].copy_(worker.grad_d[:B], non_blocking=True)
             worker.done.record(worker.stream)
         worker.done.synchronize()
+        if grad:
+            return worker.out_h[:B].numpy().copy(), worker.grad_h[:B].numpy().copy()
         return worker.out_h[:B].numpy().copy()
 
 
@@ -168,21 +188,29 @@ class Server:
             w.start()
 
     # ------------------------------------------------------------------
-    def submit(self, events, lam, prec: int = 0) -> Ticket:
+    def _need(self, events, B, prec, grad) -> int:
+        return (self.ex.scratch_bytes(events, B, prec, grad=True) if grad
+                else self.ex.scratch_bytes(events, B, prec))
+
+    def submit(self, events, lam, prec: int = 0, grad: bool = False) -> Ticket:
         lam = np.ascontiguousarray(np.atleast_2d(lam), dtype=np.float64)
         width = getattr(self.ex, "lam_width", 14)
         if lam.ndim != 2 or lam.shape[1] != width or lam.shape[0] < 1:
             raise ValueError(f"lam must be [B, {width}] with B >= 1")
         if lam.shape[0] > self.max_fused:
             raise ValueError(f"B = {lam.shape[0]} exceeds max_fused = {self.max_fused}")
-        need = self.ex.scratch_bytes(events, lam.shape[0], prec)
+        grad = bool(grad)
+        if grad and width != 14:
+            raise ValueError("the adjoint takes the unsmoothed mass model (14-wide lambda rows)")
+        need = self._need(events, lam.shape[0], prec, grad)
         if self.budget and need > self.budget:
             raise MemoryError(f"request needs {need} bytes, over the budget of {self.budget}")
         with self._cv:
             if self._stop:
                 raise RuntimeError("server is closed")
             t = Ticket(self._next_id, events, lam, prec, time.perf_counter(), need=need,
-                       small=0 < need <= self.small_bytes if self.small_bytes else False)
+                       small=0 < need <= self.small_bytes if self.small_bytes else False,
+                       grad=grad)
             self._next_id += 1
             if self._t0 is None:
                 self._t0 = t.t_submit
@@ -190,7 +218,7 @@ class Server:
             self._cv.notify_all()
         return t
 
-    def wait(self, ticket: Ticket, timeout=None) -> np.ndarray:
+    def wait(self, ticket: Ticket, timeout=None):
         if not ticket.done.wait(timeout):
             raise TimeoutError(f"request {ticket.id} not done")
         if ticket.error is not None:
@@ -260,7 +288,8 @@ class Server:
         group, B = [head], head.B
         for t in self._pending:
             if t is not head and t.events is head.events and t.prec == head.prec \
-                    and t.small == head.small and B + t.B <= self.max_fused:
+                    and t.small == head.small and t.grad == head.grad \
+                    and B + t.B <= self.max_fused:
                 group.append(t)
                 B += t.B
         return group, B
@@ -290,15 +319,15 @@ class Server:
             order = list(self._pending)
         seen = set()
         for head in order:
-            key = (id(head.events), head.prec, head.small)
+            key = (id(head.events), head.prec, head.small, head.grad)
             if key in seen:
                 continue
             seen.add(key)
             group, B = self._group(head)
-            need = self.ex.scratch_bytes(head.events, B, head.prec)
+            need = self._need(head.events, B, head.prec, head.grad)
             while len(group) > 1 and not self._fits(w, need):
                 B -= group.pop().B
-                need = self.ex.scratch_bytes(head.events, B, head.prec)
+                need = self._need(head.events, B, head.prec, head.grad)
             if self._fits(w, need):
                 for t in group:
                     self._pending.remove(t)
@@ -330,7 +359,10 @@ class Server:
             lam = np.concatenate([t.lam for t in group]) if len(group) > 1 else group[0].lam
             err, out = None, None
             try:
-                out = self.ex.run(worker, group[0].events, lam, group[0].prec)
+                if group[0].grad:
+                    out = self.ex.run(worker, group[0].events, lam, group[0].prec, grad=True)
+                else:
+                    out = self.ex.run(worker, group[0].events, lam, group[0].prec)
             except BaseException as e:  # noqa: BLE001 - handed to the waiting caller
                 err = e
             t_done = time.perf_counter()
@@ -343,7 +375,10 @@ class Server:
                 for t in group:
                     t.t_start, t.t_done = t_start, t_done
                     if err is None:
-                        t.result = out[off:off + t.B].copy()
+                        if t.grad:
+                            t.result = (out[0][off:off + t.B].copy(), out[1][off:off + t.B].copy())
+                        else:
+                            t.result = out[off:off + t.B].copy()
                         self._lat.append(t_done - t.t_submit)
                         self._evals += t.B
                     else:

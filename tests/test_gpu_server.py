@@ -192,3 +192,67 @@ def test_served_results_with_the_population_options():
         assert np.array_equal(got, alone, equal_nan=True)
     assert np.isfinite(np.concatenate(served)).any()
     ctx.close()
+
+
+@pytest.mark.parametrize("chunked", [False, True], ids=["whole", "chunked"])
+def test_served_gradients_equal_the_request_alone(chunked):
+    """Gradient requests (submit(..., grad=True)) from concurrent clients,
+    mixed with ln L requests on the same event set: every served ln L and
+    gradient bitwise equal to the same chimera_lnl_grad call alone, in both
+    precisions, with the gradient calls' scratch (chimera_grad_scratch_bytes)
+    inside the HBM budget, also with fused batches cut into launch sequences
+    of one point each."""
+    from paper_2504_02034_amd import chimera
+    from paper_2504_02034_amd.server import HipExecutor, Server
+    h = handcrafted()
+    ctx = chimera.Context(n_z=h["n_z"], z_lo=h["z_lo"], z_hi=h["z_hi"])
+    try:
+        ctx.set_catalog(h["rows"], h["nz_tot"])
+        ctx.set_injections(h["idl"], h["im1"], h["im2"], h["lnp"], h["ninj"])
+        es = ctx.add_events(h["ev_pix_off"], h["pix_samp_off"], h["pix_row"], h["c_ir"],
+                            h["dl"], h["m1"], h["m2"])
+        P64, P32 = chimera.CHIMERA_FP64, chimera.CHIMERA_FP32
+        ex = HipExecutor(ctx, max_fused=32)
+        # (the pool rounds blocks up, so on this small set the sizes coincide)
+        g1 = ex.scratch_bytes(es, 1, P64, grad=True)
+        assert g1 > 0 and ex.scratch_bytes(es, 32, P64, grad=True) >= g1
+        if chunked:
+            ex.chunk_bytes = 1            # every point its own launch sequence
+        srv = Server(ex, n_workers=3, max_fused=32,
+                     hbm_budget=3 * ex.scratch_bytes(es, 32, P64, grad=True))
+        rng = np.random.default_rng(11)
+        base = synth.make_lambdas(synth.WORKLOADS["precision_300ev"], batch=60, child=77)
+        base[:, 8:11] = synth.LAMBDA_TRUTH[8:11]
+        reqs, lock = [], threading.Lock()
+
+        def client(c):
+            for r in range(4):
+                B = int(rng.integers(1, 6))
+                lam = base[rng.integers(0, base.shape[0], B)]
+                prec = P64 if (c + r) % 2 == 0 else P32
+                grad = (c + r) % 3 != 0
+                t = srv.submit(es, lam, prec, grad=grad)
+                with lock:
+                    reqs.append((t, lam, prec, grad))
+
+        threads = [threading.Thread(target=client, args=(c,)) for c in range(4)]
+        for t in threads:
+            t.start()
+        for t in threads:
+            t.join()
+        got = [(srv.wait(t, timeout=120), lam, prec, grad) for t, lam, prec, grad in reqs]
+        st = srv.stats()
+        srv.close()
+        n_grad = 0
+        for res, lam, prec, grad in got:
+            if grad:
+                n_grad += 1
+                lnl, g = ctx.lnl_grad(es, lam, prec)
+                assert np.array_equal(res[0], lnl, equal_nan=True)
+                assert np.array_equal(res[1], g, equal_nan=True)
+            else:
+                assert np.array_equal(res, ctx.lnl(es, lam, prec), equal_nan=True)
+        assert n_grad >= 4 and st["completed"] == len(got)
+        assert st["peak_bytes"] <= st["budget"]
+    finally:
+        ctx.close()

@@ -31,32 +31,42 @@ class MockExec:
         self.peak = 0
         self.releases = 0
         self.calls = []
+        self.grad_calls = []
 
     def new_worker(self):
         return object()
 
-    def scratch_bytes(self, events, B, prec):
-        return 1000 + 100 * B
+    def scratch_bytes(self, events, B, prec, grad=False):
+        return 1000 + (300 if grad else 100) * B
 
     def release(self, worker):
         with self.mu:
             self.arena[id(worker)] = 0
             self.releases += 1
 
-    def run(self, worker, events, lam, prec):
-        need = self.scratch_bytes(events, lam.shape[0], prec)
+    def run(self, worker, events, lam, prec, grad=False):
+        need = self.scratch_bytes(events, lam.shape[0], prec, grad)
         with self.mu:
             self.arena[id(worker)] = max(self.arena.get(id(worker), 0), need)
             self.peak = max(self.peak, sum(self.arena.values()))
             self.calls.append((events.tag, lam.shape[0], prec, time.perf_counter()))
+            if grad:
+                self.grad_calls.append((events.tag, lam.shape[0], prec))
         time.sleep(lam.shape[0] * self.per_point_s)
         if self.fail_tag is not None and events.tag == self.fail_tag:
             raise ValueError("executor failure")
+        if grad:
+            return value(events, lam, prec), gradient(events, lam, prec)
         return value(events, lam, prec)
 
 
 def value(events, lam, prec):
     return lam[:, 0] * 3.0 + lam[:, 5] + 1000.0 * events.tag + 0.5 * prec
+
+
+def gradient(events, lam, prec):
+    cols = list(range(6)) + list(range(8, 14))
+    return lam[:, cols] * 2.0 + events.tag + 0.25 * prec
 
 
 def lam_batch(rng, B):
@@ -298,3 +308,33 @@ def test_priority_arguments_checked():
         Server(ex, n_workers=2, reserved=1)           # reserved workers need small_bytes
     with pytest.raises(ValueError):
         Server(ex, n_workers=2, small_bytes=10, reserved=2)
+
+
+def test_gradient_requests_fuse_only_with_gradient_requests():
+    """Gradient requests (the adjoint) and ln L requests on the same event set
+    and precision: each gets its own kind of result, they are fused only with
+    their own kind, and their scratch is the gradient call's."""
+    ex = MockExec(per_point_s=2e-3)
+    srv = Server(ex, n_workers=1, max_fused=512)
+    rng = np.random.default_rng(5)
+    blocker = srv.submit(Events(9), lam_batch(rng, 20), 0)     # keeps the worker busy
+    a = Events(0)
+    reqs = [(srv.submit(a, lam, 0, grad=g), lam, g)
+            for g in (True, False, True, False, True)
+            for lam in [lam_batch(rng, 3)]]
+    assert [t.need for t, _, _ in reqs] == [1900, 1300, 1900, 1300, 1900]
+    srv.wait(blocker, timeout=30)
+    for t, lam, g in reqs:
+        got = srv.wait(t, timeout=30)
+        if g:
+            assert np.array_equal(got[0], value(a, lam, 0))
+            assert np.array_equal(got[1], gradient(a, lam, 0))
+        else:
+            assert np.array_equal(got, value(a, lam, 0))
+    srv.close()
+    assert sorted(B for _, B, _, _ in ex.calls[1:]) == [6, 9]
+    assert ex.grad_calls == [(0, 9, 0)]
+    other = Server(MockExec(), n_workers=1)
+    with pytest.raises(ValueError):
+        other.submit(a, np.zeros((1, 15)), 0, grad=True)
+    other.close()
