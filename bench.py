@@ -429,11 +429,38 @@ def serve_bench(wl, cf, inj, n_requests=300, seed=5, max_pass_s=0.05, chunk_gb=4
         lat.append(time.perf_counter() - t0 - arrivals[i])
     span64 = time.perf_counter() - t0
     lat = sorted(lat)
+    # gradient requests (the adjoint through the server, for gradient-based
+    # samplers): 64 requests of 1..8 points on the 300-event set at once,
+    # against the same requests as one call each, one after another
+    gsrv = Server(ex, n_workers=4, max_fused=512, hbm_budget=budget)
+    g_b = rng.integers(1, 9, 64)
+    g_lams = [base[rng.integers(0, base.shape[0], b)] for b in g_b]
+    gsrv.wait(gsrv.submit(sets[1], g_lams[0][:1], chimera.CHIMERA_FP32, grad=True))  # warm up
+    gsrv.reset_stats()
+    t1 = time.perf_counter()
+    for t in [gsrv.submit(sets[1], lg, chimera.CHIMERA_FP32, grad=True) for lg in g_lams]:
+        gsrv.wait(t)
+    g_span = time.perf_counter() - t1
+    g_st = gsrv.stats()
+    gsrv.close()
+    t1 = time.perf_counter()
+    for lg in g_lams:
+        ctx.lnl_grad(sets[1], lg, chimera.CHIMERA_FP32)
+    g_seq = time.perf_counter() - t1
+    grad_serving = {"requests": 64, "points": int(g_b.sum()), "event_set": sizes[1],
+                    "server_points_per_s": round(float(g_b.sum()) / g_span, 1),
+                    "p50_ms": round(g_st["p50_ms"], 3), "p99_ms": round(g_st["p99_ms"], 3),
+                    "requests_per_launch": round(g_st["requests_per_launch"], 3),
+                    "one_call_each_points_per_s": round(float(g_b.sum()) / g_seq, 1)}
+    log(f"serving gradients: {grad_serving['server_points_per_s']:.0f} points/s through the "
+        f"server ({grad_serving['requests_per_launch']:.2f} requests per launch), "
+        f"{grad_serving['one_call_each_points_per_s']:.0f} points/s one call each")
     ctx.close()
     log(f"serving: FP32 server p50 {st['p50_ms']:.1f} ms p99 {st['p99_ms']:.1f} ms, "
         f"{st['requests_per_launch']:.2f} requests per launch, slowdown over alone p50 "
         f"{np.percentile(slow, 50):.2f} p99 {np.percentile(slow, 99):.2f}")
     return {
+        "gradient_requests": grad_serving,
         "requests": n_requests, "event_sets": list(sizes), "samples_per_event": 4096,
         "batch": "log-uniform 1..512",
         "saturated_fp32_evals_per_s": round(float(B.sum()) / t_sat, 1),
