@@ -309,7 +309,8 @@ chimera_status chimera_lambda_width(chimera_ctx* ctx, int32_t* width);
  *           bin; all samples at one redshift: one point there).  The
  *           bandwidth and the 1/N normalisation stay those of the samples.
  * Later evaluation calls on the set use the options; chimera_lnl_grad
- * refuses a set with other than the defaults (EINVAL).  Synchronous; waits
+ * takes the Epanechnikov kernel on unbinned samples and refuses a binned set
+ * (EINVAL).  Synchronous; waits
  * for the device, so no call may be using the set.  EINVAL on a bad shape,
  * n_bins out of range or an unknown set; ERANGE when the set's pixel slots
  * times n_bins exceed 2^31 - 1. */
