@@ -289,8 +289,31 @@ def bandwidth_grad(z, w, dlw, dz_p, dz_grid):
 # ---------------------------------------------------------------------------
 # one event, selection, ln L
 # ---------------------------------------------------------------------------
+def binned_points(z, w, dlw, dz, n_bins):
+    """The binned data set (likelihood.bin_samples) with its derivatives:
+    (centres, weights, d weights / dp [NG, n_bins], d centres / dp [NG, n_bins]).
+    The bins' edges follow the smallest and largest redshift, so a centre
+    moves as (1 - f) dz_lo/dp + f dz_hi/dp with f = (k + 1/2) / n_bins; a
+    bin's weight as the sum of its samples' w d ln w / dp (the samples' bins
+    held fixed)."""
+    centres, weights = L.bin_samples(z, w, n_bins)
+    lo, hi = int(np.argmin(z)), int(np.argmax(z))
+    width = (float(z[hi]) - float(z[lo])) / n_bins
+    if width > 0.0:
+        idx = np.minimum(np.floor((z - float(z[lo])) / width).astype(np.int64), n_bins - 1)
+        f = (np.arange(n_bins) + 0.5) / n_bins
+        dc = np.outer(dz[:, lo], 1.0 - f) + np.outer(dz[:, hi], f)
+    else:
+        idx = np.zeros(z.size, dtype=np.int64)
+        dc = np.repeat(dz[:, lo:lo + 1], n_bins, axis=1)
+    dW = np.zeros((dlw.shape[0], n_bins))
+    for j, b in enumerate(idx):
+        dW[:, b] += w[j] * dlw[:, j]
+    return centres, weights, dW, dc
+
+
 def event_grad(pix_z, pix_w, pix_dlw, pix_dz, pix_c, pix_rows, grid, tau, gz, dlng, T=None,
-               pix_drows=None, shape="gaussian"):
+               pix_drows=None, shape="gaussian", n_bins=0):
     """(I_i, d ln I_i / dp [12]); pix_drows: d row / d Om of each pixel's row
     (an incomplete catalogue), or None.
 
@@ -313,6 +336,13 @@ def event_grad(pix_z, pix_w, pix_dlw, pix_dz, pix_c, pix_rows, grid, tau, gz, dl
     G = np.zeros(NG)
     drs = pix_drows if pix_drows is not None else [None] * len(pix_rows)
     for zr, wr, lw, zz, c, nr, dnr in zip(pix_z, pix_w, pix_dlw, pix_dz, pix_c, pix_rows, drs):
+        if n_bins:
+            # the bins stand in for the samples: a bin's w d ln w / dp is its
+            # dW / dp, and its centre moves with the range's ends
+            zr, wr, dW, dc = binned_points(zr, wr, lw, zz, n_bins)
+            with np.errstate(divide="ignore", invalid="ignore"):
+                lw = np.where(wr > 0, dW / np.where(wr > 0, wr, 1.0), 0.0)
+            zz = dc
         f = tau * nr * gz
         u = grid[None, :] - zr[:, None]
         if shape == "epanechnikov":
@@ -377,11 +407,12 @@ def selection_grad(inj: L.InjectionSet, cat: L.Catalog, lam):
 
 
 def lnl_grad(events, cat: L.Catalog, inj: L.InjectionSet, lam, T=None, kernel="many1d",
-             shape="gaussian"):
+             shape="gaussian", n_bins=0):
     """dict(lnl, grad[12], lnI[E], dlnI[E, 12], ln_xi, dln_xi[12]).
 
-    shape: the KDE kernel, "gaussian" or "epanechnikov" (see event_grad), on
-    the unbinned samples.
+    shape: the KDE kernel, "gaussian" or "epanechnikov" (see event_grad);
+    n_bins > 0: the binned data sets (binned_points; the bandwidth stays the
+    samples').
 
     kernel "single1d" (eq. gw-kernel-single1d): the sum over pixels of S_ir
     times the grid sum of n_r g KDE is, by linearity, the grid sum of
@@ -427,7 +458,8 @@ def lnl_grad(events, cat: L.Catalog, inj: L.InjectionSet, lam, T=None, kernel="m
                 zs.append(z); ws.append(w); lws.append(lw); zzs.append(zz)
                 cs.append(c); rs.append(row); drs.append(drow)
             per_event.append(event_grad(zs, ws, lws, zzs, cs, rs, grid, tau, gz, dlng, T,
-                                        drs if drows is not None else None, shape))
+                                        drs if drows is not None else None, shape,
+                                        n_bins))
     except cosmo.NonMonotone:
         return out
     out["ln_xi"] = math.log(xi) if xi > 0 else -np.inf
