@@ -308,9 +308,8 @@ chimera_status chimera_lambda_width(chimera_ctx* ctx, int32_t* width);
  *           summed weight of its samples (the largest redshift in the last
  *           bin; all samples at one redshift: one point there).  The
  *           bandwidth and the 1/N normalisation stay those of the samples.
- * Later evaluation calls on the set use the options; chimera_lnl_grad
- * takes the Epanechnikov kernel on unbinned samples and refuses a binned set
- * (EINVAL).  Synchronous; waits
+ * Later evaluation calls on the set use the options, chimera_lnl_grad
+ * included.  Synchronous; waits
  * for the device, so no call may be using the set.  EINVAL on a bad shape,
  * n_bins out of range or an unknown set; ERANGE when the set's pixel slots
  * times n_bins exceed 2^31 - 1. */
@@ -403,8 +402,10 @@ chimera_status chimera_release_scratch(chimera_ctx* ctx, void* hip_stream);
  * Epanechnikov kernel (chimera_set_event_kde, Sect. 2.3's compact option,
  * unbinned) is differentiated with k = 1 - u^2/W^2 on its support
  * |u| <= W = sqrt(5) h (dk/dz_j = 2u/W^2, h dk/dh = 2u^2/W^2; k vanishes on
- * the support's edge).  EINVAL for a binned set (n_bins > 0), a 3D set, or a
- * context with the smoothed mass edge on. */
+ * the support's edge).  A binned set (n_bins > 0) is differentiated through
+ * its bins: a bin's weight moves with its samples' weights (the samples'
+ * bins held fixed) and its centre with the ends of the data set's redshift
+ * range.  EINVAL for a 3D set or a context with the smoothed mass edge on. */
 chimera_status chimera_lnl_grad(chimera_ctx* ctx, const chimera_events* ev, const double* lam,
                                 int64_t B, int32_t prec, double* lnl, double* grad, int32_t mem,
                                 void* hip_stream);

@@ -1556,7 +1556,8 @@ chimera_status chimera_selection_xi(chimera_ctx* ctx, const double* lam, int64_t
 constexpr double kGradScratchCap = 16.0 * (1ull << 30);
 
 int64_t grad_lambda_chunk(const chimera_events* ev, int64_t B, bool f32) {
-  const double per = (double)ev->n_samp * grad_sample_bytes(f32) + 8.0 * ev->E * 23.0;
+  const double nbp = ev->n_bins ? (double)ev->P * ev->n_bins : 0.0;   // binned sets' points
+  const double per = ((double)ev->n_samp + nbp) * grad_sample_bytes(f32) + 8.0 * ev->E * 23.0;
   const int64_t c = (int64_t)std::max(1.0, std::floor(kGradScratchCap / per));
   return std::min(B, c);
 }
@@ -1601,6 +1602,12 @@ static chimera_status run_grad_chunk(chimera_ctx* ctx, const chimera_events* ev,
     a.sc = cv.take<double>((size_t)B * 2 * ev->n_samp);
     a.sd = f32 ? (void*)cv.take<float>((size_t)B * kGradDerivFields * ev->n_samp)
                : (void*)cv.take<double>((size_t)B * kGradDerivFields * ev->n_samp);
+    if (ev->n_bins) {
+      const size_t NB = (size_t)ev->P * ev->n_bins;
+      a.bsc = cv.take<double>((size_t)B * 2 * NB);
+      a.bsd = f32 ? (void*)cv.take<float>((size_t)B * kGradDerivFields * NB)
+                  : (void*)cv.take<double>((size_t)B * kGradDerivFields * NB);
+    }
     a.lnI = cv.take<double>((size_t)B * E);
     a.dlnI = cv.take<double>((size_t)B * E * CHIMERA_NGRAD);
     *lam_d = host ? cv.take<double>((size_t)B * CHIMERA_NLAM) : nullptr;
@@ -1660,6 +1667,10 @@ static chimera_status run_grad_chunk(chimera_ctx* ctx, const chimera_events* ev,
   a.E = E; a.B = (int)B; a.S = ev->n_samp; a.f32 = f32 ? 1 : 0;
   a.trunc = f32 ? ctx->cfg.trunc_fp32 : ctx->cfg.trunc_fp64;
   a.shape = ev->shape;
+  a.bins = ev->n_bins;
+  a.n_slots = ev->P;
+  a.ev_slot_off = ev->ev_slot_off; a.slot_row = ev->slot_row;
+  a.pix_off = ev->pix_off; a.pix_idx = ev->pix_idx;
   sa.P = P; sa.Q = a.Q; sa.flag_mono = fm; sa.flag_range = fr;
   sa.chi = chi; sa.chio = chio; sa.inv = inv; sa.dtab = dtab; sa.g = g;
   sa.ntot = compl_ ? ntot_eff : ctx->ntot;
@@ -1701,9 +1712,8 @@ chimera_status chimera_lnl_grad(chimera_ctx* ctx, const chimera_events* ev, cons
   if (s != CHIMERA_OK) return s;
   if (!ev) return fail(CHIMERA_EINVAL, "null event set");
   if (!lnl || !grad) return fail(CHIMERA_EINVAL, "null output");
-  if (ev->n_bins != 0 || ev->V != 0)
-    return fail(CHIMERA_EINVAL,
-                "the adjoint takes the many-1D or single-1D kernels on unbinned samples");
+  if (ev->V != 0)
+    return fail(CHIMERA_EINVAL, "the adjoint takes the many-1D or single-1D kernels");
   if (ctx->nlam != CHIMERA_NLAM)
     return fail(CHIMERA_EINVAL, "the adjoint takes the unsmoothed mass model (no delta_m)");
   return run_grad(ctx, ev, lam, B, prec, lnl, grad, mem, hip_stream);

@@ -27,6 +27,8 @@
 //                     r_(g+1) = r_g exp(-dz^2/h^2), or (EPAN) the
 //                     Epanechnikov kernel's support with its polynomial
 //                     k = 1 - u^2/W^2 per point
+// k_bin_grad          binned sets: per (slot, lambda) each bin's point and
+//                     derivative coefficients, from its samples'
 // k_selection_grad    per (injection chunk, lambda) partial sums
 // k_grad_final        ln L and d ln L / dp per lambda, fixed order
 #include <math.h>
@@ -572,6 +574,77 @@ __device__ __forceinline__ void window_sums_epan(const CT* __restrict__ nrow,
   if (gi <= hi) step(gi, m0);
 }
 
+// Binned data sets (Sect. 2.3): each slot's n_bins equal-width bins over the
+// redshift range of its samples, a point at each bin's centre carrying its
+// samples' summed weight.  One wave per (slot, lambda), lanes over bins: a
+// bin's samples are a run of the slot's distance order (redshift order, as
+// d_L^gw increases), found by two binary searches with the forward pass's
+// bin arithmetic; the bin's c W, its d ln W/dp = sum c w d ln w/dp / sum c w
+// (the samples' bins held fixed) and its centre's dz/dp = (1 - f) dz_lo/dp +
+// f dz_hi/dp (f = (k + 1/2) / n_bins; the range's ends are the first and last
+// sample) go to bsc / bsd in the layout of the samples' sc / sd, so that
+// k_event_grad sums the bins as it sums samples.
+template <bool F32>
+__global__ __launch_bounds__(kGradBS) void k_bin_grad(GradArgs a) {
+  using CT = typename std::conditional<F32, float, double>::type;
+  constexpr int SPB = kGradBS / 64;
+  int it, b;
+  if (!decode_item_lambda((a.n_slots + SPB - 1) / SPB, a.B, it, b)) return;
+  const int p = it * SPB + (int)(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (p >= a.n_slots) return;
+  if (a.P[b].flag | a.flag_mono[b] | a.flag_range[b]) return;
+  const int nb = a.bins;
+  const long long S = a.S, NB = (long long)a.n_slots * nb;
+  const int j0 = a.pix_off[p], n = a.pix_off[p + 1] - j0;
+  const int* idx = a.pix_idx + j0;
+  const double* scb = a.sc + (size_t)b * 2 * S;
+  const CT* sdb = (const CT*)a.sd + (size_t)b * kSD * S;
+  double* bsc = a.bsc + (size_t)b * 2 * NB;
+  CT* bsd = (CT*)a.bsd + (size_t)b * kSD * NB;
+  const double zlo = n > 0 ? scb[idx[0]] : 0.0, zhi = n > 0 ? scb[idx[n - 1]] : 0.0;
+  const double width = (zhi - zlo) / (double)nb;
+  auto bin_of = [&](int j) {
+    if (!(width > 0.0)) return 0;
+    const double f = floor((scb[idx[j]] - zlo) / width);
+    return f >= (double)(nb - 1) ? nb - 1 : (int)f;
+  };
+  auto first_at_least = [&](int k) {     // first position whose bin is >= k
+    int lo = 0, hi = n;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (bin_of(mid) < k) lo = mid + 1;
+      else hi = mid;
+    }
+    return lo;
+  };
+  for (int k = lane; k < nb; k += 64) {
+    const int j1 = first_at_least(k), j2 = first_at_least(k + 1);
+    double W = 0.0, D[kNS];
+#pragma unroll
+    for (int q = 0; q < kNS; ++q) D[q] = 0.0;
+    for (int j = j1; j < j2; ++j) {
+      const int q = idx[j];
+      const double cw = scb[S + q];
+      W += cw;
+#pragma unroll
+      for (int r = 0; r < kNS; ++r) D[r] += cw * (double)sdb[(size_t)r * S + q];
+    }
+    const long long o = (long long)p * nb + k;
+    bsc[o] = width > 0.0 ? zlo + ((double)k + 0.5) * width : zlo;
+    bsc[NB + o] = W;
+#pragma unroll
+    for (int r = 0; r < kNS; ++r) bsd[(size_t)r * NB + o] = (CT)(W > 0.0 ? D[r] / W : 0.0);
+    const double f = width > 0.0 ? ((double)k + 0.5) / (double)nb : 0.0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const double dlo = n > 0 ? (double)sdb[(size_t)(kNS + r) * S + idx[0]] : 0.0;
+      const double dhi = n > 0 ? (double)sdb[(size_t)(kNS + r) * S + idx[n - 1]] : 0.0;
+      bsd[(size_t)(kNS + r) * NB + o] = (CT)((1.0 - f) * dlo + f * dhi);
+    }
+  }
+}
+
 // Kernel sums and their parameter contractions, one (event, lambda) per
 // workgroup, one sample per thread, from the coefficients the bandwidth
 // kernel stored.  The grid factor and its six derivatives over the union of
@@ -602,8 +675,10 @@ __global__ __launch_bounds__(kGradBS) void k_event_grad(GradArgs a) {
     }
     return;
   }
-  const int s0 = a.ev_samp_off[e];
-  const int ns = a.ev_samp_off[e + 1] - s0;
+  // the event's points: its samples, or its slots' bins (slot-major)
+  const int s0 = a.bins ? a.ev_slot_off[e] * a.bins : a.ev_samp_off[e];
+  const int ns = a.bins ? (a.ev_slot_off[e + 1] - a.ev_slot_off[e]) * a.bins
+                        : a.ev_samp_off[e + 1] - s0;
   const double dz = a.g.dz, inv_h2 = 1.0 / (h * h);
   // the window's half-width in units of h: the Gaussian's truncation, or the
   // Epanechnikov kernel's support
@@ -673,8 +748,9 @@ __global__ __launch_bounds__(kGradBS) void k_event_grad(GradArgs a) {
     const double gcd = rint((z - a.g.z_lo) * a.g.inv_dz);
     const double delta = a.g.z_lo + gcd * dz - z;
     const CT m0 = (CT)(lo_d - gcd);
-    const CT* nrow = nzt + (size_t)a.samp_row[q] * nz;
-    const CT* mrow = COMPL ? mzt + (size_t)a.samp_row[q] * nz : nullptr;
+    const int rq = a.bins ? a.slot_row[q / a.bins] : a.samp_row[q];
+    const CT* nrow = nzt + (size_t)rq * nz;
+    const CT* mrow = COMPL ? mzt + (size_t)rq * nz : nullptr;
     CT sA = 0, sB = 0, sC = 0, sE[6] = {0, 0, 0, 0, 0, 0};
     if (EPAN) {
       const CT invW2 = (CT)(1.0 / (W * W));
@@ -884,23 +960,34 @@ hipError_t launch_grad(const GradArgs& a, const SelGradArgs& sa, GradFinalArgs f
   if (a.E > 0) {
     k_event_bandwidth_grad<<<(unsigned)nb, kGradBS, 0, st>>>(a);
     CH_LAUNCH_CHECK();
+    // binned sets: the window sums run over the bins' points
+    GradArgs ab = a;
+    if (a.bins > 0) {
+      const long long bbk = item_lambda_blocks((a.n_slots + kGradBS / 64 - 1) / (kGradBS / 64), a.B);
+      if (f32) k_bin_grad<true><<<(unsigned)bbk, kGradBS, 0, st>>>(a);
+      else k_bin_grad<false><<<(unsigned)bbk, kGradBS, 0, st>>>(a);
+      CH_LAUNCH_CHECK();
+      ab.sc = a.bsc;
+      ab.sd = a.bsd;
+      ab.S = (long long)a.n_slots * a.bins;
+    }
     const size_t lds32 = kGradStageElems * sizeof(float), lds64 = kGradStageElems * sizeof(double);
     const bool ep = a.shape == kShapeEpanechnikov;
     if (a.mz64) {
       if (ep) {
-        if (f32) k_event_grad<true, true, true><<<(unsigned)nb, kGradBS, lds32, st>>>(a);
-        else k_event_grad<false, true, true><<<(unsigned)nb, kGradBS, lds64, st>>>(a);
+        if (f32) k_event_grad<true, true, true><<<(unsigned)nb, kGradBS, lds32, st>>>(ab);
+        else k_event_grad<false, true, true><<<(unsigned)nb, kGradBS, lds64, st>>>(ab);
       } else {
-        if (f32) k_event_grad<true, true, false><<<(unsigned)nb, kGradBS, lds32, st>>>(a);
-        else k_event_grad<false, true, false><<<(unsigned)nb, kGradBS, lds64, st>>>(a);
+        if (f32) k_event_grad<true, true, false><<<(unsigned)nb, kGradBS, lds32, st>>>(ab);
+        else k_event_grad<false, true, false><<<(unsigned)nb, kGradBS, lds64, st>>>(ab);
       }
     } else {
       if (ep) {
-        if (f32) k_event_grad<true, false, true><<<(unsigned)nb, kGradBS, lds32, st>>>(a);
-        else k_event_grad<false, false, true><<<(unsigned)nb, kGradBS, lds64, st>>>(a);
+        if (f32) k_event_grad<true, false, true><<<(unsigned)nb, kGradBS, lds32, st>>>(ab);
+        else k_event_grad<false, false, true><<<(unsigned)nb, kGradBS, lds64, st>>>(ab);
       } else {
-        if (f32) k_event_grad<true, false, false><<<(unsigned)nb, kGradBS, lds32, st>>>(a);
-        else k_event_grad<false, false, false><<<(unsigned)nb, kGradBS, lds64, st>>>(a);
+        if (f32) k_event_grad<true, false, false><<<(unsigned)nb, kGradBS, lds32, st>>>(ab);
+        else k_event_grad<false, false, false><<<(unsigned)nb, kGradBS, lds64, st>>>(ab);
       }
     }
     CH_LAUNCH_CHECK();

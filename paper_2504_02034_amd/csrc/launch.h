@@ -236,7 +236,18 @@ struct GradArgs {
   const double* lnm2d;
   int E, B;
   double trunc;
-  int shape;                // kShapeGaussian / kShapeEpanechnikov (unbinned samples)
+  int shape;                // kShapeGaussian / kShapeEpanechnikov
+  // binned data sets (bins > 0: bins per pixel slot): the slots' samples by
+  // distance, each slot's row, and per (lambda, bin) the bin's point and
+  // derivative coefficients in the layout of sc / sd (k_bin_grad)
+  int bins;
+  int n_slots;
+  const int* ev_slot_off;   // [E+1]
+  const int* slot_row;      // [n_slots]
+  const int* pix_off;       // [n_slots+1]
+  const int* pix_idx;       // sample positions of each slot, by distance
+  double* bsc;              // [B][2][n_slots bins]
+  void* bsd;                // [B][13][n_slots bins]
   double* hd;               // [B][E][10] h and d ln h/dp (written by the bandwidth kernel)
   double* sc;               // [B][2][S] z and c w of each sample (bandwidth kernel)
   void* sd;                 // [B][13][S] d ln w/dp, dz/dp: double, or float when f32
