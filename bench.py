@@ -654,18 +654,20 @@ def main():
                        "over_forward": round(sec / (res[name]["wall"] / k * lam_g.shape[0] / B), 2)}
             log(f"grad {name}: {sec * 1e3:.2f} ms for {lam_g.shape[0]} lambda")
         g.update(grad_checks(ctx, es, lam_g))
-        # the same points with the Epanechnikov kernel (unbinned samples)
-        ctx.set_event_kde(es, chimera.CHIMERA_KDE_EPANECHNIKOV, 0)
-        try:
-            ge = {}
-            for name, prec in (("fp64", chimera.CHIMERA_FP64), ("fp32", chimera.CHIMERA_FP32)):
-                sec = time_grad(ctx, es, lam_g, prec, 3)
-                ge[name] = {"ms": round(sec * 1e3, 3),
-                            "over_gaussian": round(sec * 1e3 / g[name]["ms"], 3)}
-                log(f"grad epanechnikov {name}: {sec * 1e3:.2f} ms for {lam_g.shape[0]} lambda")
-            g["epanechnikov"] = ge
-        finally:
-            ctx.set_event_kde(es)
+        # the same points with the Epanechnikov kernel, and on 16-bin data sets
+        for label, shape, nbins in (("epanechnikov", chimera.CHIMERA_KDE_EPANECHNIKOV, 0),
+                                    ("gaussian_16_bins", chimera.CHIMERA_KDE_GAUSSIAN, 16)):
+            ctx.set_event_kde(es, shape, nbins)
+            try:
+                ge = {}
+                for name, prec in (("fp64", chimera.CHIMERA_FP64), ("fp32", chimera.CHIMERA_FP32)):
+                    sec = time_grad(ctx, es, lam_g, prec, 3)
+                    ge[name] = {"ms": round(sec * 1e3, 3),
+                                "over_gaussian": round(sec * 1e3 / g[name]["ms"], 3)}
+                    log(f"grad {label} {name}: {sec * 1e3:.2f} ms for {lam_g.shape[0]} lambda")
+                g[label] = ge
+            finally:
+                ctx.set_event_kde(es)
         line["grad"] = g
     if not args.no_variants:
         line["kernel_variants"] = variants_bench(ctx, es, p, ev, lam_t, res, args.steps,
