@@ -576,21 +576,35 @@ __device__ __forceinline__ void window_sums_epan(const CT* __restrict__ nrow,
 
 // Binned data sets (Sect. 2.3): each slot's n_bins equal-width bins over the
 // redshift range of its samples, a point at each bin's centre carrying its
-// samples' summed weight.  One wave per (slot, lambda), lanes over bins: a
-// bin's samples are a run of the slot's distance order (redshift order, as
-// d_L^gw increases), found by two binary searches with the forward pass's
-// bin arithmetic; the bin's c W, its d ln W/dp = sum c w d ln w/dp / sum c w
+// samples' summed weight.  One wave per (slot, lambda): a bin's samples are
+// a run of the slot's distance order (redshift order, as d_L^gw increases),
+// with the forward pass's bin arithmetic; the bin's c W, its d ln W/dp = sum c w d ln w/dp / sum c w
 // (the samples' bins held fixed) and its centre's dz/dp = (1 - f) dz_lo/dp +
 // f dz_hi/dp (f = (k + 1/2) / n_bins; the range's ends are the first and last
 // sample) go to bsc / bsd in the layout of the samples' sc / sd, so that
 // k_event_grad sums the bins as it sums samples.
+// Up to kBinScan bins per slot the sums come from one pass over the slot's
+// samples, 64 at a time, lanes over samples: the bins along the lanes never
+// decrease, so a segmented scan over the lanes sums each bin's run and the
+// run's last lane adds it to the bin's LDS accumulators (as the forward
+// binning kernel does); more bins take the binary searches below.
+constexpr int kBinScan = 128;
+
+__device__ __forceinline__ void wave_fence_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 template <bool F32>
 __global__ __launch_bounds__(kGradBS) void k_bin_grad(GradArgs a) {
   using CT = typename std::conditional<F32, float, double>::type;
   constexpr int SPB = kGradBS / 64;
+  __shared__ double bacc[SPB][kBinScan][1 + kNS];
   int it, b;
   if (!decode_item_lambda((a.n_slots + SPB - 1) / SPB, a.B, it, b)) return;
-  const int p = it * SPB + (int)(threadIdx.x >> 6);
+  const int wv = (int)(threadIdx.x >> 6);
+  const int p = it * SPB + wv;
   const int lane = threadIdx.x & 63;
   if (p >= a.n_slots) return;
   if (a.P[b].flag | a.flag_mono[b] | a.flag_range[b]) return;
@@ -618,17 +632,61 @@ __global__ __launch_bounds__(kGradBS) void k_bin_grad(GradArgs a) {
     }
     return lo;
   };
+  const bool scan = nb <= kBinScan;
+  double(*acc)[1 + kNS] = bacc[wv];
+  if (scan) {
+    for (int k = lane; k < nb; k += 64)
+#pragma unroll
+      for (int r = 0; r <= kNS; ++r) acc[k][r] = 0.0;
+    wave_fence_barrier();
+    for (int c0 = 0; c0 < n; c0 += 64) {
+      const int j = c0 + lane;
+      const bool valid = j < n;
+      int bin = 1 << 30;
+      double v[1 + kNS];
+#pragma unroll
+      for (int r = 0; r <= kNS; ++r) v[r] = 0.0;
+      if (valid) {
+        const int q = idx[j];
+        bin = bin_of(j);
+        v[0] = scb[S + q];
+#pragma unroll
+        for (int r = 0; r < kNS; ++r) v[1 + r] = v[0] * (double)sdb[(size_t)r * S + q];
+      }
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const int bu = __shfl_up(bin, o, 64);
+        const bool same = lane >= o && bu == bin;
+#pragma unroll
+        for (int r = 0; r <= kNS; ++r) {
+          const double u = __shfl_up(v[r], o, 64);
+          if (same) v[r] += u;
+        }
+      }
+      const int bn = __shfl_down(bin, 1, 64);
+      if (valid && (lane == 63 || bn != bin))
+#pragma unroll
+        for (int r = 0; r <= kNS; ++r) acc[bin][r] += v[r];
+      wave_fence_barrier();
+    }
+  }
   for (int k = lane; k < nb; k += 64) {
-    const int j1 = first_at_least(k), j2 = first_at_least(k + 1);
     double W = 0.0, D[kNS];
 #pragma unroll
     for (int q = 0; q < kNS; ++q) D[q] = 0.0;
-    for (int j = j1; j < j2; ++j) {
-      const int q = idx[j];
-      const double cw = scb[S + q];
-      W += cw;
+    if (scan) {
+      W = acc[k][0];
 #pragma unroll
-      for (int r = 0; r < kNS; ++r) D[r] += cw * (double)sdb[(size_t)r * S + q];
+      for (int r = 0; r < kNS; ++r) D[r] = acc[k][1 + r];
+    } else {
+      const int j1 = first_at_least(k), j2 = first_at_least(k + 1);
+      for (int j = j1; j < j2; ++j) {
+        const int q = idx[j];
+        const double cw = scb[S + q];
+        W += cw;
+#pragma unroll
+        for (int r = 0; r < kNS; ++r) D[r] += cw * (double)sdb[(size_t)r * S + q];
+      }
     }
     const long long o = (long long)p * nb + k;
     bsc[o] = width > 0.0 ? zlo + ((double)k + 0.5) * width : zlo;
