@@ -65,3 +65,38 @@ def test_binned_gradient_matches_oracle(small, kernel, shape, n_bins):
     e32 = rel_err(g32[fin], grad[fin])
     print(kernel, shape, n_bins, "FP32 vs FP64", e32.max())
     assert e32.max() <= 1e-2
+
+
+@pytest.mark.parametrize("kernel,shape", [("many1d", "gaussian"), ("single1d", "epanechnikov")])
+def test_binned_gradient_with_incomplete_catalogue(small, kernel, shape):
+    """Binned sets with an incomplete catalogue: the completed rows and their
+    Om derivative under the bins (16 per data set), against the oracle at
+    1e-8."""
+    import copy
+    from oracle import gradient as G
+    d, chimera, ctx, sets, lam = small
+    ev = sets[kernel]
+    p_rows, missing = synth.make_completeness(d.prep.row_pix, d.wl.nside, d.grid)
+    o_cat = copy.copy(d.o_cat)
+    o_cat.p_compl = {int(px): p_rows[i] for i, px in enumerate(d.prep.row_pix)}
+    o_cat.missing = missing
+    ctx.set_completeness(p_rows, missing)
+    ctx.set_event_kde(ev, SHAPES[shape], 16)
+    try:
+        lnl, grad = ctx.lnl_grad(ev, lam, chimera.CHIMERA_FP64)
+        lnl_f = ctx.lnl(ev, lam, chimera.CHIMERA_FP64)
+    finally:
+        ctx.set_event_kde(ev)
+        ctx.set_completeness(None)
+    fin = np.isfinite(lnl)
+    assert fin.sum() >= 3 and np.array_equal(np.isfinite(lnl_f), fin)
+    T = 8.6 if shape == "gaussian" else None
+    for b in range(lam.shape[0]):
+        ref = G.lnl_grad(d.o_events, o_cat, d.o_inj, lam[b], T=T, kernel=kernel, shape=shape,
+                         n_bins=16)
+        if not np.isfinite(ref["lnl"]):
+            assert not np.isfinite(lnl[b])
+            continue
+        assert abs(lnl[b] - ref["lnl"]) <= 1e-10 * max(1.0, abs(ref["lnl"])), (b, lnl[b])
+        err = rel_err(grad[b], ref["grad"])
+        assert np.all(err <= 1e-8), (b, err)
